@@ -1,0 +1,30 @@
+"""Build the CPU oracle shared library (gcc, no GPU code).
+
+Test infrastructure only: the resulting ``liboracle.so`` is loaded by the
+test suite, the smoke check and the benchmark's CPU-baseline leg.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["maxflow.c", "assignment.c"]
+TARGET = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    tmp = TARGET + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+           "-o", tmp] + srcs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, TARGET)
+    return TARGET
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

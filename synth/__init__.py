@@ -1,0 +1,21 @@
+"""Seeded synthetic inputs for both sides of every parity check.
+
+This module only draws random numbers and lays them out as int32 buffers; it
+contains none of the max-flow or assignment arithmetic.  The CPU oracle and
+the HIP library both consume exactly the arrays produced here.
+
+Every generator seeds ``numpy.random.default_rng`` with
+``SeedSequence([config_id, instance_id, seed])`` (PCG64); draw order is
+row-major and part of the definition of each workload.
+"""
+from .grids import (GridInstance, grid_uniform, grid_blobs, grid_batch,
+                    grid_random_small, grid_from_pairs)
+from .assign import (assign_uniform, assign_points, assign_batch,
+                     assign_random_small, TRAIN_BRANCH)
+
+__all__ = [
+    "GridInstance", "grid_uniform", "grid_blobs", "grid_batch",
+    "grid_random_small", "grid_from_pairs",
+    "assign_uniform", "assign_points", "assign_batch", "assign_random_small",
+    "TRAIN_BRANCH",
+]
