@@ -1,0 +1,275 @@
+/*
+ * lpr.h -- C ABI of the lock-free push-relabel library for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Two forms of the same lock-free push-relabel method ("Parallel
+ * implementation of flow and matching algorithms", A. Lupinska):
+ *
+ *   1. Maximum flow / minimum cut on 4-connected grid networks (Section 4:
+ *      flow network definitions in Section 3, the lock-free push/relabel of
+ *      Algorithm 4.5 with the global and gap relabelling of Section 4.2 and
+ *      Algorithm 4.8).
+ *   2. The dense assignment problem by cost scaling (Section 5: the reduction
+ *      to min-cost flow, the Min-Cost loop of Algorithm 5.0, the Refine of
+ *      Algorithm 5.2 and the lock-free push/relabel of Algorithm 5.4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers documented as "device" must be device memory of the current HIP
+ *    device (hipMalloc'd or a torch CUDA tensor); "host" pointers are read
+ *    only during the call.  All buffers are caller-owned; the library keeps
+ *    no pointer after it returns.
+ *  - `workspace` is a caller-owned device buffer of at least the size the
+ *    matching *_workspace() function returns (any alignment is accepted; the
+ *    library aligns internally).  The solve entry points allocate no device
+ *    memory of their own.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it and every solve call RETURNS AFTER COMPLETION
+ *    (it synchronises the stream), so the status covers convergence.
+ *  - The return code is the only error channel; the library never aborts.
+ *    lpr_last_error() gives a thread-local description of the last failure.
+ *  - Results that are unique (flow value, minimal source side, optimal
+ *    total cost) are deterministic.  The flow decomposition, the permutation
+ *    among equal-cost optima and the prices may differ between runs: this is
+ *    inherent to lock-free execution.
+ */
+#ifndef LPR_H
+#define LPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LPR_OK = 0,
+    LPR_EINVAL = -1,  /* bad shape, offset, pointer or a negative capacity */
+    LPR_ERANGE = -2,  /* a value too large for the fixed-width arithmetic  */
+    LPR_ENOMEM = -3,  /* workspace smaller than required                   */
+    LPR_EDEVICE = -4, /* a HIP runtime error (text in lpr_last_error)      */
+    LPR_EBUDGET = -5  /* the round / operation budget ran out              */
+} lpr_status;
+
+/* Thread-local, NUL-terminated description of the most recent failure of a
+ * call made by this thread ("" if none).  Owned by the library. */
+const char *lpr_last_error(void);
+
+/* Library version string, e.g. "lpr 0.1.0 gfx950".  Owned by the library. */
+const char *lpr_version(void);
+
+/* ======================================================================== */
+/* Form 1: 4-connected grid maximum flow / minimum cut                      */
+/* ======================================================================== */
+
+/* Limits: every capacity must lie in [0, LPR_GRID_MAX_CAP]; larger values
+ * give LPR_ERANGE.  Excesses and residuals are int32 on the device; with this
+ * bound no sum of a pixel's incident capacities can overflow. */
+#define LPR_GRID_MAX_CAP ((1 << 26) - 1)
+
+/* Option flags for lpr_grid_opts.flags. */
+#define LPR_GRID_TIME_KERNELS 0x1 /* time every push-sweep and BFS launch
+                                     with HIP events into lpr_grid_stats */
+
+typedef struct {
+    int32_t sweeps_per_relabel; /* push-sweep launches between global
+                                   relabels (the paper's CYCLE, counted in
+                                   launches); 0 = library default        */
+    int32_t local_iters;        /* push/relabel iterations each tile runs in
+                                   on-chip memory per sweep launch; 0 = def. */
+    int32_t tile_rows;          /* tile height in pixels: 8, 16 or 32 (tile
+                                   width is 64); 0 = library default      */
+    int32_t max_rounds;         /* budget of global-relabel rounds; 0 =
+                                   default (1 << 16)                       */
+    int32_t flags;              /* LPR_GRID_* bits                          */
+    int32_t reserved[3];        /* must be 0                                */
+} lpr_grid_opts;
+
+typedef struct {
+    int64_t rounds;          /* global relabels performed (BFS + gap)       */
+    int64_t sweeps;          /* push-sweep launches                         */
+    int64_t bfs_passes;      /* tile-relaxation launches of the BFS         */
+    int64_t tiles_swept;     /* tiles processed, summed over sweep launches */
+    int64_t pushes;          /* push operations                             */
+    int64_t relabels;        /* relabel operations                          */
+    int64_t cut_passes;      /* tile-relaxation launches of the cut closure */
+    int32_t tile_rows;       /* tile height actually used                   */
+    int32_t local_iters;     /* local iterations actually used              */
+    int32_t sweeps_per_relabel;
+    int32_t reserved;
+    double sweep_ms;         /* with LPR_GRID_TIME_KERNELS: summed duration
+                                of all push-sweep launches (HIP events)    */
+    double bfs_ms;           /* same, for the BFS relaxation launches       */
+    double total_ms;         /* wall time of the device work (HIP events)   */
+} lpr_grid_stats;
+
+/* Device workspace bytes needed by lpr_grid_maxflow for an H x W grid. */
+size_t lpr_grid_maxflow_workspace(int32_t H, int32_t W);
+
+/*
+ * Maximum s-t flow value and minimal minimum-cut source side of one grid.
+ *
+ * Network (Section 3; grid construction of Section 4.3): nodes are the H*W
+ * pixels p = i*W + j (row-major) plus a source s and a sink t.  Arcs:
+ *   s -> p     capacity cap_src[p]
+ *   p -> t     capacity cap_snk[p]
+ *   p -> p+1   capacity cap_right[p]  (ignored in the last column)
+ *   p -> p-1   capacity cap_left[p]   (ignored in the first column)
+ *   p -> p+W   capacity cap_down[p]   (ignored in the last row)
+ *   p -> p-W   capacity cap_up[p]     (ignored in the first row)
+ * All six arrays are device int32 [H*W], read only.
+ *
+ * Outputs (device):
+ *   flow_value   int64 [1]: |f*|, the maximum flow value = min cut capacity.
+ *   source_side  uint8 [H*W] or NULL: 1 iff p belongs to S_min, the source
+ *                side of the unique minimal minimum cut (the residual closure
+ *                of the pixels that hold excess in the maximum preflow).
+ * opts may be NULL (defaults).  stats may be NULL.
+ * Errors: LPR_EINVAL (H or W < 1, H*W >= 2^30, NULL inputs, negative
+ * capacity), LPR_ERANGE (capacity > LPR_GRID_MAX_CAP), LPR_ENOMEM (workspace
+ * too small), LPR_EBUDGET (max_rounds exhausted, or a global relabel that
+ * needs more tile passes than 16 x tiles + 1024; outputs unspecified),
+ * LPR_EDEVICE.
+ */
+lpr_status lpr_grid_maxflow(int32_t H, int32_t W,
+                            const int32_t *cap_src, const int32_t *cap_snk,
+                            const int32_t *cap_right, const int32_t *cap_left,
+                            const int32_t *cap_down, const int32_t *cap_up,
+                            int64_t *flow_value, uint8_t *source_side,
+                            const lpr_grid_opts *opts, lpr_grid_stats *stats,
+                            void *workspace, size_t workspace_bytes,
+                            void *stream);
+
+/* Device workspace bytes for lpr_grid_maxflow_batched (H, W: host [B]). */
+size_t lpr_grid_maxflow_batched_workspace(int32_t B, const int32_t *H,
+                                          const int32_t *W);
+
+/*
+ * B independent grid networks solved together: every phase launch covers the
+ * tiles of all unfinished instances, and finished instances retire.
+ *   H, W         host int32 [B]: shape of instance b.
+ *   node_offset  host int64 [B+1]: node_offset[0] = 0 and node_offset[b+1] =
+ *                node_offset[b] + H[b]*W[b]; instance b occupies elements
+ *                [node_offset[b], node_offset[b+1]) of every packed array.
+ *   cap_*        device int32 [node_offset[B]], packed as above, each
+ *                instance laid out as in lpr_grid_maxflow.
+ *   flow_values  device int64 [B].
+ *   source_side  device uint8 [node_offset[B]] (packed) or NULL.
+ * Errors as for lpr_grid_maxflow; offsets that are not the prefix sums of
+ * H*W give LPR_EINVAL.
+ */
+lpr_status lpr_grid_maxflow_batched(int32_t B, const int32_t *H,
+                                    const int32_t *W,
+                                    const int64_t *node_offset,
+                                    const int32_t *cap_src,
+                                    const int32_t *cap_snk,
+                                    const int32_t *cap_right,
+                                    const int32_t *cap_left,
+                                    const int32_t *cap_down,
+                                    const int32_t *cap_up,
+                                    int64_t *flow_values,
+                                    uint8_t *source_side,
+                                    const lpr_grid_opts *opts,
+                                    lpr_grid_stats *stats, void *workspace,
+                                    size_t workspace_bytes, void *stream);
+
+/* ======================================================================== */
+/* Form 2: dense assignment by cost scaling                                  */
+/* ======================================================================== */
+
+/* Costs must satisfy |c| <= LPR_ASSIGN_MAX_COST; n <= LPR_ASSIGN_MAX_N. */
+#define LPR_ASSIGN_MAX_COST ((1 << 24) - 1)
+#define LPR_ASSIGN_MAX_N 2048
+
+#define LPR_ASSIGN_TIME_KERNELS 0x1 /* time the solve kernel with HIP events */
+
+typedef struct {
+    int32_t alpha;                  /* epsilon divisor per refine; 0 -> 8    */
+    int32_t flags;                  /* LPR_ASSIGN_* bits                     */
+    int64_t eps0;                   /* initial epsilon of the Min-Cost loop in
+                                       scaled units (costs times 2n+1); the
+                                       first refine runs at eps0/alpha.
+                                       0 -> max|c| * (2n+1)                  */
+    const int64_t *init_col_prices; /* device int64 [n] (packed for batched)
+                                       scaled starting prices of Y, or NULL
+                                       for all zero                          */
+    int64_t max_ops;                /* budget of push+relabel operations per
+                                       instance; 0 -> 64 n^2 + 2^20          */
+    int64_t max_ms;                 /* wall-clock budget of the solve kernel,
+                                       checked on the device after every
+                                       phase; 0 -> 20000 ms                  */
+    int64_t reserved;               /* must be 0                             */
+} lpr_assign_opts;
+
+typedef struct {
+    int64_t refines;    /* refine calls (summed over instances)           */
+    int64_t phases;     /* X-phase / Y-phase rounds (summed)              */
+    int64_t pushes;     /* push operations                                */
+    int64_t relabels;   /* relabel operations                             */
+    int64_t scans;      /* arc scans of X rows (each reads n costs)       */
+    int64_t reserved[3];
+    double kernel_ms;   /* with LPR_ASSIGN_TIME_KERNELS: solve kernel time */
+    double total_ms;    /* device time of the whole call (HIP events)      */
+} lpr_assign_stats;
+
+/* Device workspace bytes needed by lpr_assign_solve for size n. */
+size_t lpr_assign_workspace(int32_t n);
+
+/*
+ * Optimal assignment of the complete bipartite graph X x Y, |X| = |Y| = n,
+ * given as a device int32 row-major n x n matrix `cost` (row x in X, column y
+ * in Y).  maximize = 1 solves the problem as stated in Section 3 (maximum
+ * total weight; internally the weights are negated), maximize = 0 minimises.
+ *
+ * Method (Section 5): costs are scaled by S = 2n+1; starting from eps0 the
+ * Min-Cost loop runs Refine at eps <- max(1, floor(eps/alpha)) until a refine
+ * at eps = 1 (i.e. 1/(2n+1) < 1/n in cost units) has finished.  Each refine
+ * unmatches everything, sets row prices by Algorithm 5.2 and applies the
+ * push/relabel of Algorithm 5.4 to active nodes until the pseudoflow is a
+ * flow (a perfect matching).  The result is optimal for any starting prices.
+ *
+ * Outputs (device): row_to_col int32 [n] (a permutation), total int64 [1]
+ * (sum of the given cost entries on the assignment), col_prices int64 [n] or
+ * NULL (final scaled prices of Y for the minimised costs, a 1-optimality
+ * certificate together with the assignment).
+ * Errors: LPR_EINVAL (n < 1 or n > LPR_ASSIGN_MAX_N, NULL pointers),
+ * LPR_ERANGE (|cost| > LPR_ASSIGN_MAX_COST), LPR_ENOMEM, LPR_EBUDGET,
+ * LPR_EDEVICE.
+ */
+lpr_status lpr_assign_solve(int32_t n, const int32_t *cost, int32_t maximize,
+                            int32_t *row_to_col, int64_t *total,
+                            int64_t *col_prices, const lpr_assign_opts *opts,
+                            lpr_assign_stats *stats, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/* Device workspace bytes for lpr_assign_solve_batched (n: host [B]). */
+size_t lpr_assign_batched_workspace(int32_t B, const int32_t *n);
+
+/*
+ * B independent assignment instances solved in one launch (one workgroup
+ * per instance, largest first).
+ *   n            host int32 [B].
+ *   cost_offset  host int64 [B+1]: prefix sums of n[b]^2; instance b's matrix
+ *                is costs[cost_offset[b] .. cost_offset[b+1]) (row-major).
+ *   costs        device int32 [cost_offset[B]].
+ *   row_to_col   device int32 [sum n] packed by the prefix sums of n.
+ *   totals       device int64 [B].
+ *   col_prices   device int64 [sum n] packed, or NULL.
+ *   opts->init_col_prices, when given, is packed like col_prices.
+ * Errors as for lpr_assign_solve.
+ */
+lpr_status lpr_assign_solve_batched(int32_t B, const int32_t *n,
+                                    const int64_t *cost_offset,
+                                    const int32_t *costs, int32_t maximize,
+                                    int32_t *row_to_col, int64_t *totals,
+                                    int64_t *col_prices,
+                                    const lpr_assign_opts *opts,
+                                    lpr_assign_stats *stats, void *workspace,
+                                    size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPR_H */

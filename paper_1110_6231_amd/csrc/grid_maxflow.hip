@@ -1,0 +1,1016 @@
+// Form 1: lock-free push-relabel maximum flow / minimum cut on 4-connected
+// grid networks, for gfx950.
+//
+// Method (Section 4): Hong's lock-free push-relabel (Algorithm 4.5) -- every
+// active pixel finds its lowest residual neighbour and either pushes
+// min(e, u_f) to it with atomic updates of the two residuals and the two
+// excesses, or relabels itself to that neighbour's height + 1 with a plain
+// store (only the owner writes its height).  Phases of pushing alternate with
+// an exact global relabel (backward BFS from t, Algorithm 4.4) followed by the
+// gap step (unscanned pixels get h = |V|), as in the hybrid scheme of
+// Algorithm 4.8 and Section 4.6.  The run stops when, right after a global
+// relabel, no pixel has e > 0 and h < |V| (equivalent to e(s) + e(t) reaching
+// ExcessTotal).  The maximum flow value is e(t) = sum_p (cap_snk - u_f(p,t));
+// the minimal cut side is the residual closure of the pixels with excess.
+//
+// GPU design (not the paper's Fermi design):
+//  * SoA state, one int32 array each for e, h, and the residuals of p->right,
+//    p->left, p->down, p->up and p->t; the arc p->s is never used again after
+//    the initial saturation (pixels with h >= |V| are never discharged).
+//  * 64 x TH tiles, one 256-thread workgroup per tile.  A sweep launch loads a
+//    tile into LDS and runs `local_iters` lock-free iterations there with LDS
+//    atomics; pushes that cross the tile edge go straight to global memory
+//    with device-scope atomics, and the tile's own edge values are merged back
+//    by atomic deltas.  Every value a pixel reads of another pixel is a lower
+//    bound of the true one (excess and residuals are only decreased by their
+//    owner, heights only grow between global relabels), which is exactly the
+//    staleness Hong's argument admits.
+//  * Active-tile flags double-buffered across sweep launches so that quiet
+//    tiles cost one flag read.
+//  * The BFS (and the cut closure) is a Bellman-Ford style relaxation run to a
+//    local fixpoint inside each LDS tile; tiles whose edge values changed mark
+//    their neighbours dirty, and passes repeat until no tile is dirty.  The
+//    least fixpoint is exactly the BFS level of every pixel.
+//  * Batched solves share every launch: the tile table spans all instances,
+//    and an instance whose count reaches zero retires from later rounds.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <vector>
+
+#include "lpr_internal.h"
+
+namespace lpr {
+namespace grid {
+
+constexpr int TW = 64;        // tile width: one wavefront per tile row
+constexpr int NT = 256;       // threads per tile workgroup
+constexpr int RPP = NT / TW;  // tile rows covered per thread pass (4)
+constexpr int MAX_PASS_SLOTS = 64;
+
+struct Inst {
+    int64_t off;      // first pixel of the instance in the packed arrays
+    int32_t H, W;
+    int32_t tiles_x, tiles_y;
+    int32_t tile_base;
+    int32_t HV;       // |V| = H*W + 2, the gap height
+};
+
+struct Scalars {
+    unsigned long long total_active;
+    int32_t err;
+    int32_t pad;
+    int32_t pass_count[MAX_PASS_SLOTS];
+};
+
+struct Dev {
+    int32_t *e, *h, *rr, *rl, *rd, *ru, *rs;
+    const int32_t *cap_src, *cap_snk, *cap_r, *cap_l, *cap_d, *cap_u;
+    const Inst *inst;
+    const int32_t *tile_inst;
+    unsigned long long *inst_active;  // per-instance active pixels (last count)
+    int32_t *done;                    // per-instance: no active pixel left
+    unsigned long long *counters;     // pushes, relabels, tiles swept
+    Scalars *sc;
+    int32_t ntiles;
+    int32_t ninst;
+};
+
+struct Geo {
+    int inst, H, W, HV, y0, x0, tx, ty, tiles_x, tiles_y;
+    int64_t off;
+};
+
+template <int TH>
+__device__ inline Geo tile_geo(const Dev &D, int t) {
+    Geo g;
+    g.inst = D.tile_inst[t];
+    const Inst I = D.inst[g.inst];
+    g.H = I.H;
+    g.W = I.W;
+    g.HV = I.HV;
+    g.off = I.off;
+    g.tiles_x = I.tiles_x;
+    g.tiles_y = I.tiles_y;
+    int lt = t - I.tile_base;
+    g.ty = lt / I.tiles_x;
+    g.tx = lt - g.ty * I.tiles_x;
+    g.y0 = g.ty * TH;
+    g.x0 = g.tx * TW;
+    return g;
+}
+
+// Loads the one-pixel halo of a tile's labels/heights into rows 0 and TH+1
+// and columns 0 and TW+1 of `s` (|V| outside the grid); corners unused.
+template <int TH>
+__device__ inline void load_halo(const Dev &D, const Geo &g, int c,
+                                 int32_t (*s)[TW + 2]) {
+    const int tid = threadIdx.x;
+    const int x = g.x0 + c;
+    if (tid < TW) {
+        int32_t v = g.HV;
+        if (x < g.W && g.y0 > 0) v = D.h[g.off + int64_t(g.y0 - 1) * g.W + x];
+        s[0][c + 1] = v;
+    } else if (tid < 2 * TW) {
+        int32_t v = g.HV;
+        if (x < g.W && g.y0 + TH < g.H)
+            v = D.h[g.off + int64_t(g.y0 + TH) * g.W + x];
+        s[TH + 1][c + 1] = v;
+    } else if (tid < 2 * TW + TH) {
+        const int r = tid - 2 * TW, y = g.y0 + r;
+        int32_t v = g.HV;
+        if (y < g.H && g.x0 > 0) v = D.h[g.off + int64_t(y) * g.W + g.x0 - 1];
+        s[r + 1][0] = v;
+    } else if (tid < 2 * TW + 2 * TH) {
+        const int r = tid - 2 * TW - TH, y = g.y0 + r;
+        int32_t v = g.HV;
+        if (y < g.H && g.x0 + TW < g.W)
+            v = D.h[g.off + int64_t(y) * g.W + g.x0 + TW];
+        s[r + 1][TW + 1] = v;
+    }
+}
+
+__device__ inline unsigned long long block_sum_u64(unsigned long long v) {
+    __shared__ unsigned long long red[NT / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    unsigned long long s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// Init (Algorithm 4.5 / 4.7): u_f = u on pixel arcs and pixel->t, the source
+// arcs saturated (e(p) = u(s,p)), h = 0.  Border arcs that would leave the
+// grid get residual 0.  Capacities are validated on the way.
+// ---------------------------------------------------------------------------
+template <int TH>
+__global__ __launch_bounds__(NT) void k_init(Dev D) {
+    const Geo g = tile_geo<TH>(D, blockIdx.x);
+    const int c = threadIdx.x & (TW - 1);
+    int bad = 0;
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int r = (threadIdx.x >> 6) + RPP * k;
+        const int y = g.y0 + r, x = g.x0 + c;
+        if (y >= g.H || x >= g.W) continue;
+        const int64_t p = g.off + int64_t(y) * g.W + x;
+        const int32_t src = D.cap_src[p], snk = D.cap_snk[p];
+        const int32_t cr = (x + 1 < g.W) ? D.cap_r[p] : 0;
+        const int32_t cl = (x > 0) ? D.cap_l[p] : 0;
+        const int32_t cd = (y + 1 < g.H) ? D.cap_d[p] : 0;
+        const int32_t cu = (y > 0) ? D.cap_u[p] : 0;
+        const int32_t mn = min(min(min(src, snk), min(cr, cl)), min(cd, cu));
+        const int32_t mx = max(max(max(src, snk), max(cr, cl)), max(cd, cu));
+        if (mn < 0) bad |= 1;
+        if (mx > LPR_GRID_MAX_CAP) bad |= 2;
+        D.e[p] = src;
+        D.rs[p] = snk;
+        D.rr[p] = cr;
+        D.rl[p] = cl;
+        D.rd[p] = cd;
+        D.ru[p] = cu;
+        D.h[p] = 0;
+    }
+    if (bad) atomicOr(&D.sc->err, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Global relabel seed (Algorithm 4.4 from t): level 1 for pixels with a
+// residual arc to t, |V| (= "not scanned") elsewhere.  Tiles of retired
+// instances are left untouched and not marked.
+// ---------------------------------------------------------------------------
+template <int TH>
+__global__ __launch_bounds__(NT) void k_bfs_seed(Dev D, int32_t *dirty_cur,
+                                                 int32_t *dirty_next) {
+    const int t = blockIdx.x;
+    const Geo g = tile_geo<TH>(D, t);
+    const bool retired = D.done[g.inst] != 0;
+    if (threadIdx.x == 0) {
+        dirty_cur[t] = retired ? 0 : 1;
+        dirty_next[t] = 0;
+    }
+    if (retired) return;
+    const int c = threadIdx.x & (TW - 1);
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int r = (threadIdx.x >> 6) + RPP * k;
+        const int y = g.y0 + r, x = g.x0 + c;
+        if (y >= g.H || x >= g.W) continue;
+        const int64_t p = g.off + int64_t(y) * g.W + x;
+        D.h[p] = D.rs[p] > 0 ? 1 : g.HV;
+    }
+}
+
+// Cut-closure seed: label 0 for pixels holding excess, |V| elsewhere.
+template <int TH>
+__global__ __launch_bounds__(NT) void k_cut_seed(Dev D, int32_t *dirty_cur,
+                                                 int32_t *dirty_next) {
+    const int t = blockIdx.x;
+    const Geo g = tile_geo<TH>(D, t);
+    if (threadIdx.x == 0) {
+        dirty_cur[t] = 1;
+        dirty_next[t] = 0;
+    }
+    const int c = threadIdx.x & (TW - 1);
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int r = (threadIdx.x >> 6) + RPP * k;
+        const int y = g.y0 + r, x = g.x0 + c;
+        if (y >= g.H || x >= g.W) continue;
+        const int64_t p = g.off + int64_t(y) * g.W + x;
+        D.h[p] = D.e[p] > 0 ? 0 : g.HV;
+    }
+}
+
+template <int TH>
+__global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
+    const Geo g = tile_geo<TH>(D, blockIdx.x);
+    const int c = threadIdx.x & (TW - 1);
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int r = (threadIdx.x >> 6) + RPP * k;
+        const int y = g.y0 + r, x = g.x0 + c;
+        if (y >= g.H || x >= g.W) continue;
+        const int64_t p = g.off + int64_t(y) * g.W + x;
+        side[p] = D.h[p] < g.HV ? 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile relaxation to a local fixpoint.
+//   BFS (CUT = false): lab(p) = min(lab(p), lab(q) + 1) over arcs p->q with
+//     u_f > 0 -- the backward BFS of Algorithm 4.4 from t; its least fixpoint
+//     is the BFS level, |V| where t is unreachable (the gap of Section 4.2).
+//   CUT (CUT = true):  lab(p) = min(lab(p), lab(q)) over arcs q->p with
+//     u_f > 0 -- forward reachability from the excess pixels.
+// ---------------------------------------------------------------------------
+template <int TH, bool CUT>
+__global__ __launch_bounds__(NT) void k_relax(Dev D, int32_t *dirty_cur,
+                                              int32_t *dirty_next,
+                                              int32_t *pass_count) {
+    const int t = blockIdx.x;
+    if (!__syncthreads_or(dirty_cur[t] != 0)) return;
+    if (threadIdx.x == 0) dirty_cur[t] = 0;
+    const Geo g = tile_geo<TH>(D, t);
+    constexpr int NP = TH / RPP;
+    constexpr int INC = CUT ? 0 : 1;
+    __shared__ int32_t s_d[TH + 2][TW + 2];
+    __shared__ int32_t s_edge;
+    const int c = threadIdx.x & (TW - 1);
+    const int r0 = threadIdx.x >> 6;
+    const int HV = g.HV;
+    int32_t dreg[NP], dld[NP];
+    uint32_t mask[NP];
+    if (threadIdx.x == 0) s_edge = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int r = r0 + RPP * k;
+        const int y = g.y0 + r, x = g.x0 + c;
+        int32_t d = HV;
+        uint32_t m = 0;
+        if (y < g.H && x < g.W) {
+            const int64_t p = g.off + int64_t(y) * g.W + x;
+            d = D.h[p];
+            if (!CUT) {
+                m = (D.rr[p] > 0 ? 1u : 0u) | (D.rl[p] > 0 ? 2u : 0u) |
+                    (D.rd[p] > 0 ? 4u : 0u) | (D.ru[p] > 0 ? 8u : 0u);
+            } else {
+                if (x + 1 < g.W && D.rl[p + 1] > 0) m |= 1u;
+                if (x > 0 && D.rr[p - 1] > 0) m |= 2u;
+                if (y + 1 < g.H && D.ru[p + g.W] > 0) m |= 4u;
+                if (y > 0 && D.rd[p - g.W] > 0) m |= 8u;
+            }
+        }
+        dreg[k] = d;
+        dld[k] = d;
+        mask[k] = m;
+        s_d[r + 1][c + 1] = d;
+    }
+    // halo: the row above, the row below, the column left and right
+    load_halo<TH>(D, g, c, s_d);
+    __syncthreads();
+    for (;;) {
+        bool changed = false;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int r = r0 + RPP * k;
+            const uint32_t m = mask[k];
+            if (!m) continue;
+            int32_t nd = dreg[k];
+            if (m & 1u) nd = min(nd, s_d[r + 1][c + 2] + INC);
+            if (m & 2u) nd = min(nd, s_d[r + 1][c] + INC);
+            if (m & 4u) nd = min(nd, s_d[r + 2][c + 1] + INC);
+            if (m & 8u) nd = min(nd, s_d[r][c + 1] + INC);
+            if (nd < dreg[k]) {
+                dreg[k] = nd;
+                s_d[r + 1][c + 1] = nd;
+                changed = true;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    int edge = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        if (dreg[k] == dld[k]) continue;
+        const int r = r0 + RPP * k;
+        const int64_t p = g.off + int64_t(g.y0 + r) * g.W + g.x0 + c;
+        D.h[p] = dreg[k];
+        if (c == TW - 1) edge |= 1;
+        if (c == 0) edge |= 2;
+        if (r == TH - 1) edge |= 4;
+        if (r == 0) edge |= 8;
+    }
+    if (edge) atomicOr(&s_edge, edge);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_edge) {
+        const int e = s_edge;
+        int nb[4] = {-1, -1, -1, -1};
+        if ((e & 1) && g.tx + 1 < g.tiles_x) nb[0] = t + 1;
+        if ((e & 2) && g.tx > 0) nb[1] = t - 1;
+        if ((e & 4) && g.ty + 1 < g.tiles_y) nb[2] = t + g.tiles_x;
+        if ((e & 8) && g.ty > 0) nb[3] = t - g.tiles_x;
+        for (int i = 0; i < 4; ++i)
+            if (nb[i] >= 0 && atomicExch(&dirty_next[nb[i]], 1) == 0)
+                atomicAdd(pass_count, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Count active pixels (e > 0, h < |V|) right after a global relabel; seeds
+// the active-tile flags of the next push phase.
+// ---------------------------------------------------------------------------
+template <int TH>
+__global__ __launch_bounds__(NT) void k_count(Dev D, int32_t *act_cur,
+                                              int32_t *act_next) {
+    const int t = blockIdx.x;
+    const Geo g = tile_geo<TH>(D, t);
+    unsigned long long cnt = 0;
+    if (!D.done[g.inst]) {
+        const int c = threadIdx.x & (TW - 1);
+#pragma unroll
+        for (int k = 0; k < TH / RPP; ++k) {
+            const int r = (threadIdx.x >> 6) + RPP * k;
+            const int y = g.y0 + r, x = g.x0 + c;
+            if (y >= g.H || x >= g.W) continue;
+            const int64_t p = g.off + int64_t(y) * g.W + x;
+            cnt += (D.e[p] > 0 && D.h[p] < g.HV) ? 1 : 0;
+        }
+    }
+    const unsigned long long s = block_sum_u64(cnt);
+    if (threadIdx.x == 0) {
+        act_cur[t] = s > 0 ? 1 : 0;
+        act_next[t] = 0;
+        if (s) atomicAdd(&D.inst_active[g.inst], s);
+    }
+}
+
+// Retire instances with no active pixel and publish the total.
+__global__ void k_count_finish(Dev D) {
+    unsigned long long tot = 0;
+    for (int i = threadIdx.x; i < D.ninst; i += blockDim.x) {
+        const unsigned long long a = D.inst_active[i];
+        if (a == 0) D.done[i] = 1;
+        tot += a;
+    }
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+    __shared__ unsigned long long red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+        D.sc->total_active = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Push sweep: `L` lock-free push/relabel iterations of Algorithm 4.5 per
+// active tile, in LDS.
+// ---------------------------------------------------------------------------
+template <int TH>
+__global__ __launch_bounds__(NT) void k_sweep(Dev D, int32_t *act_cur,
+                                              int32_t *act_next, int L) {
+    const int t = blockIdx.x;
+    if (!__syncthreads_or(act_cur[t] != 0)) return;
+    if (threadIdx.x == 0) act_cur[t] = 0;
+    const Geo g = tile_geo<TH>(D, t);
+    constexpr int NP = TH / RPP;
+    __shared__ int32_t s_e[TH][TW], s_rr[TH][TW], s_rl[TH][TW], s_rd[TH][TW],
+        s_ru[TH][TW];
+    __shared__ int32_t s_h[TH + 2][TW + 2];
+    const int c = threadIdx.x & (TW - 1);
+    const int r0 = threadIdx.x >> 6;
+    const int HV = g.HV;
+    int32_t hreg[NP], rsreg[NP], h0[NP], rs0[NP], e0[NP], rr0[NP], rl0[NP],
+        rd0[NP], ru0[NP];
+    uint32_t valid = 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int r = r0 + RPP * k;
+        const int y = g.y0 + r, x = g.x0 + c;
+        int32_t e = 0, h = HV, rs = 0, rr = 0, rl = 0, rd = 0, ru = 0;
+        if (y < g.H && x < g.W) {
+            valid |= 1u << k;
+            const int64_t p = g.off + int64_t(y) * g.W + x;
+            e = D.e[p];
+            h = D.h[p];
+            rs = D.rs[p];
+            rr = D.rr[p];
+            rl = D.rl[p];
+            rd = D.rd[p];
+            ru = D.ru[p];
+        }
+        e0[k] = e;
+        h0[k] = h;
+        hreg[k] = h;
+        rs0[k] = rs;
+        rsreg[k] = rs;
+        rr0[k] = rr;
+        rl0[k] = rl;
+        rd0[k] = rd;
+        ru0[k] = ru;
+        s_e[r][c] = e;
+        s_rr[r][c] = rr;
+        s_rl[r][c] = rl;
+        s_rd[r][c] = rd;
+        s_ru[r][c] = ru;
+        s_h[r + 1][c + 1] = h;
+    }
+    load_halo<TH>(D, g, c, s_h);
+    __syncthreads();
+
+    unsigned pushes = 0, relabels = 0;
+    for (int it = 0; it < L; ++it) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            if (!((valid >> k) & 1u)) continue;
+            const int r = r0 + RPP * k;
+            const int32_t e = s_e[r][c];
+            const int32_t hh = hreg[k];
+            if (e <= 0 || hh >= HV) continue;
+            any = true;
+            // lowest residual neighbour; scan order t, right, left, down, up
+            int32_t best = INT_MAX, cap = 0;
+            int dir = -1;
+            if (rsreg[k] > 0) {
+                best = 0;
+                dir = 0;
+                cap = rsreg[k];
+            }
+            // residual arcs leaving the grid are 0 by construction; the
+            // position tests only guard the atomics below
+            const int gx = g.x0 + c, gy = g.y0 + r;
+            const int32_t vr = s_rr[r][c];
+            if (vr > 0 && gx + 1 < g.W) {
+                const int32_t hq = s_h[r + 1][c + 2];
+                if (hq < best) { best = hq; dir = 1; cap = vr; }
+            }
+            const int32_t vl = s_rl[r][c];
+            if (vl > 0 && gx > 0) {
+                const int32_t hq = s_h[r + 1][c];
+                if (hq < best) { best = hq; dir = 2; cap = vl; }
+            }
+            const int32_t vd = s_rd[r][c];
+            if (vd > 0 && gy + 1 < g.H) {
+                const int32_t hq = s_h[r + 2][c + 1];
+                if (hq < best) { best = hq; dir = 3; cap = vd; }
+            }
+            const int32_t vu = s_ru[r][c];
+            if (vu > 0 && gy > 0) {
+                const int32_t hq = s_h[r][c + 1];
+                if (hq < best) { best = hq; dir = 4; cap = vu; }
+            }
+            if (dir >= 0 && hh > best) {
+                // PUSH delta = min(e', u_f(x, y~)) towards y~
+                const int32_t d = min(e, cap);
+                atomicSub(&s_e[r][c], d);
+                const int64_t p = g.off + int64_t(gy) * g.W + gx;
+                switch (dir) {
+                    case 0:
+                        rsreg[k] -= d;
+                        break;
+                    case 1:
+                        atomicSub(&s_rr[r][c], d);
+                        if (c + 1 < TW) {
+                            atomicAdd(&s_rl[r][c + 1], d);
+                            atomicAdd(&s_e[r][c + 1], d);
+                        } else {
+                            atomicAdd(&D.rl[p + 1], d);
+                            atomicAdd(&D.e[p + 1], d);
+                            act_next[t + 1] = 1;
+                        }
+                        break;
+                    case 2:
+                        atomicSub(&s_rl[r][c], d);
+                        if (c > 0) {
+                            atomicAdd(&s_rr[r][c - 1], d);
+                            atomicAdd(&s_e[r][c - 1], d);
+                        } else {
+                            atomicAdd(&D.rr[p - 1], d);
+                            atomicAdd(&D.e[p - 1], d);
+                            act_next[t - 1] = 1;
+                        }
+                        break;
+                    case 3:
+                        atomicSub(&s_rd[r][c], d);
+                        if (r + 1 < TH) {
+                            atomicAdd(&s_ru[r + 1][c], d);
+                            atomicAdd(&s_e[r + 1][c], d);
+                        } else {
+                            atomicAdd(&D.ru[p + g.W], d);
+                            atomicAdd(&D.e[p + g.W], d);
+                            act_next[t + g.tiles_x] = 1;
+                        }
+                        break;
+                    default:
+                        atomicSub(&s_ru[r][c], d);
+                        if (r > 0) {
+                            atomicAdd(&s_rd[r - 1][c], d);
+                            atomicAdd(&s_e[r - 1][c], d);
+                        } else {
+                            atomicAdd(&D.rd[p - g.W], d);
+                            atomicAdd(&D.e[p - g.W], d);
+                            act_next[t - g.tiles_x] = 1;
+                        }
+                        break;
+                }
+                ++pushes;
+            } else {
+                // RELABEL h(x) = h~ + 1 (owner-only store); no residual arc
+                // or a height past |V| freezes the pixel (gap height).
+                const int32_t nh = (dir < 0 || best >= HV - 1) ? HV : best + 1;
+                hreg[k] = nh;
+                s_h[r + 1][c + 1] = nh;
+                ++relabels;
+            }
+        }
+        if (!__syncthreads_or(any)) break;
+    }
+    __syncthreads();
+
+    bool active_end = false;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        if (!((valid >> k) & 1u)) continue;
+        const int r = r0 + RPP * k;
+        const int y = g.y0 + r, x = g.x0 + c;
+        const int64_t p = g.off + int64_t(y) * g.W + x;
+        const bool xr = (c == TW - 1) && (x + 1 < g.W);
+        const bool xl = (c == 0) && (x > 0);
+        const bool xd = (r == TH - 1) && (y + 1 < g.H);
+        const bool xu = (r == 0) && (y > 0);
+        const int32_t e = s_e[r][c];
+        if (e != e0[k]) {
+            if (xr | xl | xd | xu) atomicAdd(&D.e[p], e - e0[k]);
+            else D.e[p] = e;
+        }
+        if (hreg[k] != h0[k]) D.h[p] = hreg[k];
+        if (rsreg[k] != rs0[k]) D.rs[p] = rsreg[k];
+        int32_t v = s_rr[r][c];
+        if (v != rr0[k]) {
+            if (xr) atomicAdd(&D.rr[p], v - rr0[k]);
+            else D.rr[p] = v;
+        }
+        v = s_rl[r][c];
+        if (v != rl0[k]) {
+            if (xl) atomicAdd(&D.rl[p], v - rl0[k]);
+            else D.rl[p] = v;
+        }
+        v = s_rd[r][c];
+        if (v != rd0[k]) {
+            if (xd) atomicAdd(&D.rd[p], v - rd0[k]);
+            else D.rd[p] = v;
+        }
+        v = s_ru[r][c];
+        if (v != ru0[k]) {
+            if (xu) atomicAdd(&D.ru[p], v - ru0[k]);
+            else D.ru[p] = v;
+        }
+        active_end |= (e > 0 && hreg[k] < HV);
+    }
+    if (__syncthreads_or(active_end) && threadIdx.x == 0) act_next[t] = 1;
+    const unsigned long long sp = block_sum_u64(pushes);
+    const unsigned long long srl = block_sum_u64(relabels);
+    if (threadIdx.x == 0) {
+        if (sp) atomicAdd(&D.counters[0], sp);
+        if (srl) atomicAdd(&D.counters[1], srl);
+        atomicAdd(&D.counters[2], 1ull);
+    }
+}
+
+// Flow value e(t) = sum_p (u(p,t) - u_f(p,t)) per instance (int64).
+template <int TH>
+__global__ __launch_bounds__(NT) void k_flow_value(Dev D, int64_t *flow) {
+    const Geo g = tile_geo<TH>(D, blockIdx.x);
+    const int c = threadIdx.x & (TW - 1);
+    unsigned long long s = 0;
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int r = (threadIdx.x >> 6) + RPP * k;
+        const int y = g.y0 + r, x = g.x0 + c;
+        if (y >= g.H || x >= g.W) continue;
+        const int64_t p = g.off + int64_t(y) * g.W + x;
+        s += (unsigned long long)(int64_t(D.cap_snk[p]) - D.rs[p]);
+    }
+    const unsigned long long tot = block_sum_u64(s);
+    if (threadIdx.x == 0 && tot)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&flow[g.inst]), tot);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct Layout {
+    int32_t *st[7];
+    int32_t *tile_inst, *act[2], *dirty[2], *done;
+    Inst *inst;
+    unsigned long long *inst_active, *counters;
+    Scalars *sc;
+};
+
+static Carver carve(Carver cv, int64_t N, int64_t T, int B, Layout *L) {
+    for (int i = 0; i < 7; ++i) L->st[i] = cv.take<int32_t>(size_t(N));
+    L->tile_inst = cv.take<int32_t>(size_t(T));
+    L->act[0] = cv.take<int32_t>(size_t(T));
+    L->act[1] = cv.take<int32_t>(size_t(T));
+    L->dirty[0] = cv.take<int32_t>(size_t(T));
+    L->dirty[1] = cv.take<int32_t>(size_t(T));
+    L->inst = cv.take<Inst>(size_t(B));
+    L->inst_active = cv.take<unsigned long long>(size_t(B));
+    L->done = cv.take<int32_t>(size_t(B));
+    L->counters = cv.take<unsigned long long>(8);
+    L->sc = cv.take<Scalars>(1);
+    return cv;
+}
+
+static int64_t tiles_for(int32_t H, int32_t W, int TH) {
+    return int64_t(ceil_div(W, TW)) * ceil_div(H, TH);
+}
+
+static size_t workspace_bytes(int B, const int32_t *H, const int32_t *W) {
+    int64_t N = 0, T = 0;
+    for (int b = 0; b < B; ++b) {
+        N += int64_t(H[b]) * W[b];
+        T += tiles_for(H[b], W[b], 8);  // smallest tile height: most tiles
+    }
+    Layout L;
+    Carver cv = carve(Carver(), N, T, B, &L);
+    return cv.used();
+}
+
+template <int TH>
+struct Kern {
+    static void init(dim3 g, hipStream_t s, const Dev &D) {
+        hipLaunchKernelGGL(k_init<TH>, g, dim3(NT), 0, s, D);
+    }
+    static void bfs_seed(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
+        hipLaunchKernelGGL(k_bfs_seed<TH>, g, dim3(NT), 0, s, D, a, b);
+    }
+    static void cut_seed(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
+        hipLaunchKernelGGL(k_cut_seed<TH>, g, dim3(NT), 0, s, D, a, b);
+    }
+    static void relax(bool cut, dim3 g, hipStream_t s, const Dev &D, int32_t *a,
+                      int32_t *b, int32_t *pc) {
+        if (cut) hipLaunchKernelGGL((k_relax<TH, true>), g, dim3(NT), 0, s, D, a, b, pc);
+        else hipLaunchKernelGGL((k_relax<TH, false>), g, dim3(NT), 0, s, D, a, b, pc);
+    }
+    static void count(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
+        hipLaunchKernelGGL(k_count<TH>, g, dim3(NT), 0, s, D, a, b);
+    }
+    static void sweep(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b, int L) {
+        hipLaunchKernelGGL(k_sweep<TH>, g, dim3(NT), 0, s, D, a, b, L);
+    }
+    static void flow(dim3 g, hipStream_t s, const Dev &D, int64_t *f) {
+        hipLaunchKernelGGL(k_flow_value<TH>, g, dim3(NT), 0, s, D, f);
+    }
+    static void cut_write(dim3 g, hipStream_t s, const Dev &D, uint8_t *side) {
+        hipLaunchKernelGGL(k_cut_write<TH>, g, dim3(NT), 0, s, D, side);
+    }
+};
+
+struct Params {
+    int TH, L, K, max_rounds;
+    bool timing;
+};
+
+// Runs relaxation passes until no tile is dirty.  Pass counters are cleared
+// per batch; the last slot of a batch being 0 means the fixpoint is reached.
+template <int TH>
+static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
+                                    Layout &Lw, int *dirty_sel, dim3 grid,
+                                    EventTimer &tm, int64_t *passes) {
+    int batch = 8;
+    const int64_t guard = 16 * int64_t(D.ntiles) + 1024;
+    for (int64_t done_passes = 0;; done_passes += batch) {
+        if (done_passes > guard) {
+            set_error("relaxation did not reach its fixpoint within %lld passes",
+                      (long long)guard);
+            return LPR_EBUDGET;
+        }
+        LPR_TRY(fill_i32(Lw.sc->pass_count, 0, batch, s));
+        for (int i = 0; i < batch; ++i) {
+            int ev = tm.begin();
+            Kern<TH>::relax(cut, grid, s, D, Lw.dirty[*dirty_sel],
+                            Lw.dirty[*dirty_sel ^ 1], Lw.sc->pass_count + i);
+            tm.end(ev);
+            *dirty_sel ^= 1;
+        }
+        LPR_TRY_HIP(hipGetLastError());
+        *passes += batch;
+        int32_t last = 0;
+        LPR_TRY_HIP(hipMemcpyAsync(&last, Lw.sc->pass_count + batch - 1,
+                                   sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LPR_TRY_HIP(hipStreamSynchronize(s));
+        if (last == 0) return LPR_OK;
+        batch = std::min(batch * 2, MAX_PASS_SLOTS);
+    }
+}
+
+template <int TH>
+static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
+                        const std::vector<int32_t> &tile_inst, Dev D,
+                        Layout &Lw, int64_t *flow_values, uint8_t *side,
+                        lpr_grid_stats *stats, hipStream_t s) {
+    const int T = int(tile_inst.size());
+    const dim3 grid(T);
+    EventTimer t_sweep(s), t_bfs(s);
+    if (P.timing) {
+        t_sweep.enable();
+        t_bfs.enable();
+    }
+    double sweep_ms = 0, bfs_ms = 0;
+    int64_t rounds = 0, sweeps = 0, bfs_passes = 0, cut_passes = 0;
+
+    LPR_TRY_HIP(hipMemcpyAsync(Lw.inst, insts.data(), sizeof(Inst) * B,
+                               hipMemcpyHostToDevice, s));
+    LPR_TRY_HIP(hipMemcpyAsync(Lw.tile_inst, tile_inst.data(),
+                               sizeof(int32_t) * T, hipMemcpyHostToDevice, s));
+    LPR_TRY(fill_i32(Lw.done, 0, B, s));
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.counters), 0, 8, s));
+    LPR_TRY(fill_i32(&Lw.sc->err, 0, 1, s));
+    Kern<TH>::init(grid, s, D);
+    LPR_TRY_HIP(hipGetLastError());
+
+    int dirty_sel = 0, act_sel = 0;
+    bool converged = false;
+    for (; rounds < P.max_rounds; ++rounds) {
+        Kern<TH>::bfs_seed(grid, s, D, Lw.dirty[dirty_sel], Lw.dirty[dirty_sel ^ 1]);
+        LPR_TRY_HIP(hipGetLastError());
+        LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, &dirty_sel, grid, t_bfs,
+                                      &bfs_passes));
+        LPR_TRY(t_bfs.harvest(&bfs_ms));
+        LPR_TRY(t_sweep.harvest(&sweep_ms));
+        LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.inst_active), 0, B, s));
+        Kern<TH>::count(grid, s, D, Lw.act[act_sel], Lw.act[act_sel ^ 1]);
+        hipLaunchKernelGGL(k_count_finish, dim3(1), dim3(256), 0, s, D);
+        LPR_TRY_HIP(hipGetLastError());
+        Scalars host;
+        LPR_TRY_HIP(hipMemcpyAsync(&host, Lw.sc, offsetof(Scalars, pass_count),
+                                   hipMemcpyDeviceToHost, s));
+        LPR_TRY_HIP(hipStreamSynchronize(s));
+        if (host.err) {
+            set_error(host.err & 1 ? "negative capacity"
+                                   : "capacity exceeds LPR_GRID_MAX_CAP");
+            return host.err & 1 ? LPR_EINVAL : LPR_ERANGE;
+        }
+        if (host.total_active == 0) {
+            converged = true;
+            break;
+        }
+        for (int k = 0; k < P.K; ++k) {
+            int ev = t_sweep.begin();
+            Kern<TH>::sweep(grid, s, D, Lw.act[act_sel], Lw.act[act_sel ^ 1], P.L);
+            t_sweep.end(ev);
+            act_sel ^= 1;
+        }
+        LPR_TRY_HIP(hipGetLastError());
+        sweeps += P.K;
+    }
+    if (!converged) {
+        set_error("grid max-flow: round budget (%d) exhausted", P.max_rounds);
+        return LPR_EBUDGET;
+    }
+    LPR_TRY(fill_i64(flow_values, 0, B, s));
+    Kern<TH>::flow(grid, s, D, flow_values);
+    LPR_TRY_HIP(hipGetLastError());
+    if (side) {
+        // every instance takes part in the closure
+        LPR_TRY(fill_i32(Lw.done, 0, B, s));
+        Kern<TH>::cut_seed(grid, s, D, Lw.dirty[dirty_sel], Lw.dirty[dirty_sel ^ 1]);
+        LPR_TRY_HIP(hipGetLastError());
+        EventTimer none(s);
+        LPR_TRY(relax_to_fixpoint<TH>(true, s, D, Lw, &dirty_sel, grid, none,
+                                      &cut_passes));
+        Kern<TH>::cut_write(grid, s, D, side);
+        LPR_TRY_HIP(hipGetLastError());
+    }
+    unsigned long long cnt[8];
+    LPR_TRY_HIP(hipMemcpyAsync(cnt, Lw.counters, sizeof(cnt),
+                               hipMemcpyDeviceToHost, s));
+    LPR_TRY_HIP(hipStreamSynchronize(s));
+    LPR_TRY(t_bfs.harvest(&bfs_ms));
+    LPR_TRY(t_sweep.harvest(&sweep_ms));
+    if (stats) {
+        stats->rounds = rounds + 1;
+        stats->sweeps = sweeps;
+        stats->bfs_passes = bfs_passes;
+        stats->cut_passes = cut_passes;
+        stats->pushes = int64_t(cnt[0]);
+        stats->relabels = int64_t(cnt[1]);
+        stats->tiles_swept = int64_t(cnt[2]);
+        stats->tile_rows = TH;
+        stats->local_iters = P.L;
+        stats->sweeps_per_relabel = P.K;
+        stats->sweep_ms = sweep_ms;
+        stats->bfs_ms = bfs_ms;
+    }
+    return LPR_OK;
+}
+
+static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
+                      const int64_t *node_offset, const int32_t *const caps[6],
+                      int64_t *flow_values, uint8_t *side,
+                      const lpr_grid_opts *opts, lpr_grid_stats *stats,
+                      void *workspace, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (B < 1 || !H || !W || !node_offset) {
+        set_error("invalid batch description");
+        return LPR_EINVAL;
+    }
+    for (int i = 0; i < 6; ++i)
+        if (!caps[i]) {
+            set_error("NULL capacity array");
+            return LPR_EINVAL;
+        }
+    if (!flow_values || !workspace) {
+        set_error("NULL flow_values or workspace");
+        return LPR_EINVAL;
+    }
+    if (node_offset[0] != 0) {
+        set_error("node_offset[0] must be 0");
+        return LPR_EINVAL;
+    }
+    for (int b = 0; b < B; ++b) {
+        if (H[b] < 1 || W[b] < 1 || int64_t(H[b]) * W[b] >= (int64_t(1) << 30)) {
+            set_error("instance %d: bad shape %d x %d", b, H[b], W[b]);
+            return LPR_EINVAL;
+        }
+        if (node_offset[b + 1] != node_offset[b] + int64_t(H[b]) * W[b]) {
+            set_error("node_offset is not the prefix sum of H*W at %d", b);
+            return LPR_EINVAL;
+        }
+    }
+    Params P;
+    P.TH = 16;
+    P.L = 16;
+    P.K = 8;
+    P.max_rounds = 1 << 16;
+    P.timing = false;
+    if (opts) {
+        if (opts->tile_rows) P.TH = opts->tile_rows;
+        if (opts->local_iters) P.L = opts->local_iters;
+        if (opts->sweeps_per_relabel) P.K = opts->sweeps_per_relabel;
+        if (opts->max_rounds) P.max_rounds = opts->max_rounds;
+        P.timing = (opts->flags & LPR_GRID_TIME_KERNELS) != 0;
+    }
+    if (!(P.TH == 8 || P.TH == 16 || P.TH == 32) || P.L < 1 || P.L > 4096 ||
+        P.K < 1 || P.K > 4096 || P.max_rounds < 1) {
+        set_error("invalid lpr_grid_opts");
+        return LPR_EINVAL;
+    }
+    const int64_t N = node_offset[B];
+    std::vector<Inst> insts(B);
+    std::vector<int32_t> tile_inst;
+    for (int b = 0; b < B; ++b) {
+        Inst &I = insts[b];
+        I.off = node_offset[b];
+        I.H = H[b];
+        I.W = W[b];
+        I.tiles_x = ceil_div(W[b], TW);
+        I.tiles_y = ceil_div(H[b], P.TH);
+        I.tile_base = int32_t(tile_inst.size());
+        I.HV = H[b] * W[b] + 2;
+        tile_inst.insert(tile_inst.end(), size_t(I.tiles_x) * I.tiles_y, b);
+    }
+    const int64_t T = int64_t(tile_inst.size());
+    if (T >= (int64_t(1) << 31)) {
+        set_error("too many tiles");
+        return LPR_EINVAL;
+    }
+    const size_t need = workspace_bytes(B, H, W);
+    if (ws_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+        return LPR_ENOMEM;
+    }
+    Layout Lw;
+    Carver cv = carve(Carver(workspace, ws_bytes), N, T, B, &Lw);
+    if (!cv.fits()) {
+        set_error("workspace layout overflow");
+        return LPR_ENOMEM;
+    }
+    Dev D;
+    D.e = Lw.st[0];
+    D.h = Lw.st[1];
+    D.rr = Lw.st[2];
+    D.rl = Lw.st[3];
+    D.rd = Lw.st[4];
+    D.ru = Lw.st[5];
+    D.rs = Lw.st[6];
+    D.cap_src = caps[0];
+    D.cap_snk = caps[1];
+    D.cap_r = caps[2];
+    D.cap_l = caps[3];
+    D.cap_d = caps[4];
+    D.cap_u = caps[5];
+    D.inst = Lw.inst;
+    D.tile_inst = Lw.tile_inst;
+    D.inst_active = Lw.inst_active;
+    D.done = Lw.done;
+    D.counters = Lw.counters;
+    D.sc = Lw.sc;
+    D.ntiles = int32_t(T);
+    D.ninst = B;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CallTimer call(s);
+    call.start();
+    lpr_status st;
+    switch (P.TH) {
+        case 8:
+            st = solve<8>(P, B, insts, tile_inst, D, Lw, flow_values, side, stats, s);
+            break;
+        case 16:
+            st = solve<16>(P, B, insts, tile_inst, D, Lw, flow_values, side, stats, s);
+            break;
+        default:
+            st = solve<32>(P, B, insts, tile_inst, D, Lw, flow_values, side, stats, s);
+            break;
+    }
+    if (st != LPR_OK) {
+        (void)hipStreamSynchronize(s);
+        return st;
+    }
+    double ms = 0;
+    LPR_TRY(call.stop_ms(&ms));
+    if (stats) stats->total_ms = ms;
+    return LPR_OK;
+}
+
+}  // namespace grid
+}  // namespace lpr
+
+using namespace lpr;
+
+extern "C" size_t lpr_grid_maxflow_workspace(int32_t H, int32_t W) {
+    if (H < 1 || W < 1) return 0;
+    return grid::workspace_bytes(1, &H, &W);
+}
+
+extern "C" size_t lpr_grid_maxflow_batched_workspace(int32_t B, const int32_t *H,
+                                                      const int32_t *W) {
+    if (B < 1 || !H || !W) return 0;
+    for (int b = 0; b < B; ++b)
+        if (H[b] < 1 || W[b] < 1) return 0;
+    return grid::workspace_bytes(B, H, W);
+}
+
+extern "C" lpr_status lpr_grid_maxflow(int32_t H, int32_t W,
+                                       const int32_t *cap_src,
+                                       const int32_t *cap_snk,
+                                       const int32_t *cap_right,
+                                       const int32_t *cap_left,
+                                       const int32_t *cap_down,
+                                       const int32_t *cap_up,
+                                       int64_t *flow_value,
+                                       uint8_t *source_side,
+                                       const lpr_grid_opts *opts,
+                                       lpr_grid_stats *stats, void *workspace,
+                                       size_t workspace_bytes, void *stream) {
+    const int32_t *caps[6] = {cap_src, cap_snk, cap_right, cap_left, cap_down, cap_up};
+    const int64_t off[2] = {0, int64_t(H) * W};
+    if (H < 1 || W < 1) {
+        clear_error();
+        set_error("bad shape %d x %d", H, W);
+        return LPR_EINVAL;
+    }
+    return grid::run(1, &H, &W, off, caps, flow_value, source_side, opts, stats,
+                     workspace, workspace_bytes, stream);
+}
+
+extern "C" lpr_status lpr_grid_maxflow_batched(
+    int32_t B, const int32_t *H, const int32_t *W, const int64_t *node_offset,
+    const int32_t *cap_src, const int32_t *cap_snk, const int32_t *cap_right,
+    const int32_t *cap_left, const int32_t *cap_down, const int32_t *cap_up,
+    int64_t *flow_values, uint8_t *source_side, const lpr_grid_opts *opts,
+    lpr_grid_stats *stats, void *workspace, size_t workspace_bytes,
+    void *stream) {
+    const int32_t *caps[6] = {cap_src, cap_snk, cap_right, cap_left, cap_down, cap_up};
+    return grid::run(B, H, W, node_offset, caps, flow_values, source_side, opts,
+                     stats, workspace, workspace_bytes, stream);
+}

@@ -1,0 +1,348 @@
+"""Thin ctypes binding of the C ABI in ``include/lpr.h``.
+
+Argument marshalling only: every step of the solves runs in the HIP library
+(``liblpr.so``).  PyTorch is used for device memory (outputs and the
+workspace) and for the current stream.  If the library is missing the calls
+raise immediately -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblpr.so")
+
+LPR_OK, LPR_EINVAL, LPR_ERANGE, LPR_ENOMEM, LPR_EDEVICE, LPR_EBUDGET = (
+    0, -1, -2, -3, -4, -5)
+STATUS_NAMES = {0: "LPR_OK", -1: "LPR_EINVAL", -2: "LPR_ERANGE",
+                -3: "LPR_ENOMEM", -4: "LPR_EDEVICE", -5: "LPR_EBUDGET"}
+LPR_GRID_MAX_CAP = (1 << 26) - 1
+LPR_ASSIGN_MAX_COST = (1 << 24) - 1
+LPR_ASSIGN_MAX_N = 2048
+LPR_GRID_TIME_KERNELS = 0x1
+LPR_ASSIGN_TIME_KERNELS = 0x1
+
+# Every symbol the header declares (checked by the ABI test).
+EXPORTED = [
+    "lpr_last_error", "lpr_version",
+    "lpr_grid_maxflow_workspace", "lpr_grid_maxflow",
+    "lpr_grid_maxflow_batched_workspace", "lpr_grid_maxflow_batched",
+    "lpr_assign_workspace", "lpr_assign_solve",
+    "lpr_assign_batched_workspace", "lpr_assign_solve_batched",
+]
+
+
+class LprError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridOpts(ctypes.Structure):
+    _fields_ = [("sweeps_per_relabel", ctypes.c_int32),
+                ("local_iters", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class GridStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("sweeps", ctypes.c_int64),
+                ("bfs_passes", ctypes.c_int64),
+                ("tiles_swept", ctypes.c_int64), ("pushes", ctypes.c_int64),
+                ("relabels", ctypes.c_int64), ("cut_passes", ctypes.c_int64),
+                ("tile_rows", ctypes.c_int32), ("local_iters", ctypes.c_int32),
+                ("sweeps_per_relabel", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("sweep_ms", ctypes.c_double), ("bfs_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+class AssignOpts(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("eps0", ctypes.c_int64),
+                ("init_col_prices", ctypes.c_void_p),
+                ("max_ops", ctypes.c_int64),
+                ("max_ms", ctypes.c_int64),
+                ("reserved", ctypes.c_int64)]
+
+
+class AssignStats(ctypes.Structure):
+    _fields_ = [("refines", ctypes.c_int64), ("phases", ctypes.c_int64),
+                ("pushes", ctypes.c_int64), ("relabels", ctypes.c_int64),
+                ("scans", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3),
+                ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
+def _struct_dict(s) -> dict:
+    return {k: getattr(s, k) for k, _ in s._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -m paper_1110_6231_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.lpr_last_error.restype = ctypes.c_char_p
+    L.lpr_last_error.argtypes = []
+    L.lpr_version.restype = ctypes.c_char_p
+    L.lpr_version.argtypes = []
+    L.lpr_grid_maxflow_workspace.restype = sz
+    L.lpr_grid_maxflow_workspace.argtypes = [i32, i32]
+    L.lpr_grid_maxflow.restype = ctypes.c_int
+    L.lpr_grid_maxflow.argtypes = [i32, i32] + [vp] * 6 + [
+        vp, vp, ctypes.POINTER(GridOpts), ctypes.POINTER(GridStats), vp, sz, vp]
+    L.lpr_grid_maxflow_batched_workspace.restype = sz
+    L.lpr_grid_maxflow_batched_workspace.argtypes = [i32, i32p, i32p]
+    L.lpr_grid_maxflow_batched.restype = ctypes.c_int
+    L.lpr_grid_maxflow_batched.argtypes = [i32, i32p, i32p, i64p] + [vp] * 6 + [
+        vp, vp, ctypes.POINTER(GridOpts), ctypes.POINTER(GridStats), vp, sz, vp]
+    L.lpr_assign_workspace.restype = sz
+    L.lpr_assign_workspace.argtypes = [i32]
+    L.lpr_assign_solve.restype = ctypes.c_int
+    L.lpr_assign_solve.argtypes = [i32, vp, i32, vp, vp, vp,
+                                   ctypes.POINTER(AssignOpts),
+                                   ctypes.POINTER(AssignStats), vp, sz, vp]
+    L.lpr_assign_batched_workspace.restype = sz
+    L.lpr_assign_batched_workspace.argtypes = [i32, i32p]
+    L.lpr_assign_solve_batched.restype = ctypes.c_int
+    L.lpr_assign_solve_batched.argtypes = [i32, i32p, i64p, vp, i32, vp, vp, vp,
+                                           ctypes.POINTER(AssignOpts),
+                                           ctypes.POINTER(AssignStats), vp, sz,
+                                           vp]
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().lpr_last_error().decode()
+
+
+def version() -> str:
+    return lib().lpr_version().decode()
+
+
+def _check(status: int, where: str):
+    if status != LPR_OK:
+        raise LprError(status, where, last_error())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_i32(a, device):
+    import torch
+    if isinstance(a, torch.Tensor):
+        assert a.dtype == torch.int32 and a.is_contiguous() and a.is_cuda
+        return a
+    return torch.as_tensor(np.ascontiguousarray(a, np.int32), device=device)
+
+
+def _i32_arr(vals):
+    arr = (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def _i64_arr(vals):
+    return (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+
+
+def _workspace(nbytes: int, device):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+# Grid max-flow
+# ---------------------------------------------------------------------------
+def make_grid_opts(sweeps_per_relabel=0, local_iters=0, tile_rows=0,
+                   max_rounds=0, flags=0) -> GridOpts:
+    o = GridOpts()
+    o.sweeps_per_relabel = sweeps_per_relabel
+    o.local_iters = local_iters
+    o.tile_rows = tile_rows
+    o.max_rounds = max_rounds
+    o.flags = flags
+    return o
+
+
+def lpr_grid_maxflow_workspace(H: int, W: int) -> int:
+    return int(lib().lpr_grid_maxflow_workspace(H, W))
+
+
+def lpr_grid_maxflow(H, W, cap_src, cap_snk, cap_right, cap_left, cap_down,
+                     cap_up, want_cut=True, opts: GridOpts | None = None,
+                     workspace=None, stream=None, device="cuda"):
+    """Solve one grid (see lpr_grid_maxflow in include/lpr.h).
+
+    Capacities: int32 arrays of H*W (torch CUDA tensors or host arrays, the
+    latter are copied to the device first).  Returns (flow_value (int),
+    source_side (torch uint8 [H*W] on the device, or None), stats dict)."""
+    import torch
+    caps = [_dev_i32(a, device) for a in (cap_src, cap_snk, cap_right,
+                                          cap_left, cap_down, cap_up)]
+    dev = caps[0].device
+    for c in caps:
+        assert c.numel() == H * W
+    flow = torch.zeros(1, dtype=torch.int64, device=dev)
+    side = torch.empty(H * W, dtype=torch.uint8, device=dev) if want_cut else None
+    need = lpr_grid_maxflow_workspace(H, W)
+    ws = workspace if workspace is not None else _workspace(need, dev)
+    st = GridStats()
+    rc = lib().lpr_grid_maxflow(
+        H, W, *[_ptr(c) for c in caps], _ptr(flow), _ptr(side),
+        ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+        _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_grid_maxflow")
+    return int(flow.item()), side, _struct_dict(st)
+
+
+def lpr_grid_maxflow_batched_workspace(Hs, Ws) -> int:
+    return int(lib().lpr_grid_maxflow_batched_workspace(
+        len(Hs), _i32_arr(Hs), _i32_arr(Ws)))
+
+
+def lpr_grid_maxflow_batched(Hs, Ws, caps_packed, want_cut=True,
+                             opts: GridOpts | None = None, workspace=None,
+                             stream=None):
+    """Solve B grids in shared launches (lpr_grid_maxflow_batched).
+
+    caps_packed: six int32 CUDA tensors, each the concatenation of the
+    instances' arrays.  Returns (flow_values int64 tensor [B], packed
+    source_side uint8 tensor or None, stats dict)."""
+    import torch
+    B = len(Hs)
+    offs = np.zeros(B + 1, np.int64)
+    offs[1:] = np.cumsum(np.asarray(Hs, np.int64) * np.asarray(Ws, np.int64))
+    caps = list(caps_packed)
+    dev = caps[0].device
+    for c in caps:
+        assert c.dtype == torch.int32 and c.is_contiguous() and c.numel() == offs[-1]
+    flows = torch.zeros(B, dtype=torch.int64, device=dev)
+    side = (torch.empty(int(offs[-1]), dtype=torch.uint8, device=dev)
+            if want_cut else None)
+    need = lpr_grid_maxflow_batched_workspace(Hs, Ws)
+    ws = workspace if workspace is not None else _workspace(need, dev)
+    st = GridStats()
+    rc = lib().lpr_grid_maxflow_batched(
+        B, _i32_arr(Hs), _i32_arr(Ws), _i64_arr(offs), *[_ptr(c) for c in caps],
+        _ptr(flows), _ptr(side),
+        ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+        _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_grid_maxflow_batched")
+    return flows, side, _struct_dict(st)
+
+
+# ---------------------------------------------------------------------------
+# Assignment
+# ---------------------------------------------------------------------------
+def make_assign_opts(alpha=0, eps0=0, init_col_prices=None, max_ops=0,
+                     flags=0, max_ms=0) -> AssignOpts:
+    o = AssignOpts()
+    o.max_ms = max_ms
+    o.alpha = alpha
+    o.eps0 = eps0
+    o.init_col_prices = None if init_col_prices is None else init_col_prices.data_ptr()
+    o.max_ops = max_ops
+    o.flags = flags
+    return o
+
+
+def lpr_assign_workspace(n: int) -> int:
+    return int(lib().lpr_assign_workspace(n))
+
+
+def lpr_assign_solve(cost, maximize=False, opts: AssignOpts | None = None,
+                     want_prices=True, workspace=None, stream=None,
+                     device="cuda"):
+    """Solve one n x n assignment (lpr_assign_solve).  Returns (row_to_col
+    int32 tensor, total (int), col_prices int64 tensor or None, stats)."""
+    import torch
+    c = _dev_i32(cost, device)
+    n = int(c.shape[0])
+    assert c.numel() == n * n
+    dev = c.device
+    r2c = torch.empty(n, dtype=torch.int32, device=dev)
+    tot = torch.zeros(1, dtype=torch.int64, device=dev)
+    prices = torch.empty(n, dtype=torch.int64, device=dev) if want_prices else None
+    ws = workspace if workspace is not None else _workspace(lpr_assign_workspace(n), dev)
+    st = AssignStats()
+    rc = lib().lpr_assign_solve(
+        n, _ptr(c), int(bool(maximize)), _ptr(r2c), _ptr(tot), _ptr(prices),
+        ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+        _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_assign_solve")
+    return r2c, int(tot.item()), prices, _struct_dict(st)
+
+
+def lpr_assign_batched_workspace(ns) -> int:
+    return int(lib().lpr_assign_batched_workspace(len(ns), _i32_arr(ns)))
+
+
+@dataclass
+class PackedAssign:
+    """Instances packed for lpr_assign_solve_batched."""
+    ns: list
+    cost_offset: np.ndarray
+    row_offset: np.ndarray
+    costs: object  # int32 CUDA tensor
+
+    @staticmethod
+    def from_matrices(mats, device="cuda"):
+        import torch
+        ns = [int(m.shape[0]) for m in mats]
+        co = np.zeros(len(ns) + 1, np.int64)
+        co[1:] = np.cumsum(np.asarray(ns, np.int64) ** 2)
+        ro = np.zeros(len(ns) + 1, np.int64)
+        ro[1:] = np.cumsum(ns)
+        flat = np.concatenate([np.ascontiguousarray(m, np.int32).ravel()
+                               for m in mats])
+        return PackedAssign(ns, co, ro, torch.as_tensor(flat, device=device))
+
+
+def lpr_assign_solve_batched(packed: PackedAssign, maximize=False,
+                             opts: AssignOpts | None = None, want_prices=True,
+                             workspace=None, stream=None):
+    """Solve B instances in one launch.  Returns (row_to_col packed int32,
+    totals int64 tensor [B], col_prices packed or None, stats)."""
+    import torch
+    B = len(packed.ns)
+    dev = packed.costs.device
+    rows = int(packed.row_offset[-1])
+    r2c = torch.empty(rows, dtype=torch.int32, device=dev)
+    tots = torch.zeros(B, dtype=torch.int64, device=dev)
+    prices = torch.empty(rows, dtype=torch.int64, device=dev) if want_prices else None
+    ws = workspace if workspace is not None else _workspace(
+        lpr_assign_batched_workspace(packed.ns), dev)
+    st = AssignStats()
+    rc = lib().lpr_assign_solve_batched(
+        B, _i32_arr(packed.ns), _i64_arr(packed.cost_offset), _ptr(packed.costs),
+        int(bool(maximize)), _ptr(r2c), _ptr(tots), _ptr(prices),
+        ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+        _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_assign_solve_batched")
+    return r2c, tots, prices, _struct_dict(st)

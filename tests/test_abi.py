@@ -1,0 +1,65 @@
+"""C-ABI contract checks that need no GPU: the library builds and loads,
+exports every function include/lpr.h declares, and its host-side sizing
+functions and constants agree with the header."""
+import os
+import re
+
+import pytest
+
+from paper_1110_6231_amd import lpr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lpr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_expected_api():
+    assert declared_functions() == sorted(lpr.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = lpr.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_version_and_empty_error():
+    assert lpr.version().startswith("lpr ")
+    assert isinstance(lpr.last_error(), str)
+
+
+def test_constants_match_header():
+    text = open(HEADER).read()
+    assert "#define LPR_GRID_MAX_CAP ((1 << 26) - 1)" in text
+    assert lpr.LPR_GRID_MAX_CAP == (1 << 26) - 1
+    assert "#define LPR_ASSIGN_MAX_COST ((1 << 24) - 1)" in text
+    assert lpr.LPR_ASSIGN_MAX_COST == (1 << 24) - 1
+    assert "#define LPR_ASSIGN_MAX_N 2048" in text
+
+
+def test_workspace_sizes():
+    w = lpr.lpr_grid_maxflow_workspace(1024, 1024)
+    # at least the seven int32 state arrays
+    assert w >= 7 * 4 * 1024 * 1024
+    assert lpr.lpr_grid_maxflow_workspace(0, 5) == 0
+    assert lpr.lpr_grid_maxflow_workspace(1, 1) > 0
+    wb = lpr.lpr_grid_maxflow_batched_workspace([1024], [1024])
+    assert wb == w
+    w2 = lpr.lpr_grid_maxflow_batched_workspace([100, 37], [64, 129])
+    assert w2 >= 7 * 4 * (100 * 64 + 37 * 129)
+    assert lpr.lpr_assign_workspace(0) == 0
+    assert lpr.lpr_assign_workspace(512) > 0
+    assert lpr.lpr_assign_batched_workspace([64, 128, 512]) > 0
+
+
+def test_struct_layouts():
+    import ctypes
+    assert ctypes.sizeof(lpr.GridOpts) == 32
+    assert ctypes.sizeof(lpr.AssignOpts) == 48
+    assert ctypes.sizeof(lpr.GridStats) == 7 * 8 + 4 * 4 + 3 * 8
+    assert ctypes.sizeof(lpr.AssignStats) == 8 * 8 + 2 * 8

@@ -1,0 +1,122 @@
+"""GPU parity for dense assignment: the HIP library against the CPU oracle.
+
+The optimal total is unique and must equal the Hungarian oracle exactly; the
+returned permutation must be valid and cost that total; the returned scaled
+column prices must certify 1-optimality (hence optimality) independently of
+the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from certificates import is_permutation, scaled_eps_certificate
+from oracle import brute
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1110_6231_amd import lpr  # noqa: E402
+
+
+def check(cost, maximize=False, opts=None):
+    n = cost.shape[0]
+    print(f"[assign] n={n} max={maximize}", flush=True)
+    r2c, tot, prices, st = lpr.lpr_assign_solve(cost, maximize=maximize,
+                                                opts=opts)
+    r2c = r2c.cpu().numpy()
+    want = oracle.assign(cost, maximize=maximize)[1]
+    assert tot == want, (n, tot, want, st)
+    assert is_permutation(r2c, n)
+    assert int(cost[np.arange(n), r2c].astype(np.int64).sum()) == tot
+    cmin = -cost.astype(np.int64) if maximize else cost
+    assert scaled_eps_certificate(cmin, r2c, prices.cpu().numpy())
+    return st
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_bruteforce(n):
+    for seed in range(4):
+        c = synth.assign_random_small(n, seed)
+        want, _ = brute.assign_bruteforce(c)
+        r2c, tot, _, _ = lpr.lpr_assign_solve(c)
+        assert tot == want
+
+
+@pytest.mark.parametrize("n", [63, 64, 65, 100, 257, 700])
+def test_random_sizes(n):
+    check(synth.assign_random_small(n, seed=n, lo=-1000, hi=1000))
+    check(synth.assign_random_small(n, seed=n + 1, lo=0, hi=1000), maximize=True)
+
+
+def test_uniform_config_n1024():
+    """The dense n = 1024 max-weight workload (weights U{0..1000}, alpha 8)."""
+    for seed in range(2):
+        st = check(synth.assign_uniform(1024, seed=seed), maximize=True)
+        print("[assign] n=1024 stats", st, flush=True)
+
+
+def test_points_config():
+    for k in range(4):
+        check(synth.assign_points(64 + 149 * k, seed=0, instance=k + 1))
+
+
+def test_closed_forms():
+    n = 90
+    check(np.full((n, n), 17, np.int32))
+    g = np.random.default_rng(3)
+    a, b = g.integers(0, 60, n), g.integers(0, 60, n)
+    c = np.outer(a, b).astype(np.int32)
+    r2c, tot, _, _ = lpr.lpr_assign_solve(c)
+    assert tot == int((np.sort(a) * np.sort(b)[::-1]).sum())
+    a, b = g.integers(-500, 500, n), g.integers(-500, 500, n)
+    c = np.abs(a[:, None] - b[None, :]).astype(np.int32)
+    r2c, tot, _, _ = lpr.lpr_assign_solve(c)
+    assert tot == int(np.abs(np.sort(a) - np.sort(b)).sum())
+    # a single popular column: every row bids for it first
+    c = np.full((n, n), 500, np.int32)
+    c[:, 7] = g.integers(0, 10, n)
+    check(c)
+
+
+def test_alpha_eps_and_warm_start():
+    c = synth.assign_points(300, seed=4, instance=9)
+    for alpha in (2, 10, 16):
+        check(c, opts=lpr.make_assign_opts(alpha=alpha))
+    check(c, opts=lpr.make_assign_opts(eps0=1))
+    g = np.random.default_rng(0)
+    garbage = torch.as_tensor(g.integers(-10**9, 10**9, 300), device="cuda")
+    check(c, opts=lpr.make_assign_opts(init_col_prices=garbage))
+
+
+def test_batched():
+    mats = [synth.assign_points(n, seed=1, instance=k + 1)
+            for k, n in enumerate([64, 300, 129, 512, 77, 200])]
+    packed = lpr.PackedAssign.from_matrices(mats)
+    print("[assign] batched", packed.ns, flush=True)
+    r2c, tots, prices, st = lpr.lpr_assign_solve_batched(packed)
+    r2c = r2c.cpu().numpy()
+    prices = prices.cpu().numpy()
+    tots = tots.cpu().numpy()
+    for k, m in enumerate(mats):
+        a, b = packed.row_offset[k], packed.row_offset[k + 1]
+        assert tots[k] == oracle.assign(m)[1]
+        assert is_permutation(r2c[a:b], m.shape[0])
+        assert scaled_eps_certificate(m, r2c[a:b], prices[a:b])
+
+
+def test_errors():
+    c = synth.assign_random_small(20, 0)
+    big = c.copy()
+    big[3, 4] = lpr.LPR_ASSIGN_MAX_COST + 1
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_assign_solve(big)
+    assert e.value.status == lpr.LPR_ERANGE
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_assign_solve(synth.assign_uniform(300, seed=1), maximize=True,
+                             opts=lpr.make_assign_opts(max_ops=50))
+    assert e.value.status == lpr.LPR_EBUDGET
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_assign_solve(c, opts=lpr.make_assign_opts(alpha=1))
+    assert e.value.status == lpr.LPR_EINVAL
+    check(c)

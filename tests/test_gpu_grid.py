@@ -1,0 +1,167 @@
+"""GPU parity for grid max-flow: the HIP library against the CPU oracle.
+
+Flow value and the minimal source side S_min are unique, so both must match
+the oracle exactly (int64 value, byte-for-byte side).  Sizes span several
+64 x TH tiles with ragged right and bottom tails; the full 1024 x 1024
+graph-cut workload runs in the benchmark's launch configuration (defaults).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from certificates import grid_cut_value
+from oracle import brute
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1110_6231_amd import lpr  # noqa: E402
+
+
+def gpu_solve(inst, opts=None, want_cut=True):
+    print(f"[grid] {inst.name} {inst.H}x{inst.W}", flush=True)
+    v, side, st = lpr.lpr_grid_maxflow(inst.H, inst.W, *inst.arrays(),
+                                       want_cut=want_cut, opts=opts)
+    return v, (side.cpu().numpy() if side is not None else None), st
+
+
+def check_against_oracle(inst, opts=None):
+    want_v, want_side = oracle.grid_maxflow(inst, "fifo")
+    v, side, st = gpu_solve(inst, opts)
+    assert v == want_v, (inst.name, v, want_v, st)
+    np.testing.assert_array_equal(side, want_side, err_msg=inst.name)
+    return st
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 3),
+                                   (1, 9), (3, 4)])
+def test_tiny_bruteforce(shape):
+    H, W = shape
+    for seed in range(4):
+        inst = synth.grid_random_small(H, W, seed)
+        want_v, want_side = brute.grid_min_cut_bruteforce(inst)
+        v, side, _ = gpu_solve(inst)
+        assert v == want_v
+        np.testing.assert_array_equal(side, want_side)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_uniform64_config(seed):
+    check_against_oracle(synth.grid_uniform(64, 64, seed))
+
+
+@pytest.mark.parametrize("H,W", [(37, 70), (100, 129), (17, 200), (130, 65)])
+@pytest.mark.parametrize("tile_rows", [8, 16, 32])
+def test_ragged_shapes_all_tiles(H, W, tile_rows):
+    inst = synth.grid_random_small(H, W, seed=H + W, max_cap=40, max_term=60)
+    check_against_oracle(inst, lpr.make_grid_opts(tile_rows=tile_rows))
+
+
+@pytest.mark.parametrize("K,L", [(1, 1), (3, 2), (16, 64), (64, 4)])
+def test_schedules(K, L):
+    inst = synth.grid_blobs(150, 170, seed=4)
+    check_against_oracle(inst, lpr.make_grid_opts(sweeps_per_relabel=K,
+                                                  local_iters=L))
+
+
+def test_blobs_medium_and_long_paths():
+    check_against_oracle(synth.grid_blobs(256, 300, seed=2))
+    check_against_oracle(synth.grid_blobs(200, 260, seed=3, pair_scale=200.0))
+
+
+def test_closed_forms():
+    H, W = 70, 90
+    z = np.zeros(H * W, np.int32)
+    zero = synth.GridInstance(H, W, z, z, z, z, z, z, "zero")
+    v, side, _ = gpu_solve(zero)
+    assert v == 0 and side.sum() == 0
+    base = synth.grid_uniform(H, W, seed=7)
+    iso = synth.GridInstance(H, W, base.cap_src, base.cap_snk, z, z, z, z, "iso")
+    v, side, _ = gpu_solve(iso)
+    assert v == 0
+    np.testing.assert_array_equal(side, (base.cap_src > 0).astype(np.uint8))
+    g = np.random.default_rng(1)
+    src = g.integers(0, 40, H * W).astype(np.int32)
+    snk = g.integers(0, 40, H * W).astype(np.int32)
+    both = synth.GridInstance(H, W, src, snk, z, z, z, z, "both")
+    v, side, _ = gpu_solve(both)
+    assert v == int(np.minimum(src, snk).astype(np.int64).sum())
+    np.testing.assert_array_equal(side, (src > snk).astype(np.uint8))
+
+
+def test_chain_long_path():
+    W = 1000
+    src = np.zeros(W, np.int32)
+    snk = np.zeros(W, np.int32)
+    src[0], snk[-1] = 77, 91
+    g = np.random.default_rng(3)
+    right = g.integers(60, 100, W - 1)
+    inst = synth.grid_from_pairs(1, W, src, snk, right[None], right[None],
+                                 np.zeros((0, W)), np.zeros((0, W)), "chain")
+    v, side, _ = gpu_solve(inst)
+    assert v == min(77, 91, int(right.min()))
+    want_v, want_side = oracle.grid_maxflow(inst, "fifo")
+    np.testing.assert_array_equal(side, want_side)
+
+
+def test_batched_matches_single():
+    insts = [synth.grid_random_small(40 + 13 * k, 30 + 29 * k, seed=k,
+                                     max_cap=30) for k in range(5)]
+    insts.append(synth.grid_blobs(150, 200, seed=1))
+    insts.append(synth.grid_uniform(64, 64, seed=2))
+    Hs = [i.H for i in insts]
+    Ws = [i.W for i in insts]
+    caps = [torch.as_tensor(np.concatenate([getattr(i, f) for i in insts]),
+                            device="cuda")
+            for f in ("cap_src", "cap_snk", "cap_right", "cap_left",
+                      "cap_down", "cap_up")]
+    print("[grid] batched", list(zip(Hs, Ws)), flush=True)
+    flows, side, st = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps)
+    flows = flows.cpu().numpy()
+    side = side.cpu().numpy()
+    off = 0
+    for k, inst in enumerate(insts):
+        want_v, want_side = oracle.grid_maxflow(inst, "fifo")
+        assert flows[k] == want_v, k
+        np.testing.assert_array_equal(side[off:off + inst.n_pixels], want_side)
+        off += inst.n_pixels
+
+
+def test_full_size_graph_cut_1024():
+    """The 1024 x 1024 graph-cut workload at the benchmark's configuration:
+    exact flow value and S_min against the oracle, and the cut certificate."""
+    inst = synth.grid_blobs(1024, 1024, seed=0)
+    want_v, want_side = oracle.grid_maxflow(inst, "fifo")
+    v, side, st = gpu_solve(inst)
+    print("[grid] 1024^2 stats", st, flush=True)
+    assert v == want_v
+    np.testing.assert_array_equal(side, want_side)
+    assert grid_cut_value(inst, side) == v
+
+
+def test_errors():
+    inst = synth.grid_uniform(20, 20, seed=0)
+    arrs = [a.copy() for a in inst.arrays()]
+    arrs[2][5] = -1
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_grid_maxflow(20, 20, *arrs)
+    assert e.value.status == lpr.LPR_EINVAL
+    arrs = [a.copy() for a in inst.arrays()]
+    arrs[0][7] = lpr.LPR_GRID_MAX_CAP + 1
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_grid_maxflow(20, 20, *arrs)
+    assert e.value.status == lpr.LPR_ERANGE
+    small_ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_grid_maxflow(20, 20, *inst.arrays(), workspace=small_ws)
+    assert e.value.status == lpr.LPR_ENOMEM
+    big = synth.grid_blobs(300, 300, seed=5)
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_grid_maxflow(300, 300, *big.arrays(),
+                             opts=lpr.make_grid_opts(max_rounds=1,
+                                                     sweeps_per_relabel=1,
+                                                     local_iters=1))
+    assert e.value.status == lpr.LPR_EBUDGET
+    # the library stays usable after every error
+    check_against_oracle(synth.grid_uniform(64, 64, seed=1))
