@@ -83,7 +83,11 @@ def test_alpha_eps_and_warm_start():
     c = synth.assign_points(300, seed=4, instance=9)
     for alpha in (2, 10, 16):
         check(c, opts=lpr.make_assign_opts(alpha=alpha))
-    check(c, opts=lpr.make_assign_opts(eps0=1))
+    # a small starting epsilon skips the coarse refines (any eps0 is exact;
+    # a single refine at eps = 1 from zero prices is only cheap when small)
+    check(c, opts=lpr.make_assign_opts(eps0=5000))
+    check(synth.assign_random_small(30, 5, lo=0, hi=40),
+          opts=lpr.make_assign_opts(eps0=1))
     g = np.random.default_rng(0)
     garbage = torch.as_tensor(g.integers(-10**9, 10**9, 300), device="cuda")
     check(c, opts=lpr.make_assign_opts(init_col_prices=garbage))
