@@ -1,0 +1,194 @@
+"""Benchmark: lock-free push-relabel on one MI355X.
+
+One step = one complete solve of the 1024 x 1024 graph-cut grid (32 Gaussian
+blobs plus N(0, 0.1^2) noise, int32 capacities): init, push sweeps, global
+relabels with gap, termination, flow value and the minimal cut.  Inputs are
+resident in HBM before the timed region; outputs and workspace are
+preallocated.  The JSON line also carries the dense assignment leg (n = 1024,
+weights U{0..1000}, max-weight) and the batched assignment leg (256
+optical-flow-like instances), the roofline of the dominant kernel (the push
+sweep) and the CPU oracle timed on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid maxflow Mvertex/s + assignment solves/s, learned vs plain; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+# Bytes the push sweep must move per pixel of a processed tile: the seven
+# int32 state words (e, h, four neighbour residuals, sink residual) read into
+# LDS and written back.
+SWEEP_BYTES_PER_PIXEL = 56
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle baseline")
+    ap.add_argument("--no-assign", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def grid_leg(args, torch, lpr, synth):
+    inst = synth.grid_blobs(1024, 1024, seed=0)
+    dev = torch.device("cuda:0")
+    caps = [torch.as_tensor(a, device=dev) for a in inst.arrays()]
+    HW = inst.H * inst.W
+    ws = torch.empty(lpr.lpr_grid_maxflow_workspace(inst.H, inst.W),
+                     dtype=torch.uint8, device=dev)
+    opts = lpr.make_grid_opts()
+    for _ in range(args.warmup):
+        v, _, _ = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=opts,
+                                       workspace=ws)
+    print(f"[bench] grid warmup done, flow={v}", file=sys.stderr, flush=True)
+    timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
+    stream = torch.cuda.current_stream()
+    sweep_ms = 0.0
+    tiles = 0
+    sweeps = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        v, side, st = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=timed,
+                                           workspace=ws, stream=stream)
+        sweep_ms += st["sweep_ms"]
+        tiles += st["tiles_swept"]
+        sweeps += st["sweeps"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = wall * 1e3 / args.steps
+    tile_px = st["tile_rows"] * 64
+    sweep_bytes = tiles * tile_px * SWEEP_BYTES_PER_PIXEL
+    avg_launch_ms = sweep_ms / max(sweeps, 1)
+    achieved = (sweep_bytes / max(sweeps, 1)) / (avg_launch_ms * 1e-3) / 1e9
+    return dict(inst=inst, flow=v, ms=ms, HW=HW, stats=st,
+                roofline={"bound": "hbm", "achieved": round(achieved, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(achieved / HBM_PEAK_GBS, 4),
+                          "traffic": None,
+                          "kernel": "k_sweep<16>",
+                          "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+                          "bytes_per_launch": int(sweep_bytes / max(sweeps, 1)),
+                          "launches": sweeps})
+
+
+def assign_leg(args, torch, lpr, synth):
+    dev = torch.device("cuda:0")
+    cost = torch.as_tensor(synth.assign_uniform(1024, seed=0), device=dev)
+    ws = torch.empty(lpr.lpr_assign_workspace(1024), dtype=torch.uint8, device=dev)
+    lpr.lpr_assign_solve(cost, maximize=True, workspace=ws)
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, tot, _, st = lpr.lpr_assign_solve(cost, maximize=True, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    out = {"workload": "dense assignment n=1024, weights U{0..1000}, "
+                       "max-weight, alpha=8, plain start",
+           "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(dt * 1e3, 3),
+           "total": tot, "refines": st["refines"], "phases": st["phases"],
+           "pushes": st["pushes"], "relabels": st["relabels"]}
+    mats = synth.assign_batch(seed=0)
+    packed = lpr.PackedAssign.from_matrices(mats, device=dev)
+    wsb = torch.empty(lpr.lpr_assign_batched_workspace(packed.ns),
+                      dtype=torch.uint8, device=dev)
+    lpr.lpr_assign_solve_batched(packed, workspace=wsb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, tots, _, stb = lpr.lpr_assign_solve_batched(packed, workspace=wsb)
+    torch.cuda.synchronize()
+    dtb = (time.perf_counter() - t0) / reps
+    out["batched"] = {"workload": "256 optical-flow-like instances, "
+                                  "n ~ U{64..512}, min-cost, plain start",
+                      "solves_per_s": round(len(mats) / dtb, 1),
+                      "ms_per_batch": round(dtb * 1e3, 3),
+                      "phases": stb["phases"]}
+    return out
+
+
+def cpu_leg(args, inst):
+    import oracle
+    oracle.lib()
+    reps, t_used = 0, 0.0
+    t0 = time.perf_counter()
+    while t_used < args.cpu_seconds and reps < 50:
+        v, _ = oracle.grid_maxflow(inst, "fifo")
+        reps += 1
+        t_used = time.perf_counter() - t0
+    mv = inst.H * inst.W * reps / t_used / 1e6
+    return {"value": round(mv, 4), "unit": "Mvertex/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{reps} full solves of the same 1024x1024 graph cut by "
+                      f"the FIFO push-relabel oracle (global + gap relabel, "
+                      f"single thread), {t_used:.1f} s"}, v
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} "
+              "is not supported (the batched workloads would shard by "
+              "instance, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_1110_6231_amd import lpr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    g = grid_leg(args, torch, lpr, synth)
+    out = {
+        "metric": METRIC,
+        "value": round(g["HW"] / (g["ms"] * 1e-3) / 1e6, 3),
+        "unit": "Mvertex/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(g["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "4-connected grid graph cut 1024x1024, int32: "
+                               "32 Gaussian blobs + N(0,0.1) noise; terminals "
+                               "rint(100|I-0.5|), pairs rint(50 exp(-dI^2/"
+                               "(2*0.05^2))); seed 0",
+                   "pixels": g["HW"], "flow_value": g["flow"],
+                   "global_relabels": g["stats"]["rounds"],
+                   "sweeps": g["stats"]["sweeps"],
+                   "tile": f"64x{g['stats']['tile_rows']}",
+                   "local_iters": g["stats"]["local_iters"],
+                   "sweeps_per_relabel": g["stats"]["sweeps_per_relabel"]},
+        "roofline": g["roofline"],
+    }
+    if not args.no_assign:
+        out["assignment"] = assign_leg(args, torch, lpr, synth)
+    if not args.no_cpu:
+        cb, cpu_flow = cpu_leg(args, g["inst"])
+        assert cpu_flow == g["flow"], (cpu_flow, g["flow"])
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
