@@ -11,21 +11,27 @@
 // c'_p(v,w) = c(v,w) - p(w); if c'_p + p(v) < 0 it pushes one unit along that
 // arc with atomic excess updates, otherwise it relabels p(v) = -(c'_p + eps).
 //
-// GPU design.  One 1024-thread workgroup owns an instance for the whole
-// solve; prices, excesses and the matching live in LDS, the cost matrix stays
-// in global memory (L2 / MALL resident for the sizes served).  Active nodes
-// are processed in alternating X and Y phases separated by workgroup
-// barriers -- one admissible schedule of the lock-free method that keeps the
-// prices a node reads fixed while it scans:
-//   X phase: one wavefront per active x scans its cost row (lane-strided,
-//     coalesced) and reduces (c'_p, y) to the minimum with the smallest y on
-//     ties; it relabels if the best arc is not admissible (after which it is)
-//     and pushes its unit: mate[x] = y~, atomic prepend of x to y~'s list of
+// GPU design.  A prep kernel spread over the whole GPU computes max|c| per
+// instance and, where |c| < 2^15, a compact int16 copy of the costs (half the
+// bytes per row scan; a 1024 x 1024 instance then fits one XCD's L2).  One
+// 1024-thread workgroup then owns an instance for the whole solve; prices,
+// excesses and the matching live in LDS.  Active nodes are processed in
+// alternating X and Y phases separated by workgroup barriers -- one admissible
+// schedule of the lock-free method that keeps the prices a node reads fixed
+// while it scans:
+//   X phase: one wavefront per active x scans its cost row (all loads in
+//     flight at once) and reduces (c'_p, y) to a minimum with DPP exchanges;
+//     it relabels if the best arc is not admissible (after which it is) and
+//     pushes its unit: mate[x] = y~, atomic prepend of x to y~'s list of
 //     matched rows, atomic increment of e(y~).
 //   Y phase: one thread per y that became active (e(y) >= 1) applies the same
 //     operation to y until e(y) = 0: its residual arcs are the reverses (y,x)
 //     of its matched rows, the least c'_p(y,x) = -c(x,y) - p(x) is pushed back
 //     (x unmatched, e(x) = 1) after a relabel when not admissible.
+//   Serial tail: when at most TAIL_ENTER rows are active (the long chains at
+//     the end of a refine), one wavefront runs pushes and push-backs back to
+//     back with no block barrier -- a sequential trace of the same operations
+//     -- and returns the queue to the phases if it grows.
 // The refine's initialisation and the first X phase share one scan of every
 // row: after p(x) = -(min + eps) the minimising arc is admissible.
 #include <algorithm>
@@ -40,9 +46,13 @@ namespace assign {
 
 constexpr int NT = 1024;
 constexpr int NW = NT / 64;
+constexpr int TAIL_ENTER = 2;  // serial tail when at most this many rows bid
+constexpr int TAIL_EXIT = 8;   // back to phases when the queue grows past this
+constexpr unsigned C16_MAX = 32767;
 
 struct AInst {
-    int64_t cost_off;  // first cost entry of the instance
+    int64_t cost_off;  // first cost entry of the instance (int32 input)
+    int64_t c16_off;   // first entry of its int16 copy (16-byte aligned)
     int32_t n;
     int32_t row_off;   // offset of the instance in packed per-row outputs
 };
@@ -51,6 +61,8 @@ struct AArgs {
     const AInst *inst;
     const int32_t *order;
     const int32_t *costs;
+    const int16_t *c16;
+    const unsigned *cmax;
     int32_t sign;      // +1 minimise c, -1 maximise (solve with c = -w)
     int32_t alpha;
     int64_t eps0;      // 0: max|c| * S
@@ -64,90 +76,260 @@ struct AArgs {
     int32_t *status;  // per instance: 0 ok, 1 budget, 2 range, 3 internal
 };
 
-// Least (value, index) over one cost row: c'_p(x,y) = S*sign*c(x,y) - p(y),
-// ties broken towards the smallest y.  Result valid in every lane.
-__device__ inline void row_min(const int32_t *__restrict__ row,
-                               const int64_t *py, int n, int64_t sgnS,
-                               int lane, int64_t &best, int &arg) {
-    int64_t b = LLONG_MAX;
-    int a = INT_MAX;
-    int y = lane;
-    for (; y + 192 < n; y += 256) {
-        const int32_t c0 = row[y], c1 = row[y + 64], c2 = row[y + 128],
-                      c3 = row[y + 192];
-        const int64_t v0 = int64_t(c0) * sgnS - py[y];
-        const int64_t v1 = int64_t(c1) * sgnS - py[y + 64];
-        const int64_t v2 = int64_t(c2) * sgnS - py[y + 128];
-        const int64_t v3 = int64_t(c3) * sgnS - py[y + 192];
-        if (v0 < b) { b = v0; a = y; }
-        if (v1 < b) { b = v1; a = y + 64; }
-        if (v2 < b) { b = v2; a = y + 128; }
-        if (v3 < b) { b = v3; a = y + 192; }
+// max|c| per instance and the saturated int16 copy (used only when max|c|
+// fits).  grid = (blocks per instance, B).
+__global__ __launch_bounds__(256) void k_prep(const AInst *inst,
+                                              const int32_t *costs,
+                                              int16_t *c16, unsigned *cmax) {
+    const AInst I = inst[blockIdx.y];
+    const int64_t nn = int64_t(I.n) * I.n;
+    const int32_t *src = costs + I.cost_off;
+    int16_t *dst = c16 + I.c16_off;
+    unsigned m = 0;
+    for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < nn;
+         k += int64_t(gridDim.x) * 256) {
+        const int32_t c = src[k];
+        m = max(m, c < 0 ? 0u - unsigned(c) : unsigned(c));
+        dst[k] = int16_t(max(-32768, min(32767, c)));
     }
-    for (; y < n; y += 64) {
-        const int64_t v = int64_t(row[y]) * sgnS - py[y];
-        if (v < b) { b = v; a = y; }
+    for (int o = 32; o > 0; o >>= 1) m = max(m, unsigned(__shfl_xor(int(m), o, 64)));
+    __shared__ unsigned red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = max(max(red[0], red[1]), max(red[2], red[3]));
+        if (m) atomicMax(&cmax[blockIdx.y], m);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const int64_t ob = __shfl_xor(b, o, 64);
-        const int oa = __shfl_xor(a, o, 64);
-        if (ob < b || (ob == b && oa < a)) {
-            b = ob;
-            a = oa;
-        }
-    }
-    best = b;
-    arg = a;
 }
 
-__global__ __launch_bounds__(NT) void k_assign(AArgs A) {
-    const int slot = A.order[blockIdx.x];
-    const AInst I = A.inst[slot];
+__device__ inline int64_t readlane64(int64_t v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(int(uint32_t(uint64_t(v))), lane);
+    const int hi = __builtin_amdgcn_readlane(int(uint32_t(uint64_t(v) >> 32)), lane);
+    return int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+
+template <int CTRL>
+__device__ inline int64_t dpp_min64(int64_t v) {
+    const int lo = __builtin_amdgcn_mov_dpp(int(uint32_t(uint64_t(v))), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(int(uint32_t(uint64_t(v) >> 32)), CTRL, 0xf, 0xf, false);
+    const int64_t o = int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+    return o < v ? o : v;
+}
+
+// Minimum of an int64 over the 64 lanes of a fully active wavefront, as a
+// wave-uniform value: DPP exchanges inside each row of 16 lanes (xor 1,
+// xor 2, half-row mirror, row mirror) and then the four row minima.
+__device__ inline int64_t wave_min64(int64_t v) {
+    v = dpp_min64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_min64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_min64<0x141>(v);  // row_half_mirror
+    v = dpp_min64<0x140>(v);  // row_mirror
+    int64_t m = readlane64(v, 0);
+    const int64_t m1 = readlane64(v, 16), m2 = readlane64(v, 32),
+                  m3 = readlane64(v, 48);
+    m = m1 < m ? m1 : m;
+    m = m2 < m ? m2 : m;
+    return m3 < m ? m3 : m;
+}
+
+// Folds cost c of column y into the lane's running minimum.
+__device__ inline void fold(int64_t v, int y, int c, int64_t &b, int &a, int &ca) {
+    if (v < b) {
+        b = v;
+        a = y;
+        ca = c;
+    }
+}
+
+// Per-lane part of the row scan: int32 costs.
+__device__ inline void lane_scan(const int32_t *__restrict__ row,
+                                 const int64_t *py, int n, int32_t sgnS,
+                                 int lane, int64_t &b, int &a, int &ca) {
+    if ((reinterpret_cast<uintptr_t>(row) & 15) == 0 && (n & 3) == 0) {
+        const int4 *row4 = reinterpret_cast<const int4 *>(row);
+        const int nq = n >> 2;
+        for (int base = 0; base < nq; base += 256) {
+            int4 cv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = base + lane + 64 * i;
+                cv[i] = q < nq ? row4[q] : make_int4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = base + lane + 64 * i;
+                if (q < nq) {
+                    const int y = 4 * q;
+                    fold(int64_t(cv[i].x) * sgnS - py[y], y, cv[i].x, b, a, ca);
+                    fold(int64_t(cv[i].y) * sgnS - py[y + 1], y + 1, cv[i].y, b, a, ca);
+                    fold(int64_t(cv[i].z) * sgnS - py[y + 2], y + 2, cv[i].z, b, a, ca);
+                    fold(int64_t(cv[i].w) * sgnS - py[y + 3], y + 3, cv[i].w, b, a, ca);
+                }
+            }
+        }
+    } else {
+        for (int base = 0; base < n; base += 1024) {
+            int32_t cv[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int y = base + lane + 64 * i;
+                cv[i] = y < n ? row[y] : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int y = base + lane + 64 * i;
+                if (y < n) fold(int64_t(cv[i]) * sgnS - py[y], y, cv[i], b, a, ca);
+            }
+        }
+    }
+}
+
+// Per-lane part of the row scan: int16 costs (8 per 16-byte load).
+__device__ inline void lane_scan(const int16_t *__restrict__ row,
+                                 const int64_t *py, int n, int32_t sgnS,
+                                 int lane, int64_t &b, int &a, int &ca) {
+    if ((reinterpret_cast<uintptr_t>(row) & 15) == 0 && (n & 7) == 0) {
+        const int4 *row8 = reinterpret_cast<const int4 *>(row);
+        const int no = n >> 3;
+        for (int base = 0; base < no; base += 128) {
+            int4 cv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int q = base + lane + 64 * i;
+                cv[i] = q < no ? row8[q] : make_int4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int q = base + lane + 64 * i;
+                if (q < no) {
+                    const int y = 8 * q;
+                    const int w[4] = {cv[i].x, cv[i].y, cv[i].z, cv[i].w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int lo = int(int16_t(w[j] & 0xffff));
+                        const int hi = w[j] >> 16;
+                        fold(int64_t(lo) * sgnS - py[y + 2 * j], y + 2 * j, lo, b, a, ca);
+                        fold(int64_t(hi) * sgnS - py[y + 2 * j + 1], y + 2 * j + 1, hi, b, a, ca);
+                    }
+                }
+            }
+        }
+    } else {
+        for (int base = 0; base < n; base += 1024) {
+            int cv[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int y = base + lane + 64 * i;
+                cv[i] = y < n ? int(row[y]) : 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int y = base + lane + 64 * i;
+                if (y < n) fold(int64_t(cv[i]) * sgnS - py[y], y, cv[i], b, a, ca);
+            }
+        }
+    }
+}
+
+// Least part-reduced cost over one cost row, c'_p(x,y) = S*sign*c(x,y) - p(y),
+// with an argmin y~ and c(x, y~).  Every load of a 1024-column chunk is in
+// flight before any is consumed, so a scan costs one memory round trip per
+// chunk.  Results are wave-uniform.  Called by all 64 lanes of a wavefront.
+template <typename T>
+__device__ inline void row_min(const T *__restrict__ row, const int64_t *py,
+                               int n, int64_t sgnS, int lane, int64_t &best,
+                               int &arg, int &carg) {
+    int64_t b = LLONG_MAX;
+    int a = 0, ca = 0;
+    // |S*sign| <= 2*2048+1, so every product is a 32 x 32 -> 64 multiply
+    lane_scan(row, py, n, int32_t(sgnS), lane, b, a, ca);
+    const int64_t m = wave_min64(b);
+    const unsigned long long hit = __ballot(b == m);
+    const int src = __ffsll((long long)hit) - 1;
+    best = m;
+    arg = __builtin_amdgcn_readlane(a, src);
+    carg = __builtin_amdgcn_readlane(ca, src);
+}
+
+struct Shared {
+    int64_t *py, *px;
+    int64_t *bv;  // b(x) = c(x, mate[x]) * S*sign + p(x), fixed while matched
+    int32_t *ey, *head, *nxt, *mate, *xl, *yl;
+};
+
+// Operation of Algorithm 5.4 applied to an active column y until e(y) = 0.
+// Its residual arcs are the reverses (y,x) of its matched rows, with
+// c'_p(y,x) = -c(x,y) - p(x); the least one (largest b(x) = c(x,y) + p(x),
+// ties to the smallest x; p(x) cannot change while x is matched, so b(x) is
+// recorded when x pushes) is pushed back, after a relabel
+// p(y) = -(c'_p + eps) when it is not admissible.  Every pushed-back row is
+// handed to `emit`.  Only the caller touches y's list while this runs.
+template <typename Emit>
+__device__ inline bool resolve_column(int y, int64_t eps, const Shared &L,
+                                      unsigned long long &pushes,
+                                      unsigned long long &relabels, Emit emit) {
+    while (L.ey[y] >= 1) {
+        int prev = -1, cur = L.head[y], bprev = -1, bx = -1;
+        int64_t bb = LLONG_MIN;
+        while (cur >= 0) {
+            const int64_t b = L.bv[cur];
+            if (b > bb || (b == bb && cur < bx)) {
+                bb = b;
+                bx = cur;
+                bprev = prev;
+            }
+            prev = cur;
+            cur = L.nxt[cur];
+        }
+        if (bx < 0) return false;  // e(y) >= 1 implies >= 2 matched rows
+        if (!(bb > L.py[y])) {     // not admissible: relabel
+            L.py[y] = bb - eps;
+            ++relabels;
+        }
+        if (bprev < 0) L.head[y] = L.nxt[bx];
+        else L.nxt[bprev] = L.nxt[bx];
+        L.mate[bx] = -1;
+        L.ey[y] -= 1;
+        ++pushes;
+        emit(bx);
+    }
+    return true;
+}
+
+template <typename T>
+__device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
+                               const T *__restrict__ C, unsigned cmax,
+                               unsigned char *smem) {
     const int n = I.n;
-    const int32_t *__restrict__ C = A.costs + I.cost_off;
-    extern __shared__ __align__(16) unsigned char smem[];
-    int64_t *py = reinterpret_cast<int64_t *>(smem);
-    int64_t *px = py + n;
-    int32_t *ey = reinterpret_cast<int32_t *>(px + n);
-    int32_t *head = ey + n;
-    int32_t *nxt = head + n;
-    int32_t *mate = nxt + n;
-    int32_t *xl = mate + n;  // rows pushed back in the last Y phase
-    int32_t *yl = xl + n;    // columns made active in the last X phase
-    __shared__ int s_nx, s_ny, s_stop;
+    Shared L;
+    L.py = reinterpret_cast<int64_t *>(smem);
+    L.px = L.py + n;
+    L.bv = L.px + n;
+    L.ey = reinterpret_cast<int32_t *>(L.bv + n);
+    L.head = L.ey + n;
+    L.nxt = L.head + n;
+    L.mate = L.nxt + n;
+    L.xl = L.mate + n;  // active rows (circular queue in the serial tail)
+    L.yl = L.xl + n;    // columns made active by the last X phase
+    int64_t *py = L.py, *px = L.px;
+    __shared__ int s_nx, s_ny, s_stop, s_qh;
     __shared__ unsigned long long s_cnt[5];
-    __shared__ unsigned s_red[NW];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t t_start = wall_clock64();
     const int64_t S = 2 * int64_t(n) + 1;
     const int64_t sgnS = int64_t(A.sign) * S;
-
-    // C = max |c| (Algorithm 5.0 starts at eps = C, here in scaled units)
-    unsigned cmax = 0;
-    const int64_t nn = int64_t(n) * n;
-    for (int64_t k = tid; k < nn; k += NT) {
-        const int32_t c = C[k];
-        cmax = max(cmax, c < 0 ? 0u - unsigned(c) : unsigned(c));
-    }
-    for (int o = 32; o > 0; o >>= 1) cmax = max(cmax, (unsigned)__shfl_xor((int)cmax, o, 64));
-    if (lane == 0) s_red[wave] = cmax;
     if (tid < 5) s_cnt[tid] = 0;
     if (tid == 0) {
         s_nx = 0;
         s_ny = 0;
         s_stop = 0;
+        s_qh = 0;
     }
     for (int y = tid; y < n; y += NT)
         py[y] = A.init_prices ? A.init_prices[I.row_off + y] : 0;
     __syncthreads();
-    cmax = 0;
-    for (int i = 0; i < NW; ++i) cmax = max(cmax, s_red[i]);
-    if (cmax > unsigned(LPR_ASSIGN_MAX_COST)) {
-        if (tid == 0) A.status[slot] = 2;
-        return;
-    }
+    // Algorithm 5.0 starts at eps = C (largest |cost|), here in scaled units
     int64_t eps = A.eps0 > 0 ? A.eps0 : (cmax > 0 ? int64_t(cmax) * S : 1);
     const int64_t alpha = A.alpha;
 
@@ -156,21 +338,22 @@ __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
         if (eps < 1) eps = 1;
         // ---- Refine init (Algorithm 5.2): f <- 0, e(x) = 1, e(y) = -1 ----
         for (int y = tid; y < n; y += NT) {
-            head[y] = -1;
-            ey[y] = -1;
+            L.head[y] = -1;
+            L.ey[y] = -1;
         }
         __syncthreads();
         // p(x) = -min_y {c'_p(x,y) + eps}; the minimising arc is then
         // admissible (c_p = -eps), so x pushes its unit along it at once.
         for (int x = wave; x < n; x += NW) {
             int64_t best;
-            int arg;
-            row_min(C + int64_t(x) * n, py, n, sgnS, lane, best, arg);
+            int arg, carg;
+            row_min(C + int64_t(x) * n, py, n, sgnS, lane, best, arg, carg);
             if (lane == 0) {
                 px[x] = -(best + eps);
-                mate[x] = arg;
-                nxt[x] = atomicExch(&head[arg], x);
-                if (atomicAdd(&ey[arg], 1) == 0) yl[atomicAdd(&s_ny, 1)] = arg;
+                L.mate[x] = arg;
+                L.bv[x] = int64_t(carg) * sgnS + px[x];
+                L.nxt[x] = atomicExch(&L.head[arg], x);
+                if (atomicAdd(&L.ey[arg], 1) == 0) L.yl[atomicAdd(&s_ny, 1)] = arg;
             }
         }
         if (tid == 0) {
@@ -184,69 +367,99 @@ __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
             const int ny = s_ny;
             unsigned long long my_push = 0, my_rel = 0;
             for (int j = tid; j < ny; j += NT) {
-                const int y = yl[j];
-                const int64_t *pxc = px;
-                while (ey[y] >= 1) {
-                    int prev = -1, cur = head[y], bprev = -1, bx = -1;
-                    int64_t bb = LLONG_MIN;
-                    while (cur >= 0) {
-                        // c'_p(y,x) = -c(x,y) - p(x); minimum <=> max b(x)
-                        const int64_t b = int64_t(C[int64_t(cur) * n + y]) * sgnS + pxc[cur];
-                        if (b > bb || (b == bb && cur < bx)) {
-                            bb = b;
-                            bx = cur;
-                            bprev = prev;
-                        }
-                        prev = cur;
-                        cur = nxt[cur];
-                    }
-                    if (bx < 0) {  // cannot happen: e(y) >= 1 means >= 2 rows
-                        atomicOr(&s_stop, 2);
-                        break;
-                    }
-                    if (!(bb > py[y])) {  // not admissible: relabel
-                        py[y] = bb - eps;
-                        ++my_rel;
-                    }
-                    if (bprev < 0) head[y] = nxt[bx];
-                    else nxt[bprev] = nxt[bx];
-                    mate[bx] = -1;
-                    ey[y] -= 1;
-                    ++my_push;
-                    xl[atomicAdd(&s_nx, 1)] = bx;
-                }
+                const bool ok = resolve_column(
+                    L.yl[j], eps, L, my_push, my_rel,
+                    [&](int bx) { L.xl[atomicAdd(&s_nx, 1)] = bx; });
+                if (!ok) atomicOr(&s_stop, 2);
             }
             if (my_push) atomicAdd(&s_cnt[2], my_push);
             if (my_rel) atomicAdd(&s_cnt[3], my_rel);
             __syncthreads();
-            const int nx = s_nx;
+            int nx = s_nx;
             if (tid == 0) {
                 s_ny = 0;
+                s_qh = 0;
                 atomicAdd(&s_cnt[1], 1ull);
                 if ((long long)(s_cnt[2] + s_cnt[3]) > A.max_ops ||
                     wall_clock64() - t_start > A.max_ticks)
-                    s_stop = 1;
+                    s_stop |= 1;
             }
             __syncthreads();
-            const bool stop = s_stop != 0;
+            if (nx == 0 || s_stop) break;
+            if (nx <= TAIL_ENTER) {
+                // ---- serial tail ----
+                if (wave == 0) {
+                    // circular queue over xl: head position, tail position
+                    // and length, wrapped without division
+                    int qh = 0, qt = nx == n ? 0 : nx, qlen = nx;
+                    unsigned long long tp = 0, tr = 0, ts = 0;
+                    int stop = 0;
+                    while (qlen > 0 && qlen <= TAIL_EXIT) {
+                        const int x = L.xl[qh];
+                        if (++qh == n) qh = 0;
+                        --qlen;
+                        int64_t best;
+                        int arg, carg;
+                        row_min(C + int64_t(x) * n, py, n, sgnS, lane, best, arg, carg);
+                        if (best + px[x] >= 0) {
+                            px[x] = -(best + eps);
+                            ++tr;
+                        }
+                        L.mate[x] = arg;
+                        L.bv[x] = int64_t(carg) * sgnS + px[x];
+                        L.nxt[x] = L.head[arg];
+                        L.head[arg] = x;
+                        L.ey[arg] += 1;
+                        ++tp;
+                        ++ts;
+                        if (!resolve_column(arg, eps, L, tp, tr, [&](int bx) {
+                                L.xl[qt] = bx;
+                                if (++qt == n) qt = 0;
+                                ++qlen;
+                            })) {
+                            stop = 2;
+                            break;
+                        }
+                        if ((ts & 127) == 0 &&
+                            ((long long)(s_cnt[2] + s_cnt[3] + tp + tr) > A.max_ops ||
+                             wall_clock64() - t_start > A.max_ticks)) {
+                            stop = 1;
+                            break;
+                        }
+                    }
+                    if (lane == 0) {
+                        s_nx = qlen;
+                        s_qh = qh;
+                        s_stop |= stop;
+                        atomicAdd(&s_cnt[2], tp);
+                        atomicAdd(&s_cnt[3], tr);
+                        atomicAdd(&s_cnt[4], ts);
+                    }
+                }
+                __syncthreads();
+                nx = s_nx;
+                if (nx == 0 || s_stop) break;
+            }
+            const int qh0 = s_qh;
+            __syncthreads();
             if (tid == 0) s_nx = 0;
-            if (nx == 0 || stop) break;
             // ---- X phase: every pushed-back row bids again ----
             unsigned long long x_rel = 0, x_ops = 0;
             for (int i = wave; i < nx; i += NW) {
                 ++x_ops;
-                const int x = xl[i];
+                const int x = L.xl[qh0 + i < n ? qh0 + i : qh0 + i - n];
                 int64_t best;
-                int arg;
-                row_min(C + int64_t(x) * n, py, n, sgnS, lane, best, arg);
+                int arg, carg;
+                row_min(C + int64_t(x) * n, py, n, sgnS, lane, best, arg, carg);
                 if (lane == 0) {
                     if (best + px[x] >= 0) {  // relabel, then the arc is admissible
                         px[x] = -(best + eps);
                         ++x_rel;
                     }
-                    mate[x] = arg;
-                    nxt[x] = atomicExch(&head[arg], x);
-                    if (atomicAdd(&ey[arg], 1) == 0) yl[atomicAdd(&s_ny, 1)] = arg;
+                    L.mate[x] = arg;
+                    L.bv[x] = int64_t(carg) * sgnS + px[x];
+                    L.nxt[x] = atomicExch(&L.head[arg], x);
+                    if (atomicAdd(&L.ey[arg], 1) == 0) L.yl[atomicAdd(&s_ny, 1)] = arg;
                 }
             }
             if (lane == 0 && x_ops) {
@@ -264,11 +477,12 @@ __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
     if (s_stop) {
         if (tid == 0) A.status[slot] = (s_stop & 2) ? 3 : 1;
     } else {
+        const int32_t *C32 = A.costs + I.cost_off;
         long long part = 0;
         for (int x = tid; x < n; x += NT) {
-            const int y = mate[x];
+            const int y = L.mate[x];
             A.row_to_col[I.row_off + x] = y;
-            part += C[int64_t(x) * n + y];
+            part += C32[int64_t(x) * n + y];
         }
         if (A.col_prices)
             for (int y = tid; y < n; y += NT) A.col_prices[I.row_off + y] = py[y];
@@ -286,25 +500,50 @@ __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
     if (tid < 5 && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
 }
 
-static size_t lds_bytes(int nmax) { return size_t(nmax) * 44 + 64; }
+__global__ __launch_bounds__(NT) void k_assign(AArgs A) {
+    const int slot = A.order[blockIdx.x];
+    const AInst I = A.inst[slot];
+    extern __shared__ __align__(16) unsigned char smem[];
+    const unsigned cmax = A.cmax[slot];
+    if (cmax > unsigned(LPR_ASSIGN_MAX_COST)) {
+        if (threadIdx.x == 0) A.status[slot] = 2;
+        return;
+    }
+    if (cmax <= C16_MAX)
+        solve_instance<int16_t>(A, I, slot, A.c16 + I.c16_off, cmax, smem);
+    else
+        solve_instance<int32_t>(A, I, slot, A.costs + I.cost_off, cmax, smem);
+}
+
+static size_t lds_bytes(int nmax) { return size_t(nmax) * 48 + 64; }
 
 struct Layout {
     AInst *inst;
     int32_t *order, *status;
+    unsigned *cmax;
     unsigned long long *counters;
+    int16_t *c16;
 };
 
-static Carver carve(Carver cv, int B, Layout *L) {
+static int64_t c16_elems(int B, const int32_t *n) {
+    int64_t e = 0;
+    for (int b = 0; b < B; ++b) e += (int64_t(n[b]) * n[b] + 7) & ~int64_t(7);
+    return e;
+}
+
+static Carver carve(Carver cv, int B, const int32_t *n, Layout *L) {
     L->inst = cv.take<AInst>(size_t(B));
     L->order = cv.take<int32_t>(size_t(B));
     L->status = cv.take<int32_t>(size_t(B));
+    L->cmax = cv.take<unsigned>(size_t(B));
     L->counters = cv.take<unsigned long long>(8);
+    L->c16 = cv.take<int16_t>(size_t(c16_elems(B, n)));
     return cv;
 }
 
-static size_t workspace_bytes(int B) {
+static size_t workspace_bytes(int B, const int32_t *n) {
     Layout L;
-    return carve(Carver(), B, &L).used();
+    return carve(Carver(), B, n, &L).used();
 }
 
 static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
@@ -324,21 +563,25 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     }
     int nmax = 0;
     std::vector<AInst> insts(B);
-    int64_t rows = 0;
+    int64_t rows = 0, c16 = 0, nnmax = 0;
     for (int b = 0; b < B; ++b) {
         if (n[b] < 1 || n[b] > LPR_ASSIGN_MAX_N) {
             set_error("instance %d: n = %d outside [1, %d]", b, n[b], LPR_ASSIGN_MAX_N);
             return LPR_EINVAL;
         }
-        if (cost_offset[b + 1] != cost_offset[b] + int64_t(n[b]) * n[b]) {
+        const int64_t nn = int64_t(n[b]) * n[b];
+        if (cost_offset[b + 1] != cost_offset[b] + nn) {
             set_error("cost_offset is not the prefix sum of n^2 at %d", b);
             return LPR_EINVAL;
         }
         insts[b].cost_off = cost_offset[b];
+        insts[b].c16_off = c16;
         insts[b].n = n[b];
         insts[b].row_off = int32_t(rows);
         rows += n[b];
+        c16 += (nn + 7) & ~int64_t(7);
         nmax = std::max(nmax, n[b]);
+        nnmax = std::max(nnmax, nn);
     }
     if (rows >= (int64_t(1) << 31)) {
         set_error("too many rows");
@@ -361,12 +604,13 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         set_error("invalid lpr_assign_opts");
         return LPR_EINVAL;
     }
-    if (ws_bytes < workspace_bytes(B)) {
-        set_error("workspace too small: %zu < %zu bytes", ws_bytes, workspace_bytes(B));
+    const size_t need = workspace_bytes(B, n);
+    if (ws_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
         return LPR_ENOMEM;
     }
     Layout L;
-    carve(Carver(workspace, ws_bytes), B, &L);
+    carve(Carver(workspace, ws_bytes), B, n, &L);
     std::vector<int32_t> order(B);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
@@ -380,10 +624,16 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
                                hipMemcpyHostToDevice, s));
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.counters), 0, 8, s));
     LPR_TRY(fill_i32(L.status, -1, B, s));
+    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.cmax), 0, B, s));
+    const int gx = int(std::min<int64_t>(512, std::max<int64_t>(1, (nnmax + 4095) / 4096)));
+    hipLaunchKernelGGL(k_prep, dim3(gx, B), dim3(256), 0, s, L.inst, costs, L.c16, L.cmax);
+    LPR_TRY_HIP(hipGetLastError());
     AArgs A;
     A.inst = L.inst;
     A.order = L.order;
     A.costs = costs;
+    A.c16 = L.c16;
+    A.cmax = L.cmax;
     A.sign = maximize ? -1 : 1;
     A.alpha = alpha;
     A.eps0 = eps0;
@@ -458,12 +708,14 @@ using namespace lpr;
 
 extern "C" size_t lpr_assign_workspace(int32_t n) {
     if (n < 1) return 0;
-    return assign::workspace_bytes(1);
+    return assign::workspace_bytes(1, &n);
 }
 
 extern "C" size_t lpr_assign_batched_workspace(int32_t B, const int32_t *n) {
     if (B < 1 || !n) return 0;
-    return assign::workspace_bytes(B);
+    for (int b = 0; b < B; ++b)
+        if (n[b] < 1) return 0;
+    return assign::workspace_bytes(B, n);
 }
 
 extern "C" lpr_status lpr_assign_solve(int32_t n, const int32_t *cost,
