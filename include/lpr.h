@@ -199,7 +199,10 @@ typedef struct {
     int64_t max_ms;                 /* wall-clock budget of the solve kernel,
                                        checked on the device after every
                                        phase; 0 -> 20000 ms                  */
-    int64_t reserved;               /* must be 0                             */
+    const int64_t *eps0_per_instance; /* device int64 [B] or NULL: initial
+                                       epsilon per instance (> 0), overrides
+                                       eps0 (for starts whose accuracy is
+                                       known per instance)                   */
 } lpr_assign_opts;
 
 typedef struct {
@@ -267,6 +270,78 @@ lpr_status lpr_assign_solve_batched(int32_t B, const int32_t *n,
                                     const lpr_assign_opts *opts,
                                     lpr_assign_stats *stats, void *workspace,
                                     size_t workspace_bytes, void *stream);
+
+/* ======================================================================== */
+/* Learned warm start for cost scaling (not part of the paper's method)     */
+/* ======================================================================== */
+/*
+ * A permutation-equivariant price network predicts the column prices p(Y)
+ * that cost scaling starts from, so that the Min-Cost loop of Algorithm 5.0
+ * can start at a small epsilon.  Refine recomputes the row prices from p(Y)
+ * (Algorithm 5.2), so lpr_assign_solve stays exact whatever is predicted.
+ *
+ * Features: 16 per column, symmetric over rows -- with sc = mean|c| and
+ * z = c/sc, rr = z - rowmin(z): the 8 smallest z of the column, mean and std
+ * of z, the 2 smallest rr, mean rr, a two-pass min-plus dual estimate and a
+ * soft minimum of rr at temperature 0.1 (both centred per instance), log(n)/6.
+ * Network per instance (columns as the set): H_l = relu(H_{l-1} W_l +
+ * mean_cols(H_{l-1}) U_l + b_l) for l = 1..3 (width 128), q = H_3 w_o + b_o.
+ * Parameters: one float32 vector of lpr_pricenet_param_count() values,
+ * W1 [16,128], U1 [16,128], b1 [128], W2 [128,128], U2 [128,128], b2 [128],
+ * W3, U3 [128,128], b3 [128], w_o [128], b_o [1], row-major, concatenated.
+ * Matrix products run on BF16 matrix cores with FP32 accumulation.
+ *
+ * Instances are described as for lpr_assign_solve_batched (host n [B], host
+ * cost_offset [B+1], device costs); per-column arrays are packed by the
+ * prefix sums of n.  maximize negates the costs first.  All calls return
+ * after completion.  Errors: LPR_EINVAL, LPR_ENOMEM, LPR_EDEVICE.
+ */
+#define LPR_PRICENET_FEATURES 16
+#define LPR_PRICENET_WIDTH 128
+
+size_t lpr_pricenet_param_count(void);
+
+/* Device workspace bytes for any lpr_pricenet_* call on these instances. */
+size_t lpr_pricenet_workspace(int32_t B, const int32_t *n);
+
+/* Column features (device float [sum n, 16], or NULL) and cost scales
+ * sc (device float [B], or NULL). */
+lpr_status lpr_pricenet_features(int32_t B, const int32_t *n,
+                                 const int64_t *cost_offset,
+                                 const int32_t *costs, int32_t maximize,
+                                 float *feats, float *scales, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+
+/* Forward pass.  params: device float [param_count].  Outputs (device, each
+ * may be NULL): q float [sum n] (raw network output); col_prices int64
+ * [sum n], the scaled start prices rint((q - mean q) * sc * (2n+1)) to pass
+ * as lpr_assign_opts.init_col_prices; eps0 int64 [B], the starting epsilon
+ * max(1, rint(kappa * sc * (2n+1))) per instance to pass as
+ * lpr_assign_opts.eps0_per_instance (kappa > 0 is the calibrated error of
+ * the network in units of sc). */
+lpr_status lpr_pricenet_infer(int32_t B, const int32_t *n,
+                              const int64_t *cost_offset, const int32_t *costs,
+                              int32_t maximize, const float *params,
+                              float kappa, float *q, int64_t *col_prices,
+                              int64_t *eps0, void *workspace,
+                              size_t workspace_bytes, void *stream);
+
+/* One training step on a batch.  target_prices: device int64 [sum n], scaled
+ * column prices of an optimal solution (e.g. lpr_assign_solve's col_prices);
+ * they are normalised to t = (p - mean p) / (sc (2n+1)) internally.  Loss
+ * (1/sum n) sum ((q - mean q) - t)^2 goes to loss_out (device float [1], or
+ * NULL) and its gradient to grad_out (device float [param_count], or NULL).
+ * step = 0 computes loss and gradient only; step >= 1 also applies Adam
+ * (beta 0.9 / 0.999, bias correction for that step) to params with the
+ * caller-owned moments adam_m, adam_v (device float [param_count]). */
+lpr_status lpr_pricenet_train_step(int32_t B, const int32_t *n,
+                                   const int64_t *cost_offset,
+                                   const int32_t *costs, int32_t maximize,
+                                   const int64_t *target_prices, float *params,
+                                   float *grad_out, float *adam_m,
+                                   float *adam_v, int32_t step, float lr,
+                                   float *loss_out, void *workspace,
+                                   size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

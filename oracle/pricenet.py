@@ -1,0 +1,171 @@
+"""CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+
+Float64 reference of the learned warm start for cost scaling: the column
+features, the permutation-equivariant price network, its loss and the
+gradients.  The paper has no learned component; the definitions below are
+the specification the GPU kernels implement, so this module restates them as
+plainly as possible (numpy, no batching tricks).
+
+Features of an n x n cost matrix c (minimised), for every column y; all of
+them are symmetric functions over the rows x (invariant to row order) and
+move with their column (equivariant to column order):
+  sc      = mean |c| over the matrix (1 if that is 0); z = c / sc
+  rr(x,y) = z(x,y) - min_y' z(x,y')               (row-reduced cost)
+  f0..f7  = the 8 smallest z(., y), ascending (the largest repeats if n < 8)
+  f8, f9  = mean and (population) standard deviation of z(., y)
+  f10,f11 = the 2 smallest rr(., y)
+  f12     = mean rr(., y)
+  f13     = v2(y) - mean_y v2, where u2(x) = min_y (z(x,y) - f10(y)) and
+            v2(y) = min_x (z(x,y) - u2(x))  (two alternating min passes of
+            the dual problem started from f10)
+  f14     = s(y) - mean_y s, s(y) = -TAU log sum_x exp(-rr(x,y) / TAU)
+  f15     = log(n) / 6
+
+Network (DeepSets-style, equivariant over columns; H0 = features [n, 16]):
+  H_l = relu(H_{l-1} W_l + 1 mean_y(H_{l-1}) U_l + 1 b_l),  l = 1, 2, 3
+  q   = H_3 w_o + b_o                     (normalised price per column)
+Widths: 16 -> 128 -> 128 -> 128 -> 1.  Parameter vector layout (float32 on
+the device): W1 [16,128], U1 [16,128], b1 [128], W2, U2 [128,128], b2,
+W3, U3 [128,128], b3, w_o [128], b_o [1] -- each row-major, concatenated.
+
+Loss over a batch of instances with centred targets t (normalised prices):
+  L = (1 / sum_i n_i) sum_i sum_y ((q_y - mean_i q) - t_y)^2
+Scaled integer start prices for the solver: p(y) = rint(q_y * sc * (2n+1)).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+F_IN = 16
+WIDTH = 128
+TAU = 0.1
+LAYERS = [(F_IN, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH)]
+
+
+def param_shapes():
+    shapes = []
+    for (k, m) in LAYERS:
+        shapes += [("W", (k, m)), ("U", (k, m)), ("b", (m,))]
+    shapes += [("wo", (WIDTH,)), ("bo", (1,))]
+    return shapes
+
+
+def param_count():
+    return int(sum(np.prod(s) for _, s in param_shapes()))
+
+
+def unpack(theta):
+    theta = np.asarray(theta, np.float64)
+    out, off = [], 0
+    for _, s in param_shapes():
+        k = int(np.prod(s))
+        out.append(theta[off:off + k].reshape(s))
+        off += k
+    assert off == len(theta)
+    return out
+
+
+def init_params(seed=0):
+    """He-style initialisation (float32 values)."""
+    g = np.random.default_rng(np.random.SeedSequence([77, seed]))
+    parts = []
+    for name, s in param_shapes():
+        if name in ("W", "U"):
+            parts.append(g.normal(0, np.sqrt(1.0 / s[0]), s).ravel())
+        elif name == "wo":
+            parts.append(g.normal(0, np.sqrt(1.0 / s[0]), s).ravel())
+        else:
+            parts.append(np.zeros(s).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def features(cost, maximize=False):
+    """[n, 16] float64 features and the cost scale sc (see module doc)."""
+    c = np.asarray(cost, np.float64)
+    if maximize:
+        c = -c
+    n = c.shape[0]
+    sc = np.abs(c).mean()
+    if sc == 0:
+        sc = 1.0
+    z = c / sc
+    rr = z - z.min(axis=1, keepdims=True)
+    f = np.zeros((n, F_IN))
+    zs = np.sort(z, axis=0)
+    rs = np.sort(rr, axis=0)
+    for k in range(8):
+        f[:, k] = zs[min(k, n - 1)]
+    f[:, 8] = z.mean(axis=0)
+    f[:, 9] = z.std(axis=0)
+    f[:, 10] = rs[0]
+    f[:, 11] = rs[min(1, n - 1)]
+    f[:, 12] = rr.mean(axis=0)
+    u2 = (z - f[:, 10][None, :]).min(axis=1)
+    v2 = (z - u2[:, None]).min(axis=0)
+    f[:, 13] = v2 - v2.mean()
+    m = rr.min(axis=0)
+    s = m - TAU * np.log(np.exp(-(rr - m[None, :]) / TAU).sum(axis=0))
+    f[:, 14] = s - s.mean()
+    f[:, 15] = np.log(n) / 6.0
+    return f, sc
+
+
+def forward(theta, feats_list):
+    """Outputs q per instance and the cache for backward."""
+    P = unpack(theta)
+    outs, caches = [], []
+    for X in feats_list:
+        H = np.asarray(X, np.float64)
+        cache = []
+        for l in range(3):
+            W, U, b = P[3 * l], P[3 * l + 1], P[3 * l + 2]
+            Z = H @ W + H.mean(axis=0, keepdims=True) @ U + b[None, :]
+            cache.append((H, Z))
+            H = np.maximum(Z, 0.0)
+        q = H @ P[9] + P[10][0]
+        outs.append(q)
+        caches.append((cache, H))
+    return outs, caches
+
+
+def loss_and_grad(theta, feats_list, targets):
+    """Shift-invariant MSE over a batch and its gradient (float64)."""
+    P = unpack(theta)
+    outs, caches = forward(theta, feats_list)
+    N = sum(len(t) for t in targets)
+    L = 0.0
+    grads = [np.zeros_like(p) for p in P]
+    for q, t, (cache, H3) in zip(outs, targets, caches):
+        r = (q - q.mean()) - (np.asarray(t, np.float64) - np.mean(t))
+        L += (r ** 2).sum() / N
+        dq = 2.0 * r / N            # d/dq of the centred residual (sum r = 0)
+        grads[9] += H3.T @ dq
+        grads[10][0] += dq.sum()
+        dH = np.outer(dq, P[9])
+        for l in (2, 1, 0):
+            W, U = P[3 * l], P[3 * l + 1]
+            Hin, Z = cache[l]
+            dZ = dH * (Z > 0)
+            n = Hin.shape[0]
+            grads[3 * l] += Hin.T @ dZ
+            grads[3 * l + 1] += np.outer(Hin.mean(axis=0), dZ.sum(axis=0))
+            grads[3 * l + 2] += dZ.sum(axis=0)
+            dH = dZ @ W.T + np.outer(np.ones(n), dZ.sum(axis=0) @ U.T) / n
+    return L, np.concatenate([g.ravel() for g in grads])
+
+
+def predict_prices(theta, cost, maximize=False):
+    """Integer scaled start prices for one instance."""
+    f, sc = features(cost, maximize)
+    q = forward(theta, [f])[0][0]
+    q = q - q.mean()
+    n = f.shape[0]
+    return np.rint(q * sc * (2 * n + 1)).astype(np.int64)
+
+
+def bf16_round(a):
+    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)

@@ -66,6 +66,7 @@ struct AArgs {
     int32_t sign;      // +1 minimise c, -1 maximise (solve with c = -w)
     int32_t alpha;
     int64_t eps0;      // 0: max|c| * S
+    const int64_t *eps0_inst;  // per-instance override, or null
     const int64_t *init_prices;
     int32_t *row_to_col;
     int64_t *totals;
@@ -331,6 +332,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     __syncthreads();
     // Algorithm 5.0 starts at eps = C (largest |cost|), here in scaled units
     int64_t eps = A.eps0 > 0 ? A.eps0 : (cmax > 0 ? int64_t(cmax) * S : 1);
+    if (A.eps0_inst && A.eps0_inst[slot] > 0) eps = A.eps0_inst[slot];
     const int64_t alpha = A.alpha;
 
     for (;;) {
@@ -590,9 +592,10 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     int32_t alpha = 8;
     int64_t eps0 = 0, max_ops = 64 * int64_t(nmax) * nmax + (int64_t(1) << 20);
     int64_t max_ms = 20000;
-    const int64_t *init = nullptr;
+    const int64_t *init = nullptr, *eps0_inst = nullptr;
     bool timing = false;
     if (opts) {
+        eps0_inst = opts->eps0_per_instance;
         if (opts->alpha) alpha = opts->alpha;
         eps0 = opts->eps0;
         init = opts->init_col_prices;
@@ -637,6 +640,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     A.sign = maximize ? -1 : 1;
     A.alpha = alpha;
     A.eps0 = eps0;
+    A.eps0_inst = eps0_inst;
     A.init_prices = init;
     A.row_to_col = row_to_col;
     A.totals = totals;

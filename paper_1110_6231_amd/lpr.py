@@ -33,7 +33,11 @@ EXPORTED = [
     "lpr_grid_maxflow_batched_workspace", "lpr_grid_maxflow_batched",
     "lpr_assign_workspace", "lpr_assign_solve",
     "lpr_assign_batched_workspace", "lpr_assign_solve_batched",
+    "lpr_pricenet_param_count", "lpr_pricenet_workspace",
+    "lpr_pricenet_features", "lpr_pricenet_infer", "lpr_pricenet_train_step",
 ]
+PRICENET_FEATURES = 16
+PRICENET_WIDTH = 128
 
 
 class LprError(RuntimeError):
@@ -69,7 +73,7 @@ class AssignOpts(ctypes.Structure):
                 ("init_col_prices", ctypes.c_void_p),
                 ("max_ops", ctypes.c_int64),
                 ("max_ms", ctypes.c_int64),
-                ("reserved", ctypes.c_int64)]
+                ("eps0_per_instance", ctypes.c_void_p)]
 
 
 class AssignStats(ctypes.Structure):
@@ -126,6 +130,18 @@ def lib():
                                            ctypes.POINTER(AssignOpts),
                                            ctypes.POINTER(AssignStats), vp, sz,
                                            vp]
+    L.lpr_pricenet_param_count.restype = sz
+    L.lpr_pricenet_param_count.argtypes = []
+    L.lpr_pricenet_workspace.restype = sz
+    L.lpr_pricenet_workspace.argtypes = [i32, i32p]
+    L.lpr_pricenet_features.restype = ctypes.c_int
+    L.lpr_pricenet_features.argtypes = [i32, i32p, i64p, vp, i32, vp, vp, vp, sz, vp]
+    L.lpr_pricenet_infer.restype = ctypes.c_int
+    L.lpr_pricenet_infer.argtypes = [i32, i32p, i64p, vp, i32, vp, ctypes.c_float,
+                                     vp, vp, vp, vp, sz, vp]
+    L.lpr_pricenet_train_step.restype = ctypes.c_int
+    L.lpr_pricenet_train_step.argtypes = [i32, i32p, i64p, vp, i32, vp, vp, vp, vp,
+                                          vp, i32, ctypes.c_float, vp, vp, sz, vp]
     _lib = L
     return L
 
@@ -261,9 +277,11 @@ def lpr_grid_maxflow_batched(Hs, Ws, caps_packed, want_cut=True,
 # Assignment
 # ---------------------------------------------------------------------------
 def make_assign_opts(alpha=0, eps0=0, init_col_prices=None, max_ops=0,
-                     flags=0, max_ms=0) -> AssignOpts:
+                     flags=0, max_ms=0, eps0_per_instance=None) -> AssignOpts:
     o = AssignOpts()
     o.max_ms = max_ms
+    o.eps0_per_instance = (None if eps0_per_instance is None
+                           else eps0_per_instance.data_ptr())
     o.alpha = alpha
     o.eps0 = eps0
     o.init_col_prices = None if init_col_prices is None else init_col_prices.data_ptr()
@@ -346,3 +364,81 @@ def lpr_assign_solve_batched(packed: PackedAssign, maximize=False,
         _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "lpr_assign_solve_batched")
     return r2c, tots, prices, _struct_dict(st)
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start (price network)
+# ---------------------------------------------------------------------------
+def lpr_pricenet_param_count() -> int:
+    return int(lib().lpr_pricenet_param_count())
+
+
+def lpr_pricenet_workspace(ns) -> int:
+    return int(lib().lpr_pricenet_workspace(len(ns), _i32_arr(ns)))
+
+
+def _net_ws(packed, workspace):
+    if workspace is not None:
+        return workspace
+    return _workspace(lpr_pricenet_workspace(packed.ns), packed.costs.device)
+
+
+def lpr_pricenet_features(packed: PackedAssign, maximize=False, workspace=None,
+                          stream=None):
+    """Column features [sum n, 16] (float32) and cost scales [B]."""
+    import torch
+    dev = packed.costs.device
+    R = int(packed.row_offset[-1])
+    B = len(packed.ns)
+    feats = torch.empty((R, PRICENET_FEATURES), dtype=torch.float32, device=dev)
+    scales = torch.empty(B, dtype=torch.float32, device=dev)
+    ws = _net_ws(packed, workspace)
+    rc = lib().lpr_pricenet_features(
+        B, _i32_arr(packed.ns), _i64_arr(packed.cost_offset), _ptr(packed.costs),
+        int(bool(maximize)), _ptr(feats), _ptr(scales), _ptr(ws), ws.numel(),
+        _stream(stream))
+    _check(rc, "lpr_pricenet_features")
+    return feats, scales
+
+
+def lpr_pricenet_infer(packed: PackedAssign, params, maximize=False,
+                       kappa=None, workspace=None, stream=None):
+    """Network output q (float32 [sum n]), scaled start prices (int64
+    [sum n]) and, when kappa is given, the per-instance starting epsilon
+    (int64 [B]); otherwise the third value is None."""
+    import torch
+    dev = packed.costs.device
+    R = int(packed.row_offset[-1])
+    q = torch.empty(R, dtype=torch.float32, device=dev)
+    prices = torch.empty(R, dtype=torch.int64, device=dev)
+    eps = (torch.empty(len(packed.ns), dtype=torch.int64, device=dev)
+           if kappa is not None else None)
+    ws = _net_ws(packed, workspace)
+    rc = lib().lpr_pricenet_infer(
+        len(packed.ns), _i32_arr(packed.ns), _i64_arr(packed.cost_offset),
+        _ptr(packed.costs), int(bool(maximize)), _ptr(params),
+        float(kappa or 0.0), _ptr(q), _ptr(prices), _ptr(eps), _ptr(ws),
+        ws.numel(), _stream(stream))
+    _check(rc, "lpr_pricenet_infer")
+    return q, prices, eps
+
+
+def lpr_pricenet_train_step(packed: PackedAssign, target_prices, params,
+                            adam_m=None, adam_v=None, step=0, lr=1e-3,
+                            maximize=False, want_grad=False, workspace=None,
+                            stream=None):
+    """One training step (step 0: loss and gradient only).  Returns
+    (loss float, gradient tensor or None)."""
+    import torch
+    dev = packed.costs.device
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    grad = (torch.empty(lpr_pricenet_param_count(), dtype=torch.float32,
+                        device=dev) if want_grad else None)
+    ws = _net_ws(packed, workspace)
+    rc = lib().lpr_pricenet_train_step(
+        len(packed.ns), _i32_arr(packed.ns), _i64_arr(packed.cost_offset),
+        _ptr(packed.costs), int(bool(maximize)), _ptr(target_prices),
+        _ptr(params), _ptr(grad), _ptr(adam_m), _ptr(adam_v), int(step),
+        float(lr), _ptr(loss), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_pricenet_train_step")
+    return float(loss.item()), grad

@@ -1,0 +1,148 @@
+"""Train the warm-start price network on the GPU with the library's kernels.
+
+Data: seeded optical-flow-like instances from the training branch of the
+generator (disjoint from the evaluation instances), n ~ U{64..512}.
+Targets: the column prices of optimal solutions produced by the library's own
+cost-scaling solver.  Optimal prices are not unique, so after each round the
+targets are refreshed with the prices of solves started from the network's
+current prediction (the optimum nearest to what the network can express).
+The starting epsilon is calibrated on held-out validation instances: per
+instance eps0 = kappa * sc * (2n+1) (sc = mean |c|), kappa chosen from a grid
+by measured time-to-optimal.  The plain start (p = 0, eps0 = max|c| (2n+1))
+is the reference.
+
+Usage: python -m paper_1110_6231_amd.train_pricenet --out weights.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                               "pricenet_weights.npz")
+KAPPA_GRID = [2.0 ** k for k in range(-8, 2)]
+
+
+def init_params(seed=0):
+    """He-style initialisation of the flat parameter vector (float32)."""
+    g = np.random.default_rng(np.random.SeedSequence([77, seed]))
+    parts = []
+    for (k, m) in ((16, 128), (128, 128), (128, 128)):
+        parts += [g.normal(0, np.sqrt(1.0 / k), (k, m)).ravel(),
+                  g.normal(0, np.sqrt(1.0 / k), (k, m)).ravel(),
+                  np.zeros(m)]
+    parts += [g.normal(0, np.sqrt(1.0 / 128), 128), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def load_weights(path=DEFAULT_WEIGHTS):
+    """(params float32 [P], kappa float, meta dict); no pickles."""
+    with np.load(path, allow_pickle=False) as z:
+        params = z["params"].astype(np.float32)
+        kappa = float(z["kappa"])
+        meta = json.loads(str(z["meta"]))
+    return params, kappa, meta
+
+
+def learned_solve(packed, params, kappa, lpr, ws_net=None, ws_solve=None):
+    """Features + network + warm-started solve, all in the library."""
+    _, prices, eps = lpr.lpr_pricenet_infer(packed, params, kappa=kappa,
+                                            workspace=ws_net)
+    opts = lpr.make_assign_opts(init_col_prices=prices, eps0_per_instance=eps)
+    return lpr.lpr_assign_solve_batched(packed, opts=opts, workspace=ws_solve)
+
+
+def timed(fn, torch, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--train-batches", type=int, default=4)
+    ap.add_argument("--minibatch", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--rounds", type=int, default=6)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--refresh-kappa", type=float, default=0.0625)
+    args = ap.parse_args()
+
+    import torch
+
+    import synth
+    from paper_1110_6231_amd import lpr
+
+    assert torch.cuda.is_available()
+    t_start = time.perf_counter()
+    train = []
+    for s in range(args.train_batches):
+        mats = synth.assign_batch(seed=s, count=256, train=True)
+        for i in range(0, len(mats), args.minibatch):
+            train.append(lpr.PackedAssign.from_matrices(mats[i:i + args.minibatch]))
+    val = lpr.PackedAssign.from_matrices(
+        synth.assign_batch(seed=1000, count=64, train=True))
+    print(f"[train] {len(train)} minibatches, data ready "
+          f"{time.perf_counter() - t_start:.1f}s", flush=True)
+    targets = [lpr.lpr_assign_solve_batched(p)[2] for p in train]
+    params = torch.as_tensor(init_params(0), device="cuda")
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    step = 0
+    g = np.random.default_rng(0)
+    for rnd in range(args.rounds):
+        for ep in range(args.epochs):
+            losses = []
+            for i in g.permutation(len(train)):
+                step += 1
+                loss, _ = lpr.lpr_pricenet_train_step(
+                    train[i], targets[i], params, m, v, step=step, lr=args.lr)
+                losses.append(loss)
+            print(f"[train] round {rnd} epoch {ep} loss {np.mean(losses):.5f}",
+                  flush=True)
+        # refresh: the optimum nearest to the current prediction
+        targets = []
+        for p in train:
+            _, _, pr, _ = learned_solve(p, params, args.refresh_kappa, lpr)
+            targets.append(pr)
+    # calibrate kappa on validation instances by measured time-to-optimal
+    t_plain, (_, tot_plain, _, st_plain) = timed(
+        lambda: lpr.lpr_assign_solve_batched(val), torch)
+    best = None
+    for kappa in KAPPA_GRID:
+        t, (_, tot, _, st) = timed(
+            lambda: learned_solve(val, params, kappa, lpr), torch)
+        assert torch.equal(tot, tot_plain)
+        print(f"[calib] kappa {kappa:7.2f}: {t * 1e3:8.2f} ms "
+              f"(plain {t_plain * 1e3:.2f} ms), ops "
+              f"{st['pushes'] + st['relabels']} vs "
+              f"{st_plain['pushes'] + st_plain['relabels']}", flush=True)
+        if best is None or t < best[0]:
+            best = (t, kappa)
+    meta = {"features": 16, "width": 128, "layers": 3, "steps": step,
+            "rounds": args.rounds, "epochs": args.epochs, "lr": args.lr,
+            "train_instances": 256 * args.train_batches,
+            "val_speedup": t_plain / best[0], "kappa_grid": KAPPA_GRID}
+    np.savez(args.out, params=params.cpu().numpy(), kappa=np.float64(best[1]),
+             meta=np.array(json.dumps(meta)))
+    print(f"[train] saved {args.out}: kappa {best[1]}, validation speedup "
+          f"{t_plain / best[0]:.2f}x, {time.perf_counter() - t_start:.1f}s",
+          flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+"""GPU checks of the price network: features against the float64 oracle,
+forward and gradient against the oracle fed the same BF16-rounded inputs and
+weights (tolerance set by the bf16 mantissa, 2^-8), training reduces the
+loss, and warm-started solves stay exact."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import pricenet as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1110_6231_amd import lpr  # noqa: E402
+
+
+def _packed(mats):
+    return lpr.PackedAssign.from_matrices(mats)
+
+
+def _cpu_inputs(theta32, feats_gpu, offs):
+    """The oracle's view of what the GPU multiplies: bf16 features, bf16 W;
+    U, biases and the head stay float32."""
+    th = theta32.astype(np.float64).copy()
+    for off, size in ((0, 2048), (4224, 16384), (37120, 16384)):
+        th[off:off + size] = P.bf16_round(theta32[off:off + size])
+    fb = P.bf16_round(feats_gpu)
+    return th, [fb[offs[k]:offs[k + 1]] for k in range(len(offs) - 1)]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_features_match_oracle():
+    mats = [synth.assign_points(n, seed=2, instance=k + 1)
+            for k, n in enumerate([64, 150, 333])]
+    mats.append(synth.assign_random_small(5, 3, lo=0, hi=9))
+    packed = _packed(mats)
+    print("[net] features", packed.ns, flush=True)
+    F, sc = lpr.lpr_pricenet_features(packed)
+    F = F.cpu().numpy()
+    sc = sc.cpu().numpy()
+    for k, m in enumerate(mats):
+        fw, scw = P.features(m)
+        a, b = packed.row_offset[k], packed.row_offset[k + 1]
+        assert abs(sc[k] - scw) <= 1e-5 * scw
+        np.testing.assert_allclose(F[a:b], fw, atol=3e-3, rtol=1e-3)
+
+
+def test_forward_and_gradient_match_oracle():
+    mats = [synth.assign_points(n, seed=3, instance=k + 1)
+            for k, n in enumerate([64, 97, 200])]
+    packed = _packed(mats)
+    theta = P.init_params(7)
+    g = np.random.default_rng(1)
+    theta = (theta + g.normal(0, 0.02, theta.shape)).astype(np.float32)
+    params = torch.as_tensor(theta, device="cuda")
+    print("[net] forward/backward", packed.ns, flush=True)
+    q, prices, _ = lpr.lpr_pricenet_infer(packed, params)
+    F, sc = lpr.lpr_pricenet_features(packed)
+    th, feats = _cpu_inputs(theta, F.cpu().numpy(), packed.row_offset)
+    q_cpu = P.forward(th, feats)[0]
+    q_gpu = q.cpu().numpy()
+    offs = packed.row_offset
+    for k in range(len(mats)):
+        assert rel(q_gpu[offs[k]:offs[k + 1]], q_cpu[k]) < 3e-2
+    # targets: the solver's own prices for each instance
+    tp = []
+    for m in mats:
+        _, _, p, _ = lpr.lpr_assign_solve(m)
+        tp.append(p)
+    tgt = torch.cat(tp)
+    loss, grad = lpr.lpr_pricenet_train_step(packed, tgt, params, step=0,
+                                             want_grad=True)
+    scn = sc.cpu().numpy()
+    targets = []
+    for k, m in enumerate(mats):
+        n = m.shape[0]
+        t = tp[k].cpu().numpy().astype(np.float64)
+        targets.append((t - t.mean()) / (scn[k] * (2 * n + 1)))
+    L_cpu, g_cpu = P.loss_and_grad(th, feats, targets)
+    assert abs(loss - L_cpu) <= 3e-2 * L_cpu
+    g_gpu = grad.cpu().numpy().astype(np.float64)
+    assert rel(g_gpu, g_cpu) < 5e-2
+    # every parameter block, not just the norm of the whole vector
+    off = 0
+    for name, shape in P.param_shapes():
+        size = int(np.prod(shape))
+        if name != "bo":
+            assert rel(g_gpu[off:off + size], g_cpu[off:off + size]) < 8e-2, name
+        off += size
+
+
+def test_training_reduces_loss_and_solves_stay_exact():
+    mats = synth.assign_batch(seed=0, count=12, train=True)
+    packed = _packed(mats)
+    _, _, tp, _ = lpr.lpr_assign_solve_batched(packed)
+    params = torch.as_tensor(P.init_params(0), device="cuda")
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    first = None
+    for step in range(1, 61):
+        loss, _ = lpr.lpr_pricenet_train_step(packed, tp, params, m, v,
+                                              step=step, lr=2e-3)
+        first = first if first is not None else loss
+    print(f"[net] loss {first:.4f} -> {loss:.4f}", flush=True)
+    assert loss < 0.85 * first
+    q, prices, eps = lpr.lpr_pricenet_infer(packed, params, kappa=64.0)
+    sc = [np.abs(m).mean() for m in mats]
+    want = [max(1, round(64.0 * s * (2 * m.shape[0] + 1))) for s, m in zip(sc, mats)]
+    got = eps.cpu().numpy()
+    for g_, w_ in zip(got, want):
+        assert abs(int(g_) - w_) <= 1e-5 * w_ + 1
+    opts = lpr.make_assign_opts(init_col_prices=prices, eps0_per_instance=eps)
+    r2c, tots, _, st = lpr.lpr_assign_solve_batched(packed, opts=opts)
+    tots = tots.cpu().numpy()
+    for k, mat in enumerate(mats):
+        assert tots[k] == oracle.assign(mat)[1]
+
+
+def test_learned_start_gain_on_held_out_instances():
+    """The committed network (trained by train_pricenet.py on the training
+    branch) against the plain start on evaluation instances it never saw:
+    both exact; the learned start must need fewer push/relabel operations.
+    The measured ratios are printed."""
+    import time
+    from paper_1110_6231_amd.train_pricenet import learned_solve, load_weights
+
+    theta, kappa, meta = load_weights()
+    params = torch.as_tensor(theta, device="cuda")
+    mats = synth.assign_batch(seed=0, count=64)
+    packed = _packed(mats)
+    _, tot_p, _, st_p = lpr.lpr_assign_solve_batched(packed)
+    _, tot_l, _, st_l = learned_solve(packed, params, kappa, lpr)
+    assert torch.equal(tot_p, tot_l)
+    want = np.array([oracle.assign(m)[1] for m in mats[:8]])
+    np.testing.assert_array_equal(tot_l.cpu().numpy()[:8], want)
+    ops_p = st_p["pushes"] + st_p["relabels"]
+    ops_l = st_l["pushes"] + st_l["relabels"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        lpr.lpr_assign_solve_batched(packed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        learned_solve(packed, params, kappa, lpr)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(f"[net] held-out ops plain {ops_p} learned {ops_l} "
+          f"({ops_p / ops_l:.2f}x); time plain {(t1 - t0) / 3 * 1e3:.1f} ms "
+          f"learned {(t2 - t1) / 3 * 1e3:.1f} ms", flush=True)
+    assert ops_l < ops_p

@@ -1,0 +1,120 @@
+"""Pins for the float64 price-network oracle (CPU only).
+
+The network is this project's addition, so its oracle is pinned by
+properties: central finite differences of the loss, exact column
+equivariance / row invariance, closed-form features of a constant matrix,
+library routines for order statistics and deviations, shift invariance of
+the loss, and torch's own bfloat16 rounding.
+"""
+import heapq
+import math
+import statistics
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pricenet as P
+
+
+def _batch(seed, sizes):
+    feats = [P.features(synth.assign_random_small(n, seed + n, lo=0, hi=60))[0]
+             for n in sizes]
+    g = np.random.default_rng(seed)
+    targets = [g.normal(0, 1, n) for n in sizes]
+    targets = [t - t.mean() for t in targets]
+    return feats, targets
+
+
+def test_param_layout():
+    assert P.param_count() == 70145
+    theta = P.init_params(0)
+    parts = P.unpack(theta)
+    assert [p.shape for p in parts] == [s for _, s in P.param_shapes()]
+
+
+def test_finite_differences():
+    feats, targets = _batch(3, [5, 9])
+    theta = P.init_params(1).astype(np.float64)
+    g = np.random.default_rng(2)
+    theta += g.normal(0, 0.05, theta.shape)   # move off the init symmetry
+    L, grad = P.loss_and_grad(theta, feats, targets)
+    assert L > 0
+    idx = np.concatenate([g.choice(len(theta), 60, replace=False),
+                          [70016, 70144, 4096, 69888]])
+    h = 1e-6
+    for i in idx:
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        fd = (P.loss_and_grad(tp, feats, targets)[0] -
+              P.loss_and_grad(tm, feats, targets)[0]) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, grad[i])
+
+
+def test_equivariance_and_invariance():
+    c = synth.assign_points(40, seed=1, instance=3)
+    f, sc = P.features(c)
+    g = np.random.default_rng(0)
+    pc = g.permutation(40)
+    pr = g.permutation(40)
+    fc, _ = P.features(c[:, pc])
+    np.testing.assert_allclose(fc, f[pc], rtol=1e-12, atol=1e-12)
+    fr, _ = P.features(c[pr])
+    np.testing.assert_allclose(fr, f, rtol=1e-12, atol=1e-12)
+    theta = P.init_params(4)
+    q = P.forward(theta, [f])[0][0]
+    qc = P.forward(theta, [fc])[0][0]
+    np.testing.assert_allclose(qc, q[pc], rtol=1e-10, atol=1e-10)
+
+
+def test_constant_matrix_features():
+    n = 12
+    f, sc = P.features(np.full((n, n), 7))
+    assert sc == 7
+    np.testing.assert_allclose(f[:, :9], 1.0)
+    np.testing.assert_allclose(f[:, 9:15], 0.0, atol=1e-12)
+    np.testing.assert_allclose(f[:, 15], math.log(n) / 6)
+
+
+def test_features_against_library_routines():
+    c = synth.assign_random_small(23, 9, lo=-40, hi=90)
+    f, sc = P.features(c)
+    z = c / np.abs(c).mean()
+    rr = z - z.min(axis=1, keepdims=True)
+    for y in (0, 5, 22):
+        col = [float(v) for v in z[:, y]]
+        np.testing.assert_allclose(f[y, :8], heapq.nsmallest(8, col))
+        assert math.isclose(f[y, 8], math.fsum(col) / len(col))
+        assert math.isclose(f[y, 9], statistics.pstdev(col), rel_tol=1e-9)
+        rcol = [float(v) for v in rr[:, y]]
+        np.testing.assert_allclose(f[y, 10:12], heapq.nsmallest(2, rcol))
+    # the two alternating min passes of f13 by explicit loops
+    n = 23
+    v1 = [min(rr[x, y] for x in range(n)) for y in range(n)]
+    u2 = [min(z[x, y] - v1[y] for y in range(n)) for x in range(n)]
+    v2 = np.array([min(z[x, y] - u2[x] for x in range(n)) for y in range(n)])
+    np.testing.assert_allclose(f[:, 13], v2 - v2.mean(), atol=1e-12)
+    s = np.array([-P.TAU * math.log(math.fsum(math.exp(-rr[x, y] / P.TAU)
+                                               for x in range(n)))
+                  for y in range(n)])
+    np.testing.assert_allclose(f[:, 14], s - s.mean(), atol=1e-9)
+
+
+def test_loss_shift_invariance():
+    feats, targets = _batch(5, [7, 11])
+    theta = P.init_params(2).astype(np.float64)
+    L0, _ = P.loss_and_grad(theta, feats, targets)
+    L1, _ = P.loss_and_grad(theta, feats, [t + 3.0 for t in targets])
+    theta2 = theta.copy(); theta2[-1] += 5.0     # output bias
+    L2, _ = P.loss_and_grad(theta2, feats, targets)
+    assert math.isclose(L0, L1, rel_tol=1e-12) and math.isclose(L0, L2, rel_tol=1e-12)
+    q = P.forward(theta, feats)[0]
+    Lz, _ = P.loss_and_grad(theta, feats, [qq - qq.mean() for qq in q])
+    assert Lz < 1e-20
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    x = np.random.default_rng(0).normal(0, 3, 1000).astype(np.float32)
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(P.bf16_round(x), ref)
