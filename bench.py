@@ -105,22 +105,49 @@ def assign_leg(args, torch, lpr, synth):
            "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(dt * 1e3, 3),
            "total": tot, "refines": st["refines"], "phases": st["phases"],
            "pushes": st["pushes"], "relabels": st["relabels"]}
+    from paper_1110_6231_amd.train_pricenet import learned_solve, load_weights
     mats = synth.assign_batch(seed=0)
     packed = lpr.PackedAssign.from_matrices(mats, device=dev)
     wsb = torch.empty(lpr.lpr_assign_batched_workspace(packed.ns),
                       dtype=torch.uint8, device=dev)
-    lpr.lpr_assign_solve_batched(packed, workspace=wsb)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        _, tots, _, stb = lpr.lpr_assign_solve_batched(packed, workspace=wsb)
-    torch.cuda.synchronize()
-    dtb = (time.perf_counter() - t0) / reps
+    wsn = torch.empty(lpr.lpr_pricenet_workspace(packed.ns), dtype=torch.uint8,
+                      device=dev)
+    theta, kappa, _ = load_weights()
+    params = torch.as_tensor(theta, device=dev)
+
+    def plain():
+        return lpr.lpr_assign_solve_batched(packed, workspace=wsb)
+
+    def learned():
+        return learned_solve(packed, params, kappa, lpr, ws_net=wsn, ws_solve=wsb)
+
+    def median_time(fn, k=5):
+        fn()
+        ts = []
+        for _ in range(k):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), r
+
+    tp, (_, tot_p, _, stp) = median_time(plain)
+    tl, (_, tot_l, _, stl) = median_time(learned)
+    assert torch.equal(tot_p, tot_l), "learned start changed an optimum"
     out["batched"] = {"workload": "256 optical-flow-like instances, "
-                                  "n ~ U{64..512}, min-cost, plain start",
-                      "solves_per_s": round(len(mats) / dtb, 1),
-                      "ms_per_batch": round(dtb * 1e3, 3),
-                      "phases": stb["phases"]}
+                                  "n ~ U{64..512}, min-cost",
+                      "plain": {"solves_per_s": round(len(mats) / tp, 1),
+                                "ms_per_batch": round(tp * 1e3, 3),
+                                "ops": stp["pushes"] + stp["relabels"]},
+                      "learned": {"solves_per_s": round(len(mats) / tl, 1),
+                                  "ms_per_batch": round(tl * 1e3, 3),
+                                  "ops": stl["pushes"] + stl["relabels"],
+                                  "kappa": kappa},
+                      "time_to_optimal_plain_over_learned": round(tp / tl, 3),
+                      "ops_plain_over_learned": round(
+                          (stp["pushes"] + stp["relabels"]) /
+                          (stl["pushes"] + stl["relabels"]), 3)}
     return out
 
 
@@ -146,7 +173,7 @@ def main():
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} "
               "is not supported (the batched workloads would shard by "
-              "instance, see DESIGN.md)", file=sys.stderr)
+              "instance across GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
 
