@@ -57,13 +57,21 @@ def grid_leg(args, torch, lpr, synth):
         v, _, _ = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=opts,
                                        workspace=ws)
     print(f"[bench] grid warmup done, flow={v}", file=sys.stderr, flush=True)
-    timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
     stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        v, side, st = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=opts,
+                                           workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = wall * 1e3 / args.steps
+    # The same K solves again with HIP events around every group of push-sweep
+    # launches (on the library's stream) for the dominant kernel's duration.
+    timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
     sweep_ms = 0.0
     tiles = 0
     sweeps = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for _ in range(args.steps):
         v, side, st = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=timed,
                                            workspace=ws, stream=stream)
@@ -71,8 +79,6 @@ def grid_leg(args, torch, lpr, synth):
         tiles += st["tiles_swept"]
         sweeps += st["sweeps"]
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = wall * 1e3 / args.steps
     tile_px = st["tile_rows"] * 64
     sweep_bytes = tiles * tile_px * SWEEP_BYTES_PER_PIXEL
     avg_launch_ms = sweep_ms / max(sweeps, 1)
@@ -82,7 +88,7 @@ def grid_leg(args, torch, lpr, synth):
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(achieved / HBM_PEAK_GBS, 4),
                           "traffic": None,
-                          "kernel": "k_sweep<16>",
+                          "kernel": f"k_sweep<{st['tile_rows']}>",
                           "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                           "bytes_per_launch": int(sweep_bytes / max(sweeps, 1)),
                           "launches": sweeps})

@@ -36,6 +36,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "lpr_internal.h"
@@ -370,12 +371,17 @@ __global__ __launch_bounds__(NT) void k_count(Dev D, int32_t *act_cur,
     }
 }
 
-// Retire instances with no active pixel and publish the total.
-__global__ void k_count_finish(Dev D) {
+// Retire instances with no active pixel and publish the total.  The count
+// is exact only after the BFS reached its fixpoint: when `bfs_open` is given
+// and nonzero (the last relaxation pass still marked tiles dirty), labels can
+// still be |V| above their BFS level, so nothing is retired and the host
+// finishes the BFS and counts again.
+__global__ void k_count_finish(Dev D, const int32_t *bfs_open) {
+    const bool exact = bfs_open == nullptr || *bfs_open == 0;
     unsigned long long tot = 0;
     for (int i = threadIdx.x; i < D.ninst; i += blockDim.x) {
         const unsigned long long a = D.inst_active[i];
-        if (a == 0) D.done[i] = 1;
+        if (a == 0 && exact) D.done[i] = 1;
         tot += a;
     }
     for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
@@ -715,13 +721,13 @@ static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
             return LPR_EBUDGET;
         }
         LPR_TRY(fill_i32(Lw.sc->pass_count, 0, batch, s));
+        const int ev = tm.begin();
         for (int i = 0; i < batch; ++i) {
-            int ev = tm.begin();
             Kern<TH>::relax(cut, grid, s, D, Lw.dirty[*dirty_sel],
                             Lw.dirty[*dirty_sel ^ 1], Lw.sc->pass_count + i);
-            tm.end(ev);
             *dirty_sel ^= 1;
         }
+        tm.end(ev);
         LPR_TRY_HIP(hipGetLastError());
         *passes += batch;
         int32_t last = 0;
@@ -733,11 +739,155 @@ static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
     }
 }
 
+// Count active pixels (after an exact global relabel) into the scalars and
+// seed the active-tile flags act[0] (read by the next sweep).
+template <int TH>
+static lpr_status enqueue_count(hipStream_t s, const Dev &D, Layout &Lw, dim3 grid,
+                                int B, const int32_t *bfs_open) {
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.inst_active), 0, B, s));
+    Kern<TH>::count(grid, s, D, Lw.act[0], Lw.act[1]);
+    hipLaunchKernelGGL(k_count_finish, dim3(1), dim3(256), 0, s, D, bfs_open);
+    LPR_TRY_HIP(hipGetLastError());
+    return LPR_OK;
+}
+
+// One round of the hybrid scheme (Algorithm 4.8 with the heuristic on the
+// device): K push sweeps, the global relabel seed, P BFS relaxation passes
+// and the count.  K and P are even, so every double-buffer selection is back
+// where it started and the same sequence (or its graph) serves every round.
+template <int TH>
+static lpr_status enqueue_round(hipStream_t s, const Dev &D, Layout &Lw, dim3 grid,
+                                int B, int K, int L, int P, EventTimer *t_sweep,
+                                EventTimer *t_bfs) {
+    int ev = t_sweep ? t_sweep->begin() : -1;
+    for (int k = 0; k < K; ++k)
+        Kern<TH>::sweep(grid, s, D, Lw.act[k & 1], Lw.act[(k & 1) ^ 1], L);
+    if (t_sweep) t_sweep->end(ev);
+    Kern<TH>::bfs_seed(grid, s, D, Lw.dirty[0], Lw.dirty[1]);
+    LPR_TRY(fill_i32(Lw.sc->pass_count, 0, P, s));
+    ev = t_bfs ? t_bfs->begin() : -1;
+    for (int i = 0; i < P; ++i)
+        Kern<TH>::relax(false, grid, s, D, Lw.dirty[i & 1], Lw.dirty[(i & 1) ^ 1],
+                        Lw.sc->pass_count + i);
+    if (t_bfs) t_bfs->end(ev);
+    LPR_TRY(enqueue_count<TH>(s, D, Lw, grid, B, Lw.sc->pass_count + P - 1));
+    return LPR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Round graphs: the kernels of one round captured once per (buffers, shape,
+// schedule) and replayed with a single launch per round.
+// ---------------------------------------------------------------------------
+struct GraphKey {
+    int device;
+    const void *ws;
+    const void *caps[6];
+    int64_t N;
+    int B, T, TH, K, L, P;
+    bool operator==(const GraphKey &o) const {
+        return device == o.device && ws == o.ws && N == o.N && B == o.B &&
+               T == o.T && TH == o.TH && K == o.K && L == o.L && P == o.P &&
+               std::equal(caps, caps + 6, o.caps);
+    }
+};
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    uint64_t stamp;
+};
+
+static std::mutex g_graph_mu;
+static std::vector<GraphEntry> g_graphs;
+static uint64_t g_graph_clock = 0;
+constexpr size_t MAX_GRAPHS = 8;
+
+static lpr_status capture_stream(int device, hipStream_t *out) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, hipStream_t>> streams;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &p : streams)
+        if (p.first == device) {
+            *out = p.second;
+            return LPR_OK;
+        }
+    hipStream_t st;
+    LPR_TRY_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    streams.emplace_back(device, st);
+    *out = st;
+    return LPR_OK;
+}
+
+// Finds or captures the round graph for `key` and launches it on `s` (under
+// the cache lock, so an eviction cannot destroy it in between).
+template <int TH>
+static lpr_status launch_round_graph(const GraphKey &key, const Dev &D, Layout &Lw,
+                                     dim3 grid, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto &e : g_graphs)
+        if (e.key == key) {
+            e.stamp = ++g_graph_clock;
+            LPR_TRY_HIP(hipGraphLaunch(e.exec, s));
+            return LPR_OK;
+        }
+    hipStream_t cs;
+    LPR_TRY(capture_stream(key.device, &cs));
+    hipGraph_t g;
+    LPR_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const lpr_status st = enqueue_round<TH>(cs, D, Lw, grid, key.B, key.K, key.L,
+                                            key.P, nullptr, nullptr);
+    const hipError_t ce = hipStreamEndCapture(cs, &g);
+    if (st != LPR_OK) return st;
+    if (ce != hipSuccess) {
+        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
+        return LPR_EDEVICE;
+    }
+    hipGraphExec_t ex;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+        return LPR_EDEVICE;
+    }
+    if (g_graphs.size() >= MAX_GRAPHS) {
+        auto lru = std::min_element(g_graphs.begin(), g_graphs.end(),
+                                    [](const GraphEntry &a, const GraphEntry &b) {
+                                        return a.stamp < b.stamp;
+                                    });
+        (void)hipGraphExecDestroy(lru->exec);
+        g_graphs.erase(lru);
+    }
+    g_graphs.push_back(GraphEntry{key, ex, ++g_graph_clock});
+    LPR_TRY_HIP(hipGraphLaunch(ex, s));
+    return LPR_OK;
+}
+
+// Pinned host copy of the scalars, one per calling thread.
+static lpr_status host_scalars(Scalars **out) {
+    static thread_local Scalars *h = nullptr;
+    if (!h) LPR_TRY_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(Scalars)));
+    *out = h;
+    return LPR_OK;
+}
+
+template <int TH>
+static lpr_status read_scalars(hipStream_t s, Layout &Lw, Scalars **host) {
+    LPR_TRY(host_scalars(host));
+    LPR_TRY_HIP(hipMemcpyAsync(*host, Lw.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    LPR_TRY_HIP(hipStreamSynchronize(s));
+    if ((*host)->err) {
+        set_error((*host)->err & 1 ? "negative capacity"
+                                   : "capacity exceeds LPR_GRID_MAX_CAP");
+        return (*host)->err & 1 ? LPR_EINVAL : LPR_ERANGE;
+    }
+    return LPR_OK;
+}
+
 template <int TH>
 static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
                         const std::vector<int32_t> &tile_inst, Dev D,
-                        Layout &Lw, int64_t *flow_values, uint8_t *side,
-                        lpr_grid_stats *stats, hipStream_t s) {
+                        Layout &Lw, const GraphKey &base_key, int64_t *flow_values,
+                        uint8_t *side, lpr_grid_stats *stats, hipStream_t s) {
     const int T = int(tile_inst.size());
     const dim3 grid(T);
     EventTimer t_sweep(s), t_bfs(s);
@@ -758,40 +908,58 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
     Kern<TH>::init(grid, s, D);
     LPR_TRY_HIP(hipGetLastError());
 
-    int dirty_sel = 0, act_sel = 0;
+    // First global relabel: eager, to its fixpoint; its pass count sets the
+    // number of BFS passes per later round.
+    int dirty_sel = 0;
+    Kern<TH>::bfs_seed(grid, s, D, Lw.dirty[0], Lw.dirty[1]);
+    LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, &dirty_sel, grid, t_bfs,
+                                  &bfs_passes));
+    int PB = int(std::min<int64_t>(MAX_PASS_SLOTS, std::max<int64_t>(4, bfs_passes / 2 + 2)));
+    PB += PB & 1;
+    LPR_TRY(enqueue_count<TH>(s, D, Lw, grid, B, nullptr));
+    Scalars *host = nullptr;
+    LPR_TRY(read_scalars<TH>(s, Lw, &host));
+    const bool use_graph = !P.timing && (P.K % 2 == 0);
     bool converged = false;
-    for (; rounds < P.max_rounds; ++rounds) {
-        Kern<TH>::bfs_seed(grid, s, D, Lw.dirty[dirty_sel], Lw.dirty[dirty_sel ^ 1]);
-        LPR_TRY_HIP(hipGetLastError());
-        LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, &dirty_sel, grid, t_bfs,
-                                      &bfs_passes));
-        LPR_TRY(t_bfs.harvest(&bfs_ms));
-        LPR_TRY(t_sweep.harvest(&sweep_ms));
-        LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.inst_active), 0, B, s));
-        Kern<TH>::count(grid, s, D, Lw.act[act_sel], Lw.act[act_sel ^ 1]);
-        hipLaunchKernelGGL(k_count_finish, dim3(1), dim3(256), 0, s, D);
-        LPR_TRY_HIP(hipGetLastError());
-        Scalars host;
-        LPR_TRY_HIP(hipMemcpyAsync(&host, Lw.sc, offsetof(Scalars, pass_count),
-                                   hipMemcpyDeviceToHost, s));
-        LPR_TRY_HIP(hipStreamSynchronize(s));
-        if (host.err) {
-            set_error(host.err & 1 ? "negative capacity"
-                                   : "capacity exceeds LPR_GRID_MAX_CAP");
-            return host.err & 1 ? LPR_EINVAL : LPR_ERANGE;
-        }
-        if (host.total_active == 0) {
+    for (;;) {
+        if (host->total_active == 0) {
             converged = true;
             break;
         }
-        for (int k = 0; k < P.K; ++k) {
-            int ev = t_sweep.begin();
-            Kern<TH>::sweep(grid, s, D, Lw.act[act_sel], Lw.act[act_sel ^ 1], P.L);
-            t_sweep.end(ev);
-            act_sel ^= 1;
-        }
-        LPR_TRY_HIP(hipGetLastError());
+        if (rounds >= P.max_rounds) break;
+        ++rounds;
         sweeps += P.K;
+        bfs_passes += PB;
+        if (use_graph) {
+            GraphKey key = base_key;
+            key.K = P.K;
+            key.L = P.L;
+            key.P = PB;
+            LPR_TRY(launch_round_graph<TH>(key, D, Lw, grid, s));
+        } else {
+            // odd K alternates the active-flag buffers; keep it on the eager path
+            if (P.K % 2) {
+                LPR_TRY(enqueue_round<TH>(s, D, Lw, grid, B, P.K + 1, P.L, PB,
+                                          &t_sweep, &t_bfs));
+                sweeps += 1;
+            } else {
+                LPR_TRY(enqueue_round<TH>(s, D, Lw, grid, B, P.K, P.L, PB, &t_sweep,
+                                          &t_bfs));
+            }
+        }
+        LPR_TRY(read_scalars<TH>(s, Lw, &host));
+        if (host->pass_count[PB - 1] != 0) {
+            // the BFS needed more than PB passes: finish it, recount, and give
+            // the following rounds more passes
+            dirty_sel = 0;
+            LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, &dirty_sel, grid, t_bfs,
+                                          &bfs_passes));
+            LPR_TRY(enqueue_count<TH>(s, D, Lw, grid, B, nullptr));
+            LPR_TRY(read_scalars<TH>(s, Lw, &host));
+            PB = std::min(MAX_PASS_SLOTS, PB + 4);
+        }
+        LPR_TRY(t_bfs.harvest(&bfs_ms));
+        LPR_TRY(t_sweep.harvest(&sweep_ms));
     }
     if (!converged) {
         set_error("grid max-flow: round budget (%d) exhausted", P.max_rounds);
@@ -802,8 +970,8 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
     LPR_TRY_HIP(hipGetLastError());
     if (side) {
         // every instance takes part in the closure
-        LPR_TRY(fill_i32(Lw.done, 0, B, s));
-        Kern<TH>::cut_seed(grid, s, D, Lw.dirty[dirty_sel], Lw.dirty[dirty_sel ^ 1]);
+        dirty_sel = 0;
+        Kern<TH>::cut_seed(grid, s, D, Lw.dirty[0], Lw.dirty[1]);
         LPR_TRY_HIP(hipGetLastError());
         EventTimer none(s);
         LPR_TRY(relax_to_fixpoint<TH>(true, s, D, Lw, &dirty_sel, grid, none,
@@ -868,9 +1036,9 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
         }
     }
     Params P;
-    P.TH = 16;
+    P.TH = 8;
     P.L = 16;
-    P.K = 8;
+    P.K = 4;
     P.max_rounds = 1 << 16;
     P.timing = false;
     if (opts) {
@@ -938,18 +1106,26 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     D.ntiles = int32_t(T);
     D.ninst = B;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    GraphKey key{};
+    LPR_TRY_HIP(hipGetDevice(&key.device));
+    key.ws = workspace;
+    for (int i = 0; i < 6; ++i) key.caps[i] = caps[i];
+    key.N = N;
+    key.B = B;
+    key.T = int(T);
+    key.TH = P.TH;
     CallTimer call(s);
     call.start();
     lpr_status st;
     switch (P.TH) {
         case 8:
-            st = solve<8>(P, B, insts, tile_inst, D, Lw, flow_values, side, stats, s);
+            st = solve<8>(P, B, insts, tile_inst, D, Lw, key, flow_values, side, stats, s);
             break;
         case 16:
-            st = solve<16>(P, B, insts, tile_inst, D, Lw, flow_values, side, stats, s);
+            st = solve<16>(P, B, insts, tile_inst, D, Lw, key, flow_values, side, stats, s);
             break;
         default:
-            st = solve<32>(P, B, insts, tile_inst, D, Lw, flow_values, side, stats, s);
+            st = solve<32>(P, B, insts, tile_inst, D, Lw, key, flow_values, side, stats, s);
             break;
     }
     if (st != LPR_OK) {
