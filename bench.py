@@ -42,6 +42,10 @@ def parse():
                     help="skip the CPU oracle baseline")
     ap.add_argument("--no-assign", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-batched-grid", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run plain copies of a known size (counter "
+                         "calibration) and exit")
     return ap.parse_args()
 
 
@@ -92,6 +96,59 @@ def grid_leg(args, torch, lpr, synth):
                           "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                           "bytes_per_launch": int(sweep_bytes / max(sweeps, 1)),
                           "launches": sweeps})
+
+
+def grid_batched_leg(args, torch, lpr, synth):
+    """The batched graph-cut workload (64 grids, H, W in [128, 512], plus one
+    2048 x 2048 grid with pair weights x4) solved by one batched call."""
+    insts = synth.grid_batch(seed=0)
+    Hs = [i.H for i in insts]
+    Ws = [i.W for i in insts]
+    dev = torch.device("cuda:0")
+    caps = [torch.as_tensor(np.concatenate([getattr(i, f) for i in insts]),
+                            device=dev)
+            for f in ("cap_src", "cap_snk", "cap_right", "cap_left",
+                      "cap_down", "cap_up")]
+    ws = torch.empty(lpr.lpr_grid_maxflow_batched_workspace(Hs, Ws),
+                     dtype=torch.uint8, device=dev)
+    px = sum(i.n_pixels for i in insts)
+    lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, workspace=ws)
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        flows, _, st = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
+    _, _, sti = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, opts=timed, workspace=ws)
+    tile_px = sti["tile_rows"] * 64
+    per_launch = sti["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL / max(sti["sweeps"], 1)
+    avg_ms = sti["sweep_ms"] / max(sti["sweeps"], 1)
+    ach = per_launch / (avg_ms * 1e-3) / 1e9
+    return {"workload": "64 blob graph cuts (H, W ~ U{128..512}) + one 2048x2048 "
+                        "graph cut with pair weights x4, one batched call",
+            "pixels": px, "ms_per_batch": round(dt * 1e3, 3),
+            "mvertex_per_s": round(px / dt / 1e6, 2),
+            "flow_2048": int(flows[-1].item()),
+            "global_relabels": st["rounds"], "sweeps": st["sweeps"],
+            "sweep_roofline": {"achieved_GBps": round(ach, 1),
+                               "frac": round(ach / HBM_PEAK_GBS, 4),
+                               "avg_launch_us": round(avg_ms * 1e3, 3),
+                               "bytes_per_launch": int(per_launch)}}
+
+
+def copy_probe(torch, mib=256, reps=5):
+    """Plain device-to-device copies of a known size, for calibrating
+    rocprofv3's FETCH_SIZE / WRITE_SIZE counters."""
+    n = mib * 2 ** 20 // 4
+    a = torch.arange(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "launches": reps}), flush=True)
 
 
 def assign_leg(args, torch, lpr, synth):
@@ -188,6 +245,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     g = grid_leg(args, torch, lpr, synth)
     out = {
         "metric": METRIC,
@@ -214,6 +274,8 @@ def main():
                    "sweeps_per_relabel": g["stats"]["sweeps_per_relabel"]},
         "roofline": g["roofline"],
     }
+    if not args.no_batched_grid:
+        out["grid_batched"] = grid_batched_leg(args, torch, lpr, synth)
     if not args.no_assign:
         out["assignment"] = assign_leg(args, torch, lpr, synth)
     if not args.no_cpu:

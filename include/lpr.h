@@ -75,11 +75,13 @@ const char *lpr_version(void);
 typedef struct {
     int32_t sweeps_per_relabel; /* push-sweep launches between global
                                    relabels (the paper's CYCLE, counted in
-                                   launches); 0 = library default        */
+                                   launches); 0 = tuned default; an odd
+                                   count is rounded up to even            */
     int32_t local_iters;        /* push/relabel iterations each tile runs in
-                                   on-chip memory per sweep launch; 0 = def. */
+                                   on-chip memory per sweep launch; 0 =
+                                   tuned default                          */
     int32_t tile_rows;          /* tile height in pixels: 8, 16 or 32 (tile
-                                   width is 64); 0 = library default      */
+                                   width is 64); 0 = tuned default        */
     int32_t max_rounds;         /* budget of global-relabel rounds; 0 =
                                    default (1 << 16)                       */
     int32_t flags;              /* LPR_GRID_* bits                          */
@@ -173,6 +175,29 @@ lpr_status lpr_grid_maxflow_batched(int32_t B, const int32_t *H,
                                     const lpr_grid_opts *opts,
                                     lpr_grid_stats *stats, void *workspace,
                                     size_t workspace_bytes, void *stream);
+
+/*
+ * Schedule autotuner for the grid solver.  Solves the given batch (same
+ * arguments as lpr_grid_maxflow_batched; flow_values device int64 [B]
+ * receives the flow values) under every schedule of tile rows {8,16,32} x
+ * local iterations {4,8,16,32} x sweeps per relabel {2,4,8}, each `reps`
+ * times after one warm-up run (1 <= reps <= 100), timed with HIP events, and
+ * returns the fastest in `best` (host, may be NULL) with its time in ms
+ * (host, may be NULL).  The winner becomes the default schedule of this
+ * process for the batch's size class (floor(log2(total pixels))) -- used
+ * whenever opts is NULL or leaves a schedule field 0 -- and is written to
+ * the file named by the environment variable LPR_GRID_TUNE_FILE, if set,
+ * which later processes read.  Every schedule must produce the same flow
+ * values; a disagreement returns LPR_EDEVICE.  Other errors as for
+ * lpr_grid_maxflow_batched.
+ */
+lpr_status lpr_grid_tune(int32_t B, const int32_t *H, const int32_t *W,
+                         const int64_t *node_offset, const int32_t *cap_src,
+                         const int32_t *cap_snk, const int32_t *cap_right,
+                         const int32_t *cap_left, const int32_t *cap_down,
+                         const int32_t *cap_up, int64_t *flow_values,
+                         int32_t reps, lpr_grid_opts *best, double *best_ms,
+                         void *workspace, size_t workspace_bytes, void *stream);
 
 /* ======================================================================== */
 /* Form 2: dense assignment by cost scaling                                  */

@@ -35,7 +35,10 @@
 //    and an instance whose count reaches zero retires from later rounds.
 #include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -1002,6 +1005,67 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
     return LPR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Schedules: (tile rows, local iterations, sweeps per relabel) per size class
+// (floor(log2(total pixels))).  Defaults come from a sweep on MI355X;
+// lpr_grid_tune replaces them per class for this process and, when the
+// environment variable LPR_GRID_TUNE_FILE names a file, persists them there
+// (one "class tile_rows local_iters sweeps_per_relabel" line per class).
+// ---------------------------------------------------------------------------
+struct Sched {
+    int TH, L, K;
+};
+
+static std::mutex g_sched_mu;
+static std::map<int, Sched> g_sched;
+static bool g_sched_loaded = false;
+
+static int size_class(int64_t N) {
+    int c = 0;
+    while ((int64_t(1) << (c + 1)) <= N) ++c;
+    return c;
+}
+
+static bool valid_sched(const Sched &s) {
+    return (s.TH == 8 || s.TH == 16 || s.TH == 32) && s.L >= 1 && s.L <= 4096 &&
+           s.K >= 1 && s.K <= 4096;
+}
+
+static void load_sched_file_locked() {
+    if (g_sched_loaded) return;
+    g_sched_loaded = true;
+    const char *path = std::getenv("LPR_GRID_TUNE_FILE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    int c;
+    Sched sc;
+    while (std::fscanf(f, "%d %d %d %d", &c, &sc.TH, &sc.L, &sc.K) == 4)
+        if (c >= 0 && c < 64 && valid_sched(sc)) g_sched[c] = sc;
+    std::fclose(f);
+}
+
+static Sched default_sched(int64_t N) {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    load_sched_file_locked();
+    const auto it = g_sched.find(size_class(N));
+    if (it != g_sched.end()) return it->second;
+    return Sched{8, 16, 4};
+}
+
+static void store_sched(int64_t N, const Sched &sc) {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    load_sched_file_locked();
+    g_sched[size_class(N)] = sc;
+    const char *path = std::getenv("LPR_GRID_TUNE_FILE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    for (const auto &e : g_sched)
+        std::fprintf(f, "%d %d %d %d\n", e.first, e.second.TH, e.second.L, e.second.K);
+    std::fclose(f);
+}
+
 static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
                       const int64_t *node_offset, const int32_t *const caps[6],
                       int64_t *flow_values, uint8_t *side,
@@ -1035,10 +1099,11 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
             return LPR_EINVAL;
         }
     }
+    const Sched ds = default_sched(node_offset[B]);
     Params P;
-    P.TH = 8;
-    P.L = 16;
-    P.K = 4;
+    P.TH = ds.TH;
+    P.L = ds.L;
+    P.K = ds.K;
     P.max_rounds = 1 << 16;
     P.timing = false;
     if (opts) {
@@ -1189,4 +1254,68 @@ extern "C" lpr_status lpr_grid_maxflow_batched(
     const int32_t *caps[6] = {cap_src, cap_snk, cap_right, cap_left, cap_down, cap_up};
     return grid::run(B, H, W, node_offset, caps, flow_values, source_side, opts,
                      stats, workspace, workspace_bytes, stream);
+}
+
+extern "C" lpr_status lpr_grid_tune(int32_t B, const int32_t *H, const int32_t *W,
+                                    const int64_t *node_offset,
+                                    const int32_t *cap_src, const int32_t *cap_snk,
+                                    const int32_t *cap_right, const int32_t *cap_left,
+                                    const int32_t *cap_down, const int32_t *cap_up,
+                                    int64_t *flow_values, int32_t reps,
+                                    lpr_grid_opts *best, double *best_ms,
+                                    void *workspace, size_t workspace_bytes,
+                                    void *stream) {
+    const int32_t *caps[6] = {cap_src, cap_snk, cap_right, cap_left, cap_down, cap_up};
+    if (B < 1 || !node_offset || !flow_values || reps < 1 || reps > 100) {
+        clear_error();
+        set_error("invalid tuning arguments");
+        return LPR_EINVAL;
+    }
+    static const int THs[3] = {8, 16, 32};
+    static const int Ls[4] = {4, 8, 16, 32};
+    static const int Ks[3] = {2, 4, 8};
+    std::vector<int64_t> ref(B), got(B);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double best_t = 1e300;
+    grid::Sched best_s{8, 16, 4};
+    bool have_ref = false;
+    for (int th : THs)
+        for (int l : Ls)
+            for (int k : Ks) {
+                lpr_grid_opts o{};
+                o.tile_rows = th;
+                o.local_iters = l;
+                o.sweeps_per_relabel = k;
+                double t_min = 1e300;
+                for (int r = 0; r <= reps; ++r) {  // the first run warms up
+                    lpr_grid_stats st{};
+                    LPR_TRY(grid::run(B, H, W, node_offset, caps, flow_values, nullptr,
+                                      &o, &st, workspace, workspace_bytes, stream));
+                    if (r > 0) t_min = std::min(t_min, st.total_ms);
+                }
+                LPR_TRY_HIP(hipMemcpyAsync(got.data(), flow_values, sizeof(int64_t) * B,
+                                           hipMemcpyDeviceToHost, s));
+                LPR_TRY_HIP(hipStreamSynchronize(s));
+                if (!have_ref) {
+                    ref = got;
+                    have_ref = true;
+                } else if (got != ref) {
+                    set_error("schedules disagree on a flow value (tile rows %d, "
+                              "local iterations %d, sweeps %d)", th, l, k);
+                    return LPR_EDEVICE;
+                }
+                if (t_min < best_t) {
+                    best_t = t_min;
+                    best_s = grid::Sched{th, l, k};
+                }
+            }
+    grid::store_sched(node_offset[B], best_s);
+    if (best) {
+        *best = lpr_grid_opts{};
+        best->tile_rows = best_s.TH;
+        best->local_iters = best_s.L;
+        best->sweeps_per_relabel = best_s.K;
+    }
+    if (best_ms) *best_ms = best_t;
+    return LPR_OK;
 }

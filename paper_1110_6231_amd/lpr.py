@@ -31,6 +31,7 @@ EXPORTED = [
     "lpr_last_error", "lpr_version",
     "lpr_grid_maxflow_workspace", "lpr_grid_maxflow",
     "lpr_grid_maxflow_batched_workspace", "lpr_grid_maxflow_batched",
+    "lpr_grid_tune",
     "lpr_assign_workspace", "lpr_assign_solve",
     "lpr_assign_batched_workspace", "lpr_assign_solve_batched",
     "lpr_pricenet_param_count", "lpr_pricenet_workspace",
@@ -117,6 +118,9 @@ def lib():
     L.lpr_grid_maxflow_batched.restype = ctypes.c_int
     L.lpr_grid_maxflow_batched.argtypes = [i32, i32p, i32p, i64p] + [vp] * 6 + [
         vp, vp, ctypes.POINTER(GridOpts), ctypes.POINTER(GridStats), vp, sz, vp]
+    L.lpr_grid_tune.restype = ctypes.c_int
+    L.lpr_grid_tune.argtypes = [i32, i32p, i32p, i64p] + [vp] * 6 + [
+        vp, i32, ctypes.POINTER(GridOpts), ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.lpr_assign_workspace.restype = sz
     L.lpr_assign_workspace.argtypes = [i32]
     L.lpr_assign_solve.restype = ctypes.c_int
@@ -271,6 +275,30 @@ def lpr_grid_maxflow_batched(Hs, Ws, caps_packed, want_cut=True,
         _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "lpr_grid_maxflow_batched")
     return flows, side, _struct_dict(st)
+
+
+def lpr_grid_tune(Hs, Ws, caps_packed, reps=2, workspace=None, stream=None):
+    """Schedule search (lpr_grid_tune).  Returns (schedule dict, best ms,
+    flow values of the batch as an int64 tensor)."""
+    import torch
+    B = len(Hs)
+    offs = np.zeros(B + 1, np.int64)
+    offs[1:] = np.cumsum(np.asarray(Hs, np.int64) * np.asarray(Ws, np.int64))
+    caps = list(caps_packed)
+    dev = caps[0].device
+    flows = torch.zeros(B, dtype=torch.int64, device=dev)
+    ws = workspace if workspace is not None else _workspace(
+        lpr_grid_maxflow_batched_workspace(Hs, Ws), dev)
+    best = GridOpts()
+    ms = ctypes.c_double(0.0)
+    rc = lib().lpr_grid_tune(B, _i32_arr(Hs), _i32_arr(Ws), _i64_arr(offs),
+                             *[_ptr(c) for c in caps], _ptr(flows), int(reps),
+                             ctypes.byref(best), ctypes.byref(ms), _ptr(ws),
+                             ws.numel(), _stream(stream))
+    _check(rc, "lpr_grid_tune")
+    sched = {"tile_rows": best.tile_rows, "local_iters": best.local_iters,
+             "sweeps_per_relabel": best.sweeps_per_relabel}
+    return sched, ms.value, flows
 
 
 # ---------------------------------------------------------------------------

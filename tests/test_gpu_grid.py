@@ -165,3 +165,56 @@ def test_errors():
     assert e.value.status == lpr.LPR_EBUDGET
     # the library stays usable after every error
     check_against_oracle(synth.grid_uniform(64, 64, seed=1))
+
+
+def _pack(insts):
+    return [torch.as_tensor(np.concatenate([getattr(i, f) for i in insts]),
+                            device="cuda")
+            for f in ("cap_src", "cap_snk", "cap_right", "cap_left",
+                      "cap_down", "cap_up")]
+
+
+def test_full_batched_workload_against_golden():
+    """The batched graph-cut workload: 64 blob grids with H, W in
+    [128, 512] plus one 2048 x 2048 grid with pair weights x4, in one batched
+    call, at the library's default schedule.  Flow values and S_min must
+    match the oracle's stored values (tests/golden/make_grid_golden.py)."""
+    import hashlib
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "grid_golden.json")))["batch_seed0"]
+    insts = synth.grid_batch(seed=0)
+    Hs = [i.H for i in insts]
+    Ws = [i.W for i in insts]
+    print("[grid] full batched workload", len(insts), sum(i.n_pixels for i in insts),
+          flush=True)
+    flows, side, st = lpr.lpr_grid_maxflow_batched(Hs, Ws, _pack(insts))
+    print("[grid] batched stats", st, flush=True)
+    flows = flows.cpu().numpy()
+    side = side.cpu().numpy()
+    off = 0
+    for k, (inst, rec) in enumerate(zip(insts, gold)):
+        assert rec["name"] == inst.name
+        assert flows[k] == rec["flow"], (k, inst.name)
+        s = side[off:off + inst.n_pixels]
+        assert hashlib.sha256(s.tobytes()).hexdigest() == rec["source_side_sha256"], k
+        off += inst.n_pixels
+
+
+def test_autotuner_is_exact_and_sets_default():
+    insts = [synth.grid_blobs(160 + 40 * k, 230, seed=k) for k in range(3)]
+    Hs = [i.H for i in insts]
+    Ws = [i.W for i in insts]
+    caps = _pack(insts)
+    sched, ms, flows = lpr.lpr_grid_tune(Hs, Ws, caps, reps=1)
+    print("[grid] tuned", sched, ms, flush=True)
+    assert sched["tile_rows"] in (8, 16, 32) and ms > 0
+    want = [oracle.grid_maxflow(i, "fifo")[0] for i in insts]
+    assert list(flows.cpu().numpy()) == want
+    f2, _, st = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, want_cut=False)
+    assert list(f2.cpu().numpy()) == want
+    assert (st["tile_rows"], st["local_iters"]) == (sched["tile_rows"],
+                                                    sched["local_iters"])
+    k = sched["sweeps_per_relabel"]
+    assert st["sweeps_per_relabel"] == k
