@@ -7,7 +7,8 @@ resident in HBM before the timed region; outputs and workspace are
 preallocated.  The JSON line also carries the dense assignment leg (n = 1024,
 weights U{0..1000}, max-weight) and the batched assignment leg (256
 optical-flow-like instances), the roofline of the dominant kernel (the push
-sweep) and the CPU oracle timed on this host.
+sweep or the global-relabel relaxation, whichever takes more time) and the CPU
+oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -31,6 +32,10 @@ HBM_PEAK_GBS = 8000.0
 # int32 state words (e, h, four neighbour residuals, sink residual) read into
 # LDS and written back.
 SWEEP_BYTES_PER_PIXEL = 56
+# Bytes one pass of the global-relabel relaxation must move per pixel of a
+# relaxed tile: the height and the four neighbour residuals read, the height
+# written.
+RELAX_BYTES_PER_PIXEL = 24
 
 
 def parse():
@@ -72,30 +77,71 @@ def grid_leg(args, torch, lpr, synth):
     ms = wall * 1e3 / args.steps
     # The same K solves again with HIP events around every group of push-sweep
     # launches (on the library's stream) for the dominant kernel's duration.
+    # The same K solves again with HIP events around every group of push-sweep
+    # and relaxation launches (on the library's stream) for the durations of
+    # the two kernels that take the time.
     timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
-    sweep_ms = 0.0
-    tiles = 0
-    sweeps = 0
+    acc = dict(sweep_ms=0.0, bfs_ms=0.0, tiles_swept=0, tiles_relaxed=0,
+               sweeps=0, bfs_passes=0)
     for _ in range(args.steps):
         v, side, st = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=timed,
                                            workspace=ws, stream=stream)
-        sweep_ms += st["sweep_ms"]
-        tiles += st["tiles_swept"]
-        sweeps += st["sweeps"]
+        for k in acc:
+            acc[k] += st[k]
     torch.cuda.synchronize()
     tile_px = st["tile_rows"] * 64
-    sweep_bytes = tiles * tile_px * SWEEP_BYTES_PER_PIXEL
-    avg_launch_ms = sweep_ms / max(sweeps, 1)
-    achieved = (sweep_bytes / max(sweeps, 1)) / (avg_launch_ms * 1e-3) / 1e9
-    return dict(inst=inst, flow=v, ms=ms, HW=HW, stats=st,
-                roofline={"bound": "hbm", "achieved": round(achieved, 1),
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(achieved / HBM_PEAK_GBS, 4),
-                          "traffic": None,
-                          "kernel": f"k_sweep<{st['tile_rows']}>",
-                          "avg_launch_us": round(avg_launch_ms * 1e3, 3),
-                          "bytes_per_launch": int(sweep_bytes / max(sweeps, 1)),
-                          "launches": sweeps})
+    legs = {
+        f"k_sweep<{st['tile_rows']}>": kernel_roofline(
+            acc["sweep_ms"], acc["sweeps"],
+            acc["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL),
+        f"k_relax<{st['tile_rows']},false>": kernel_roofline(
+            acc["bfs_ms"], acc["bfs_passes"],
+            acc["tiles_relaxed"] * tile_px * RELAX_BYTES_PER_PIXEL),
+    }
+    dominant = max(legs, key=lambda k: legs[k]["total_ms"])
+    roof = dict(legs[dominant])
+    roof["kernel"] = dominant
+    roof["traffic"] = traffic_for(dominant, st["tile_rows"])
+    others = {k: v for k, v in legs.items() if k != dominant}
+    return dict(inst=inst, flow=v, ms=ms, HW=HW, stats=st, roofline=roof,
+                other_kernels=others)
+
+
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch, averaged over the dispatches of the 1024 x 1024 solve), scaled by
+# what the same counters read for a plain copy of known size (FETCH_SIZE
+# x 2.0, WRITE_SIZE x 1.0).  Each entry holds the sha256 of the kernel's
+# source file at measurement time; a changed source reports null.
+MEASURED_TRAFFIC = {}
+
+
+def source_sha(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_for(kernel, tile_rows):
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_1110_6231_amd", "csrc", "grid_maxflow.hip")
+    if source_sha(src) != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def kernel_roofline(total_ms, launches, algo_bytes):
+    """Algorithmic bytes per launch / average launch duration (HIP events)."""
+    launches = max(launches, 1)
+    avg_ms = total_ms / launches
+    achieved = (algo_bytes / launches) / max(avg_ms * 1e-3, 1e-12) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(avg_ms * 1e3, 3),
+            "bytes_per_launch": int(algo_bytes / launches),
+            "launches": launches, "total_ms": round(total_ms, 3)}
 
 
 def grid_batched_leg(args, torch, lpr, synth):
@@ -123,19 +169,18 @@ def grid_batched_leg(args, torch, lpr, synth):
     timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
     _, _, sti = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, opts=timed, workspace=ws)
     tile_px = sti["tile_rows"] * 64
-    per_launch = sti["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL / max(sti["sweeps"], 1)
-    avg_ms = sti["sweep_ms"] / max(sti["sweeps"], 1)
-    ach = per_launch / (avg_ms * 1e-3) / 1e9
+    sweep = kernel_roofline(sti["sweep_ms"], sti["sweeps"],
+                            sti["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL)
+    relax = kernel_roofline(sti["bfs_ms"], sti["bfs_passes"],
+                            sti["tiles_relaxed"] * tile_px * RELAX_BYTES_PER_PIXEL)
     return {"workload": "64 blob graph cuts (H, W ~ U{128..512}) + one 2048x2048 "
                         "graph cut with pair weights x4, one batched call",
             "pixels": px, "ms_per_batch": round(dt * 1e3, 3),
             "mvertex_per_s": round(px / dt / 1e6, 2),
             "flow_2048": int(flows[-1].item()),
             "global_relabels": st["rounds"], "sweeps": st["sweeps"],
-            "sweep_roofline": {"achieved_GBps": round(ach, 1),
-                               "frac": round(ach / HBM_PEAK_GBS, 4),
-                               "avg_launch_us": round(avg_ms * 1e3, 3),
-                               "bytes_per_launch": int(per_launch)}}
+            f"k_sweep<{sti['tile_rows']}>": sweep,
+            f"k_relax<{sti['tile_rows']},false>": relax}
 
 
 def copy_probe(torch, mib=256, reps=5):
@@ -273,6 +318,7 @@ def main():
                    "local_iters": g["stats"]["local_iters"],
                    "sweeps_per_relabel": g["stats"]["sweeps_per_relabel"]},
         "roofline": g["roofline"],
+        "other_kernels": g["other_kernels"],
     }
     if not args.no_batched_grid:
         out["grid_batched"] = grid_batched_leg(args, torch, lpr, synth)

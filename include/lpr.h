@@ -96,6 +96,7 @@ typedef struct {
     int64_t pushes;          /* push operations                             */
     int64_t relabels;        /* relabel operations                          */
     int64_t cut_passes;      /* tile-relaxation launches of the cut closure */
+    int64_t tiles_relaxed;   /* tiles processed by the BFS relaxation       */
     int32_t tile_rows;       /* tile height actually used                   */
     int32_t local_iters;     /* local iterations actually used              */
     int32_t sweeps_per_relabel;
@@ -159,7 +160,7 @@ size_t lpr_grid_maxflow_batched_workspace(int32_t B, const int32_t *H,
  *   flow_values  device int64 [B].
  *   source_side  device uint8 [node_offset[B]] (packed) or NULL.
  * Errors as for lpr_grid_maxflow; offsets that are not the prefix sums of
- * H*W give LPR_EINVAL.
+ * H*W, or a batch of 2^30 pixels or more, give LPR_EINVAL.
  */
 lpr_status lpr_grid_maxflow_batched(int32_t B, const int32_t *H,
                                     const int32_t *W,

@@ -26,6 +26,14 @@ COMMON = [
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
+# Per-file additions.  The grid kernels keep each tile column's state in
+# per-row register arrays indexed by unrolled constants; promoting those
+# arrays to vector registers before unrolling makes the compiler copy whole
+# vectors around the iteration loop (three times the registers, occupancy 1).
+PER_FILE = {
+    "grid_maxflow.hip": ["-mllvm", "-disable-promote-alloca-to-vector"],
+}
+
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
@@ -34,7 +42,8 @@ def sources():
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + PER_FILE.get(os.path.basename(src), []) + \
+        ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -52,6 +52,14 @@ constexpr int NT = 256;       // threads per tile workgroup
 constexpr int RPP = NT / TW;  // tile rows covered per thread pass (4)
 constexpr int MAX_PASS_SLOTS = 64;
 
+// Element at a 32-bit byte offset from a wave-uniform base: every per-pixel
+// array shares the offset, so the compiler keeps one VGPR per pixel instead of
+// a 64-bit address per array (the batch holds fewer than 2^30 pixels).
+template <class T>
+__device__ __forceinline__ T &at(T *base, uint32_t byte_off) {
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
+
 struct Inst {
     int64_t off;      // first pixel of the instance in the packed arrays
     int32_t H, W;
@@ -74,7 +82,8 @@ struct Dev {
     const int32_t *tile_inst;
     unsigned long long *inst_active;  // per-instance active pixels (last count)
     int32_t *done;                    // per-instance: no active pixel left
-    unsigned long long *counters;     // pushes, relabels, tiles swept
+    unsigned long long *counters;     // pushes, relabels, tiles swept,
+                                      // tiles relaxed (BFS), tiles relaxed (cut)
     Scalars *sc;
     int32_t ntiles;
     int32_t ninst;
@@ -252,93 +261,116 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 //     is the BFS level, |V| where t is unreachable (the gap of Section 4.2).
 //   CUT (CUT = true):  lab(p) = min(lab(p), lab(q)) over arcs q->p with
 //     u_f > 0 -- forward reachability from the excess pixels.
+// One wavefront per 64 x TH tile, no block barrier: lane c owns column c of
+// the tile in registers.  An iteration takes the horizontal neighbours'
+// current labels by cross-lane shuffles (lanes 0 and 63 use the halo
+// columns), then runs a downward and an upward pass along its column, which
+// settles every vertical path inside the tile at once.  Iterations repeat
+// until no label of the tile changes (a wavefront vote).  Labels only
+// decrease and every value read from a neighbouring tile is an upper bound
+// of its final value, so concurrent tiles reach the same least fixpoint.
 // ---------------------------------------------------------------------------
 template <int TH, bool CUT>
-__global__ __launch_bounds__(NT) void k_relax(Dev D, int32_t *dirty_cur,
+__global__ __launch_bounds__(256) void k_relax(Dev D, int32_t *dirty_cur,
                                               int32_t *dirty_next,
                                               int32_t *pass_count) {
-    const int t = blockIdx.x;
-    if (!__syncthreads_or(dirty_cur[t] != 0)) return;
-    if (threadIdx.x == 0) dirty_cur[t] = 0;
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= D.ntiles) return;                // wave-uniform
+    if (dirty_cur[t] == 0) return;            // wave-uniform (same address)
+    if (lane == 0) dirty_cur[t] = 0;
     const Geo g = tile_geo<TH>(D, t);
-    constexpr int NP = TH / RPP;
     constexpr int INC = CUT ? 0 : 1;
-    __shared__ int32_t s_d[TH + 2][TW + 2];
-    __shared__ int32_t s_edge;
-    const int c = threadIdx.x & (TW - 1);
-    const int r0 = threadIdx.x >> 6;
     const int HV = g.HV;
-    int32_t dreg[NP], dld[NP];
-    uint32_t mask[NP];
-    if (threadIdx.x == 0) s_edge = 0;
+    const int x = g.x0 + lane;
+    const bool colv = x < g.W;
+    int32_t d[TH], d0[TH];
+    uint32_t mR = 0, mL = 0, mD = 0, mU = 0;  // bit r: arc usable in row r
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        const int r = r0 + RPP * k;
-        const int y = g.y0 + r, x = g.x0 + c;
-        int32_t d = HV;
-        uint32_t m = 0;
-        if (y < g.H && x < g.W) {
+    for (int r = 0; r < TH; ++r) {
+        const int y = g.y0 + r;
+        d[r] = HV;
+        if (colv && y < g.H) {
             const int64_t p = g.off + int64_t(y) * g.W + x;
-            d = D.h[p];
+            d[r] = D.h[p];
             if (!CUT) {
-                m = (D.rr[p] > 0 ? 1u : 0u) | (D.rl[p] > 0 ? 2u : 0u) |
-                    (D.rd[p] > 0 ? 4u : 0u) | (D.ru[p] > 0 ? 8u : 0u);
+                mR |= uint32_t(D.rr[p] > 0) << r;
+                mL |= uint32_t(D.rl[p] > 0) << r;
+                mD |= uint32_t(D.rd[p] > 0) << r;
+                mU |= uint32_t(D.ru[p] > 0) << r;
             } else {
-                if (x + 1 < g.W && D.rl[p + 1] > 0) m |= 1u;
-                if (x > 0 && D.rr[p - 1] > 0) m |= 2u;
-                if (y + 1 < g.H && D.ru[p + g.W] > 0) m |= 4u;
-                if (y > 0 && D.rd[p - g.W] > 0) m |= 8u;
+                if (x + 1 < g.W) mR |= uint32_t(D.rl[p + 1] > 0) << r;
+                if (x > 0) mL |= uint32_t(D.rr[p - 1] > 0) << r;
+                if (y + 1 < g.H) mD |= uint32_t(D.ru[p + g.W] > 0) << r;
+                if (y > 0) mU |= uint32_t(D.rd[p - g.W] > 0) << r;
             }
         }
-        dreg[k] = d;
-        dld[k] = d;
-        mask[k] = m;
-        s_d[r + 1][c + 1] = d;
+        d0[r] = d[r];
     }
-    // halo: the row above, the row below, the column left and right
-    load_halo<TH>(D, g, c, s_d);
-    __syncthreads();
+    // halo: row above / below (every lane), column left (lane 0) / right (63)
+    int32_t top = HV, bot = HV, hside[TH];
+    if (colv && g.y0 > 0) top = D.h[g.off + int64_t(g.y0 - 1) * g.W + x];
+    if (colv && g.y0 + TH < g.H) bot = D.h[g.off + int64_t(g.y0 + TH) * g.W + x];
+    const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
+#pragma unroll
+    for (int r = 0; r < TH; ++r) {
+        const int y = g.y0 + r;
+        hside[r] = HV;
+        if ((lane == 0 || lane == 63) && hx >= 0 && hx < g.W && y < g.H)
+            hside[r] = D.h[g.off + int64_t(y) * g.W + hx];
+    }
     for (;;) {
         bool changed = false;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int r = r0 + RPP * k;
-            const uint32_t m = mask[k];
-            if (!m) continue;
-            int32_t nd = dreg[k];
-            if (m & 1u) nd = min(nd, s_d[r + 1][c + 2] + INC);
-            if (m & 2u) nd = min(nd, s_d[r + 1][c] + INC);
-            if (m & 4u) nd = min(nd, s_d[r + 2][c + 1] + INC);
-            if (m & 8u) nd = min(nd, s_d[r][c + 1] + INC);
-            if (nd < dreg[k]) {
-                dreg[k] = nd;
-                s_d[r + 1][c + 1] = nd;
-                changed = true;
+        for (int r = 0; r < TH; ++r) {
+            int32_t left = __shfl_up(d[r], 1, 64);
+            int32_t right = __shfl_down(d[r], 1, 64);
+            if (lane == 0) left = hside[r];
+            if (lane == 63) right = hside[r];
+            int32_t nd = d[r];
+            if ((mL >> r) & 1u) nd = min(nd, left + INC);
+            if ((mR >> r) & 1u) nd = min(nd, right + INC);
+            changed |= nd < d[r];
+            d[r] = nd;
+        }
+#pragma unroll
+        for (int r = 0; r < TH; ++r) {
+            const int32_t up = r == 0 ? top : d[r - 1];
+            if ((mU >> r) & 1u) {
+                const int32_t nd = min(d[r], up + INC);
+                changed |= nd < d[r];
+                d[r] = nd;
             }
         }
-        if (!__syncthreads_or(changed)) break;
-    }
-    int edge = 0;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        if (dreg[k] == dld[k]) continue;
-        const int r = r0 + RPP * k;
-        const int64_t p = g.off + int64_t(g.y0 + r) * g.W + g.x0 + c;
-        D.h[p] = dreg[k];
-        if (c == TW - 1) edge |= 1;
-        if (c == 0) edge |= 2;
-        if (r == TH - 1) edge |= 4;
-        if (r == 0) edge |= 8;
+        for (int r = TH - 1; r >= 0; --r) {
+            const int32_t dn = r == TH - 1 ? bot : d[r + 1];
+            if ((mD >> r) & 1u) {
+                const int32_t nd = min(d[r], dn + INC);
+                changed |= nd < d[r];
+                d[r] = nd;
+            }
+        }
+        if (!__any(changed)) break;
     }
-    if (edge) atomicOr(&s_edge, edge);
-    __syncthreads();
-    if (threadIdx.x == 0 && s_edge) {
-        const int e = s_edge;
+    bool ch_top = false, ch_bot = false, ch_col = false;
+#pragma unroll
+    for (int r = 0; r < TH; ++r) {
+        if (d[r] == d0[r]) continue;
+        D.h[g.off + int64_t(g.y0 + r) * g.W + x] = d[r];
+        ch_col = true;
+        if (r == 0) ch_top = true;
+        if (r == TH - 1) ch_bot = true;
+    }
+    const bool e_top = __any(ch_top), e_bot = __any(ch_bot);
+    const bool e_left = __any(lane == 0 && ch_col), e_right = __any(lane == 63 && ch_col);
+    if (lane == 0) {
+        atomicAdd(&D.counters[CUT ? 4 : 3], 1ull);
         int nb[4] = {-1, -1, -1, -1};
-        if ((e & 1) && g.tx + 1 < g.tiles_x) nb[0] = t + 1;
-        if ((e & 2) && g.tx > 0) nb[1] = t - 1;
-        if ((e & 4) && g.ty + 1 < g.tiles_y) nb[2] = t + g.tiles_x;
-        if ((e & 8) && g.ty > 0) nb[3] = t - g.tiles_x;
+        if (e_right && g.tx + 1 < g.tiles_x) nb[0] = t + 1;
+        if (e_left && g.tx > 0) nb[1] = t - 1;
+        if (e_bot && g.ty + 1 < g.tiles_y) nb[2] = t + g.tiles_x;
+        if (e_top && g.ty > 0) nb[3] = t - g.tiles_x;
         for (int i = 0; i < 4; ++i)
             if (nb[i] >= 0 && atomicExch(&dirty_next[nb[i]], 1) == 0)
                 atomicAdd(pass_count, 1);
@@ -400,216 +432,240 @@ __global__ void k_count_finish(Dev D, const int32_t *bfs_open) {
 
 // ---------------------------------------------------------------------------
 // Push sweep: `L` lock-free push/relabel iterations of Algorithm 4.5 per
-// active tile, in LDS.
+// active 64 x TH tile, one wavefront per tile, no block barrier.  Lane c owns
+// column c of the tile in registers (e, h, the four neighbour residuals and
+// the sink residual of each of its TH pixels).  An iteration walks the rows
+// top to bottom: the lane reads its horizontal neighbours' current heights by
+// cross-lane shuffles (lanes 0 and 63 use the halo heights), picks the lowest
+// residual neighbour and pushes or relabels; a push inside the column updates
+// the registers directly, a push to the lane on the left or right is handed
+// over by a shuffle right after the row, and flow pushed across the tile edge
+// is summed per pixel and applied to global memory with device-scope atomics
+// when the visit ends (activating that tile) -- for the other tile the push
+// is fulfilled a little later, which Hong's argument admits.  The tile's own
+// excesses on its edge are merged back by atomic deltas, so pushes that other
+// tiles make into it meanwhile are kept.  Every value read of another
+// pixel is a lower bound of the true one (excess and residuals only shrink
+// by their owner's pushes, heights only grow between global relabels), the
+// staleness Hong's argument admits.
 // ---------------------------------------------------------------------------
 template <int TH>
-__global__ __launch_bounds__(NT) void k_sweep(Dev D, int32_t *act_cur,
+__global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
                                               int32_t *act_next, int L) {
-    const int t = blockIdx.x;
-    if (!__syncthreads_or(act_cur[t] != 0)) return;
-    if (threadIdx.x == 0) act_cur[t] = 0;
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= D.ntiles) return;           // wave-uniform
+    if (act_cur[t] == 0) return;         // wave-uniform (same address)
+    if (lane == 0) act_cur[t] = 0;
     const Geo g = tile_geo<TH>(D, t);
-    constexpr int NP = TH / RPP;
-    __shared__ int32_t s_e[TH][TW], s_rr[TH][TW], s_rl[TH][TW], s_rd[TH][TW],
-        s_ru[TH][TW];
-    __shared__ int32_t s_h[TH + 2][TW + 2];
-    const int c = threadIdx.x & (TW - 1);
-    const int r0 = threadIdx.x >> 6;
     const int HV = g.HV;
-    int32_t hreg[NP], rsreg[NP], h0[NP], rs0[NP], e0[NP], rr0[NP], rl0[NP],
-        rd0[NP], ru0[NP];
+    const int x = g.x0 + lane;
+    const bool colv = x < g.W;
+    int32_t e[TH], h[TH], rs[TH], rr[TH], rl[TH], rd[TH], ru[TH];
     uint32_t valid = 0;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        const int r = r0 + RPP * k;
-        const int y = g.y0 + r, x = g.x0 + c;
-        int32_t e = 0, h = HV, rs = 0, rr = 0, rl = 0, rd = 0, ru = 0;
-        if (y < g.H && x < g.W) {
-            valid |= 1u << k;
-            const int64_t p = g.off + int64_t(y) * g.W + x;
-            e = D.e[p];
-            h = D.h[p];
-            rs = D.rs[p];
-            rr = D.rr[p];
-            rl = D.rl[p];
-            rd = D.rd[p];
-            ru = D.ru[p];
+    for (int r = 0; r < TH; ++r) {
+        const int y = g.y0 + r;
+        e[r] = 0; h[r] = HV; rs[r] = 0; rr[r] = 0; rl[r] = 0; rd[r] = 0; ru[r] = 0;
+        if (colv && y < g.H) {
+            valid |= 1u << r;
+            const uint32_t o = 4u * uint32_t(g.off + int64_t(y) * g.W + x);
+            e[r] = at(D.e, o);
+            h[r] = at(D.h, o);
+            rs[r] = at(D.rs, o);
+            rr[r] = at(D.rr, o);
+            rl[r] = at(D.rl, o);
+            rd[r] = at(D.rd, o);
+            ru[r] = at(D.ru, o);
         }
-        e0[k] = e;
-        h0[k] = h;
-        hreg[k] = h;
-        rs0[k] = rs;
-        rsreg[k] = rs;
-        rr0[k] = rr;
-        rl0[k] = rl;
-        rd0[k] = rd;
-        ru0[k] = ru;
-        s_e[r][c] = e;
-        s_rr[r][c] = rr;
-        s_rl[r][c] = rl;
-        s_rd[r][c] = rd;
-        s_ru[r][c] = ru;
-        s_h[r + 1][c + 1] = h;
     }
-    load_halo<TH>(D, g, c, s_h);
-    __syncthreads();
-
+    // Excess at load time, for the delta merge of edge pixels.  Residuals of
+    // arcs that leave the tile are decremented in global memory at push time
+    // (other tiles only ever increase them there), so they are never written
+    // back; everything else is stored plainly if it changed (bit per row).
+    int32_t e0[TH];
+#pragma unroll
+    for (int r = 0; r < TH; ++r) e0[r] = e[r];
+    uint32_t ch_h = 0, ch_rs = 0, ch_rr = 0, ch_rl = 0, ch_rd = 0, ch_ru = 0;
+    // flow pushed out of the tile (lanes 0 / 63 sideways, rows 0 / TH-1
+    // vertically), applied to the neighbouring tiles when the visit ends
+    int32_t outH[TH];
+#pragma unroll
+    for (int r = 0; r < TH; ++r) outH[r] = 0;
+    int32_t outU = 0, outD = 0;
+    // halo heights (read once; heights only grow, so these are lower bounds)
+    int32_t top = HV, bot = HV, hside[TH];
+    const uint32_t o0 = 4u * uint32_t(g.off + int64_t(g.y0) * g.W + x);  // row 0
+    const uint32_t ow = 4u * uint32_t(g.W);                                // one row
+    if (colv && g.y0 > 0) top = at(D.h, o0 - ow);
+    if (colv && g.y0 + TH < g.H) bot = at(D.h, o0 + TH * ow);
+    const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
+#pragma unroll
+    for (int r = 0; r < TH; ++r) {
+        const int y = g.y0 + r;
+        hside[r] = HV;
+        if ((lane == 0 || lane == 63) && hx >= 0 && hx < g.W && y < g.H)
+            hside[r] = at(D.h, o0 + r * ow + 4u * uint32_t(hx - x));
+    }
     unsigned pushes = 0, relabels = 0;
+    bool touch_l = false, touch_r = false, touch_u = false, touch_d = false;
     for (int it = 0; it < L; ++it) {
         bool any = false;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            if (!((valid >> k) & 1u)) continue;
-            const int r = r0 + RPP * k;
-            const int32_t e = s_e[r][c];
-            const int32_t hh = hreg[k];
-            if (e <= 0 || hh >= HV) continue;
-            any = true;
-            // lowest residual neighbour; scan order t, right, left, down, up
-            int32_t best = INT_MAX, cap = 0;
-            int dir = -1;
-            if (rsreg[k] > 0) {
-                best = 0;
-                dir = 0;
-                cap = rsreg[k];
-            }
-            // residual arcs leaving the grid are 0 by construction; the
-            // position tests only guard the atomics below
-            const int gx = g.x0 + c, gy = g.y0 + r;
-            const int32_t vr = s_rr[r][c];
-            if (vr > 0 && gx + 1 < g.W) {
-                const int32_t hq = s_h[r + 1][c + 2];
-                if (hq < best) { best = hq; dir = 1; cap = vr; }
-            }
-            const int32_t vl = s_rl[r][c];
-            if (vl > 0 && gx > 0) {
-                const int32_t hq = s_h[r + 1][c];
-                if (hq < best) { best = hq; dir = 2; cap = vl; }
-            }
-            const int32_t vd = s_rd[r][c];
-            if (vd > 0 && gy + 1 < g.H) {
-                const int32_t hq = s_h[r + 2][c + 1];
-                if (hq < best) { best = hq; dir = 3; cap = vd; }
-            }
-            const int32_t vu = s_ru[r][c];
-            if (vu > 0 && gy > 0) {
-                const int32_t hq = s_h[r][c + 1];
-                if (hq < best) { best = hq; dir = 4; cap = vu; }
-            }
-            if (dir >= 0 && hh > best) {
-                // PUSH delta = min(e', u_f(x, y~)) towards y~
-                const int32_t d = min(e, cap);
-                atomicSub(&s_e[r][c], d);
-                const int64_t p = g.off + int64_t(gy) * g.W + gx;
-                switch (dir) {
-                    case 0:
-                        rsreg[k] -= d;
-                        break;
-                    case 1:
-                        atomicSub(&s_rr[r][c], d);
-                        if (c + 1 < TW) {
-                            atomicAdd(&s_rl[r][c + 1], d);
-                            atomicAdd(&s_e[r][c + 1], d);
+        for (int r = 0; r < TH; ++r) {
+            int32_t hl = __shfl_up(h[r], 1, 64);
+            int32_t hr = __shfl_down(h[r], 1, 64);
+            if (lane == 0) hl = hside[r];
+            if (lane == 63) hr = hside[r];
+            int32_t sendR = 0, sendL = 0;
+            const int y = g.y0 + r;
+            if (((valid >> r) & 1u) && e[r] > 0 && h[r] < HV) {
+                any = true;
+                // lowest residual neighbour; scan order t, right, left, down, up
+                int32_t best = INT_MAX, cap = 0;
+                int dir = -1;
+                if (rs[r] > 0) { best = 0; dir = 0; cap = rs[r]; }
+                if (rr[r] > 0 && x + 1 < g.W && hr < best) { best = hr; dir = 1; cap = rr[r]; }
+                if (rl[r] > 0 && x > 0 && hl < best) { best = hl; dir = 2; cap = rl[r]; }
+                const int32_t hd = r + 1 < TH ? h[r + 1] : bot;
+                if (rd[r] > 0 && y + 1 < g.H && hd < best) { best = hd; dir = 3; cap = rd[r]; }
+                const int32_t hu = r > 0 ? h[r - 1] : top;
+                if (ru[r] > 0 && y > 0 && hu < best) { best = hu; dir = 4; cap = ru[r]; }
+                if (dir >= 0 && h[r] > best) {
+                    // PUSH delta = min(e', u_f(x, y~)) towards y~
+                    const int32_t d = min(e[r], cap);
+                    e[r] -= d;
+                    if (dir == 0) {
+                        rs[r] -= d;
+                        ch_rs |= 1u << r;
+                    } else if (dir == 1) {
+                        rr[r] -= d;
+                        if (lane < 63) {
+                            sendR = d;
+                            ch_rr |= 1u << r;
                         } else {
-                            atomicAdd(&D.rl[p + 1], d);
-                            atomicAdd(&D.e[p + 1], d);
-                            act_next[t + 1] = 1;
+                            outH[r] += d;
                         }
-                        break;
-                    case 2:
-                        atomicSub(&s_rl[r][c], d);
-                        if (c > 0) {
-                            atomicAdd(&s_rr[r][c - 1], d);
-                            atomicAdd(&s_e[r][c - 1], d);
+                    } else if (dir == 2) {
+                        rl[r] -= d;
+                        if (lane > 0) {
+                            sendL = d;
+                            ch_rl |= 1u << r;
                         } else {
-                            atomicAdd(&D.rr[p - 1], d);
-                            atomicAdd(&D.e[p - 1], d);
-                            act_next[t - 1] = 1;
+                            outH[r] += d;
                         }
-                        break;
-                    case 3:
-                        atomicSub(&s_rd[r][c], d);
+                    } else if (dir == 3) {
+                        rd[r] -= d;
                         if (r + 1 < TH) {
-                            atomicAdd(&s_ru[r + 1][c], d);
-                            atomicAdd(&s_e[r + 1][c], d);
+                            ru[r + 1] += d;
+                            e[r + 1] += d;
+                            ch_rd |= 1u << r;
+                            ch_ru |= 1u << (r + 1);
                         } else {
-                            atomicAdd(&D.ru[p + g.W], d);
-                            atomicAdd(&D.e[p + g.W], d);
-                            act_next[t + g.tiles_x] = 1;
+                            outD += d;
                         }
-                        break;
-                    default:
-                        atomicSub(&s_ru[r][c], d);
+                    } else {
+                        ru[r] -= d;
                         if (r > 0) {
-                            atomicAdd(&s_rd[r - 1][c], d);
-                            atomicAdd(&s_e[r - 1][c], d);
+                            rd[r - 1] += d;
+                            e[r - 1] += d;
+                            ch_ru |= 1u << r;
+                            ch_rd |= 1u << (r - 1);
                         } else {
-                            atomicAdd(&D.rd[p - g.W], d);
-                            atomicAdd(&D.e[p - g.W], d);
-                            act_next[t - g.tiles_x] = 1;
+                            outU += d;
                         }
-                        break;
+                    }
+                    ++pushes;
+                } else {
+                    // RELABEL h(x) = h~ + 1 (owner only); no residual arc or
+                    // a height past |V| freezes the pixel (gap height)
+                    h[r] = (dir < 0 || best >= HV - 1) ? HV : best + 1;
+                    ch_h |= 1u << r;
+                    ++relabels;
                 }
-                ++pushes;
-            } else {
-                // RELABEL h(x) = h~ + 1 (owner-only store); no residual arc
-                // or a height past |V| freezes the pixel (gap height).
-                const int32_t nh = (dir < 0 || best >= HV - 1) ? HV : best + 1;
-                hreg[k] = nh;
-                s_h[r + 1][c + 1] = nh;
-                ++relabels;
+            }
+            // hand the horizontal pushes of this row to the neighbour lanes
+            const int32_t fromL = __shfl_up(sendR, 1, 64);
+            const int32_t fromR = __shfl_down(sendL, 1, 64);
+            if (lane > 0 && fromL) {
+                rl[r] += fromL;
+                e[r] += fromL;
+                ch_rl |= 1u << r;
+            }
+            if (lane < 63 && fromR) {
+                rr[r] += fromR;
+                e[r] += fromR;
+                ch_rr |= 1u << r;
             }
         }
-        if (!__syncthreads_or(any)) break;
+        if (!__any(any)) break;
     }
-    __syncthreads();
-
+    // write back: plain stores where only this tile writes, an atomic delta
+    // for the excess of pixels that other tiles can push into
     bool active_end = false;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        if (!((valid >> k) & 1u)) continue;
-        const int r = r0 + RPP * k;
-        const int y = g.y0 + r, x = g.x0 + c;
-        const int64_t p = g.off + int64_t(y) * g.W + x;
-        const bool xr = (c == TW - 1) && (x + 1 < g.W);
-        const bool xl = (c == 0) && (x > 0);
-        const bool xd = (r == TH - 1) && (y + 1 < g.H);
-        const bool xu = (r == 0) && (y > 0);
-        const int32_t e = s_e[r][c];
-        if (e != e0[k]) {
-            if (xr | xl | xd | xu) atomicAdd(&D.e[p], e - e0[k]);
-            else D.e[p] = e;
+    for (int r = 0; r < TH; ++r) {
+        if (!((valid >> r) & 1u)) continue;
+        const int y = g.y0 + r;
+        const uint32_t o = o0 + r * ow;
+        const bool edge = (lane == 63 && x + 1 < g.W) || (lane == 0 && x > 0) ||
+                          (r == TH - 1 && y + 1 < g.H) || (r == 0 && y > 0);
+        if (e[r] != e0[r]) {
+            if (edge) atomicAdd(&at(D.e, o), e[r] - e0[r]);
+            else at(D.e, o) = e[r];
         }
-        if (hreg[k] != h0[k]) D.h[p] = hreg[k];
-        if (rsreg[k] != rs0[k]) D.rs[p] = rsreg[k];
-        int32_t v = s_rr[r][c];
-        if (v != rr0[k]) {
-            if (xr) atomicAdd(&D.rr[p], v - rr0[k]);
-            else D.rr[p] = v;
+        const uint32_t b = 1u << r;
+        if (ch_h & b) at(D.h, o) = h[r];
+        if (ch_rs & b) at(D.rs, o) = rs[r];
+        if (ch_rr & b) at(D.rr, o) = rr[r];
+        if (ch_rl & b) at(D.rl, o) = rl[r];
+        if (ch_rd & b) at(D.rd, o) = rd[r];
+        if (ch_ru & b) at(D.ru, o) = ru[r];
+        active_end |= e[r] > 0 && h[r] < HV;
+        // pushes out of the tile: own residual down, neighbour's reverse
+        // residual and excess up
+        if (outH[r]) {
+            if (lane == 63) {
+                atomicSub(&at(D.rr, o), outH[r]);
+                atomicAdd(&at(D.rl, o + 4), outH[r]);
+                atomicAdd(&at(D.e, o + 4), outH[r]);
+                touch_r = true;
+            } else {
+                atomicSub(&at(D.rl, o), outH[r]);
+                atomicAdd(&at(D.rr, o - 4), outH[r]);
+                atomicAdd(&at(D.e, o - 4), outH[r]);
+                touch_l = true;
+            }
         }
-        v = s_rl[r][c];
-        if (v != rl0[k]) {
-            if (xl) atomicAdd(&D.rl[p], v - rl0[k]);
-            else D.rl[p] = v;
+        if (r == 0 && outU) {
+            atomicSub(&at(D.ru, o), outU);
+            atomicAdd(&at(D.rd, o - ow), outU);
+            atomicAdd(&at(D.e, o - ow), outU);
+            touch_u = true;
         }
-        v = s_rd[r][c];
-        if (v != rd0[k]) {
-            if (xd) atomicAdd(&D.rd[p], v - rd0[k]);
-            else D.rd[p] = v;
+        if (r == TH - 1 && outD) {
+            atomicSub(&at(D.rd, o), outD);
+            atomicAdd(&at(D.ru, o + ow), outD);
+            atomicAdd(&at(D.e, o + ow), outD);
+            touch_d = true;
         }
-        v = s_ru[r][c];
-        if (v != ru0[k]) {
-            if (xu) atomicAdd(&D.ru[p], v - ru0[k]);
-            else D.ru[p] = v;
-        }
-        active_end |= (e > 0 && hreg[k] < HV);
     }
-    if (__syncthreads_or(active_end) && threadIdx.x == 0) act_next[t] = 1;
-    const unsigned long long sp = block_sum_u64(pushes);
-    const unsigned long long srl = block_sum_u64(relabels);
-    if (threadIdx.x == 0) {
-        if (sp) atomicAdd(&D.counters[0], sp);
-        if (srl) atomicAdd(&D.counters[1], srl);
+    const bool a_end = __any(active_end);
+    const bool a_l = __any(touch_l), a_r = __any(touch_r);
+    const bool a_u = __any(touch_u), a_d = __any(touch_d);
+    unsigned long long np = pushes, nr = relabels;
+    for (int o = 32; o > 0; o >>= 1) {
+        np += __shfl_xor(np, o, 64);
+        nr += __shfl_xor(nr, o, 64);
+    }
+    if (lane == 0) {
+        if (a_end) act_next[t] = 1;
+        if (a_l) act_next[t - 1] = 1;
+        if (a_r) act_next[t + 1] = 1;
+        if (a_u) act_next[t - g.tiles_x] = 1;
+        if (a_d) act_next[t + g.tiles_x] = 1;
+        if (np) atomicAdd(&D.counters[0], np);
+        if (nr) atomicAdd(&D.counters[1], nr);
         atomicAdd(&D.counters[2], 1ull);
     }
 }
@@ -685,16 +741,18 @@ struct Kern {
     static void cut_seed(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
         hipLaunchKernelGGL(k_cut_seed<TH>, g, dim3(NT), 0, s, D, a, b);
     }
+    // one wavefront per tile, four tiles per 256-thread block
     static void relax(bool cut, dim3 g, hipStream_t s, const Dev &D, int32_t *a,
                       int32_t *b, int32_t *pc) {
-        if (cut) hipLaunchKernelGGL((k_relax<TH, true>), g, dim3(NT), 0, s, D, a, b, pc);
-        else hipLaunchKernelGGL((k_relax<TH, false>), g, dim3(NT), 0, s, D, a, b, pc);
+        const dim3 gw((g.x + 3) / 4);
+        if (cut) hipLaunchKernelGGL((k_relax<TH, true>), gw, dim3(NT), 0, s, D, a, b, pc);
+        else hipLaunchKernelGGL((k_relax<TH, false>), gw, dim3(NT), 0, s, D, a, b, pc);
     }
     static void count(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
         hipLaunchKernelGGL(k_count<TH>, g, dim3(NT), 0, s, D, a, b);
     }
     static void sweep(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b, int L) {
-        hipLaunchKernelGGL(k_sweep<TH>, g, dim3(NT), 0, s, D, a, b, L);
+        hipLaunchKernelGGL(k_sweep<TH>, dim3((g.x + 3) / 4), dim3(NT), 0, s, D, a, b, L);
     }
     static void flow(dim3 g, hipStream_t s, const Dev &D, int64_t *f) {
         hipLaunchKernelGGL(k_flow_value<TH>, g, dim3(NT), 0, s, D, f);
@@ -996,6 +1054,7 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
         stats->pushes = int64_t(cnt[0]);
         stats->relabels = int64_t(cnt[1]);
         stats->tiles_swept = int64_t(cnt[2]);
+        stats->tiles_relaxed = int64_t(cnt[3]);
         stats->tile_rows = TH;
         stats->local_iters = P.L;
         stats->sweeps_per_relabel = P.K;
@@ -1098,6 +1157,11 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
             set_error("node_offset is not the prefix sum of H*W at %d", b);
             return LPR_EINVAL;
         }
+    }
+    if (node_offset[B] >= (int64_t(1) << 30)) {
+        // the kernels address a pixel's word by a 32-bit byte offset
+        set_error("batch of %lld pixels exceeds 2^30", (long long)node_offset[B]);
+        return LPR_EINVAL;
     }
     const Sched ds = default_sched(node_offset[B]);
     Params P;

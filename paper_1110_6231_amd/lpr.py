@@ -61,6 +61,7 @@ class GridStats(ctypes.Structure):
                 ("bfs_passes", ctypes.c_int64),
                 ("tiles_swept", ctypes.c_int64), ("pushes", ctypes.c_int64),
                 ("relabels", ctypes.c_int64), ("cut_passes", ctypes.c_int64),
+                ("tiles_relaxed", ctypes.c_int64),
                 ("tile_rows", ctypes.c_int32), ("local_iters", ctypes.c_int32),
                 ("sweeps_per_relabel", ctypes.c_int32),
                 ("reserved", ctypes.c_int32),
