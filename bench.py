@@ -28,10 +28,13 @@ if ROOT not in sys.path:
 
 METRIC = "grid maxflow Mvertex/s + assignment solves/s, learned vs plain; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# Bytes the push sweep must move per pixel of a processed tile: the seven
-# int32 state words (e, h, four neighbour residuals, sink residual) read into
-# LDS and written back.
-SWEEP_BYTES_PER_PIXEL = 56
+# Algorithmic bytes of the push sweep: the seven int32 state words (e, h,
+# four neighbour residuals, sink residual) of every pixel of a processed tile,
+# plus 4 bytes per relabel (the height) and 16 per push (the four words a push
+# updates: both residuals and both excesses).
+SWEEP_BYTES_PER_PIXEL = 28
+SWEEP_BYTES_PER_RELABEL = 4
+SWEEP_BYTES_PER_PUSH = 16
 # Bytes one pass of the global-relabel relaxation must move per pixel of a
 # relaxed tile: the height and the four neighbour residuals read, the height
 # written.
@@ -82,7 +85,7 @@ def grid_leg(args, torch, lpr, synth):
     # the two kernels that take the time.
     timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
     acc = dict(sweep_ms=0.0, bfs_ms=0.0, tiles_swept=0, tiles_relaxed=0,
-               sweeps=0, bfs_passes=0)
+               sweeps=0, bfs_passes=0, pushes=0, relabels=0)
     for _ in range(args.steps):
         v, side, st = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=timed,
                                            workspace=ws, stream=stream)
@@ -92,8 +95,7 @@ def grid_leg(args, torch, lpr, synth):
     tile_px = st["tile_rows"] * 64
     legs = {
         f"k_sweep<{st['tile_rows']}>": kernel_roofline(
-            acc["sweep_ms"], acc["sweeps"],
-            acc["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL),
+            acc["sweep_ms"], acc["sweeps"], sweep_bytes(acc, tile_px)),
         f"k_relax<{st['tile_rows']},false>": kernel_roofline(
             acc["bfs_ms"], acc["bfs_passes"],
             acc["tiles_relaxed"] * tile_px * RELAX_BYTES_PER_PIXEL),
@@ -129,6 +131,12 @@ def traffic_for(kernel, tile_rows):
     if source_sha(src) != rec["source_sha256"]:
         return None
     return rec["bytes_per_launch"]
+
+
+def sweep_bytes(st, tile_px):
+    return (st["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL
+            + st["relabels"] * SWEEP_BYTES_PER_RELABEL
+            + st["pushes"] * SWEEP_BYTES_PER_PUSH)
 
 
 def kernel_roofline(total_ms, launches, algo_bytes):
@@ -169,8 +177,7 @@ def grid_batched_leg(args, torch, lpr, synth):
     timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
     _, _, sti = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, opts=timed, workspace=ws)
     tile_px = sti["tile_rows"] * 64
-    sweep = kernel_roofline(sti["sweep_ms"], sti["sweeps"],
-                            sti["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL)
+    sweep = kernel_roofline(sti["sweep_ms"], sti["sweeps"], sweep_bytes(sti, tile_px))
     relax = kernel_roofline(sti["bfs_ms"], sti["bfs_passes"],
                             sti["tiles_relaxed"] * tile_px * RELAX_BYTES_PER_PIXEL)
     return {"workload": "64 blob graph cuts (H, W ~ U{128..512}) + one 2048x2048 "
@@ -212,7 +219,8 @@ def assign_leg(args, torch, lpr, synth):
                        "max-weight, alpha=8, plain start",
            "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(dt * 1e3, 3),
            "total": tot, "refines": st["refines"], "phases": st["phases"],
-           "pushes": st["pushes"], "relabels": st["relabels"]}
+           "pushes": st["pushes"], "relabels": st["relabels"],
+           "price_updates": st["price_updates"]}
     from paper_1110_6231_amd.train_pricenet import learned_solve, load_weights
     mats = synth.assign_batch(seed=0)
     packed = lpr.PackedAssign.from_matrices(mats, device=dev)

@@ -129,7 +129,7 @@ size_t lpr_grid_maxflow_workspace(int32_t H, int32_t W);
  *                side of the unique minimal minimum cut (the residual closure
  *                of the pixels that hold excess in the maximum preflow).
  * opts may be NULL (defaults).  stats may be NULL.
- * Errors: LPR_EINVAL (H or W < 1, H*W >= 2^30, NULL inputs, negative
+ * Errors: LPR_EINVAL (H or W < 1, H*W >= 2^28, NULL inputs, negative
  * capacity), LPR_ERANGE (capacity > LPR_GRID_MAX_CAP), LPR_ENOMEM (workspace
  * too small), LPR_EBUDGET (max_rounds exhausted, or a global relabel that
  * needs more tile passes than 16 x tiles + 1024; outputs unspecified),
@@ -237,7 +237,8 @@ typedef struct {
     int64_t pushes;     /* push operations                                */
     int64_t relabels;   /* relabel operations                             */
     int64_t scans;      /* arc scans of X rows (each reads n costs)       */
-    int64_t reserved[3];
+    int64_t price_updates; /* global price updates (Algorithm 5.3)        */
+    int64_t reserved[2];
     double kernel_ms;   /* with LPR_ASSIGN_TIME_KERNELS: solve kernel time */
     double total_ms;    /* device time of the whole call (HIP events)      */
 } lpr_assign_stats;

@@ -34,6 +34,15 @@
 //     -- and returns the queue to the phases if it grows.
 // The refine's initialisation and the first X phase share one scan of every
 // row: after p(x) = -(min + eps) the minimising arc is admissible.
+//   Price update (Section 5, Algorithm 5.3): when the serial tail is entered
+//     after at least `n` pushes since the last update, the workgroup runs a
+//     Dijkstra search from the deficit columns over reversed residual arcs,
+//     with arc length floor(c_p / eps) + 1 and Dial's buckets, until every
+//     active node is labelled, and lowers each price by eps x its label
+//     (unreached nodes by eps x (last label + 1)).  Shortest paths from the
+//     active rows to deficit columns become admissible at once instead of
+//     being found by one relabel at a time.  Column scans read a transposed
+//     int16 copy of the costs.
 #include <algorithm>
 #include <climits>
 #include <numeric>
@@ -62,6 +71,7 @@ struct AArgs {
     const int32_t *order;
     const int32_t *costs;
     const int16_t *c16;
+    const int16_t *c16t;  // transposed int16 copy (column y is contiguous)
     const unsigned *cmax;
     int32_t sign;      // +1 minimise c, -1 maximise (solve with c = -w)
     int32_t alpha;
@@ -73,7 +83,8 @@ struct AArgs {
     int64_t *col_prices;
     int64_t max_ops;
     uint64_t max_ticks;            // wall-clock budget in wall_clock64 ticks
-    unsigned long long *counters;  // refines, phases, pushes, relabels, scans
+    unsigned long long *counters;  // refines, phases, pushes, relabels, scans,
+                                   // price updates
     int32_t *status;  // per instance: 0 ok, 1 budget, 2 range, 3 internal
 };
 
@@ -100,6 +111,33 @@ __global__ __launch_bounds__(256) void k_prep(const AInst *inst,
     if (threadIdx.x == 0) {
         m = max(max(red[0], red[1]), max(red[2], red[3]));
         if (m) atomicMax(&cmax[blockIdx.y], m);
+    }
+}
+
+// Transposed saturated int16 copy of every instance's costs, through 64 x 64
+// LDS tiles.  grid = (B, tiles, tiles) over the largest instance.
+__global__ __launch_bounds__(256) void k_transpose16(const AInst *inst,
+                                                     const int32_t *costs,
+                                                     int16_t *c16t) {
+    const AInst I = inst[blockIdx.x];
+    const int n = I.n;
+    const int c0 = blockIdx.y * 64, r0 = blockIdx.z * 64;  // source column / row
+    if (c0 >= n || r0 >= n) return;
+    __shared__ int16_t tile[64][66];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int row = r0 + r, col = c0 + tx;
+        int16_t v = 0;
+        if (row < n && col < n) {
+            const int32_t c = costs[I.cost_off + int64_t(row) * n + col];
+            v = int16_t(max(-32768, min(32767, c)));
+        }
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int orow = c0 + r, ocol = r0 + tx;  // destination row = source column
+        if (orow < n && ocol < n) c16t[I.c16_off + int64_t(orow) * n + ocol] = tile[tx][r];
     }
 }
 
@@ -297,9 +335,145 @@ __device__ inline bool resolve_column(int y, int64_t eps, const Shared &L,
     return true;
 }
 
+__device__ inline int64_t floor_div(int64_t a, int64_t b) {  // b > 0
+    int64_t q = a / b;
+    if (a % b != 0 && a < 0) --q;
+    return q;
+}
+
+// eps * k, saturated (k >= -1, eps >= 1)
+__device__ inline int64_t mul_sat(int64_t eps, int64_t k) {
+    return k > LLONG_MAX / eps ? LLONG_MAX : eps * k;
+}
+
+struct PU {
+    int64_t *lx, *ly;  // labels (multiples of eps), LLONG_MAX = none yet
+    uint8_t *fx, *fy;  // scanned
+};
+
+// Price update heuristic (Algorithm 5.3).  Buckets are the distinct label
+// values: after the nodes of one label are scanned, the next label is the
+// least tentative label of an unscanned node (a workgroup minimum), so the
+// number of steps is the number of distinct labels, not their range.  The
+// bucket of the deficit columns is 0; scanning a column y offers every row x
+// with a residual arc (x, y) (every x not matched to y) the label
+// level + floor(c_p(x,y) / eps) + 1; scanning a row x offers its mate the
+// label level + floor(c_p(mate, x) / eps) + 1 (the reverse arc of the matched
+// pair).  An eps-optimal pseudoflow has c_p >= -eps on residual arcs, so
+// offers never fall below the current level.  The search stops once every
+// active node (unmatched row, column with e >= 1) is scanned and the current
+// bucket is empty; prices drop by eps x label, and by eps x (last label + 1)
+// for the nodes not scanned.
+// Called by the whole workgroup between phases.
+__device__ void price_update(const Shared &L, const PU &U,
+                             const int16_t *__restrict__ CT, int n, int64_t sgnS,
+                             int64_t eps, int tid) {
+    __shared__ int s_rem, s_nf, s_again;
+    __shared__ unsigned long long s_lev;
+    constexpr int64_t NONE = LLONG_MAX;
+    if (tid == 0) s_rem = 0;
+    __syncthreads();
+    int rem = 0;
+    for (int x = tid; x < n; x += NT) {
+        U.lx[x] = NONE;
+        U.fx[x] = 0;
+        rem += L.mate[x] < 0;
+    }
+    for (int y = tid; y < n; y += NT) {
+        U.ly[y] = L.ey[y] < 0 ? 0 : NONE;
+        U.fy[y] = 0;
+        rem += L.ey[y] >= 1;
+    }
+    if (rem) atomicAdd(&s_rem, rem);
+    int64_t level = 0;
+    for (;;) {
+        if (tid == 0) {
+            s_nf = 0;
+            s_again = 0;
+        }
+        __syncthreads();
+        // columns labelled `level`
+        for (int y = tid; y < n; y += NT)
+            if (!U.fy[y] && U.ly[y] == level) {
+                U.fy[y] = 1;
+                L.yl[atomicAdd(&s_nf, 1)] = y;
+                if (L.ey[y] >= 1) atomicSub(&s_rem, 1);
+            }
+        __syncthreads();
+        const int nf = s_nf;
+        if (nf > 0) {
+            for (int x = tid; x < n; x += NT) {
+                if (U.fx[x]) continue;
+                int64_t best = U.lx[x];
+                // an offer improves iff c_p < eps * (best - level - 1)
+                int64_t bound = best == NONE ? NONE : mul_sat(eps, best - level - 1);
+                const int64_t pxx = L.px[x];
+                const int mx = L.mate[x];
+                for (int j = 0; j < nf; ++j) {
+                    const int y = L.yl[j];
+                    const int64_t cp = int64_t(CT[int64_t(y) * n + x]) * sgnS + pxx - L.py[y];
+                    if (cp < bound && y != mx) {
+                        best = level + floor_div(cp, eps) + 1;
+                        bound = mul_sat(eps, best - level - 1);
+                    }
+                }
+                U.lx[x] = best;
+            }
+        }
+        __syncthreads();
+        // rows labelled `level`
+        for (int x = tid; x < n; x += NT) {
+            if (U.fx[x] || U.lx[x] != level) continue;
+            U.fx[x] = 1;
+            const int y = L.mate[x];
+            if (y < 0) {
+                atomicSub(&s_rem, 1);
+                continue;
+            }
+            if (U.fy[y]) continue;
+            // c_p(y, x) = -c(x,y) + p(y) - p(x) = p(y) - b(x)
+            const int64_t cand = level + floor_div(L.py[y] - L.bv[x], eps) + 1;
+            atomicMin(reinterpret_cast<unsigned long long *>(&U.ly[y]),
+                      (unsigned long long)cand);
+            if (cand == level) s_again = 1;
+        }
+        __syncthreads();
+        // the bucket is emptied before the search may stop, so every node
+        // left unscanned has a label above `level`
+        const bool done = s_rem <= 0, again = s_again != 0;
+        if (!again) {
+            if (done) break;
+            if (tid == 0) s_lev = ULLONG_MAX;
+            __syncthreads();
+            unsigned long long m = ULLONG_MAX;
+            for (int x = tid; x < n; x += NT)
+                if (!U.fx[x]) m = min(m, (unsigned long long)U.lx[x]);
+            for (int y = tid; y < n; y += NT)
+                if (!U.fy[y]) m = min(m, (unsigned long long)U.ly[y]);
+            for (int o = 32; o > 0; o >>= 1)
+                m = min(m, (unsigned long long)__shfl_xor((long long)m, o, 64));
+            if ((tid & 63) == 0 && m != ULLONG_MAX) atomicMin(&s_lev, m);
+            __syncthreads();
+            const unsigned long long nl = s_lev;
+            if (nl >= (unsigned long long)NONE) break;  // nothing left to reach
+            level = int64_t(nl);
+        }
+        __syncthreads();  // every thread has read the flags before the reset
+    }
+    const int64_t far = level + 1;
+    for (int x = tid; x < n; x += NT) {
+        const int64_t dp = eps * (U.fx[x] ? U.lx[x] : far);
+        L.px[x] -= dp;
+        if (L.mate[x] >= 0) L.bv[x] -= dp;
+    }
+    for (int y = tid; y < n; y += NT) L.py[y] -= eps * (U.fy[y] ? U.ly[y] : far);
+    __syncthreads();
+}
+
 template <typename T>
 __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
-                               const T *__restrict__ C, unsigned cmax,
+                               const T *__restrict__ C,
+                               const int16_t *__restrict__ CT, unsigned cmax,
                                unsigned char *smem) {
     const int n = I.n;
     Shared L;
@@ -312,20 +486,27 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     L.mate = L.nxt + n;
     L.xl = L.mate + n;  // active rows (circular queue in the serial tail)
     L.yl = L.xl + n;    // columns made active by the last X phase
+    PU U;
+    U.lx = reinterpret_cast<int64_t *>(L.yl + n);
+    U.ly = U.lx + n;
+    U.fx = reinterpret_cast<uint8_t *>(U.ly + n);
+    U.fy = U.fx + n;
     int64_t *py = L.py, *px = L.px;
     __shared__ int s_nx, s_ny, s_stop, s_qh;
-    __shared__ unsigned long long s_cnt[5];
+    __shared__ unsigned long long s_pu_mark;  // pushes at the last price update
+    __shared__ unsigned long long s_cnt[6];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t t_start = wall_clock64();
     const int64_t S = 2 * int64_t(n) + 1;
     const int64_t sgnS = int64_t(A.sign) * S;
-    if (tid < 5) s_cnt[tid] = 0;
+    if (tid < 6) s_cnt[tid] = 0;
     if (tid == 0) {
         s_nx = 0;
         s_ny = 0;
         s_stop = 0;
         s_qh = 0;
+        s_pu_mark = 0;
     }
     for (int y = tid; y < n; y += NT)
         py[y] = A.init_prices ? A.init_prices[I.row_off + y] : 0;
@@ -389,6 +570,14 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             __syncthreads();
             if (nx == 0 || s_stop) break;
             if (nx <= TAIL_ENTER) {
+                if (CT && s_cnt[2] - s_pu_mark >= (unsigned long long)n) {
+                    price_update(L, U, CT, n, sgnS, eps, tid);
+                    if (tid == 0) {
+                        s_pu_mark = s_cnt[2];
+                        atomicAdd(&s_cnt[5], 1ull);
+                    }
+                    __syncthreads();
+                }
                 // ---- serial tail ----
                 if (wave == 0) {
                     // circular queue over xl: head position, tail position
@@ -396,7 +585,9 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                     int qh = 0, qt = nx == n ? 0 : nx, qlen = nx;
                     unsigned long long tp = 0, tr = 0, ts = 0;
                     int stop = 0;
-                    while (qlen > 0 && qlen <= TAIL_EXIT) {
+                    // back to the phases after n pushes, for the next price update
+                    while (qlen > 0 && qlen <= TAIL_EXIT &&
+                           (!CT || tp < (unsigned long long)n)) {
                         const int x = L.xl[qh];
                         if (++qh == n) qh = 0;
                         --qlen;
@@ -499,7 +690,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             A.status[slot] = 0;
         }
     }
-    if (tid < 5 && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
+    if (tid < 6 && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
 }
 
 __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
@@ -512,19 +703,22 @@ __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
         return;
     }
     if (cmax <= C16_MAX)
-        solve_instance<int16_t>(A, I, slot, A.c16 + I.c16_off, cmax, smem);
+        solve_instance<int16_t>(A, I, slot, A.c16 + I.c16_off, A.c16t + I.c16_off,
+                                cmax, smem);
     else
-        solve_instance<int32_t>(A, I, slot, A.costs + I.cost_off, cmax, smem);
+        solve_instance<int32_t>(A, I, slot, A.costs + I.cost_off, nullptr, cmax, smem);
 }
 
-static size_t lds_bytes(int nmax) { return size_t(nmax) * 48 + 64; }
+// py, px, b(x) (int64), e(y), head, next, mate, two lists (int32), two
+// labels (int64) and two scanned flags (uint8) per node
+static size_t lds_bytes(int nmax) { return size_t(nmax) * 66 + 64; }
 
 struct Layout {
     AInst *inst;
     int32_t *order, *status;
     unsigned *cmax;
     unsigned long long *counters;
-    int16_t *c16;
+    int16_t *c16, *c16t;
 };
 
 static int64_t c16_elems(int B, const int32_t *n) {
@@ -540,6 +734,7 @@ static Carver carve(Carver cv, int B, const int32_t *n, Layout *L) {
     L->cmax = cv.take<unsigned>(size_t(B));
     L->counters = cv.take<unsigned long long>(8);
     L->c16 = cv.take<int16_t>(size_t(c16_elems(B, n)));
+    L->c16t = cv.take<int16_t>(size_t(c16_elems(B, n)));
     return cv;
 }
 
@@ -631,11 +826,16 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     const int gx = int(std::min<int64_t>(512, std::max<int64_t>(1, (nnmax + 4095) / 4096)));
     hipLaunchKernelGGL(k_prep, dim3(gx, B), dim3(256), 0, s, L.inst, costs, L.c16, L.cmax);
     LPR_TRY_HIP(hipGetLastError());
+    const unsigned tiles = unsigned((nmax + 63) / 64);
+    hipLaunchKernelGGL(k_transpose16, dim3(B, tiles, tiles), dim3(256), 0, s, L.inst,
+                       costs, L.c16t);
+    LPR_TRY_HIP(hipGetLastError());
     AArgs A;
     A.inst = L.inst;
     A.order = L.order;
     A.costs = costs;
     A.c16 = L.c16;
+    A.c16t = L.c16t;
     A.cmax = L.cmax;
     A.sign = maximize ? -1 : 1;
     A.alpha = alpha;
@@ -681,6 +881,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         stats->pushes = int64_t(cnt[2]);
         stats->relabels = int64_t(cnt[3]);
         stats->scans = int64_t(cnt[4]);
+        stats->price_updates = int64_t(cnt[5]);
         stats->kernel_ms = kms;
         stats->total_ms = tms;
     }

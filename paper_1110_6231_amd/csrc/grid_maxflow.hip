@@ -17,20 +17,24 @@
 //  * SoA state, one int32 array each for e, h, and the residuals of p->right,
 //    p->left, p->down, p->up and p->t; the arc p->s is never used again after
 //    the initial saturation (pixels with h >= |V| are never discharged).
-//  * 64 x TH tiles, one 256-thread workgroup per tile.  A sweep launch loads a
-//    tile into LDS and runs `local_iters` lock-free iterations there with LDS
-//    atomics; pushes that cross the tile edge go straight to global memory
-//    with device-scope atomics, and the tile's own edge values are merged back
-//    by atomic deltas.  Every value a pixel reads of another pixel is a lower
-//    bound of the true one (excess and residuals are only decreased by their
-//    owner, heights only grow between global relabels), which is exactly the
-//    staleness Hong's argument admits.
+//  * 64 x TH tiles, one wavefront per tile (four tiles per 256-thread
+//    workgroup, no barrier): lane c holds column c of the tile in registers
+//    and runs `local_iters` lock-free iterations over the rows; horizontal
+//    neighbours are read and pushed to by cross-lane shuffles, vertical ones
+//    inside the lane's registers.  Flow pushed across the tile edge goes to
+//    global memory with device-scope atomics when the visit ends, and the
+//    tile's own edge excesses are merged back by atomic deltas.  Every value
+//    a pixel reads of another pixel is a lower bound of the true one (excess
+//    and residuals are only decreased by their owner, heights only grow
+//    between global relabels), which is exactly the staleness Hong's
+//    argument admits.
 //  * Active-tile flags double-buffered across sweep launches so that quiet
 //    tiles cost one flag read.
 //  * The BFS (and the cut closure) is a Bellman-Ford style relaxation run to a
-//    local fixpoint inside each LDS tile; tiles whose edge values changed mark
-//    their neighbours dirty, and passes repeat until no tile is dirty.  The
-//    least fixpoint is exactly the BFS level of every pixel.
+//    local fixpoint inside each register-resident tile; tiles whose edge
+//    values changed mark their neighbours dirty, and passes repeat until no
+//    tile is dirty.  The least fixpoint is exactly the BFS level of every
+//    pixel.
 //  * Batched solves share every launch: the tile table spans all instances,
 //    and an instance whose count reaches zero retires from later rounds.
 #include <algorithm>
@@ -51,6 +55,7 @@ constexpr int TW = 64;        // tile width: one wavefront per tile row
 constexpr int NT = 256;       // threads per tile workgroup
 constexpr int RPP = NT / TW;  // tile rows covered per thread pass (4)
 constexpr int MAX_PASS_SLOTS = 64;
+constexpr int RELAX_TH = 8;  // tile height of the relaxation kernels (BFS, cut)
 
 // Element at a 32-bit byte offset from a wave-uniform base: every per-pixel
 // array shares the offset, so the compiler keeps one VGPR per pixel instead of
@@ -60,12 +65,66 @@ __device__ __forceinline__ T &at(T *base, uint32_t byte_off) {
     return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
 }
 
+// Cross-lane moves by DPP (a VALU modifier, no LDS round trip).
+// from_left(v, f): lane i gets v of lane i-1, lane 0 gets its own f.
+// from_right(v, f): lane i gets v of lane i+1, lane 63 gets its own f.
+__device__ __forceinline__ int32_t from_left(int32_t v, int32_t f) {
+    return __builtin_amdgcn_update_dpp(f, v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+}
+__device__ __forceinline__ int32_t from_right(int32_t v, int32_t f) {
+    return __builtin_amdgcn_update_dpp(f, v, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+
+// Segmented min scans across the 64 lanes of a wavefront (Hillis-Steele
+// doubling inside each 16-lane row by DPP, then the row carries).
+// scan_from_left: v of lane x becomes min v[k] over s(x) <= k <= x, where
+// dl = x - s(x) (the lanes s(x)+1 .. x each accept their left neighbour).
+__device__ __forceinline__ int32_t scan_from_left(int32_t v, int dl, int lane) {
+#define LPR_STEP(o, ctrl)                                                    \
+    {                                                                        \
+        const int32_t t = __builtin_amdgcn_update_dpp(INT_MAX, v, ctrl, 0xF, \
+                                                      0xF, false);           \
+        if (dl >= o) v = min(v, t);                                          \
+    }
+    LPR_STEP(1, 0x111) LPR_STEP(2, 0x112) LPR_STEP(4, 0x114) LPR_STEP(8, 0x118)
+#undef LPR_STEP
+    // rows 1 and 3 take the inclusive result of lane 15 / 47 (row_bcast:15)
+    int32_t t = __builtin_amdgcn_update_dpp(INT_MAX, v, 0x142, 0xA, 0xF, false);
+    if (dl > (lane & 15)) v = min(v, t);
+    // rows 2 and 3 take the result of lane 31 (row_bcast:31)
+    t = __builtin_amdgcn_update_dpp(INT_MAX, v, 0x143, 0xC, 0xF, false);
+    if (dl > lane - 32) v = min(v, t);
+    return v;
+}
+// scan_from_right: v of lane x becomes min v[k] over x <= k <= e(x), where
+// dr = e(x) - x (the lanes x .. e(x)-1 each accept their right neighbour).
+__device__ __forceinline__ int32_t scan_from_right(int32_t v, int dr, int lane) {
+#define LPR_STEP(o, ctrl)                                                    \
+    {                                                                        \
+        const int32_t t = __builtin_amdgcn_update_dpp(INT_MAX, v, ctrl, 0xF, \
+                                                      0xF, false);           \
+        if (dr >= o) v = min(v, t);                                          \
+    }
+    LPR_STEP(1, 0x101) LPR_STEP(2, 0x102) LPR_STEP(4, 0x104) LPR_STEP(8, 0x108)
+#undef LPR_STEP
+    // rows 0 and 2 take the result of lane 16 / 48 (first lane of the next row)
+    const int32_t a = __builtin_amdgcn_readlane(v, 16);
+    const int32_t b = __builtin_amdgcn_readlane(v, 48);
+    if (!(lane & 16) && dr >= 16 - (lane & 15)) v = min(v, lane < 32 ? a : b);
+    // rows 0 and 1 take the result of lane 32
+    const int32_t c = __builtin_amdgcn_readlane(v, 32);
+    if (lane < 32 && dr >= 32 - lane) v = min(v, c);
+    return v;
+}
+
 struct Inst {
     int64_t off;      // first pixel of the instance in the packed arrays
     int32_t H, W;
     int32_t tiles_x, tiles_y;
     int32_t tile_base;
     int32_t HV;       // |V| = H*W + 2, the gap height
+    int32_t tiles_y_r;    // tile rows of the relaxation tiling (RELAX_TH)
+    int32_t tile_base_r;  // first relaxation tile of the instance
 };
 
 struct Scalars {
@@ -79,13 +138,14 @@ struct Dev {
     int32_t *e, *h, *rr, *rl, *rd, *ru, *rs;
     const int32_t *cap_src, *cap_snk, *cap_r, *cap_l, *cap_d, *cap_u;
     const Inst *inst;
-    const int32_t *tile_inst;
+    const int32_t *tile_inst;    // instance of every sweep tile (64 x TH)
+    const int32_t *tile_inst_r;  // instance of every relaxation tile (64 x RELAX_TH)
     unsigned long long *inst_active;  // per-instance active pixels (last count)
     int32_t *done;                    // per-instance: no active pixel left
     unsigned long long *counters;     // pushes, relabels, tiles swept,
                                       // tiles relaxed (BFS), tiles relaxed (cut)
     Scalars *sc;
-    int32_t ntiles;
+    int32_t ntiles, ntiles_r;
     int32_t ninst;
 };
 
@@ -94,23 +154,37 @@ struct Geo {
     int64_t off;
 };
 
-template <int TH>
+// Geometry of tile t of the sweep tiling (RT = false) or of the relaxation
+// tiling (RT = true, TH = RELAX_TH).
+template <int TH, bool RT = false>
 __device__ inline Geo tile_geo(const Dev &D, int t) {
     Geo g;
-    g.inst = D.tile_inst[t];
+    g.inst = RT ? D.tile_inst_r[t] : D.tile_inst[t];
     const Inst I = D.inst[g.inst];
     g.H = I.H;
     g.W = I.W;
     g.HV = I.HV;
     g.off = I.off;
     g.tiles_x = I.tiles_x;
-    g.tiles_y = I.tiles_y;
-    int lt = t - I.tile_base;
+    g.tiles_y = RT ? I.tiles_y_r : I.tiles_y;
+    int lt = t - (RT ? I.tile_base_r : I.tile_base);
     g.ty = lt / I.tiles_x;
     g.tx = lt - g.ty * I.tiles_x;
     g.y0 = g.ty * TH;
     g.x0 = g.tx * TW;
     return g;
+}
+
+// Tile of the calling wavefront in the wave-per-tile kernels (four tiles per
+// 256-thread workgroup).  Workgroups are dispatched to the eight XCDs round
+// robin, so workgroup b takes tile group (its XCD's first group + b / 8): each
+// XCD gets one contiguous band of tiles, whose vertical neighbours share that
+// XCD's L2.
+__device__ __forceinline__ int wave_tile() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, rem = nb & 7, xcd = b & 7;
+    const int group = xcd * q + min(xcd, rem) + (b >> 3);
+    return group * 4 + (threadIdx.x >> 6);
 }
 
 // Loads the one-pixel halo of a tile's labels/heights into rows 0 and TH+1
@@ -201,7 +275,7 @@ template <int TH>
 __global__ __launch_bounds__(NT) void k_bfs_seed(Dev D, int32_t *dirty_cur,
                                                  int32_t *dirty_next) {
     const int t = blockIdx.x;
-    const Geo g = tile_geo<TH>(D, t);
+    const Geo g = tile_geo<TH, true>(D, t);
     const bool retired = D.done[g.inst] != 0;
     if (threadIdx.x == 0) {
         dirty_cur[t] = retired ? 0 : 1;
@@ -224,7 +298,7 @@ template <int TH>
 __global__ __launch_bounds__(NT) void k_cut_seed(Dev D, int32_t *dirty_cur,
                                                  int32_t *dirty_next) {
     const int t = blockIdx.x;
-    const Geo g = tile_geo<TH>(D, t);
+    const Geo g = tile_geo<TH, true>(D, t);
     if (threadIdx.x == 0) {
         dirty_cur[t] = 1;
         dirty_next[t] = 0;
@@ -275,11 +349,11 @@ __global__ __launch_bounds__(256) void k_relax(Dev D, int32_t *dirty_cur,
                                               int32_t *dirty_next,
                                               int32_t *pass_count) {
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= D.ntiles) return;                // wave-uniform
+    const int t = wave_tile();
+    if (t >= D.ntiles_r) return;              // wave-uniform
     if (dirty_cur[t] == 0) return;            // wave-uniform (same address)
     if (lane == 0) dirty_cur[t] = 0;
-    const Geo g = tile_geo<TH>(D, t);
+    const Geo g = tile_geo<TH, true>(D, t);
     constexpr int INC = CUT ? 0 : 1;
     const int HV = g.HV;
     const int x = g.x0 + lane;
@@ -319,39 +393,48 @@ __global__ __launch_bounds__(256) void k_relax(Dev D, int32_t *dirty_cur,
         if ((lane == 0 || lane == 63) && hx >= 0 && hx < g.W && y < g.H)
             hside[r] = D.h[g.off + int64_t(y) * g.W + hx];
     }
-    for (;;) {
-        bool changed = false;
+    // Segment lengths of the horizontal scans, fixed for the whole pass:
+    // low byte x - s(x), high byte e(x) - x (see scan_from_left/right).
+    int32_t seg[TH];
+#pragma unroll
+    for (int r = 0; r < TH; ++r) {
+        const uint64_t brkL = __ballot(!((mL >> r) & 1u)) | 1ull;
+        const uint64_t brkR = __ballot(!((mR >> r) & 1u)) | (1ull << 63);
+        const uint64_t low = lane == 63 ? ~0ull : (2ull << lane) - 1;
+        const int sx = 63 - __clzll((long long)(brkL & low));
+        const int ex = lane + __ffsll((unsigned long long)(brkR >> lane)) - 1;
+        seg[r] = (lane - sx) | ((ex - lane) << 8);
+    }
+    // A row needs its horizontal scans again only after a column pass lowered
+    // one of its values (after both scans a row is at its own fixpoint).
+    uint32_t rows = TH == 32 ? ~0u : (1u << TH) - 1;  // wave-uniform
+    while (rows) {
 #pragma unroll
         for (int r = 0; r < TH; ++r) {
-            int32_t left = __shfl_up(d[r], 1, 64);
-            int32_t right = __shfl_down(d[r], 1, 64);
-            if (lane == 0) left = hside[r];
-            if (lane == 63) right = hside[r];
+            if (!((rows >> r) & 1u)) continue;
             int32_t nd = d[r];
-            if ((mL >> r) & 1u) nd = min(nd, left + INC);
-            if ((mR >> r) & 1u) nd = min(nd, right + INC);
-            changed |= nd < d[r];
+            if (lane == 0 && (mL >> r) & 1u) nd = min(nd, hside[r] + INC);
+            if (lane == 63 && (mR >> r) & 1u) nd = min(nd, hside[r] + INC);
+            nd = scan_from_left(nd - INC * lane, seg[r] & 0xff, lane) + INC * lane;
+            nd = scan_from_right(nd + INC * lane, seg[r] >> 8, lane) - INC * lane;
             d[r] = nd;
         }
+        rows = 0;
+        // columns: down, then up
 #pragma unroll
         for (int r = 0; r < TH; ++r) {
             const int32_t up = r == 0 ? top : d[r - 1];
-            if ((mU >> r) & 1u) {
-                const int32_t nd = min(d[r], up + INC);
-                changed |= nd < d[r];
-                d[r] = nd;
-            }
+            const int32_t nd = (mU >> r) & 1u ? min(d[r], up + INC) : d[r];
+            if (__any(nd < d[r])) rows |= 1u << r;
+            d[r] = nd;
         }
 #pragma unroll
         for (int r = TH - 1; r >= 0; --r) {
             const int32_t dn = r == TH - 1 ? bot : d[r + 1];
-            if ((mD >> r) & 1u) {
-                const int32_t nd = min(d[r], dn + INC);
-                changed |= nd < d[r];
-                d[r] = nd;
-            }
+            const int32_t nd = (mD >> r) & 1u ? min(d[r], dn + INC) : d[r];
+            if (__any(nd < d[r])) rows |= 1u << r;
+            d[r] = nd;
         }
-        if (!__any(changed)) break;
     }
     bool ch_top = false, ch_bot = false, ch_col = false;
 #pragma unroll
@@ -435,25 +518,29 @@ __global__ void k_count_finish(Dev D, const int32_t *bfs_open) {
 // active 64 x TH tile, one wavefront per tile, no block barrier.  Lane c owns
 // column c of the tile in registers (e, h, the four neighbour residuals and
 // the sink residual of each of its TH pixels).  An iteration walks the rows
-// top to bottom: the lane reads its horizontal neighbours' current heights by
-// cross-lane shuffles (lanes 0 and 63 use the halo heights), picks the lowest
-// residual neighbour and pushes or relabels; a push inside the column updates
-// the registers directly, a push to the lane on the left or right is handed
-// over by a shuffle right after the row, and flow pushed across the tile edge
-// is summed per pixel and applied to global memory with device-scope atomics
-// when the visit ends (activating that tile) -- for the other tile the push
-// is fulfilled a little later, which Hong's argument admits.  The tile's own
-// excesses on its edge are merged back by atomic deltas, so pushes that other
-// tiles make into it meanwhile are kept.  Every value read of another
-// pixel is a lower bound of the true one (excess and residuals only shrink
-// by their owner's pushes, heights only grow between global relabels), the
-// staleness Hong's argument admits.
+// top to bottom (rows with no active pixel are skipped as a whole): every
+// active pixel reads its horizontal neighbours' current heights by DPP
+// (lanes 0 and 63 use the halo heights), picks the lowest residual neighbour
+// and pushes or relabels.  The choice is branch-free: each candidate is the
+// key (height << 3 | direction) and the minimum key gives the lowest height
+// and, on ties, the first direction in the scan order t, right, left, down,
+// up.  A push inside the column updates the registers directly, a push to
+// the lane on the left or right is handed over by DPP right after the row.
+// Flow pushed across the tile edge only lowers the pusher's own residual
+// during the visit; the total (that residual's drop) is applied to the
+// neighbouring tile with device-scope atomics when the visit ends, which for
+// the other tile is a push fulfilled a little later, as Hong's argument
+// admits.  The tile's own edge excesses are merged back by atomic deltas, so
+// pushes that other tiles make into it meanwhile are kept.  Every value read
+// of another pixel is a lower bound of the true one (excess and residuals
+// only shrink by their owner's pushes, heights only grow between global
+// relabels), the staleness Hong's argument admits.
 // ---------------------------------------------------------------------------
 template <int TH>
 __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
                                               int32_t *act_next, int L) {
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int t = wave_tile();
     if (t >= D.ntiles) return;           // wave-uniform
     if (act_cur[t] == 0) return;         // wave-uniform (same address)
     if (lane == 0) act_cur[t] = 0;
@@ -461,15 +548,18 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
     const int HV = g.HV;
     const int x = g.x0 + lane;
     const bool colv = x < g.W;
+    const uint32_t o0 = 4u * uint32_t(g.off + int64_t(g.y0) * g.W + x);  // row 0
+    const uint32_t ow = 4u * uint32_t(g.W);                                // one row
+    // Pixels outside the grid hold e = 0, h = |V| and no residual arc, so
+    // they never act and are never chosen.
     int32_t e[TH], h[TH], rs[TH], rr[TH], rl[TH], rd[TH], ru[TH];
     uint32_t valid = 0;
 #pragma unroll
     for (int r = 0; r < TH; ++r) {
-        const int y = g.y0 + r;
         e[r] = 0; h[r] = HV; rs[r] = 0; rr[r] = 0; rl[r] = 0; rd[r] = 0; ru[r] = 0;
-        if (colv && y < g.H) {
+        if (colv && g.y0 + r < g.H) {
             valid |= 1u << r;
-            const uint32_t o = 4u * uint32_t(g.off + int64_t(y) * g.W + x);
+            const uint32_t o = o0 + r * ow;
             e[r] = at(D.e, o);
             h[r] = at(D.h, o);
             rs[r] = at(D.rs, o);
@@ -479,193 +569,167 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
             ru[r] = at(D.ru, o);
         }
     }
-    // Excess at load time, for the delta merge of edge pixels.  Residuals of
-    // arcs that leave the tile are decremented in global memory at push time
-    // (other tiles only ever increase them there), so they are never written
-    // back; everything else is stored plainly if it changed (bit per row).
-    int32_t e0[TH];
+    // Values at load time: the excess (for the delta merge of edge pixels)
+    // and the residuals of the arcs that leave the tile (lane 63 right, lane
+    // 0 left, row 0 up, row TH-1 down), whose drop is the flow pushed out.
+    int32_t e0[TH], side0[TH];
 #pragma unroll
-    for (int r = 0; r < TH; ++r) e0[r] = e[r];
-    uint32_t ch_h = 0, ch_rs = 0, ch_rr = 0, ch_rl = 0, ch_rd = 0, ch_ru = 0;
-    // flow pushed out of the tile (lanes 0 / 63 sideways, rows 0 / TH-1
-    // vertically), applied to the neighbouring tiles when the visit ends
-    int32_t outH[TH];
-#pragma unroll
-    for (int r = 0; r < TH; ++r) outH[r] = 0;
-    int32_t outU = 0, outD = 0;
+    for (int r = 0; r < TH; ++r) {
+        e0[r] = e[r];
+        side0[r] = lane == 63 ? rr[r] : rl[r];
+    }
+    const int32_t top0 = ru[0], bot0 = rd[TH - 1];
     // halo heights (read once; heights only grow, so these are lower bounds)
     int32_t top = HV, bot = HV, hside[TH];
-    const uint32_t o0 = 4u * uint32_t(g.off + int64_t(g.y0) * g.W + x);  // row 0
-    const uint32_t ow = 4u * uint32_t(g.W);                                // one row
     if (colv && g.y0 > 0) top = at(D.h, o0 - ow);
     if (colv && g.y0 + TH < g.H) bot = at(D.h, o0 + TH * ow);
     const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
 #pragma unroll
     for (int r = 0; r < TH; ++r) {
-        const int y = g.y0 + r;
         hside[r] = HV;
-        if ((lane == 0 || lane == 63) && hx >= 0 && hx < g.W && y < g.H)
+        if ((lane == 0 || lane == 63) && hx >= 0 && hx < g.W && g.y0 + r < g.H)
             hside[r] = at(D.h, o0 + r * ow + 4u * uint32_t(hx - x));
     }
-    unsigned pushes = 0, relabels = 0;
-    bool touch_l = false, touch_r = false, touch_u = false, touch_d = false;
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    uint32_t acted = 0;                        // bit r: the pixel pushed or relabelled
+    unsigned long long pushes = 0, relabels = 0;  // wave-uniform
     for (int it = 0; it < L; ++it) {
-        bool any = false;
+        bool any = false;                      // wave-uniform
 #pragma unroll
         for (int r = 0; r < TH; ++r) {
-            int32_t hl = __shfl_up(h[r], 1, 64);
-            int32_t hr = __shfl_down(h[r], 1, 64);
-            if (lane == 0) hl = hside[r];
-            if (lane == 63) hr = hside[r];
-            int32_t sendR = 0, sendL = 0;
-            const int y = g.y0 + r;
-            if (((valid >> r) & 1u) && e[r] > 0 && h[r] < HV) {
-                any = true;
-                // lowest residual neighbour; scan order t, right, left, down, up
-                int32_t best = INT_MAX, cap = 0;
-                int dir = -1;
-                if (rs[r] > 0) { best = 0; dir = 0; cap = rs[r]; }
-                if (rr[r] > 0 && x + 1 < g.W && hr < best) { best = hr; dir = 1; cap = rr[r]; }
-                if (rl[r] > 0 && x > 0 && hl < best) { best = hl; dir = 2; cap = rl[r]; }
-                const int32_t hd = r + 1 < TH ? h[r + 1] : bot;
-                if (rd[r] > 0 && y + 1 < g.H && hd < best) { best = hd; dir = 3; cap = rd[r]; }
-                const int32_t hu = r > 0 ? h[r - 1] : top;
-                if (ru[r] > 0 && y > 0 && hu < best) { best = hu; dir = 4; cap = ru[r]; }
-                if (dir >= 0 && h[r] > best) {
-                    // PUSH delta = min(e', u_f(x, y~)) towards y~
-                    const int32_t d = min(e[r], cap);
-                    e[r] -= d;
-                    if (dir == 0) {
-                        rs[r] -= d;
-                        ch_rs |= 1u << r;
-                    } else if (dir == 1) {
-                        rr[r] -= d;
-                        if (lane < 63) {
-                            sendR = d;
-                            ch_rr |= 1u << r;
-                        } else {
-                            outH[r] += d;
-                        }
-                    } else if (dir == 2) {
-                        rl[r] -= d;
-                        if (lane > 0) {
-                            sendL = d;
-                            ch_rl |= 1u << r;
-                        } else {
-                            outH[r] += d;
-                        }
-                    } else if (dir == 3) {
-                        rd[r] -= d;
-                        if (r + 1 < TH) {
-                            ru[r + 1] += d;
-                            e[r + 1] += d;
-                            ch_rd |= 1u << r;
-                            ch_ru |= 1u << (r + 1);
-                        } else {
-                            outD += d;
-                        }
-                    } else {
-                        ru[r] -= d;
-                        if (r > 0) {
-                            rd[r - 1] += d;
-                            e[r - 1] += d;
-                            ch_ru |= 1u << r;
-                            ch_rd |= 1u << (r - 1);
-                        } else {
-                            outU += d;
-                        }
-                    }
-                    ++pushes;
-                } else {
-                    // RELABEL h(x) = h~ + 1 (owner only); no residual arc or
-                    // a height past |V| freezes the pixel (gap height)
-                    h[r] = (dir < 0 || best >= HV - 1) ? HV : best + 1;
-                    ch_h |= 1u << r;
-                    ++relabels;
-                }
+            const bool active = e[r] > 0 && h[r] < HV;
+            if (!__any(active)) continue;      // wave-uniform skip
+            any = true;
+            const int32_t hl = from_left(h[r], hside[r]);
+            const int32_t hr = from_right(h[r], hside[r]);
+            const int32_t hd = r + 1 < TH ? h[r + 1] : bot;
+            const int32_t hu = r > 0 ? h[r - 1] : top;
+            uint32_t key = rs[r] > 0 ? 0u : NONE;
+            key = min(key, rr[r] > 0 ? (uint32_t(hr) << 3) | 1u : NONE);
+            key = min(key, rl[r] > 0 ? (uint32_t(hl) << 3) | 2u : NONE);
+            key = min(key, rd[r] > 0 ? (uint32_t(hd) << 3) | 3u : NONE);
+            key = min(key, ru[r] > 0 ? (uint32_t(hu) << 3) | 4u : NONE);
+            const uint32_t best = key >> 3;    // NONE >> 3 exceeds every height
+            const uint32_t dir = key & 7u;
+            const bool push = active && best < uint32_t(h[r]);
+            const bool relab = active && !push;
+            // PUSH delta = min(e', u_f(x, y~)) towards y~
+            // the chosen arc's residual (a masked maximum: a select chain over
+            // the arrays would make the compiler address them in memory)
+            const int32_t cap = max(max(max(dir == 0 ? rs[r] : 0, dir == 1 ? rr[r] : 0),
+                                        max(dir == 2 ? rl[r] : 0, dir == 3 ? rd[r] : 0)),
+                                    dir == 4 ? ru[r] : 0);
+            const int32_t d = push ? min(e[r], cap) : 0;
+            const int32_t dS = dir == 0 ? d : 0, dR = dir == 1 ? d : 0;
+            const int32_t dL = dir == 2 ? d : 0, dD = dir == 3 ? d : 0;
+            const int32_t dU = dir == 4 ? d : 0;
+            e[r] -= d;
+            rs[r] -= dS;
+            rr[r] -= dR;
+            rl[r] -= dL;
+            rd[r] -= dD;
+            ru[r] -= dU;
+            if (r + 1 < TH) {
+                ru[r + 1] += dD;
+                e[r + 1] += dD;
             }
+            if (r > 0) {
+                rd[r - 1] += dU;
+                e[r - 1] += dU;
+            }
+            // RELABEL h(x) = h~ + 1 (owner only); no residual arc or a height
+            // past |V| freezes the pixel (gap height)
+            if (relab) h[r] = best >= uint32_t(HV - 1) ? HV : int32_t(best) + 1;
             // hand the horizontal pushes of this row to the neighbour lanes
-            const int32_t fromL = __shfl_up(sendR, 1, 64);
-            const int32_t fromR = __shfl_down(sendL, 1, 64);
-            if (lane > 0 && fromL) {
-                rl[r] += fromL;
-                e[r] += fromL;
-                ch_rl |= 1u << r;
-            }
-            if (lane < 63 && fromR) {
-                rr[r] += fromR;
-                e[r] += fromR;
-                ch_rr |= 1u << r;
-            }
+            // (lane 63's push right and lane 0's push left leave the wave)
+            const int32_t inL = from_left(dR, 0);
+            const int32_t inR = from_right(dL, 0);
+            rl[r] += inL;
+            rr[r] += inR;
+            e[r] += inL + inR;
+            acted |= active ? 1u << r : 0u;
+            pushes += __popcll(__ballot(push));
+            relabels += __popcll(__ballot(relab));
         }
-        if (!__any(any)) break;
+        if (!any) break;
     }
-    // write back: plain stores where only this tile writes, an atomic delta
-    // for the excess of pixels that other tiles can push into
-    bool active_end = false;
+    // Write back the pixels whose state can have changed (they or an in-tile
+    // neighbour acted): plain stores where only this tile writes, an atomic
+    // delta for the excess of pixels that other tiles can push into, and the
+    // flow pushed out of the tile applied to both ends of the crossing arcs.
+    const uint32_t touched = acted | (acted << 1) | (acted >> 1) |
+                             uint32_t(from_left(int32_t(acted), 0)) |
+                             uint32_t(from_right(int32_t(acted), 0));
+    bool active_end = false, touch_l = false, touch_r = false;
+    bool touch_u = false, touch_d = false;
 #pragma unroll
     for (int r = 0; r < TH; ++r) {
         if (!((valid >> r) & 1u)) continue;
+        active_end |= e[r] > 0 && h[r] < HV;
+        if (!((touched >> r) & 1u)) continue;
         const int y = g.y0 + r;
         const uint32_t o = o0 + r * ow;
         const bool edge = (lane == 63 && x + 1 < g.W) || (lane == 0 && x > 0) ||
                           (r == TH - 1 && y + 1 < g.H) || (r == 0 && y > 0);
-        if (e[r] != e0[r]) {
-            if (edge) atomicAdd(&at(D.e, o), e[r] - e0[r]);
-            else at(D.e, o) = e[r];
+        if (edge) {
+            if (e[r] != e0[r]) atomicAdd(&at(D.e, o), e[r] - e0[r]);
+        } else {
+            at(D.e, o) = e[r];
         }
-        const uint32_t b = 1u << r;
-        if (ch_h & b) at(D.h, o) = h[r];
-        if (ch_rs & b) at(D.rs, o) = rs[r];
-        if (ch_rr & b) at(D.rr, o) = rr[r];
-        if (ch_rl & b) at(D.rl, o) = rl[r];
-        if (ch_rd & b) at(D.rd, o) = rd[r];
-        if (ch_ru & b) at(D.ru, o) = ru[r];
-        active_end |= e[r] > 0 && h[r] < HV;
-        // pushes out of the tile: own residual down, neighbour's reverse
-        // residual and excess up
-        if (outH[r]) {
-            if (lane == 63) {
-                atomicSub(&at(D.rr, o), outH[r]);
-                atomicAdd(&at(D.rl, o + 4), outH[r]);
-                atomicAdd(&at(D.e, o + 4), outH[r]);
+        at(D.h, o) = h[r];
+        at(D.rs, o) = rs[r];
+        if (lane < 63) at(D.rr, o) = rr[r];
+        if (lane > 0) at(D.rl, o) = rl[r];
+        if (r < TH - 1) at(D.rd, o) = rd[r];
+        if (r > 0) at(D.ru, o) = ru[r];
+        if (lane == 63) {
+            const int32_t out = side0[r] - rr[r];
+            if (out) {
+                atomicSub(&at(D.rr, o), out);
+                atomicAdd(&at(D.rl, o + 4), out);
+                atomicAdd(&at(D.e, o + 4), out);
                 touch_r = true;
-            } else {
-                atomicSub(&at(D.rl, o), outH[r]);
-                atomicAdd(&at(D.rr, o - 4), outH[r]);
-                atomicAdd(&at(D.e, o - 4), outH[r]);
+            }
+        }
+        if (lane == 0) {
+            const int32_t out = side0[r] - rl[r];
+            if (out) {
+                atomicSub(&at(D.rl, o), out);
+                atomicAdd(&at(D.rr, o - 4), out);
+                atomicAdd(&at(D.e, o - 4), out);
                 touch_l = true;
             }
         }
-        if (r == 0 && outU) {
-            atomicSub(&at(D.ru, o), outU);
-            atomicAdd(&at(D.rd, o - ow), outU);
-            atomicAdd(&at(D.e, o - ow), outU);
-            touch_u = true;
+        if (r == 0) {
+            const int32_t out = top0 - ru[0];
+            if (out) {
+                atomicSub(&at(D.ru, o), out);
+                atomicAdd(&at(D.rd, o - ow), out);
+                atomicAdd(&at(D.e, o - ow), out);
+                touch_u = true;
+            }
         }
-        if (r == TH - 1 && outD) {
-            atomicSub(&at(D.rd, o), outD);
-            atomicAdd(&at(D.ru, o + ow), outD);
-            atomicAdd(&at(D.e, o + ow), outD);
-            touch_d = true;
+        if (r == TH - 1) {
+            const int32_t out = bot0 - rd[TH - 1];
+            if (out) {
+                atomicSub(&at(D.rd, o), out);
+                atomicAdd(&at(D.ru, o + ow), out);
+                atomicAdd(&at(D.e, o + ow), out);
+                touch_d = true;
+            }
         }
     }
     const bool a_end = __any(active_end);
     const bool a_l = __any(touch_l), a_r = __any(touch_r);
     const bool a_u = __any(touch_u), a_d = __any(touch_d);
-    unsigned long long np = pushes, nr = relabels;
-    for (int o = 32; o > 0; o >>= 1) {
-        np += __shfl_xor(np, o, 64);
-        nr += __shfl_xor(nr, o, 64);
-    }
     if (lane == 0) {
         if (a_end) act_next[t] = 1;
         if (a_l) act_next[t - 1] = 1;
         if (a_r) act_next[t + 1] = 1;
         if (a_u) act_next[t - g.tiles_x] = 1;
         if (a_d) act_next[t + g.tiles_x] = 1;
-        if (np) atomicAdd(&D.counters[0], np);
-        if (nr) atomicAdd(&D.counters[1], nr);
+        if (pushes) atomicAdd(&D.counters[0], pushes);
+        if (relabels) atomicAdd(&D.counters[1], relabels);
         atomicAdd(&D.counters[2], 1ull);
     }
 }
@@ -694,19 +758,20 @@ __global__ __launch_bounds__(NT) void k_flow_value(Dev D, int64_t *flow) {
 // ---------------------------------------------------------------------------
 struct Layout {
     int32_t *st[7];
-    int32_t *tile_inst, *act[2], *dirty[2], *done;
+    int32_t *tile_inst, *tile_inst_r, *act[2], *dirty[2], *done;
     Inst *inst;
     unsigned long long *inst_active, *counters;
     Scalars *sc;
 };
 
-static Carver carve(Carver cv, int64_t N, int64_t T, int B, Layout *L) {
+static Carver carve(Carver cv, int64_t N, int64_t T, int64_t TR, int B, Layout *L) {
     for (int i = 0; i < 7; ++i) L->st[i] = cv.take<int32_t>(size_t(N));
     L->tile_inst = cv.take<int32_t>(size_t(T));
+    L->tile_inst_r = cv.take<int32_t>(size_t(TR));
     L->act[0] = cv.take<int32_t>(size_t(T));
     L->act[1] = cv.take<int32_t>(size_t(T));
-    L->dirty[0] = cv.take<int32_t>(size_t(T));
-    L->dirty[1] = cv.take<int32_t>(size_t(T));
+    L->dirty[0] = cv.take<int32_t>(size_t(TR));
+    L->dirty[1] = cv.take<int32_t>(size_t(TR));
     L->inst = cv.take<Inst>(size_t(B));
     L->inst_active = cv.take<unsigned long long>(size_t(B));
     L->done = cv.take<int32_t>(size_t(B));
@@ -720,13 +785,14 @@ static int64_t tiles_for(int32_t H, int32_t W, int TH) {
 }
 
 static size_t workspace_bytes(int B, const int32_t *H, const int32_t *W) {
-    int64_t N = 0, T = 0;
+    int64_t N = 0, T = 0, TR = 0;
     for (int b = 0; b < B; ++b) {
         N += int64_t(H[b]) * W[b];
         T += tiles_for(H[b], W[b], 8);  // smallest tile height: most tiles
+        TR += tiles_for(H[b], W[b], RELAX_TH);
     }
     Layout L;
-    Carver cv = carve(Carver(), N, T, B, &L);
+    Carver cv = carve(Carver(), N, T, TR, B, &L);
     return cv.used();
 }
 
@@ -735,18 +801,19 @@ struct Kern {
     static void init(dim3 g, hipStream_t s, const Dev &D) {
         hipLaunchKernelGGL(k_init<TH>, g, dim3(NT), 0, s, D);
     }
-    static void bfs_seed(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
-        hipLaunchKernelGGL(k_bfs_seed<TH>, g, dim3(NT), 0, s, D, a, b);
+    // the relaxation kernels run on the RELAX_TH tiling
+    static void bfs_seed(hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
+        hipLaunchKernelGGL(k_bfs_seed<RELAX_TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D, a, b);
     }
-    static void cut_seed(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
-        hipLaunchKernelGGL(k_cut_seed<TH>, g, dim3(NT), 0, s, D, a, b);
+    static void cut_seed(hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
+        hipLaunchKernelGGL(k_cut_seed<RELAX_TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D, a, b);
     }
     // one wavefront per tile, four tiles per 256-thread block
-    static void relax(bool cut, dim3 g, hipStream_t s, const Dev &D, int32_t *a,
-                      int32_t *b, int32_t *pc) {
-        const dim3 gw((g.x + 3) / 4);
-        if (cut) hipLaunchKernelGGL((k_relax<TH, true>), gw, dim3(NT), 0, s, D, a, b, pc);
-        else hipLaunchKernelGGL((k_relax<TH, false>), gw, dim3(NT), 0, s, D, a, b, pc);
+    static void relax(bool cut, hipStream_t s, const Dev &D, int32_t *a, int32_t *b,
+                      int32_t *pc) {
+        const dim3 gw((D.ntiles_r + 3) / 4);
+        if (cut) hipLaunchKernelGGL((k_relax<RELAX_TH, true>), gw, dim3(NT), 0, s, D, a, b, pc);
+        else hipLaunchKernelGGL((k_relax<RELAX_TH, false>), gw, dim3(NT), 0, s, D, a, b, pc);
     }
     static void count(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
         hipLaunchKernelGGL(k_count<TH>, g, dim3(NT), 0, s, D, a, b);
@@ -774,7 +841,7 @@ static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
                                     Layout &Lw, int *dirty_sel, dim3 grid,
                                     EventTimer &tm, int64_t *passes) {
     int batch = 8;
-    const int64_t guard = 16 * int64_t(D.ntiles) + 1024;
+    const int64_t guard = 16 * int64_t(D.ntiles_r) + 1024;
     for (int64_t done_passes = 0;; done_passes += batch) {
         if (done_passes > guard) {
             set_error("relaxation did not reach its fixpoint within %lld passes",
@@ -784,7 +851,7 @@ static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
         LPR_TRY(fill_i32(Lw.sc->pass_count, 0, batch, s));
         const int ev = tm.begin();
         for (int i = 0; i < batch; ++i) {
-            Kern<TH>::relax(cut, grid, s, D, Lw.dirty[*dirty_sel],
+            Kern<TH>::relax(cut, s, D, Lw.dirty[*dirty_sel],
                             Lw.dirty[*dirty_sel ^ 1], Lw.sc->pass_count + i);
             *dirty_sel ^= 1;
         }
@@ -824,11 +891,11 @@ static lpr_status enqueue_round(hipStream_t s, const Dev &D, Layout &Lw, dim3 gr
     for (int k = 0; k < K; ++k)
         Kern<TH>::sweep(grid, s, D, Lw.act[k & 1], Lw.act[(k & 1) ^ 1], L);
     if (t_sweep) t_sweep->end(ev);
-    Kern<TH>::bfs_seed(grid, s, D, Lw.dirty[0], Lw.dirty[1]);
+    Kern<TH>::bfs_seed(s, D, Lw.dirty[0], Lw.dirty[1]);
     LPR_TRY(fill_i32(Lw.sc->pass_count, 0, P, s));
     ev = t_bfs ? t_bfs->begin() : -1;
     for (int i = 0; i < P; ++i)
-        Kern<TH>::relax(false, grid, s, D, Lw.dirty[i & 1], Lw.dirty[(i & 1) ^ 1],
+        Kern<TH>::relax(false, s, D, Lw.dirty[i & 1], Lw.dirty[(i & 1) ^ 1],
                         Lw.sc->pass_count + i);
     if (t_bfs) t_bfs->end(ev);
     LPR_TRY(enqueue_count<TH>(s, D, Lw, grid, B, Lw.sc->pass_count + P - 1));
@@ -946,7 +1013,8 @@ static lpr_status read_scalars(hipStream_t s, Layout &Lw, Scalars **host) {
 
 template <int TH>
 static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
-                        const std::vector<int32_t> &tile_inst, Dev D,
+                        const std::vector<int32_t> &tile_inst,
+                        const std::vector<int32_t> &tile_inst_r, Dev D,
                         Layout &Lw, const GraphKey &base_key, int64_t *flow_values,
                         uint8_t *side, lpr_grid_stats *stats, hipStream_t s) {
     const int T = int(tile_inst.size());
@@ -963,6 +1031,9 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
                                hipMemcpyHostToDevice, s));
     LPR_TRY_HIP(hipMemcpyAsync(Lw.tile_inst, tile_inst.data(),
                                sizeof(int32_t) * T, hipMemcpyHostToDevice, s));
+    LPR_TRY_HIP(hipMemcpyAsync(Lw.tile_inst_r, tile_inst_r.data(),
+                               sizeof(int32_t) * tile_inst_r.size(),
+                               hipMemcpyHostToDevice, s));
     LPR_TRY(fill_i32(Lw.done, 0, B, s));
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.counters), 0, 8, s));
     LPR_TRY(fill_i32(&Lw.sc->err, 0, 1, s));
@@ -972,7 +1043,7 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
     // First global relabel: eager, to its fixpoint; its pass count sets the
     // number of BFS passes per later round.
     int dirty_sel = 0;
-    Kern<TH>::bfs_seed(grid, s, D, Lw.dirty[0], Lw.dirty[1]);
+    Kern<TH>::bfs_seed(s, D, Lw.dirty[0], Lw.dirty[1]);
     LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, &dirty_sel, grid, t_bfs,
                                   &bfs_passes));
     int PB = int(std::min<int64_t>(MAX_PASS_SLOTS, std::max<int64_t>(4, bfs_passes / 2 + 2)));
@@ -1032,7 +1103,7 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
     if (side) {
         // every instance takes part in the closure
         dirty_sel = 0;
-        Kern<TH>::cut_seed(grid, s, D, Lw.dirty[0], Lw.dirty[1]);
+        Kern<TH>::cut_seed(s, D, Lw.dirty[0], Lw.dirty[1]);
         LPR_TRY_HIP(hipGetLastError());
         EventTimer none(s);
         LPR_TRY(relax_to_fixpoint<TH>(true, s, D, Lw, &dirty_sel, grid, none,
@@ -1149,7 +1220,9 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
         return LPR_EINVAL;
     }
     for (int b = 0; b < B; ++b) {
-        if (H[b] < 1 || W[b] < 1 || int64_t(H[b]) * W[b] >= (int64_t(1) << 30)) {
+        // heights up to |V| = H*W + 2 are packed with a 3-bit direction into
+        // 32 bits by the push sweep
+        if (H[b] < 1 || W[b] < 1 || int64_t(H[b]) * W[b] >= (int64_t(1) << 28)) {
             set_error("instance %d: bad shape %d x %d", b, H[b], W[b]);
             return LPR_EINVAL;
         }
@@ -1184,7 +1257,7 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     }
     const int64_t N = node_offset[B];
     std::vector<Inst> insts(B);
-    std::vector<int32_t> tile_inst;
+    std::vector<int32_t> tile_inst, tile_inst_r;
     for (int b = 0; b < B; ++b) {
         Inst &I = insts[b];
         I.off = node_offset[b];
@@ -1194,9 +1267,13 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
         I.tiles_y = ceil_div(H[b], P.TH);
         I.tile_base = int32_t(tile_inst.size());
         I.HV = H[b] * W[b] + 2;
+        I.tiles_y_r = ceil_div(H[b], RELAX_TH);
+        I.tile_base_r = int32_t(tile_inst_r.size());
         tile_inst.insert(tile_inst.end(), size_t(I.tiles_x) * I.tiles_y, b);
+        tile_inst_r.insert(tile_inst_r.end(), size_t(I.tiles_x) * I.tiles_y_r, b);
     }
     const int64_t T = int64_t(tile_inst.size());
+    const int64_t TR = int64_t(tile_inst_r.size());
     if (T >= (int64_t(1) << 31)) {
         set_error("too many tiles");
         return LPR_EINVAL;
@@ -1207,7 +1284,7 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
         return LPR_ENOMEM;
     }
     Layout Lw;
-    Carver cv = carve(Carver(workspace, ws_bytes), N, T, B, &Lw);
+    Carver cv = carve(Carver(workspace, ws_bytes), N, T, TR, B, &Lw);
     if (!cv.fits()) {
         set_error("workspace layout overflow");
         return LPR_ENOMEM;
@@ -1228,11 +1305,13 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     D.cap_u = caps[5];
     D.inst = Lw.inst;
     D.tile_inst = Lw.tile_inst;
+    D.tile_inst_r = Lw.tile_inst_r;
     D.inst_active = Lw.inst_active;
     D.done = Lw.done;
     D.counters = Lw.counters;
     D.sc = Lw.sc;
     D.ntiles = int32_t(T);
+    D.ntiles_r = int32_t(TR);
     D.ninst = B;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GraphKey key{};
@@ -1248,13 +1327,13 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     lpr_status st;
     switch (P.TH) {
         case 8:
-            st = solve<8>(P, B, insts, tile_inst, D, Lw, key, flow_values, side, stats, s);
+            st = solve<8>(P, B, insts, tile_inst, tile_inst_r, D, Lw, key, flow_values, side, stats, s);
             break;
         case 16:
-            st = solve<16>(P, B, insts, tile_inst, D, Lw, key, flow_values, side, stats, s);
+            st = solve<16>(P, B, insts, tile_inst, tile_inst_r, D, Lw, key, flow_values, side, stats, s);
             break;
         default:
-            st = solve<32>(P, B, insts, tile_inst, D, Lw, key, flow_values, side, stats, s);
+            st = solve<32>(P, B, insts, tile_inst, tile_inst_r, D, Lw, key, flow_values, side, stats, s);
             break;
     }
     if (st != LPR_OK) {

@@ -81,7 +81,8 @@ class AssignOpts(ctypes.Structure):
 class AssignStats(ctypes.Structure):
     _fields_ = [("refines", ctypes.c_int64), ("phases", ctypes.c_int64),
                 ("pushes", ctypes.c_int64), ("relabels", ctypes.c_int64),
-                ("scans", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3),
+                ("scans", ctypes.c_int64), ("price_updates", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 2),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
