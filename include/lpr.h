@@ -80,8 +80,9 @@ typedef struct {
     int32_t local_iters;        /* push/relabel iterations each tile runs in
                                    on-chip memory per sweep launch; 0 =
                                    tuned default                          */
-    int32_t tile_rows;          /* tile height in pixels: 8, 16 or 32 (tile
-                                   width is 64); 0 = tuned default        */
+    int32_t tile_rows;          /* push-sweep tile height in pixels: 4, 8,
+                                   16 or 32 (tile width is 64); 0 = tuned
+                                   default                                */
     int32_t max_rounds;         /* budget of global-relabel rounds; 0 =
                                    default (1 << 16)                       */
     int32_t flags;              /* LPR_GRID_* bits                          */

@@ -788,7 +788,7 @@ static size_t workspace_bytes(int B, const int32_t *H, const int32_t *W) {
     int64_t N = 0, T = 0, TR = 0;
     for (int b = 0; b < B; ++b) {
         N += int64_t(H[b]) * W[b];
-        T += tiles_for(H[b], W[b], 8);  // smallest tile height: most tiles
+        T += tiles_for(H[b], W[b], 4);  // smallest tile height: most tiles
         TR += tiles_for(H[b], W[b], RELAX_TH);
     }
     Layout L;
@@ -1080,7 +1080,20 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
             }
         }
         LPR_TRY(read_scalars<TH>(s, Lw, &host));
-        if (host->pass_count[PB - 1] != 0) {
+        if (host->pass_count[PB - 1] == 0) {
+            // passes this BFS needed: up to the first that marked no tile;
+            // later rounds get that plus a margin (lowered in steps of at
+            // least 4 so that few round graphs are captured)
+            int need = PB;
+            for (int i = 0; i < PB; ++i)
+                if (host->pass_count[i] == 0) {
+                    need = i + 1;
+                    break;
+                }
+            int next = std::max(4, need + 2);
+            next += next & 1;
+            if (next <= PB - 4) PB = next;
+        } else {
             // the BFS needed more than PB passes: finish it, recount, and give
             // the following rounds more passes
             dirty_sel = 0;
@@ -1250,7 +1263,7 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
         if (opts->max_rounds) P.max_rounds = opts->max_rounds;
         P.timing = (opts->flags & LPR_GRID_TIME_KERNELS) != 0;
     }
-    if (!(P.TH == 8 || P.TH == 16 || P.TH == 32) || P.L < 1 || P.L > 4096 ||
+    if (!(P.TH == 4 || P.TH == 8 || P.TH == 16 || P.TH == 32) || P.L < 1 || P.L > 4096 ||
         P.K < 1 || P.K > 4096 || P.max_rounds < 1) {
         set_error("invalid lpr_grid_opts");
         return LPR_EINVAL;
@@ -1326,6 +1339,9 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     call.start();
     lpr_status st;
     switch (P.TH) {
+        case 4:
+            st = solve<4>(P, B, insts, tile_inst, tile_inst_r, D, Lw, key, flow_values, side, stats, s);
+            break;
         case 8:
             st = solve<8>(P, B, insts, tile_inst, tile_inst_r, D, Lw, key, flow_values, side, stats, s);
             break;
@@ -1414,7 +1430,7 @@ extern "C" lpr_status lpr_grid_tune(int32_t B, const int32_t *H, const int32_t *
         set_error("invalid tuning arguments");
         return LPR_EINVAL;
     }
-    static const int THs[3] = {8, 16, 32};
+    static const int THs[4] = {4, 8, 16, 32};
     static const int Ls[4] = {4, 8, 16, 32};
     static const int Ks[3] = {2, 4, 8};
     std::vector<int64_t> ref(B), got(B);
