@@ -210,6 +210,9 @@ lpr_status lpr_grid_tune(int32_t B, const int32_t *H, const int32_t *W,
 #define LPR_ASSIGN_MAX_N 2048
 
 #define LPR_ASSIGN_TIME_KERNELS 0x1 /* time the solve kernel with HIP events */
+#define LPR_ASSIGN_NO_START_UPDATE 0x2 /* skip the global price update that
+                                          otherwise runs right after each
+                                          refine's first push of every row  */
 
 typedef struct {
     int32_t alpha;                  /* epsilon divisor per refine; 0 -> 8    */
@@ -230,6 +233,15 @@ typedef struct {
                                        epsilon per instance (> 0), overrides
                                        eps0 (for starts whose accuracy is
                                        known per instance)                   */
+    int64_t price_update_period;    /* pushes between global price updates
+                                       (Algorithm 5.3), which run when a
+                                       refine reaches its last few active
+                                       rows; 0 -> n, -1 -> never             */
+    int32_t tail_rows;              /* a refine switches to one wavefront
+                                       running operations back to back once
+                                       at most this many rows are active;
+                                       0 -> min(32, max(8, 8192 / n))        */
+    int32_t reserved;               /* must be 0                             */
 } lpr_assign_opts;
 
 typedef struct {

@@ -28,14 +28,15 @@
 //     operation to y until e(y) = 0: its residual arcs are the reverses (y,x)
 //     of its matched rows, the least c'_p(y,x) = -c(x,y) - p(x) is pushed back
 //     (x unmatched, e(x) = 1) after a relabel when not admissible.
-//   Serial tail: when at most TAIL_ENTER rows are active (the long chains at
+//   Serial tail: when at most `tail_rows` rows are active (the long chains at
 //     the end of a refine), one wavefront runs pushes and push-backs back to
 //     back with no block barrier -- a sequential trace of the same operations
 //     -- and returns the queue to the phases if it grows.
 // The refine's initialisation and the first X phase share one scan of every
 // row: after p(x) = -(min + eps) the minimising arc is admissible.
-//   Price update (Section 5, Algorithm 5.3): when the serial tail is entered
-//     after at least `n` pushes since the last update, the workgroup runs a
+//   Price update (Section 5, Algorithm 5.3): right after each refine's first
+//     push of every row, and when the serial tail is entered after at least
+//     `n` pushes since the last update, the workgroup runs a
 //     Dijkstra search from the deficit columns over reversed residual arcs,
 //     with arc length floor(c_p / eps) + 1 and Dial's buckets, until every
 //     active node is labelled, and lowers each price by eps x its label
@@ -55,8 +56,8 @@ namespace assign {
 
 constexpr int NT = 1024;
 constexpr int NW = NT / 64;
-constexpr int TAIL_ENTER = 2;  // serial tail when at most this many rows bid
-constexpr int TAIL_EXIT = 8;   // back to phases when the queue grows past this
+constexpr int TAIL_EXIT = 8;   // back to phases when the queue grows past
+                               // max(this, 4 x the entry threshold)
 constexpr unsigned C16_MAX = 32767;
 
 struct AInst {
@@ -82,6 +83,9 @@ struct AArgs {
     int64_t *totals;
     int64_t *col_prices;
     int64_t max_ops;
+    int64_t pu_period;             // pushes between price updates; 0: n, < 0: never
+    int32_t tail_rows;             // serial tail threshold (active rows)
+    int32_t pu_start;              // price update after each refine's first push
     uint64_t max_ticks;            // wall-clock budget in wall_clock64 ticks
     unsigned long long *counters;  // refines, phases, pushes, relabels, scans,
                                    // price updates
@@ -364,8 +368,9 @@ struct PU {
 // active node (unmatched row, column with e >= 1) is scanned and the current
 // bucket is empty; prices drop by eps x label, and by eps x (last label + 1)
 // for the nodes not scanned.
-// Called by the whole workgroup between phases.
-__device__ void price_update(const Shared &L, const PU &U,
+// Called by the whole workgroup between phases; `fl` is n ints of scratch
+// for the column frontier.
+__device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
                              const int16_t *__restrict__ CT, int n, int64_t sgnS,
                              int64_t eps, int tid) {
     __shared__ int s_rem, s_nf, s_again;
@@ -396,7 +401,7 @@ __device__ void price_update(const Shared &L, const PU &U,
         for (int y = tid; y < n; y += NT)
             if (!U.fy[y] && U.ly[y] == level) {
                 U.fy[y] = 1;
-                L.yl[atomicAdd(&s_nf, 1)] = y;
+                fl[atomicAdd(&s_nf, 1)] = y;
                 if (L.ey[y] >= 1) atomicSub(&s_rem, 1);
             }
         __syncthreads();
@@ -410,7 +415,7 @@ __device__ void price_update(const Shared &L, const PU &U,
                 const int64_t pxx = L.px[x];
                 const int mx = L.mate[x];
                 for (int j = 0; j < nf; ++j) {
-                    const int y = L.yl[j];
+                    const int y = fl[j];
                     const int64_t cp = int64_t(CT[int64_t(y) * n + x]) * sgnS + pxx - L.py[y];
                     if (cp < bound && y != mx) {
                         best = level + floor_div(cp, eps) + 1;
@@ -492,6 +497,13 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     U.fx = reinterpret_cast<uint8_t *>(U.ly + n);
     U.fy = U.fx + n;
     int64_t *py = L.py, *px = L.px;
+    const unsigned long long period =
+        A.pu_period > 0 ? (unsigned long long)A.pu_period : (unsigned long long)n;
+    if (A.pu_period < 0) CT = nullptr;
+    // the tail's cost per operation grows with n (one row scan), a phase's
+    // barrier cost does not
+    const int tail_enter = A.tail_rows > 0 ? A.tail_rows : min(32, max(8, 8192 / n));
+    const int tail_exit = max(TAIL_EXIT, 4 * tail_enter);
     __shared__ int s_nx, s_ny, s_stop, s_qh;
     __shared__ unsigned long long s_pu_mark;  // pushes at the last price update
     __shared__ unsigned long long s_cnt[6];
@@ -545,6 +557,15 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             atomicAdd(&s_cnt[4], (unsigned long long)n);
         }
         __syncthreads();
+        if (CT && A.pu_start && s_ny > 0) {
+            // every row is matched here, so the row list is free scratch
+            price_update(L, U, L.xl, CT, n, sgnS, eps, tid);
+            if (tid == 0) {
+                s_pu_mark = s_cnt[2];
+                atomicAdd(&s_cnt[5], 1ull);
+            }
+            __syncthreads();
+        }
         for (;;) {
             // ---- Y phase: active columns push surplus rows back ----
             const int ny = s_ny;
@@ -569,9 +590,9 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             }
             __syncthreads();
             if (nx == 0 || s_stop) break;
-            if (nx <= TAIL_ENTER) {
-                if (CT && s_cnt[2] - s_pu_mark >= (unsigned long long)n) {
-                    price_update(L, U, CT, n, sgnS, eps, tid);
+            if (nx <= tail_enter) {
+                if (CT && s_cnt[2] - s_pu_mark >= period) {
+                    price_update(L, U, L.yl, CT, n, sgnS, eps, tid);
                     if (tid == 0) {
                         s_pu_mark = s_cnt[2];
                         atomicAdd(&s_cnt[5], 1ull);
@@ -586,8 +607,8 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                     unsigned long long tp = 0, tr = 0, ts = 0;
                     int stop = 0;
                     // back to the phases after n pushes, for the next price update
-                    while (qlen > 0 && qlen <= TAIL_EXIT &&
-                           (!CT || tp < (unsigned long long)n)) {
+                    while (qlen > 0 && qlen <= tail_exit &&
+                           (!CT || tp < period)) {
                         const int x = L.xl[qh];
                         if (++qh == n) qh = 0;
                         --qlen;
@@ -786,7 +807,8 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     }
     int32_t alpha = 8;
     int64_t eps0 = 0, max_ops = 64 * int64_t(nmax) * nmax + (int64_t(1) << 20);
-    int64_t max_ms = 20000;
+    int64_t max_ms = 20000, pu_period = 0;
+    int32_t tail_rows = 0, pu_start = 1;
     const int64_t *init = nullptr, *eps0_inst = nullptr;
     bool timing = false;
     if (opts) {
@@ -796,9 +818,13 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         init = opts->init_col_prices;
         if (opts->max_ops) max_ops = opts->max_ops;
         if (opts->max_ms) max_ms = opts->max_ms;
+        pu_period = opts->price_update_period;
+        tail_rows = opts->tail_rows;
+        pu_start = (opts->flags & LPR_ASSIGN_NO_START_UPDATE) == 0;
         timing = (opts->flags & LPR_ASSIGN_TIME_KERNELS) != 0;
     }
-    if (alpha < 2 || eps0 < 0 || max_ops < 0 || max_ms < 0) {
+    if (alpha < 2 || eps0 < 0 || max_ops < 0 || max_ms < 0 || tail_rows < 0 ||
+        tail_rows > 4096) {
         set_error("invalid lpr_assign_opts");
         return LPR_EINVAL;
     }
@@ -846,6 +872,9 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     A.totals = totals;
     A.col_prices = col_prices;
     A.max_ops = max_ops;
+    A.pu_period = pu_period;
+    A.tail_rows = tail_rows;
+    A.pu_start = pu_start;
     {
         int dev = 0, khz = 0;
         LPR_TRY_HIP(hipGetDevice(&dev));

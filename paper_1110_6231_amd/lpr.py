@@ -25,6 +25,7 @@ LPR_ASSIGN_MAX_COST = (1 << 24) - 1
 LPR_ASSIGN_MAX_N = 2048
 LPR_GRID_TIME_KERNELS = 0x1
 LPR_ASSIGN_TIME_KERNELS = 0x1
+LPR_ASSIGN_NO_START_UPDATE = 0x2
 
 # Every symbol the header declares (checked by the ABI test).
 EXPORTED = [
@@ -75,7 +76,9 @@ class AssignOpts(ctypes.Structure):
                 ("init_col_prices", ctypes.c_void_p),
                 ("max_ops", ctypes.c_int64),
                 ("max_ms", ctypes.c_int64),
-                ("eps0_per_instance", ctypes.c_void_p)]
+                ("eps0_per_instance", ctypes.c_void_p),
+                ("price_update_period", ctypes.c_int64),
+                ("tail_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class AssignStats(ctypes.Structure):
@@ -307,9 +310,12 @@ def lpr_grid_tune(Hs, Ws, caps_packed, reps=2, workspace=None, stream=None):
 # Assignment
 # ---------------------------------------------------------------------------
 def make_assign_opts(alpha=0, eps0=0, init_col_prices=None, max_ops=0,
-                     flags=0, max_ms=0, eps0_per_instance=None) -> AssignOpts:
+                     flags=0, max_ms=0, eps0_per_instance=None,
+                     price_update_period=0, tail_rows=0) -> AssignOpts:
     o = AssignOpts()
     o.max_ms = max_ms
+    o.price_update_period = price_update_period
+    o.tail_rows = tail_rows
     o.eps0_per_instance = (None if eps0_per_instance is None
                            else eps0_per_instance.data_ptr())
     o.alpha = alpha

@@ -61,14 +61,18 @@ def learned_solve(packed, params, kappa, lpr, ws_net=None, ws_solve=None):
     return lpr.lpr_assign_solve_batched(packed, opts=opts, workspace=ws_solve)
 
 
-def timed(fn, torch, reps=3):
+def timed(fn, torch, reps=5):
+    """Median wall time of `reps` runs after one warm-up (a batch finishes
+    with its slowest instance, so single runs are noisy)."""
     fn()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    ts = []
     for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         out = fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps, out
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), out
 
 
 def main():

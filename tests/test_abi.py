@@ -60,6 +60,6 @@ def test_workspace_sizes():
 def test_struct_layouts():
     import ctypes
     assert ctypes.sizeof(lpr.GridOpts) == 32
-    assert ctypes.sizeof(lpr.AssignOpts) == 48
+    assert ctypes.sizeof(lpr.AssignOpts) == 64
     assert ctypes.sizeof(lpr.GridStats) == 8 * 8 + 4 * 4 + 3 * 8
     assert ctypes.sizeof(lpr.AssignStats) == 8 * 8 + 2 * 8

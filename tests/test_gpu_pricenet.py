@@ -1,7 +1,8 @@
 """GPU checks of the price network: features against the float64 oracle,
 forward and gradient against the oracle fed the same BF16-rounded inputs and
-weights (tolerance set by the bf16 mantissa, 2^-8), training reduces the
-loss, and warm-started solves stay exact."""
+weights (forward tolerance set by the bf16 mantissa, 2^-8; the gradient's by
+the error bf16 operand rounding alone causes in float64), training reduces
+the loss, and warm-started solves stay exact."""
 import numpy as np
 import pytest
 
@@ -31,6 +32,42 @@ def _cpu_inputs(theta32, feats_gpu, offs):
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _loss_and_grad_bf16_operands(theta, feats_list, targets):
+    """The oracle's loss and gradient with the hidden activations and the
+    back-propagated pre-activation gradients rounded to bf16 where they enter
+    a product, as the GPU's BF16 GEMM operands are: the error this rounding
+    alone causes sets the scale of the gradient comparison (it grows when the
+    residual's contributions cancel)."""
+    B = P.bf16_round
+    Pp = P.unpack(theta)
+    N = sum(len(t) for t in targets)
+    grads = [np.zeros_like(x) for x in Pp]
+    for X, t in zip(feats_list, targets):
+        H = B(X)
+        cache = []
+        for l in range(3):
+            W, U, b = Pp[3 * l], Pp[3 * l + 1], Pp[3 * l + 2]
+            Z = H @ W + H.mean(axis=0, keepdims=True) @ U + b[None, :]
+            cache.append((H, Z))
+            H = B(np.maximum(Z, 0.0))
+        q = H @ Pp[9] + Pp[10][0]
+        r = (q - q.mean()) - (np.asarray(t, np.float64) - np.mean(t))
+        dq = 2.0 * r / N
+        grads[9] += H.T @ dq
+        grads[10][0] += dq.sum()
+        dH = np.outer(dq, Pp[9])
+        for l in (2, 1, 0):
+            W, U = Pp[3 * l], Pp[3 * l + 1]
+            Hin, Z = cache[l]
+            dZ = dH * (Z > 0)
+            n = Hin.shape[0]
+            grads[3 * l] += Hin.T @ B(dZ)
+            grads[3 * l + 1] += np.outer(Hin.mean(axis=0), dZ.sum(axis=0))
+            grads[3 * l + 2] += dZ.sum(axis=0)
+            dH = B(dZ) @ W.T + np.outer(np.ones(n), dZ.sum(axis=0) @ U.T) / n
+    return np.concatenate([g.ravel() for g in grads])
 
 
 def test_features_match_oracle():
@@ -66,11 +103,14 @@ def test_forward_and_gradient_match_oracle():
     offs = packed.row_offset
     for k in range(len(mats)):
         assert rel(q_gpu[offs[k]:offs[k + 1]], q_cpu[k]) < 3e-2
-    # targets: the solver's own prices for each instance
+    # targets: optimal column prices in the solver's scaled convention from
+    # the oracle's sequential cost scaling (optimal duals are not unique; fixed
+    # oracle duals keep this check of the backward pass independent of the
+    # GPU solver's schedule)
     tp = []
     for m in mats:
-        _, _, p, _ = lpr.lpr_assign_solve(m)
-        tp.append(p)
+        _, _, p, _ = oracle.cost_scaling(m)
+        tp.append(torch.as_tensor(p, device="cuda"))
     tgt = torch.cat(tp)
     loss, grad = lpr.lpr_pricenet_train_step(packed, tgt, params, step=0,
                                              want_grad=True)
@@ -83,13 +123,17 @@ def test_forward_and_gradient_match_oracle():
     L_cpu, g_cpu = P.loss_and_grad(th, feats, targets)
     assert abs(loss - L_cpu) <= 3e-2 * L_cpu
     g_gpu = grad.cpu().numpy().astype(np.float64)
-    assert rel(g_gpu, g_cpu) < 5e-2
+    g_emu = _loss_and_grad_bf16_operands(th, feats, targets)
+    # within a small multiple of what bf16 operand rounding alone causes (the
+    # GPU also rounds its transposed copies and sums in another order)
+    assert rel(g_gpu, g_cpu) < 2.5 * rel(g_emu, g_cpu) + 5e-3
     # every parameter block, not just the norm of the whole vector
     off = 0
     for name, shape in P.param_shapes():
         size = int(np.prod(shape))
         if name != "bo":
-            assert rel(g_gpu[off:off + size], g_cpu[off:off + size]) < 8e-2, name
+            a, b = g_gpu[off:off + size], g_cpu[off:off + size]
+            assert rel(a, b) < 2.5 * rel(g_emu[off:off + size], b) + 1e-2, name
         off += size
 
 
