@@ -71,6 +71,8 @@ const char *lpr_version(void);
 /* Option flags for lpr_grid_opts.flags. */
 #define LPR_GRID_TIME_KERNELS 0x1 /* time every push-sweep and BFS launch
                                      with HIP events into lpr_grid_stats */
+#define LPR_GRID_NO_GRAPH 0x2     /* launch every round's kernels one by one
+                                     instead of replaying a captured graph */
 
 typedef struct {
     int32_t sweeps_per_relabel; /* push-sweep launches between global
@@ -98,10 +100,11 @@ typedef struct {
     int64_t relabels;        /* relabel operations                          */
     int64_t cut_passes;      /* tile-relaxation launches of the cut closure */
     int64_t tiles_relaxed;   /* tiles processed by the BFS relaxation       */
-    int32_t tile_rows;       /* tile height actually used                   */
+    int32_t tile_rows;       /* push-sweep tile height actually used        */
     int32_t local_iters;     /* local iterations actually used              */
     int32_t sweeps_per_relabel;
-    int32_t reserved;
+    int32_t relax_tile_rows; /* tile height of the relaxation passes (the
+                                tiles counted by tiles_relaxed; width 64)   */
     double sweep_ms;         /* with LPR_GRID_TIME_KERNELS: summed duration
                                 of all push-sweep launches (HIP events)    */
     double bfs_ms;           /* same, for the BFS relaxation launches       */

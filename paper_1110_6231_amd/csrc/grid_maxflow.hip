@@ -55,7 +55,7 @@ constexpr int TW = 64;        // tile width: one wavefront per tile row
 constexpr int NT = 256;       // threads per tile workgroup
 constexpr int RPP = NT / TW;  // tile rows covered per thread pass (4)
 constexpr int MAX_PASS_SLOTS = 64;
-constexpr int RELAX_TH = 8;  // tile height of the relaxation kernels (BFS, cut)
+constexpr int RELAX_TH = 32;  // tile height of the relaxation kernels (BFS, cut)
 
 // Element at a 32-bit byte offset from a wave-uniform base: every per-pixel
 // array shares the offset, so the compiler keeps one VGPR per pixel instead of
@@ -180,11 +180,13 @@ __device__ inline Geo tile_geo(const Dev &D, int t) {
 // robin, so workgroup b takes tile group (its XCD's first group + b / 8): each
 // XCD gets one contiguous band of tiles, whose vertical neighbours share that
 // XCD's L2.
-__device__ __forceinline__ int wave_tile() {
+__device__ __forceinline__ int block_group() {
     const int nb = gridDim.x, b = blockIdx.x;
     const int q = nb >> 3, rem = nb & 7, xcd = b & 7;
-    const int group = xcd * q + min(xcd, rem) + (b >> 3);
-    return group * 4 + (threadIdx.x >> 6);
+    return xcd * q + min(xcd, rem) + (b >> 3);
+}
+__device__ __forceinline__ int wave_tile() {
+    return block_group() * 4 + (threadIdx.x >> 6);
 }
 
 // Loads the one-pixel halo of a tile's labels/heights into rows 0 and TH+1
@@ -335,34 +337,48 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 //     is the BFS level, |V| where t is unreachable (the gap of Section 4.2).
 //   CUT (CUT = true):  lab(p) = min(lab(p), lab(q)) over arcs q->p with
 //     u_f > 0 -- forward reachability from the excess pixels.
-// One wavefront per 64 x TH tile, no block barrier: lane c owns column c of
-// the tile in registers.  An iteration takes the horizontal neighbours'
-// current labels by cross-lane shuffles (lanes 0 and 63 use the halo
-// columns), then runs a downward and an upward pass along its column, which
-// settles every vertical path inside the tile at once.  Iterations repeat
-// until no label of the tile changes (a wavefront vote).  Labels only
-// decrease and every value read from a neighbouring tile is an upper bound
-// of its final value, so concurrent tiles reach the same least fixpoint.
-// ---------------------------------------------------------------------------
-template <int TH, bool CUT>
-__global__ __launch_bounds__(256) void k_relax(Dev D, int32_t *dirty_cur,
-                                              int32_t *dirty_next,
-                                              int32_t *pass_count) {
-    const int lane = threadIdx.x & 63;
-    const int t = wave_tile();
-    if (t >= D.ntiles_r) return;              // wave-uniform
-    if (dirty_cur[t] == 0) return;            // wave-uniform (same address)
-    if (lane == 0) dirty_cur[t] = 0;
-    const Geo g = tile_geo<TH, true>(D, t);
+// Labels only decrease and every value read from a neighbouring tile is an
+// upper bound of its final value, so concurrent tiles reach the same least
+// fixpoint; tiles whose edge labels changed mark their neighbours dirty for
+// the next pass.
+//
+// A pass runs on 64 x 32 tiles, four wavefronts per tile (one workgroup):
+// wavefront w holds rows 8w .. 8w+7 in registers (lane c owns column c) and
+// relaxes them to their local fixpoint: each row by two segmented min-plus
+// scans across the lanes (a label crosses the 64 columns in one step), then
+// a downward and an upward pass along the columns in registers; only rows a
+// column pass lowered are scanned again.  The rows where two wavefronts meet
+// are exchanged through LDS and the four relax again until a workgroup vote
+// finds no lowered boundary.  A label thus crosses 32 rows in one pass, with
+// the latency of an 8-row tile per wavefront.
+constexpr int RW = 8;  // rows per wavefront of the cooperative relaxation
+
+template <bool CUT>
+__global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
+                                               int32_t *dirty_next,
+                                               int32_t *pass_count) {
+    static_assert(RELAX_TH == 4 * RW, "four wavefronts per relaxation tile");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = block_group();
+    if (t >= D.ntiles_r) return;              // workgroup-uniform
+    const int flag = dirty_cur[t];
+    __shared__ int32_t edge[4][2][64];        // row 0 and row 7 of each wavefront
+    __shared__ int s_ch;
+    if (threadIdx.x == 0) s_ch = 0;
+    __syncthreads();                          // every thread has read the flag
+    if (flag == 0) return;                    // workgroup-uniform
+    if (threadIdx.x == 0) dirty_cur[t] = 0;
+    const Geo g = tile_geo<RELAX_TH, true>(D, t);
     constexpr int INC = CUT ? 0 : 1;
     const int HV = g.HV;
     const int x = g.x0 + lane;
     const bool colv = x < g.W;
-    int32_t d[TH], d0[TH];
+    const int yw = g.y0 + RW * w;             // first row of this wavefront
+    int32_t d[RW], d0[RW];
     uint32_t mR = 0, mL = 0, mD = 0, mU = 0;  // bit r: arc usable in row r
 #pragma unroll
-    for (int r = 0; r < TH; ++r) {
-        const int y = g.y0 + r;
+    for (int r = 0; r < RW; ++r) {
+        const int y = yw + r;
         d[r] = HV;
         if (colv && y < g.H) {
             const int64_t p = g.off + int64_t(y) * g.W + x;
@@ -381,23 +397,23 @@ __global__ __launch_bounds__(256) void k_relax(Dev D, int32_t *dirty_cur,
         }
         d0[r] = d[r];
     }
-    // halo: row above / below (every lane), column left (lane 0) / right (63)
-    int32_t top = HV, bot = HV, hside[TH];
-    if (colv && g.y0 > 0) top = D.h[g.off + int64_t(g.y0 - 1) * g.W + x];
-    if (colv && g.y0 + TH < g.H) bot = D.h[g.off + int64_t(g.y0 + TH) * g.W + x];
+    // halo: the tile's row above / below (wavefronts 0 / 3), columns left and
+    // right (lanes 0 / 63); the rows between wavefronts come from LDS
+    int32_t top = HV, bot = HV, hside[RW];
+    if (w == 0 && colv && g.y0 > 0) top = D.h[g.off + int64_t(g.y0 - 1) * g.W + x];
+    if (w == 3 && colv && g.y0 + RELAX_TH < g.H)
+        bot = D.h[g.off + int64_t(g.y0 + RELAX_TH) * g.W + x];
     const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
 #pragma unroll
-    for (int r = 0; r < TH; ++r) {
-        const int y = g.y0 + r;
+    for (int r = 0; r < RW; ++r) {
+        const int y = yw + r;
         hside[r] = HV;
         if ((lane == 0 || lane == 63) && hx >= 0 && hx < g.W && y < g.H)
             hside[r] = D.h[g.off + int64_t(y) * g.W + hx];
     }
-    // Segment lengths of the horizontal scans, fixed for the whole pass:
-    // low byte x - s(x), high byte e(x) - x (see scan_from_left/right).
-    int32_t seg[TH];
+    int32_t seg[RW];
 #pragma unroll
-    for (int r = 0; r < TH; ++r) {
+    for (int r = 0; r < RW; ++r) {
         const uint64_t brkL = __ballot(!((mL >> r) & 1u)) | 1ull;
         const uint64_t brkR = __ballot(!((mR >> r) & 1u)) | (1ull << 63);
         const uint64_t low = lane == 63 ? ~0ull : (2ull << lane) - 1;
@@ -405,55 +421,81 @@ __global__ __launch_bounds__(256) void k_relax(Dev D, int32_t *dirty_cur,
         const int ex = lane + __ffsll((unsigned long long)(brkR >> lane)) - 1;
         seg[r] = (lane - sx) | ((ex - lane) << 8);
     }
-    // A row needs its horizontal scans again only after a column pass lowered
-    // one of its values (after both scans a row is at its own fixpoint).
-    uint32_t rows = TH == 32 ? ~0u : (1u << TH) - 1;  // wave-uniform
-    while (rows) {
+    edge[w][0][lane] = d[0];
+    edge[w][1][lane] = d[RW - 1];
+    __syncthreads();
+    if (w > 0) top = edge[w - 1][1][lane];
+    if (w < 3) bot = edge[w + 1][0][lane];
+    uint32_t rows = (1u << RW) - 1;           // wavefront-uniform
+    for (;;) {
+        __syncthreads();                      // the edges above were read
+        while (rows) {
 #pragma unroll
-        for (int r = 0; r < TH; ++r) {
-            if (!((rows >> r) & 1u)) continue;
-            int32_t nd = d[r];
-            if (lane == 0 && (mL >> r) & 1u) nd = min(nd, hside[r] + INC);
-            if (lane == 63 && (mR >> r) & 1u) nd = min(nd, hside[r] + INC);
-            nd = scan_from_left(nd - INC * lane, seg[r] & 0xff, lane) + INC * lane;
-            nd = scan_from_right(nd + INC * lane, seg[r] >> 8, lane) - INC * lane;
-            d[r] = nd;
-        }
-        rows = 0;
-        // columns: down, then up
+            for (int r = 0; r < RW; ++r) {
+                if (!((rows >> r) & 1u)) continue;
+                int32_t nd = d[r];
+                if (lane == 0 && (mL >> r) & 1u) nd = min(nd, hside[r] + INC);
+                if (lane == 63 && (mR >> r) & 1u) nd = min(nd, hside[r] + INC);
+                nd = scan_from_left(nd - INC * lane, seg[r] & 0xff, lane) + INC * lane;
+                nd = scan_from_right(nd + INC * lane, seg[r] >> 8, lane) - INC * lane;
+                d[r] = nd;
+            }
+            rows = 0;
 #pragma unroll
-        for (int r = 0; r < TH; ++r) {
-            const int32_t up = r == 0 ? top : d[r - 1];
-            const int32_t nd = (mU >> r) & 1u ? min(d[r], up + INC) : d[r];
-            if (__any(nd < d[r])) rows |= 1u << r;
-            d[r] = nd;
-        }
+            for (int r = 0; r < RW; ++r) {
+                const int32_t up = r == 0 ? top : d[r - 1];
+                const int32_t nd = (mU >> r) & 1u ? min(d[r], up + INC) : d[r];
+                if (__any(nd < d[r])) rows |= 1u << r;
+                d[r] = nd;
+            }
 #pragma unroll
-        for (int r = TH - 1; r >= 0; --r) {
-            const int32_t dn = r == TH - 1 ? bot : d[r + 1];
-            const int32_t nd = (mD >> r) & 1u ? min(d[r], dn + INC) : d[r];
-            if (__any(nd < d[r])) rows |= 1u << r;
-            d[r] = nd;
+            for (int r = RW - 1; r >= 0; --r) {
+                const int32_t dn = r == RW - 1 ? bot : d[r + 1];
+                const int32_t nd = (mD >> r) & 1u ? min(d[r], dn + INC) : d[r];
+                if (__any(nd < d[r])) rows |= 1u << r;
+                d[r] = nd;
+            }
         }
+        edge[w][0][lane] = d[0];
+        edge[w][1][lane] = d[RW - 1];
+        __syncthreads();
+        if (w > 0) {
+            const int32_t v = edge[w - 1][1][lane];
+            if (__any(v < top)) rows |= 1u;
+            top = min(top, v);
+        }
+        if (w < 3) {
+            const int32_t v = edge[w + 1][0][lane];
+            if (__any(v < bot)) rows |= 1u << (RW - 1);
+            bot = min(bot, v);
+        }
+        if (!__syncthreads_or(rows != 0)) break;
     }
     bool ch_top = false, ch_bot = false, ch_col = false;
 #pragma unroll
-    for (int r = 0; r < TH; ++r) {
+    for (int r = 0; r < RW; ++r) {
         if (d[r] == d0[r]) continue;
-        D.h[g.off + int64_t(g.y0 + r) * g.W + x] = d[r];
+        D.h[g.off + int64_t(yw + r) * g.W + x] = d[r];
         ch_col = true;
-        if (r == 0) ch_top = true;
-        if (r == TH - 1) ch_bot = true;
+        if (w == 0 && r == 0) ch_top = true;
+        if (w == 3 && r == RW - 1) ch_bot = true;
     }
     const bool e_top = __any(ch_top), e_bot = __any(ch_bot);
     const bool e_left = __any(lane == 0 && ch_col), e_right = __any(lane == 63 && ch_col);
     if (lane == 0) {
+        const int bits = (e_right ? 1 : 0) | (e_left ? 2 : 0) | (e_bot ? 4 : 0) |
+                         (e_top ? 8 : 0);
+        if (bits) atomicOr(&s_ch, bits);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int bits = s_ch;
         atomicAdd(&D.counters[CUT ? 4 : 3], 1ull);
         int nb[4] = {-1, -1, -1, -1};
-        if (e_right && g.tx + 1 < g.tiles_x) nb[0] = t + 1;
-        if (e_left && g.tx > 0) nb[1] = t - 1;
-        if (e_bot && g.ty + 1 < g.tiles_y) nb[2] = t + g.tiles_x;
-        if (e_top && g.ty > 0) nb[3] = t - g.tiles_x;
+        if ((bits & 1) && g.tx + 1 < g.tiles_x) nb[0] = t + 1;
+        if ((bits & 2) && g.tx > 0) nb[1] = t - 1;
+        if ((bits & 4) && g.ty + 1 < g.tiles_y) nb[2] = t + g.tiles_x;
+        if ((bits & 8) && g.ty > 0) nb[3] = t - g.tiles_x;
         for (int i = 0; i < 4; ++i)
             if (nb[i] >= 0 && atomicExch(&dirty_next[nb[i]], 1) == 0)
                 atomicAdd(pass_count, 1);
@@ -808,12 +850,12 @@ struct Kern {
     static void cut_seed(hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
         hipLaunchKernelGGL(k_cut_seed<RELAX_TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D, a, b);
     }
-    // one wavefront per tile, four tiles per 256-thread block
+    // one 4-wavefront workgroup per relaxation tile
     static void relax(bool cut, hipStream_t s, const Dev &D, int32_t *a, int32_t *b,
                       int32_t *pc) {
-        const dim3 gw((D.ntiles_r + 3) / 4);
-        if (cut) hipLaunchKernelGGL((k_relax<RELAX_TH, true>), gw, dim3(NT), 0, s, D, a, b, pc);
-        else hipLaunchKernelGGL((k_relax<RELAX_TH, false>), gw, dim3(NT), 0, s, D, a, b, pc);
+        const dim3 gw(D.ntiles_r);
+        if (cut) hipLaunchKernelGGL((k_relax4<true>), gw, dim3(NT), 0, s, D, a, b, pc);
+        else hipLaunchKernelGGL((k_relax4<false>), gw, dim3(NT), 0, s, D, a, b, pc);
     }
     static void count(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
         hipLaunchKernelGGL(k_count<TH>, g, dim3(NT), 0, s, D, a, b);
@@ -831,7 +873,7 @@ struct Kern {
 
 struct Params {
     int TH, L, K, max_rounds;
-    bool timing;
+    bool timing, no_graph;
 };
 
 // Runs relaxation passes until no tile is dirty.  Pass counters are cleared
@@ -1051,7 +1093,7 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
     LPR_TRY(enqueue_count<TH>(s, D, Lw, grid, B, nullptr));
     Scalars *host = nullptr;
     LPR_TRY(read_scalars<TH>(s, Lw, &host));
-    const bool use_graph = !P.timing && (P.K % 2 == 0);
+    const bool use_graph = !P.timing && !P.no_graph && (P.K % 2 == 0);
     bool converged = false;
     for (;;) {
         if (host->total_active == 0) {
@@ -1142,6 +1184,7 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
         stats->tile_rows = TH;
         stats->local_iters = P.L;
         stats->sweeps_per_relabel = P.K;
+        stats->relax_tile_rows = RELAX_TH;
         stats->sweep_ms = sweep_ms;
         stats->bfs_ms = bfs_ms;
     }
@@ -1256,12 +1299,14 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     P.K = ds.K;
     P.max_rounds = 1 << 16;
     P.timing = false;
+    P.no_graph = false;
     if (opts) {
         if (opts->tile_rows) P.TH = opts->tile_rows;
         if (opts->local_iters) P.L = opts->local_iters;
         if (opts->sweeps_per_relabel) P.K = opts->sweeps_per_relabel;
         if (opts->max_rounds) P.max_rounds = opts->max_rounds;
         P.timing = (opts->flags & LPR_GRID_TIME_KERNELS) != 0;
+        P.no_graph = (opts->flags & LPR_GRID_NO_GRAPH) != 0;
     }
     if (!(P.TH == 4 || P.TH == 8 || P.TH == 16 || P.TH == 32) || P.L < 1 || P.L > 4096 ||
         P.K < 1 || P.K > 4096 || P.max_rounds < 1) {

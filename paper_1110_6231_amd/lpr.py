@@ -24,6 +24,7 @@ LPR_GRID_MAX_CAP = (1 << 26) - 1
 LPR_ASSIGN_MAX_COST = (1 << 24) - 1
 LPR_ASSIGN_MAX_N = 2048
 LPR_GRID_TIME_KERNELS = 0x1
+LPR_GRID_NO_GRAPH = 0x2
 LPR_ASSIGN_TIME_KERNELS = 0x1
 LPR_ASSIGN_NO_START_UPDATE = 0x2
 
@@ -65,7 +66,7 @@ class GridStats(ctypes.Structure):
                 ("tiles_relaxed", ctypes.c_int64),
                 ("tile_rows", ctypes.c_int32), ("local_iters", ctypes.c_int32),
                 ("sweeps_per_relabel", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("relax_tile_rows", ctypes.c_int32),
                 ("sweep_ms", ctypes.c_double), ("bfs_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double)]
 

@@ -93,6 +93,23 @@ def test_alpha_eps_and_warm_start():
     check(c, opts=lpr.make_assign_opts(init_col_prices=garbage))
 
 
+@pytest.mark.parametrize("tail,flags,period", [
+    (1, 0, 0), (2, lpr.LPR_ASSIGN_NO_START_UPDATE, 0), (64, 0, 1),
+    (4096, 0, 0), (8, 0, -1), (0, lpr.LPR_ASSIGN_NO_START_UPDATE, -1),
+    (16, 0, 37)])
+def test_schedule_options_stay_exact(tail, flags, period):
+    """Serial-tail threshold (from every row to the whole refine), the
+    refine-start price update on or off, and price updates after every push,
+    never, or at an odd period: all are admissible schedules of the same
+    operations, so the optimum and its certificate must not change."""
+    opts = lpr.make_assign_opts(tail_rows=tail, flags=flags,
+                                price_update_period=period)
+    check(synth.assign_points(257, seed=6, instance=3), opts=opts)
+    check(synth.assign_random_small(130, seed=9, lo=0, hi=300), maximize=True,
+          opts=opts)
+    check(synth.assign_random_small(7, seed=2, lo=-5, hi=5), opts=opts)
+
+
 def test_batched():
     mats = [synth.assign_points(n, seed=1, instance=k + 1)
             for k, n in enumerate([64, 300, 129, 512, 77, 200])]

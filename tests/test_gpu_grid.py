@@ -65,6 +65,12 @@ def test_schedules(K, L):
                                                   local_iters=L))
 
 
+def test_rounds_without_graph_replay():
+    inst = synth.grid_blobs(180, 140, seed=6)
+    check_against_oracle(inst, lpr.make_grid_opts(flags=lpr.LPR_GRID_NO_GRAPH))
+    check_against_oracle(inst, lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS))
+
+
 def test_blobs_medium_and_long_paths():
     check_against_oracle(synth.grid_blobs(256, 300, seed=2))
     check_against_oracle(synth.grid_blobs(200, 260, seed=3, pair_scale=200.0))
