@@ -101,10 +101,13 @@ def grid_leg(args, torch, lpr, synth):
             acc["tiles_relaxed"] * st["relax_tile_rows"] * 64 * RELAX_BYTES_PER_PIXEL),
     }
     dominant = max(legs, key=lambda k: legs[k]["total_ms"])
+    for name, leg in legs.items():
+        leg["traffic"] = traffic_for(name, st["tile_rows"])  # HBM bytes per launch
+        leg["traffic_GBps"] = (None if leg["traffic"] is None else
+                               round(leg["traffic"] / (leg["avg_launch_us"] * 1e-6) / 1e9, 1))
     roof = dict(legs[dominant])
     roof["kernel"] = dominant
-    roof["traffic"] = traffic_for(dominant, st["tile_rows"])
-    others = {k: v for k, v in legs.items() if k != dominant}
+    others = {name: leg for name, leg in legs.items() if name != dominant}
     return dict(inst=inst, flow=v, ms=ms, HW=HW, stats=st, roofline=roof,
                 other_kernels=others)
 
@@ -114,7 +117,12 @@ def grid_leg(args, torch, lpr, synth):
 # what the same counters read for a plain copy of known size (FETCH_SIZE
 # x 2.0, WRITE_SIZE x 1.0).  Each entry holds the sha256 of the kernel's
 # source file at measurement time; a changed source reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "k_relax4<false>": {"source_sha256": "3b108c51f5d6dd5c17cb9407fc70faffa7520b1768c33675ec5db94708618154",
+                  "bytes_per_launch": 5231332},  # FETCH 2476.6 KiB, WRITE 156.0 KiB
+    "k_sweep<8>": {"source_sha256": "3b108c51f5d6dd5c17cb9407fc70faffa7520b1768c33675ec5db94708618154",
+                  "bytes_per_launch": 12641226},  # FETCH 3613.7 KiB, WRITE 5118.2 KiB
+}
 
 
 def source_sha(path):
