@@ -296,7 +296,7 @@ def cpu_leg(args, inst):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} "
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} "
               "is not supported (the batched workloads would shard by "
               "instance across GPUs)", file=sys.stderr)
         sys.exit(2)

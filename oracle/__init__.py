@@ -1,7 +1,7 @@
 """CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
 
 Plain, slow, obviously correct CPU implementations of what the GPU library
-computes.  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+computes.  Only ``tests/``, the smoke check and the benchmark's
 ``cpu_baseline`` leg may import this package; the product path
 (``paper_1110_6231_amd``) never does, and no code is shared between the two
 (only the seeded generators in ``synth`` feed both).
