@@ -475,6 +475,94 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
     __syncthreads();
 }
 
+constexpr int HOT = 64;  // columns with e(y) >= HOT are resolved by the workgroup
+
+// The same operation as resolve_column for a column with many matched rows
+// (every row preferring one column makes e(y) ~ n, and the one-thread list
+// walk per push-back is then quadratic), by the whole workgroup: the matched
+// rows are gathered from mate[], bitonic-sorted by b(x) descending (ties:
+// smaller x first) -- exactly the order resolve_column pushes them back in --
+// and one thread then applies the relabels of that sequence; the first
+// e(y) rows are pushed back (appended to the row list at *nx) and the last
+// one stays.  `idx` is LDS scratch for 2n ints.  Called by every thread.
+__device__ bool resolve_hot(int y, int64_t eps, const Shared &L, int32_t *idx,
+                            int n, int *nx, int tid, unsigned long long &pushes,
+                            unsigned long long &relabels) {
+    __shared__ int s_k, s_base, s_bad;
+    __shared__ unsigned long long s_rel;
+    if (tid == 0) {
+        s_k = 0;
+        s_bad = 0;
+        s_rel = 0;
+    }
+    __syncthreads();
+    for (int x = tid; x < n; x += NT)
+        if (L.mate[x] == y) idx[atomicAdd(&s_k, 1)] = x;
+    __syncthreads();
+    const int k = s_k;
+    int m = 1;
+    while (m < k) m <<= 1;
+    for (int i = k + tid; i < m; i += NT) idx[i] = -1;  // padding sorts last
+    __syncthreads();
+    // a goes before b: larger b(x), then smaller x; padding last
+    auto before = [&](int a, int b) {
+        if (a < 0) return false;
+        if (b < 0) return true;
+        const int64_t ba = L.bv[a], bb = L.bv[b];
+        return ba > bb || (ba == bb && a < b);
+    };
+    for (int size = 2; size <= m; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < (m >> 1); i += NT) {
+                const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));
+                const int hi = lo + stride;
+                const int a = idx[lo], b = idx[hi];
+                const bool up = (lo & size) == 0;
+                if (up ? before(b, a) : before(a, b)) {
+                    idx[lo] = b;
+                    idx[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    if (tid == 0) {
+        if (k < 2 || k != L.ey[y] + 1) {
+            s_bad = 1;
+        } else {
+            int64_t p = L.py[y];
+            unsigned long long rel = 0;
+            for (int i = 0; i < k - 1; ++i) {
+                const int64_t b = L.bv[idx[i]];
+                if (!(b > p)) {  // not admissible: relabel p(y) = b - eps
+                    p = b - eps;
+                    ++rel;
+                }
+            }
+            L.py[y] = p;
+            const int keep = idx[k - 1];
+            L.head[y] = keep;
+            L.nxt[keep] = -1;
+            L.ey[y] = 0;
+            s_base = atomicAdd(nx, k - 1);
+            s_rel = rel;
+        }
+    }
+    __syncthreads();
+    if (s_bad) return false;
+    const int base = s_base;
+    for (int i = tid; i < k - 1; i += NT) {
+        const int x = idx[i];
+        L.mate[x] = -1;
+        L.xl[base + i] = x;
+    }
+    if (tid == 0) {
+        pushes += (unsigned long long)(k - 1);
+        relabels += s_rel;
+    }
+    __syncthreads();
+    return true;
+}
+
 template <typename T>
 __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                                const T *__restrict__ C,
@@ -504,7 +592,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     // barrier cost does not
     const int tail_enter = A.tail_rows > 0 ? A.tail_rows : min(32, max(8, 8192 / n));
     const int tail_exit = max(TAIL_EXIT, 4 * tail_enter);
-    __shared__ int s_nx, s_ny, s_stop, s_qh;
+    __shared__ int s_nx, s_ny, s_stop, s_qh, s_nh;
     __shared__ unsigned long long s_pu_mark;  // pushes at the last price update
     __shared__ unsigned long long s_cnt[6];
 
@@ -518,6 +606,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
         s_ny = 0;
         s_stop = 0;
         s_qh = 0;
+        s_nh = 0;
         s_pu_mark = 0;
     }
     for (int y = tid; y < n; y += NT)
@@ -570,12 +659,25 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             // ---- Y phase: active columns push surplus rows back ----
             const int ny = s_ny;
             unsigned long long my_push = 0, my_rel = 0;
+            int32_t *hot = reinterpret_cast<int32_t *>(U.ly);  // free outside updates
             for (int j = tid; j < ny; j += NT) {
+                const int y = L.yl[j];
+                if (L.ey[y] >= HOT) {
+                    hot[atomicAdd(&s_nh, 1)] = y;
+                    continue;
+                }
                 const bool ok = resolve_column(
-                    L.yl[j], eps, L, my_push, my_rel,
+                    y, eps, L, my_push, my_rel,
                     [&](int bx) { L.xl[atomicAdd(&s_nx, 1)] = bx; });
                 if (!ok) atomicOr(&s_stop, 2);
             }
+            __syncthreads();
+            const int nh = s_nh;
+            for (int j = 0; j < nh; ++j)
+                if (!resolve_hot(hot[j], eps, L, reinterpret_cast<int32_t *>(U.lx), n,
+                                 &s_nx, tid, my_push, my_rel) &&
+                    tid == 0)
+                    atomicOr(&s_stop, 2);
             if (my_push) atomicAdd(&s_cnt[2], my_push);
             if (my_rel) atomicAdd(&s_cnt[3], my_rel);
             __syncthreads();
@@ -583,6 +685,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             if (tid == 0) {
                 s_ny = 0;
                 s_qh = 0;
+                s_nh = 0;
                 atomicAdd(&s_cnt[1], 1ull);
                 if ((long long)(s_cnt[2] + s_cnt[3]) > A.max_ops ||
                     wall_clock64() - t_start > A.max_ticks)

@@ -110,6 +110,38 @@ def test_schedule_options_stay_exact(tail, flags, period):
     check(synth.assign_random_small(7, seed=2, lo=-5, hi=5), opts=opts)
 
 
+def test_maximum_size_n2048():
+    """n = LPR_ASSIGN_MAX_N (the largest LDS footprint).  The Hungarian oracle
+    is too slow here, so the checks are a closed form and the certificate:
+    for c = a_i b_j the minimum pairs a ascending with b descending
+    (rearrangement inequality), and for random costs the returned prices must
+    certify 1-optimality of the returned permutation, which proves it
+    optimal without the oracle."""
+    n = lpr.LPR_ASSIGN_MAX_N
+    g = np.random.default_rng(11)
+    a, b = g.integers(0, 180, n), g.integers(0, 180, n)
+    c = np.outer(a, b).astype(np.int32)
+    print("[assign] n=2048 rank one", flush=True)
+    r2c, tot, prices, _ = lpr.lpr_assign_solve(c)
+    assert tot == int((np.sort(a) * np.sort(b)[::-1]).astype(np.int64).sum())
+    assert is_permutation(r2c.cpu().numpy(), n)
+    assert scaled_eps_certificate(c, r2c.cpu().numpy(), prices.cpu().numpy())
+    c = synth.assign_random_small(n, seed=12, lo=0, hi=5000)
+    print("[assign] n=2048 random", flush=True)
+    r2c, tot, prices, _ = lpr.lpr_assign_solve(c, maximize=True)
+    r2c = r2c.cpu().numpy()
+    assert is_permutation(r2c, n)
+    assert int(c[np.arange(n), r2c].astype(np.int64).sum()) == tot
+    assert scaled_eps_certificate(-c.astype(np.int64), r2c, prices.cpu().numpy())
+    # int32 costs (|c| >= 2^15 takes the int32 row scans, no price update)
+    c = synth.assign_random_small(n, seed=13, lo=0, hi=1 << 20)
+    print("[assign] n=2048 int32 costs", flush=True)
+    r2c, tot, prices, _ = lpr.lpr_assign_solve(c)
+    r2c = r2c.cpu().numpy()
+    assert is_permutation(r2c, n)
+    assert scaled_eps_certificate(c, r2c, prices.cpu().numpy())
+
+
 def test_batched():
     mats = [synth.assign_points(n, seed=1, instance=k + 1)
             for k, n in enumerate([64, 300, 129, 512, 77, 200])]
