@@ -110,6 +110,16 @@ def test_schedule_options_stay_exact(tail, flags, period):
     check(synth.assign_random_small(7, seed=2, lo=-5, hi=5), opts=opts)
 
 
+def test_costs_at_the_limit():
+    """|c| up to LPR_ASSIGN_MAX_COST (2^24 - 1): the int32 row scans, scaled
+    costs near 2^36 and prices in int64; totals must match the oracle."""
+    big = lpr.LPR_ASSIGN_MAX_COST
+    for n, seed in ((40, 1), (130, 2)):
+        c = synth.assign_random_small(n, seed=seed, lo=-big, hi=big)
+        check(c)
+        check(c, maximize=True)
+
+
 def test_maximum_size_n2048():
     """n = LPR_ASSIGN_MAX_N (the largest LDS footprint).  The Hungarian oracle
     is too slow here, so the checks are a closed form and the certificate:

@@ -146,6 +146,26 @@ def test_full_size_graph_cut_1024():
     assert grid_cut_value(inst, side) == v
 
 
+def test_capacities_at_the_limit():
+    """Every capacity near LPR_GRID_MAX_CAP (2^26 - 1): a pixel's excess can
+    reach five times that, close to the int32 range, and heights stay below
+    the packed-key range; the flow value (int64) and S_min must still match
+    the oracle."""
+    big = lpr.LPR_GRID_MAX_CAP
+    inst = synth.grid_random_small(45, 77, seed=21, max_cap=big, max_term=big,
+                                   density=1.0)
+    st = check_against_oracle(inst)
+    print("[grid] limit caps", st, flush=True)
+    z = np.zeros(9, np.int32)
+    full = np.full(9, big, np.int32)
+    # a pixel fed at the limit from the source and all four neighbours
+    src = full.copy()
+    snk = z.copy()
+    snk[4] = big
+    inst = synth.GridInstance(3, 3, src, snk, full, full, full, full, "star")
+    check_against_oracle(inst)
+
+
 def test_errors():
     inst = synth.grid_uniform(20, 20, seed=0)
     arrs = [a.copy() for a in inst.arrays()]
