@@ -254,7 +254,8 @@ typedef struct {
     int64_t relabels;   /* relabel operations                             */
     int64_t scans;      /* arc scans of X rows (each reads n costs)       */
     int64_t price_updates; /* global price updates (Algorithm 5.3)        */
-    int64_t reserved[2];
+    int64_t price_update_us; /* time inside them, summed over instances   */
+    int64_t reserved;
     double kernel_ms;   /* with LPR_ASSIGN_TIME_KERNELS: solve kernel time */
     double total_ms;    /* device time of the whole call (HIP events)      */
 } lpr_assign_stats;

@@ -88,7 +88,7 @@ struct AArgs {
     int32_t pu_start;              // price update after each refine's first push
     uint64_t max_ticks;            // wall-clock budget in wall_clock64 ticks
     unsigned long long *counters;  // refines, phases, pushes, relabels, scans,
-                                   // price updates
+                                   // price updates, wall-clock ticks in them
     int32_t *status;  // per instance: 0 ok, 1 budget, 2 range, 3 internal
 };
 
@@ -373,10 +373,18 @@ struct PU {
 __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
                              const int16_t *__restrict__ CT, int n, int64_t sgnS,
                              int64_t eps, int tid) {
-    __shared__ int s_rem, s_nf, s_again;
-    __shared__ unsigned long long s_lev;
+    // per-level shared values, double-buffered by level parity so that no
+    // barrier is spent resetting them and every read precedes the next write:
+    // frontier size, active nodes scanned, next level
+    __shared__ int s_rem, s_nf[2], s_dec[2];
+    __shared__ unsigned long long s_next[2];
     constexpr int64_t NONE = LLONG_MAX;
-    if (tid == 0) s_rem = 0;
+    if (tid == 0) {
+        s_rem = 0;
+        s_nf[0] = 0;
+        s_dec[0] = 0;
+        s_next[0] = ULLONG_MAX;
+    }
     __syncthreads();
     int rem = 0;
     for (int x = tid; x < n; x += NT) {
@@ -390,22 +398,25 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
         rem += L.ey[y] >= 1;
     }
     if (rem) atomicAdd(&s_rem, rem);
+    __syncthreads();
+    int left = s_rem;  // active nodes not scanned yet (same in every thread)
     int64_t level = 0;
+    int par = 0;
     for (;;) {
-        if (tid == 0) {
-            s_nf = 0;
-            s_again = 0;
-        }
-        __syncthreads();
         // columns labelled `level`
         for (int y = tid; y < n; y += NT)
             if (!U.fy[y] && U.ly[y] == level) {
                 U.fy[y] = 1;
-                fl[atomicAdd(&s_nf, 1)] = y;
-                if (L.ey[y] >= 1) atomicSub(&s_rem, 1);
+                fl[atomicAdd(&s_nf[par], 1)] = y;
+                if (L.ey[y] >= 1) atomicAdd(&s_dec[par], 1);
             }
         __syncthreads();
-        const int nf = s_nf;
+        if (tid == 0) {  // the other parity's slots are read by nobody now
+            s_nf[par ^ 1] = 0;
+            s_dec[par ^ 1] = 0;
+            s_next[par ^ 1] = ULLONG_MAX;
+        }
+        const int nf = s_nf[par];
         if (nf > 0) {
             for (int x = tid; x < n; x += NT) {
                 if (U.fx[x]) continue;
@@ -414,25 +425,41 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
                 int64_t bound = best == NONE ? NONE : mul_sat(eps, best - level - 1);
                 const int64_t pxx = L.px[x];
                 const int mx = L.mate[x];
-                for (int j = 0; j < nf; ++j) {
-                    const int y = fl[j];
-                    const int64_t cp = int64_t(CT[int64_t(y) * n + x]) * sgnS + pxx - L.py[y];
-                    if (cp < bound && y != mx) {
-                        best = level + floor_div(cp, eps) + 1;
-                        bound = mul_sat(eps, best - level - 1);
+                // eight column loads in flight before any is used
+                for (int j0 = 0; j0 < nf; j0 += 8) {
+                    int cv[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        cv[k] = j0 + k < nf ? int(CT[int64_t(fl[j0 + k]) * n + x]) : 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        if (j0 + k >= nf) break;
+                        const int y = fl[j0 + k];
+                        const int64_t cp = int64_t(cv[k]) * sgnS + pxx - L.py[y];
+                        if (cp < bound && y != mx) {
+                            best = level + floor_div(cp, eps) + 1;
+                            bound = mul_sat(eps, best - level - 1);
+                        }
                     }
                 }
                 U.lx[x] = best;
             }
         }
         __syncthreads();
-        // rows labelled `level`
+        // rows labelled `level` offer their mates a label; at the same time
+        // the least label of any node still unscanned (including those
+        // offers) is the next bucket, `level` again if an offer equals it
+        unsigned long long m = ULLONG_MAX;
         for (int x = tid; x < n; x += NT) {
-            if (U.fx[x] || U.lx[x] != level) continue;
+            if (U.fx[x]) continue;
+            if (U.lx[x] != level) {
+                m = min(m, (unsigned long long)U.lx[x]);
+                continue;
+            }
             U.fx[x] = 1;
             const int y = L.mate[x];
             if (y < 0) {
-                atomicSub(&s_rem, 1);
+                atomicAdd(&s_dec[par], 1);
                 continue;
             }
             if (U.fy[y]) continue;
@@ -440,30 +467,23 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
             const int64_t cand = level + floor_div(L.py[y] - L.bv[x], eps) + 1;
             atomicMin(reinterpret_cast<unsigned long long *>(&U.ly[y]),
                       (unsigned long long)cand);
-            if (cand == level) s_again = 1;
+            m = min(m, (unsigned long long)cand);
         }
+        // a column's label only drops to an offer counted above, so a stale
+        // read here is still bounded by the true minimum
+        for (int y = tid; y < n; y += NT)
+            if (!U.fy[y]) m = min(m, (unsigned long long)U.ly[y]);
+        for (int o = 32; o > 0; o >>= 1)
+            m = min(m, (unsigned long long)__shfl_xor((long long)m, o, 64));
+        if ((tid & 63) == 0 && m != ULLONG_MAX) atomicMin(&s_next[par], m);
         __syncthreads();
-        // the bucket is emptied before the search may stop, so every node
-        // left unscanned has a label above `level`
-        const bool done = s_rem <= 0, again = s_again != 0;
-        if (!again) {
-            if (done) break;
-            if (tid == 0) s_lev = ULLONG_MAX;
-            __syncthreads();
-            unsigned long long m = ULLONG_MAX;
-            for (int x = tid; x < n; x += NT)
-                if (!U.fx[x]) m = min(m, (unsigned long long)U.lx[x]);
-            for (int y = tid; y < n; y += NT)
-                if (!U.fy[y]) m = min(m, (unsigned long long)U.ly[y]);
-            for (int o = 32; o > 0; o >>= 1)
-                m = min(m, (unsigned long long)__shfl_xor((long long)m, o, 64));
-            if ((tid & 63) == 0 && m != ULLONG_MAX) atomicMin(&s_lev, m);
-            __syncthreads();
-            const unsigned long long nl = s_lev;
-            if (nl >= (unsigned long long)NONE) break;  // nothing left to reach
-            level = int64_t(nl);
-        }
-        __syncthreads();  // every thread has read the flags before the reset
+        const unsigned long long next = s_next[par];
+        left -= s_dec[par];
+        if (next >= (unsigned long long)NONE) break;  // nothing left to reach
+        // stop once every active node is scanned and the bucket is empty
+        if (left <= 0 && int64_t(next) > level) break;
+        level = int64_t(next);
+        par ^= 1;
     }
     const int64_t far = level + 1;
     for (int x = tid; x < n; x += NT) {
@@ -594,13 +614,13 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     const int tail_exit = max(TAIL_EXIT, 4 * tail_enter);
     __shared__ int s_nx, s_ny, s_stop, s_qh, s_nh;
     __shared__ unsigned long long s_pu_mark;  // pushes at the last price update
-    __shared__ unsigned long long s_cnt[6];
+    __shared__ unsigned long long s_cnt[7];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t t_start = wall_clock64();
     const int64_t S = 2 * int64_t(n) + 1;
     const int64_t sgnS = int64_t(A.sign) * S;
-    if (tid < 6) s_cnt[tid] = 0;
+    if (tid < 7) s_cnt[tid] = 0;
     if (tid == 0) {
         s_nx = 0;
         s_ny = 0;
@@ -648,10 +668,12 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
         __syncthreads();
         if (CT && A.pu_start && s_ny > 0) {
             // every row is matched here, so the row list is free scratch
+            const uint64_t t0 = wall_clock64();
             price_update(L, U, L.xl, CT, n, sgnS, eps, tid);
             if (tid == 0) {
                 s_pu_mark = s_cnt[2];
                 atomicAdd(&s_cnt[5], 1ull);
+                atomicAdd(&s_cnt[6], (unsigned long long)(wall_clock64() - t0));
             }
             __syncthreads();
         }
@@ -695,10 +717,12 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             if (nx == 0 || s_stop) break;
             if (nx <= tail_enter) {
                 if (CT && s_cnt[2] - s_pu_mark >= period) {
+                    const uint64_t t0 = wall_clock64();
                     price_update(L, U, L.yl, CT, n, sgnS, eps, tid);
                     if (tid == 0) {
                         s_pu_mark = s_cnt[2];
                         atomicAdd(&s_cnt[5], 1ull);
+                        atomicAdd(&s_cnt[6], (unsigned long long)(wall_clock64() - t0));
                     }
                     __syncthreads();
                 }
@@ -814,7 +838,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             A.status[slot] = 0;
         }
     }
-    if (tid < 6 && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
+    if (tid < 7 && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
 }
 
 __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
@@ -978,8 +1002,9 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     A.pu_period = pu_period;
     A.tail_rows = tail_rows;
     A.pu_start = pu_start;
+    int khz = 0;  // wall_clock64 ticks per millisecond
     {
-        int dev = 0, khz = 0;
+        int dev = 0;
         LPR_TRY_HIP(hipGetDevice(&dev));
         LPR_TRY_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
         if (khz <= 0) khz = 100000;
@@ -1014,6 +1039,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         stats->relabels = int64_t(cnt[3]);
         stats->scans = int64_t(cnt[4]);
         stats->price_updates = int64_t(cnt[5]);
+        stats->price_update_us = int64_t(cnt[6] * 1000 / uint64_t(khz));
         stats->kernel_ms = kms;
         stats->total_ms = tms;
     }

@@ -86,7 +86,8 @@ class AssignStats(ctypes.Structure):
     _fields_ = [("refines", ctypes.c_int64), ("phases", ctypes.c_int64),
                 ("pushes", ctypes.c_int64), ("relabels", ctypes.c_int64),
                 ("scans", ctypes.c_int64), ("price_updates", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 2),
+                ("price_update_us", ctypes.c_int64),
+                ("reserved", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
