@@ -59,10 +59,23 @@ constexpr int NW = NT / 64;
 constexpr int TAIL_EXIT = 8;   // back to phases when the queue grows past
                                // max(this, 4 x the entry threshold)
 constexpr unsigned C16_MAX = 32767;
+// Row stride of the int16 copies: rows padded to a multiple of 8 entries so
+// that every row starts 16-byte aligned and is read with 16-byte loads.
+__host__ __device__ inline int ld16(int n) { return (n + 7) & ~7; }
+// Price of the padding columns of the int16 copies in the column-price
+// array: a padded entry's part-reduced cost c*S*sign - p is then ~2^62,
+// above every real one, so it never wins a row minimum.
+constexpr int64_t PAD_PRICE = -(int64_t(1) << 62);
+
+// Global-address-space views: loads through them are global (not flat)
+// memory instructions, which do not wait on the LDS counter.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) v4i *gv4i_p;
+typedef const __attribute__((address_space(1))) int32_t *gint32_p;
 
 struct AInst {
     int64_t cost_off;  // first cost entry of the instance (int32 input)
-    int64_t c16_off;   // first entry of its int16 copy (16-byte aligned)
+    int64_t c16_off;   // first entry of its int16 copies (n rows of ld16(n))
     int32_t n;
     int32_t row_off;   // offset of the instance in packed per-row outputs
 };
@@ -73,6 +86,7 @@ struct AArgs {
     const int32_t *costs;
     const int16_t *c16;
     const int16_t *c16t;  // transposed int16 copy (column y is contiguous)
+                          // both copies have row stride ld16(n)
     const unsigned *cmax;
     int32_t sign;      // +1 minimise c, -1 maximise (solve with c = -w)
     int32_t alpha;
@@ -92,21 +106,23 @@ struct AArgs {
     int32_t *status;  // per instance: 0 ok, 1 budget, 2 range, 3 internal
 };
 
-// max|c| per instance and the saturated int16 copy (used only when max|c|
-// fits).  grid = (blocks per instance, B).
+// max|c| per instance and the saturated int16 copy with row stride ld16(n)
+// (used only when max|c| fits; padding entries 0).  grid = (blocks per
+// instance, B); a block takes every gridDim.x-th row.
 __global__ __launch_bounds__(256) void k_prep(const AInst *inst,
                                               const int32_t *costs,
                                               int16_t *c16, unsigned *cmax) {
     const AInst I = inst[blockIdx.y];
-    const int64_t nn = int64_t(I.n) * I.n;
-    const int32_t *src = costs + I.cost_off;
-    int16_t *dst = c16 + I.c16_off;
+    const int n = I.n, ld = ld16(n);
     unsigned m = 0;
-    for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < nn;
-         k += int64_t(gridDim.x) * 256) {
-        const int32_t c = src[k];
-        m = max(m, c < 0 ? 0u - unsigned(c) : unsigned(c));
-        dst[k] = int16_t(max(-32768, min(32767, c)));
+    for (int r = blockIdx.x; r < n; r += gridDim.x) {
+        const int32_t *src = costs + I.cost_off + int64_t(r) * n;
+        int16_t *dst = c16 + I.c16_off + int64_t(r) * ld;
+        for (int k = threadIdx.x; k < ld; k += 256) {
+            const int32_t c = k < n ? src[k] : 0;
+            m = max(m, c < 0 ? 0u - unsigned(c) : unsigned(c));
+            dst[k] = int16_t(max(-32768, min(32767, c)));
+        }
     }
     for (int o = 32; o > 0; o >>= 1) m = max(m, unsigned(__shfl_xor(int(m), o, 64)));
     __shared__ unsigned red[4];
@@ -141,7 +157,9 @@ __global__ __launch_bounds__(256) void k_transpose16(const AInst *inst,
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
         const int orow = c0 + r, ocol = r0 + tx;  // destination row = source column
-        if (orow < n && ocol < n) c16t[I.c16_off + int64_t(orow) * n + ocol] = tile[tx][r];
+        // padding columns (ocol in [n, ld16(n))) get the tile's zeros
+        if (orow < n && ocol < ld16(n))
+            c16t[I.c16_off + int64_t(orow) * ld16(n) + ocol] = tile[tx][r];
     }
 }
 
@@ -175,101 +193,75 @@ __device__ inline int64_t wave_min64(int64_t v) {
     return m3 < m ? m3 : m;
 }
 
-// Folds cost c of column y into the lane's running minimum.
-__device__ inline void fold(int64_t v, int y, int c, int64_t &b, int &a, int &ca) {
-    if (v < b) {
-        b = v;
-        a = y;
-        ca = c;
-    }
-}
-
-// Per-lane part of the row scan: int32 costs.
+// Per-lane part of the row scan: int32 costs (row stride n, any
+// alignment).  Branch-free: out-of-range columns read p(0) and are masked.
 __device__ inline void lane_scan(const int32_t *__restrict__ row,
                                  const int64_t *py, int n, int32_t sgnS,
                                  int lane, int64_t &b, int &a, int &ca) {
-    if ((reinterpret_cast<uintptr_t>(row) & 15) == 0 && (n & 3) == 0) {
-        const int4 *row4 = reinterpret_cast<const int4 *>(row);
-        const int nq = n >> 2;
-        for (int base = 0; base < nq; base += 256) {
-            int4 cv[4];
+    const gint32_p g = (gint32_p)row;
+    for (int base = 0; base < n; base += 1024) {
+        int32_t cv[16];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int q = base + lane + 64 * i;
-                cv[i] = q < nq ? row4[q] : make_int4(0, 0, 0, 0);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int q = base + lane + 64 * i;
-                if (q < nq) {
-                    const int y = 4 * q;
-                    fold(int64_t(cv[i].x) * sgnS - py[y], y, cv[i].x, b, a, ca);
-                    fold(int64_t(cv[i].y) * sgnS - py[y + 1], y + 1, cv[i].y, b, a, ca);
-                    fold(int64_t(cv[i].z) * sgnS - py[y + 2], y + 2, cv[i].z, b, a, ca);
-                    fold(int64_t(cv[i].w) * sgnS - py[y + 3], y + 3, cv[i].w, b, a, ca);
-                }
-            }
+        for (int i = 0; i < 16; ++i) {
+            const int y = base + lane + 64 * i;
+            cv[i] = g[y < n ? y : 0];
         }
-    } else {
-        for (int base = 0; base < n; base += 1024) {
-            int32_t cv[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int y = base + lane + 64 * i;
-                cv[i] = y < n ? row[y] : 0;
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int y = base + lane + 64 * i;
-                if (y < n) fold(int64_t(cv[i]) * sgnS - py[y], y, cv[i], b, a, ca);
+        for (int i = 0; i < 16; ++i) {
+            const int y = base + lane + 64 * i;
+            const bool ok = y < n;
+            const int64_t v = int64_t(cv[i]) * sgnS - py[ok ? y : 0];
+            if (ok && v < b) {
+                b = v;
+                a = y;
+                ca = cv[i];
             }
         }
     }
 }
 
-// Per-lane part of the row scan: int16 costs (8 per 16-byte load).
+// Per-lane part of the row scan: int16 costs, row stride ld16(n), every row
+// 16-byte aligned (8 costs per load).  |c| <= 32768 and |S| <= 4097, so
+// c * S*sign is a 24 x 24-bit product; the padding columns carry PAD_PRICE
+// and never win.
 __device__ inline void lane_scan(const int16_t *__restrict__ row,
                                  const int64_t *py, int n, int32_t sgnS,
                                  int lane, int64_t &b, int &a, int &ca) {
-    if ((reinterpret_cast<uintptr_t>(row) & 15) == 0 && (n & 7) == 0) {
-        const int4 *row8 = reinterpret_cast<const int4 *>(row);
-        const int no = n >> 3;
-        for (int base = 0; base < no; base += 128) {
-            int4 cv[2];
+    const gv4i_p g = (gv4i_p)row;
+    const int no = ld16(n) >> 3;
+    for (int base = 0; base < no; base += 128) {
+        v4i cv[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int q = base + lane + 64 * i;
-                cv[i] = q < no ? row8[q] : make_int4(0, 0, 0, 0);
-            }
+        for (int i = 0; i < 2; ++i) {
+            const int q = base + lane + 64 * i;
+            cv[i] = q < no ? g[q] : v4i{0, 0, 0, 0};
+        }
+        // the chunk's minimum keeps the entry's position as a constant
+        // (8 i + j); the column is rebuilt once at the end
+        int64_t bl = b;
+        int al = -1, cl = 0;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int q = base + lane + 64 * i;
-                if (q < no) {
-                    const int y = 8 * q;
-                    const int w[4] = {cv[i].x, cv[i].y, cv[i].z, cv[i].w};
+        for (int i = 0; i < 2; ++i) {
+            const int q = base + lane + 64 * i;
+            if (q < no) {
+                const int y = 8 * q;
+                const int w[4] = {cv[i].x, cv[i].y, cv[i].z, cv[i].w};
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int lo = int(int16_t(w[j] & 0xffff));
-                        const int hi = w[j] >> 16;
-                        fold(int64_t(lo) * sgnS - py[y + 2 * j], y + 2 * j, lo, b, a, ca);
-                        fold(int64_t(hi) * sgnS - py[y + 2 * j + 1], y + 2 * j + 1, hi, b, a, ca);
+                for (int j = 0; j < 8; ++j) {
+                    const int c = j & 1 ? w[j >> 1] >> 16 : int(int16_t(w[j >> 1] & 0xffff));
+                    const int64_t v = int64_t(__mul24(c, sgnS)) - py[y + j];
+                    if (v < bl) {
+                        bl = v;
+                        al = 8 * i + j;
+                        cl = c;
                     }
                 }
             }
         }
-    } else {
-        for (int base = 0; base < n; base += 1024) {
-            int cv[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int y = base + lane + 64 * i;
-                cv[i] = y < n ? int(row[y]) : 0;
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int y = base + lane + 64 * i;
-                if (y < n) fold(int64_t(cv[i]) * sgnS - py[y], y, cv[i], b, a, ca);
-            }
+        if (al >= 0) {
+            b = bl;
+            a = 8 * (base + lane) + 512 * (al >> 3) + (al & 7);
+            ca = cl;
         }
     }
 }
@@ -284,7 +276,7 @@ __device__ inline void row_min(const T *__restrict__ row, const int64_t *py,
                                int &arg, int &carg) {
     int64_t b = LLONG_MAX;
     int a = 0, ca = 0;
-    // |S*sign| <= 2*2048+1, so every product is a 32 x 32 -> 64 multiply
+    // |S*sign| <= 2*2048+1 fits 32 bits
     lane_scan(row, py, n, int32_t(sgnS), lane, b, a, ca);
     const int64_t m = wave_min64(b);
     const unsigned long long hit = __ballot(b == m);
@@ -339,16 +331,33 @@ __device__ inline bool resolve_column(int y, int64_t eps, const Shared &L,
     return true;
 }
 
-__device__ inline int64_t floor_div(int64_t a, int64_t b) {  // b > 0
-    int64_t q = a / b;
-    if (a % b != 0 && a < 0) --q;
-    return q;
-}
+// Division by a fixed eps >= 1 without a 64-bit integer divide per call
+// (a software sequence of ~100 instructions on this hardware): the quotient
+// is estimated through a double reciprocal and corrected to the exact floor
+// by its integer remainder.  Exact for |a| < 2^62.
+struct EpsDiv {
+    int64_t eps, kmax;  // kmax = floor(LLONG_MAX / eps)
+    double inv;
+    __device__ explicit EpsDiv(int64_t e)
+        : eps(e), kmax(LLONG_MAX / e), inv(1.0 / double(e)) {}
+    __device__ int64_t floor_div(int64_t a) const {
+        int64_t q = int64_t(floor(double(a) * inv));
+        int64_t r = a - q * eps;
+        while (r < 0) {
+            --q;
+            r += eps;
+        }
+        while (r >= eps) {
+            ++q;
+            r -= eps;
+        }
+        return q;
+    }
+    // eps * k, saturated (k >= -1)
+    __device__ int64_t mul_sat(int64_t k) const { return k > kmax ? LLONG_MAX : eps * k; }
+};
 
-// eps * k, saturated (k >= -1, eps >= 1)
-__device__ inline int64_t mul_sat(int64_t eps, int64_t k) {
-    return k > LLONG_MAX / eps ? LLONG_MAX : eps * k;
-}
+constexpr int PU_LOADS = 16;  // column loads in flight per thread in a price update
 
 struct PU {
     int64_t *lx, *ly;  // labels (multiples of eps), LLONG_MAX = none yet
@@ -379,6 +388,7 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
     __shared__ int s_rem, s_nf[2], s_dec[2];
     __shared__ unsigned long long s_next[2];
     constexpr int64_t NONE = LLONG_MAX;
+    const EpsDiv D(eps);
     if (tid == 0) {
         s_rem = 0;
         s_nf[0] = 0;
@@ -422,23 +432,24 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
                 if (U.fx[x]) continue;
                 int64_t best = U.lx[x];
                 // an offer improves iff c_p < eps * (best - level - 1)
-                int64_t bound = best == NONE ? NONE : mul_sat(eps, best - level - 1);
+                int64_t bound = best == NONE ? NONE : D.mul_sat(best - level - 1);
                 const int64_t pxx = L.px[x];
                 const int mx = L.mate[x];
-                // eight column loads in flight before any is used
-                for (int j0 = 0; j0 < nf; j0 += 8) {
-                    int cv[8];
+                // PU_LOADS column loads in flight before any is used
+                for (int j0 = 0; j0 < nf; j0 += PU_LOADS) {
+                    int cv[PU_LOADS];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        cv[k] = j0 + k < nf ? int(CT[int64_t(fl[j0 + k]) * n + x]) : 0;
+                    for (int k = 0; k < PU_LOADS; ++k)
+                        cv[k] = j0 + k < nf ? int(CT[int64_t(fl[j0 + k]) * ld16(n) + x]) : 0;
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
+                    for (int k = 0; k < PU_LOADS; ++k) {
                         if (j0 + k >= nf) break;
                         const int y = fl[j0 + k];
-                        const int64_t cp = int64_t(cv[k]) * sgnS + pxx - L.py[y];
+                        // int16 costs: a 24 x 24-bit product
+                        const int64_t cp = int64_t(__mul24(cv[k], int(sgnS))) + pxx - L.py[y];
                         if (cp < bound && y != mx) {
-                            best = level + floor_div(cp, eps) + 1;
-                            bound = mul_sat(eps, best - level - 1);
+                            best = level + D.floor_div(cp) + 1;
+                            bound = D.mul_sat(best - level - 1);
                         }
                     }
                 }
@@ -464,7 +475,7 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
             }
             if (U.fy[y]) continue;
             // c_p(y, x) = -c(x,y) + p(y) - p(x) = p(y) - b(x)
-            const int64_t cand = level + floor_div(L.py[y] - L.bv[x], eps) + 1;
+            const int64_t cand = level + D.floor_div(L.py[y] - L.bv[x]) + 1;
             atomicMin(reinterpret_cast<unsigned long long *>(&U.ly[y]),
                       (unsigned long long)cand);
             m = min(m, (unsigned long long)cand);
@@ -473,9 +484,10 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
         // read here is still bounded by the true minimum
         for (int y = tid; y < n; y += NT)
             if (!U.fy[y]) m = min(m, (unsigned long long)U.ly[y]);
-        for (int o = 32; o > 0; o >>= 1)
-            m = min(m, (unsigned long long)__shfl_xor((long long)m, o, 64));
-        if ((tid & 63) == 0 && m != ULLONG_MAX) atomicMin(&s_next[par], m);
+        // every label and offer is at most NONE, which also stands for
+        // "nothing" here: the wavefront minimum by DPP
+        const int64_t wm = wave_min64(int64_t(min(m, (unsigned long long)NONE)));
+        if ((tid & 63) == 0 && wm < NONE) atomicMin(&s_next[par], (unsigned long long)wm);
         __syncthreads();
         const unsigned long long next = s_next[par];
         left -= s_dec[par];
@@ -590,8 +602,10 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                                unsigned char *smem) {
     const int n = I.n;
     Shared L;
+    // rows of the int16 copies are padded to ld16(n) entries
+    const int ldc = sizeof(T) == 2 ? ld16(n) : n;
     L.py = reinterpret_cast<int64_t *>(smem);
-    L.px = L.py + n;
+    L.px = L.py + ld16(n);
     L.bv = L.px + n;
     L.ey = reinterpret_cast<int32_t *>(L.bv + n);
     L.head = L.ey + n;
@@ -631,6 +645,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     }
     for (int y = tid; y < n; y += NT)
         py[y] = A.init_prices ? A.init_prices[I.row_off + y] : 0;
+    if (tid < ld16(n) - n) py[n + tid] = PAD_PRICE;
     __syncthreads();
     // Algorithm 5.0 starts at eps = C (largest |cost|), here in scaled units
     int64_t eps = A.eps0 > 0 ? A.eps0 : (cmax > 0 ? int64_t(cmax) * S : 1);
@@ -651,7 +666,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
         for (int x = wave; x < n; x += NW) {
             int64_t best;
             int arg, carg;
-            row_min(C + int64_t(x) * n, py, n, sgnS, lane, best, arg, carg);
+            row_min(C + int64_t(x) * ldc, py, n, sgnS, lane, best, arg, carg);
             if (lane == 0) {
                 px[x] = -(best + eps);
                 L.mate[x] = arg;
@@ -741,25 +756,54 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                         --qlen;
                         int64_t best;
                         int arg, carg;
-                        row_min(C + int64_t(x) * n, py, n, sgnS, lane, best, arg, carg);
-                        if (best + px[x] >= 0) {
-                            px[x] = -(best + eps);
+                        row_min(C + int64_t(x) * ldc, py, n, sgnS, lane, best, arg, carg);
+                        const int old = L.head[arg], e = L.ey[arg];
+                        int64_t pxx = px[x];
+                        if (best + pxx >= 0) {
+                            pxx = -(best + eps);
+                            px[x] = pxx;
                             ++tr;
                         }
-                        L.mate[x] = arg;
-                        L.bv[x] = int64_t(carg) * sgnS + px[x];
-                        L.nxt[x] = L.head[arg];
-                        L.head[arg] = x;
-                        L.ey[arg] += 1;
+                        const int64_t bx = int64_t(carg) * sgnS + pxx;
                         ++tp;
                         ++ts;
-                        if (!resolve_column(arg, eps, L, tp, tr, [&](int bx) {
-                                L.xl[qt] = bx;
-                                if (++qt == n) qt = 0;
-                                ++qlen;
-                            })) {
-                            stop = 2;
-                            break;
+                        auto emit = [&](int r) {
+                            L.xl[qt] = r;
+                            if (++qt == n) qt = 0;
+                            ++qlen;
+                        };
+                        if (e == 0 && old >= 0) {
+                            // y held exactly one row (every column is settled
+                            // between tail operations): resolve_column on the
+                            // pair {x, old} without the list walk
+                            const int64_t bo = L.bv[old];
+                            const bool back_x = bx > bo || (bx == bo && x < old);
+                            const int64_t bb = back_x ? bx : bo;
+                            if (!(bb > py[arg])) {
+                                py[arg] = bb - eps;
+                                ++tr;
+                            }
+                            if (back_x) {
+                                L.mate[x] = -1;
+                            } else {
+                                L.mate[x] = arg;
+                                L.bv[x] = bx;
+                                L.nxt[x] = -1;
+                                L.head[arg] = x;
+                                L.mate[old] = -1;
+                            }
+                            ++tp;
+                            emit(back_x ? x : old);
+                        } else {
+                            L.mate[x] = arg;
+                            L.bv[x] = bx;
+                            L.nxt[x] = old;
+                            L.head[arg] = x;
+                            L.ey[arg] = e + 1;
+                            if (!resolve_column(arg, eps, L, tp, tr, emit)) {
+                                stop = 2;
+                                break;
+                            }
                         }
                         if ((ts & 127) == 0 &&
                             ((long long)(s_cnt[2] + s_cnt[3] + tp + tr) > A.max_ops ||
@@ -791,7 +835,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                 const int x = L.xl[qh0 + i < n ? qh0 + i : qh0 + i - n];
                 int64_t best;
                 int arg, carg;
-                row_min(C + int64_t(x) * n, py, n, sgnS, lane, best, arg, carg);
+                row_min(C + int64_t(x) * ldc, py, n, sgnS, lane, best, arg, carg);
                 if (lane == 0) {
                     if (best + px[x] >= 0) {  // relabel, then the arc is admissible
                         px[x] = -(best + eps);
@@ -859,7 +903,8 @@ __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
 
 // py, px, b(x) (int64), e(y), head, next, mate, two lists (int32), two
 // labels (int64) and two scanned flags (uint8) per node
-static size_t lds_bytes(int nmax) { return size_t(nmax) * 66 + 64; }
+// prices of Y padded to ld16(n) entries, then the n-sized arrays
+static size_t lds_bytes(int nmax) { return size_t(nmax) * 66 + 64 + 64; }
 
 struct Layout {
     AInst *inst;
@@ -871,7 +916,7 @@ struct Layout {
 
 static int64_t c16_elems(int B, const int32_t *n) {
     int64_t e = 0;
-    for (int b = 0; b < B; ++b) e += (int64_t(n[b]) * n[b] + 7) & ~int64_t(7);
+    for (int b = 0; b < B; ++b) e += int64_t(n[b]) * ld16(n[b]);
     return e;
 }
 
@@ -924,7 +969,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         insts[b].n = n[b];
         insts[b].row_off = int32_t(rows);
         rows += n[b];
-        c16 += (nn + 7) & ~int64_t(7);
+        c16 += int64_t(n[b]) * ld16(n[b]);
         nmax = std::max(nmax, n[b]);
         nnmax = std::max(nnmax, nn);
     }
