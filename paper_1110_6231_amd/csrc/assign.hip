@@ -697,7 +697,10 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             const int ny = s_ny;
             unsigned long long my_push = 0, my_rel = 0;
             int32_t *hot = reinterpret_cast<int32_t *>(U.ly);  // free outside updates
-            for (int j = tid; j < ny; j += NT) {
+            // entry j goes to lane j / NW of wavefront j % NW, so that a few
+            // active columns are spread over the wavefronts rather than
+            // walking their lists in the lanes of one
+            for (int j = (tid & 63) * NW + (tid >> 6); j < ny; j += NT) {
                 const int y = L.yl[j];
                 if (L.ey[y] >= HOT) {
                     hot[atomicAdd(&s_nh, 1)] = y;
@@ -717,18 +720,22 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                     atomicOr(&s_stop, 2);
             if (my_push) atomicAdd(&s_cnt[2], my_push);
             if (my_rel) atomicAdd(&s_cnt[3], my_rel);
-            __syncthreads();
-            int nx = s_nx;
             if (tid == 0) {
+                // every thread read s_ny before the last barrier, and s_qh is
+                // read only after the next one; the budget check sees the
+                // counters of earlier phases (a safety limit, not exact)
                 s_ny = 0;
                 s_qh = 0;
-                s_nh = 0;
                 atomicAdd(&s_cnt[1], 1ull);
                 if ((long long)(s_cnt[2] + s_cnt[3]) > A.max_ops ||
                     wall_clock64() - t_start > A.max_ticks)
-                    s_stop |= 1;
+                    atomicOr(&s_stop, 1);
             }
             __syncthreads();
+            int nx = s_nx;
+            // s_nh was read by every thread before the last barrier and is
+            // next used after the X phase's barrier
+            if (tid == 0) s_nh = 0;
             if (nx == 0 || s_stop) break;
             if (nx <= tail_enter) {
                 if (CT && s_cnt[2] - s_pu_mark >= period) {
