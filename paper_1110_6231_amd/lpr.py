@@ -325,6 +325,8 @@ def make_assign_opts(alpha=0, eps0=0, init_col_prices=None, max_ops=0,
     o.init_col_prices = None if init_col_prices is None else init_col_prices.data_ptr()
     o.max_ops = max_ops
     o.flags = flags
+    # the struct holds raw device pointers: keep their tensors alive with it
+    o._keep = (init_col_prices, eps0_per_instance)
     return o
 
 

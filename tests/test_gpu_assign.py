@@ -91,6 +91,13 @@ def test_alpha_eps_and_warm_start():
     g = np.random.default_rng(0)
     garbage = torch.as_tensor(g.integers(-10**9, 10**9, 300), device="cuda")
     check(c, opts=lpr.make_assign_opts(init_col_prices=garbage))
+    # column prices spread just past and just within the 2^29 window of the
+    # 32-bit row scans (past it the scans run in int64 until a rebase fits)
+    for spread in (2**29 + 5, 2**29 - 5 * 10**6):
+        edge = np.zeros(300, np.int64)
+        edge[::2] = -spread
+        check(c, opts=lpr.make_assign_opts(
+            init_col_prices=torch.as_tensor(edge, device="cuda")))
 
 
 @pytest.mark.parametrize("tail,flags,period", [
