@@ -102,6 +102,8 @@ __device__ inline float inst_scale(const NInst &I, const unsigned long long *abs
     return m > 0 ? float(m) : 1.0f;
 }
 
+constexpr int FEAT_AHEAD = 8;  // rows loaded ahead in the column passes
+
 // Column pass 1: one thread per stacked column.
 __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
                                                     const int32_t *rinst,
@@ -124,35 +126,47 @@ __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
     float r0 = INFINITY, r1 = INFINITY;
     float sz = 0.f, szz = 0.f, srr = 0.f;
     float lm = INFINITY, ls = 0.f;  // running min of rr and sum exp(-(rr-lm)/TAU)
-    for (int x = 0; x < n; ++x) {
-        const int c = sign * col[int64_t(x) * n];
-        const float z = float(c) * inv;
-        const float rr = float(c - rm[x]) * inv;
-        sz += z;
-        szz += z * z;
-        srr += rr;
-        if (z < top[7]) {
-            float v = z;
+    // the loads of FEAT_AHEAD rows are in flight before the first is used
+    int cb[FEAT_AHEAD], mb[FEAT_AHEAD];
+    for (int x0 = 0; x0 < n; x0 += FEAT_AHEAD) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const float lo = fminf(top[k], v);
-                v = fmaxf(top[k], v);
-                top[k] = lo;
-            }
+        for (int a = 0; a < FEAT_AHEAD; ++a) {
+            const int x = x0 + a < n ? x0 + a : n - 1;
+            cb[a] = col[int64_t(x) * n];
+            mb[a] = rm[x];
         }
-        if (rr < r1) {
-            if (rr < r0) {
-                r1 = r0;
-                r0 = rr;
+#pragma unroll
+        for (int a = 0; a < FEAT_AHEAD; ++a) {
+            if (x0 + a >= n) break;
+            const int c = sign * cb[a];
+            const float z = float(c) * inv;
+            const float rr = float(c - mb[a]) * inv;
+            sz += z;
+            szz += z * z;
+            srr += rr;
+            if (z < top[7]) {
+                float v = z;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const float lo = fminf(top[k], v);
+                    v = fmaxf(top[k], v);
+                    top[k] = lo;
+                }
+            }
+            if (rr < r1) {
+                if (rr < r0) {
+                    r1 = r0;
+                    r0 = rr;
+                } else {
+                    r1 = rr;
+                }
+            }
+            if (rr < lm) {
+                ls = ls * __expf((rr - lm) / TAU) + 1.0f;
+                lm = rr;
             } else {
-                r1 = rr;
+                ls += __expf(-(rr - lm) / TAU);
             }
-        }
-        if (rr < lm) {
-            ls = ls * __expf((rr - lm) / TAU) + 1.0f;
-            lm = rr;
-        } else {
-            ls += __expf(-(rr - lm) / TAU);
         }
     }
     float *f = F + int64_t(r) * F_IN;
@@ -203,13 +217,25 @@ __global__ __launch_bounds__(256) void k_feat_cols2(const NInst *inst,
     const float inv = 1.0f / inst_scale(I, abssum, b);
     const int32_t *col = costs + I.cost_off + y;
     float mn = INFINITY;
-    for (int x = 0; x < n; ++x)
-        mn = fminf(mn, float(sign * col[int64_t(x) * n]) * inv - u2[I.row_off + x]);
+    for (int x0 = 0; x0 < n; x0 += FEAT_AHEAD) {
+        int cb[FEAT_AHEAD];
+        float ub[FEAT_AHEAD];
+#pragma unroll
+        for (int a = 0; a < FEAT_AHEAD; ++a) {
+            const int x = x0 + a < n ? x0 + a : n - 1;  // a repeat is harmless for a min
+            cb[a] = col[int64_t(x) * n];
+            ub[a] = u2[I.row_off + x];
+        }
+#pragma unroll
+        for (int a = 0; a < FEAT_AHEAD; ++a)
+            mn = fminf(mn, float(sign * cb[a]) * inv - ub[a]);
+    }
     v2[r] = mn;
 }
 
 // Per instance: centre f13 and f14, set f15, and write the bf16 network
-// input (row-major [Rp, 32] and transposed [32, Rp], zero padded).
+// input (row-major [Rp, 32] and, when XT is not null, transposed [32, Rp];
+// zero padded).
 __global__ __launch_bounds__(256) void k_feat_finish(const NInst *inst, int32_t Rp,
                                                      float *F, const float *sval,
                                                      const float *v2, __bf16 *X,
@@ -242,7 +268,7 @@ __global__ __launch_bounds__(256) void k_feat_finish(const NInst *inst, int32_t 
         for (int k = 0; k < F_PAD; ++k) {
             const __bf16 v = to_bf16(k < F_IN ? f[k] : 0.f);
             X[int64_t(r) * F_PAD + k] = v;
-            XT[int64_t(k) * Rp + r] = v;
+            if (XT) XT[int64_t(k) * Rp + r] = v;
         }
     }
 }
@@ -294,27 +320,57 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const __bf16 *A, int lda,
 // Forward pieces
 // ---------------------------------------------------------------------------
 // P[b][j] = sum_k mean_cols(H)[b][k] U[k][j] + bias[j]; also keeps the means.
-__global__ __launch_bounds__(128) void k_pool_fwd(const NInst *inst, const __bf16 *H,
-                                                  int ldh, int Kin, const float *U,
-                                                  const float *bias, float *Mout,
-                                                  float *P) {
+// 1024 threads = POOL_G groups of WID: group g sums the rows y = g (mod
+// POOL_G) of column k = tid % WID (and the terms k = g (mod POOL_G) of the
+// product), and the groups' partial sums meet in LDS.
+constexpr int POOL_G = 8;
+__global__ __launch_bounds__(POOL_G * WID) void k_pool_fwd(const NInst *inst,
+                                                           const __bf16 *H, int ldh,
+                                                           int Kin, const float *U,
+                                                           const float *bias,
+                                                           float *Mout, float *P) {
     const NInst I = inst[blockIdx.x];
+    const int k = threadIdx.x % WID, g = threadIdx.x / WID;
+    __shared__ float part[POOL_G][WID];
     __shared__ float m[WID];
-    for (int k = threadIdx.x; k < Kin; k += 128) {
-        float s = 0.f;
-        for (int y = 0; y < I.n; ++y) s += from_bf16(H[int64_t(I.row_off + y) * ldh + k]);
-        m[k] = s / I.n;
-        Mout[int64_t(blockIdx.x) * WID + k] = m[k];
+    float s = 0.f;
+    if (k < Kin) {
+        const __bf16 *h = H + int64_t(I.row_off) * ldh + k;
+        int y = g;
+        // four rows in flight per thread
+        for (; y + 3 * POOL_G < I.n; y += 4 * POOL_G) {
+            const float a0 = from_bf16(h[int64_t(y) * ldh]);
+            const float a1 = from_bf16(h[int64_t(y + POOL_G) * ldh]);
+            const float a2 = from_bf16(h[int64_t(y + 2 * POOL_G) * ldh]);
+            const float a3 = from_bf16(h[int64_t(y + 3 * POOL_G) * ldh]);
+            s += (a0 + a1) + (a2 + a3);
+        }
+        for (; y < I.n; y += POOL_G) s += from_bf16(h[int64_t(y) * ldh]);
+    }
+    part[g][k] = s;
+    __syncthreads();
+    if (g == 0) {
+        float t = 0.f;
+        for (int i = 0; i < POOL_G; ++i) t += part[i][k];
+        m[k] = k < Kin ? t / I.n : 0.f;
+        if (k < Kin) Mout[int64_t(blockIdx.x) * WID + k] = m[k];
     }
     __syncthreads();
-    const int j = threadIdx.x;
-    float s = bias[j];
-    for (int k = 0; k < Kin; ++k) s += m[k] * U[k * WID + j];
-    P[int64_t(blockIdx.x) * WID + j] = s;
+    const int j = k;
+    float t = 0.f;
+    for (int kk = g; kk < Kin; kk += POOL_G) t += m[kk] * U[kk * WID + j];
+    part[g][j] = t;
+    __syncthreads();
+    if (g == 0) {
+        float o = bias[j];
+        for (int i = 0; i < POOL_G; ++i) o += part[i][j];
+        P[int64_t(blockIdx.x) * WID + j] = o;
+    }
 }
 
-// Z += P[inst]; H = relu(Z) as bf16, row-major and transposed.  Padding rows
-// are zero.  grid = Rp / 64 blocks of 256 threads: 64 rows x 128 columns.
+// Z += P[inst]; H = relu(Z) as bf16, row-major and (when HT is not null, for
+// the backward pass) transposed.  Padding rows are zero.  grid = Rp / 64
+// blocks of 256 threads: 64 rows x 128 columns.
 __global__ __launch_bounds__(256) void k_act_fwd(const int32_t *rinst, int32_t R,
                                                  int32_t Rp, float *Z, const float *P,
                                                  __bf16 *H, __bf16 *HT) {
@@ -326,7 +382,7 @@ __global__ __launch_bounds__(256) void k_act_fwd(const int32_t *rinst, int32_t R
         Z[int64_t(r) * WID + j] = z;
         const __bf16 h = to_bf16(z > 0.f ? z : 0.f);
         H[int64_t(r) * WID + j] = h;
-        HT[int64_t(j) * Rp + r] = h;
+        if (HT) HT[int64_t(j) * Rp + r] = h;
     }
 }
 
@@ -647,7 +703,7 @@ static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
     return LPR_OK;
 }
 
-static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign) {
+static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign, bool train) {
     Layout &L = C.L;
     const int R = int(C.R);
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.abssum), 0, C.B, C.s));
@@ -663,7 +719,7 @@ static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign) {
     hipLaunchKernelGGL(k_feat_cols2, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
                        L.inst, L.rinst, costs, sign, R, L.abssum, L.u2, L.v2);
     hipLaunchKernelGGL(k_feat_finish, dim3(C.B), dim3(256), 0, C.s, L.inst,
-                       int32_t(C.Rp), L.F, L.sval, L.v2, L.X0, L.X0T);
+                       int32_t(C.Rp), L.F, L.sval, L.v2, L.X0, train ? L.X0T : nullptr);
     LPR_TRY_HIP(hipGetLastError());
     return LPR_OK;
 }
@@ -680,7 +736,8 @@ static void gemm(hipStream_t s, const __bf16 *A, int lda, const __bf16 *Bt, int 
     }
 }
 
-static lpr_status run_forward(Ctx &C, const float *params) {
+// train: also keep the transposed activations the backward pass reads
+static lpr_status run_forward(Ctx &C, const float *params, bool train) {
     Layout &L = C.L;
     const int R = int(C.R), Rp = int(C.Rp);
     hipLaunchKernelGGL(k_weights, dim3(16), dim3(256), 0, C.s, params, L.WT[0],
@@ -688,11 +745,11 @@ static lpr_status run_forward(Ctx &C, const float *params) {
     const __bf16 *Hin = L.X0;
     int ldin = F_PAD;
     for (int l = 0; l < 3; ++l) {
-        hipLaunchKernelGGL(k_pool_fwd, dim3(C.B), dim3(128), 0, C.s, L.inst, Hin, ldin,
+        hipLaunchKernelGGL(k_pool_fwd, dim3(C.B), dim3(POOL_G * WID), 0, C.s, L.inst, Hin, ldin,
                            KIN[l], params + OFF_U[l], params + OFF_B[l], L.M[l], L.P[l]);
         gemm(C.s, Hin, ldin, L.WT[l], KPAD[l], L.Z[l], WID, Rp, WID, KPAD[l], 1, false);
         hipLaunchKernelGGL(k_act_fwd, dim3(Rp / 64), dim3(256), 0, C.s, L.rinst, R, Rp,
-                           L.Z[l], L.P[l], L.H[l], L.HT[l]);
+                           L.Z[l], L.P[l], L.H[l], train ? L.HT[l] : nullptr);
         Hin = L.H[l];
         ldin = WID;
     }
@@ -757,7 +814,7 @@ extern "C" lpr_status lpr_pricenet_features(int32_t B, const int32_t *n,
                                             void *stream) {
     net::Ctx C;
     LPR_TRY(net::prepare(C, B, n, cost_offset, costs, workspace, workspace_bytes, stream));
-    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1));
+    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1, false));
     if (feats)
         LPR_TRY_HIP(hipMemcpyAsync(feats, C.L.F, sizeof(float) * C.R * net::F_IN,
                                    hipMemcpyDeviceToDevice, C.s));
@@ -790,8 +847,8 @@ extern "C" lpr_status lpr_pricenet_infer(int32_t B, const int32_t *n,
     }
     net::Ctx C;
     LPR_TRY(net::prepare(C, B, n, cost_offset, costs, workspace, workspace_bytes, stream));
-    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1));
-    LPR_TRY(net::run_forward(C, params));
+    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1, false));
+    LPR_TRY(net::run_forward(C, params, false));
     if (col_prices || eps0) {
         hipLaunchKernelGGL(net::k_prices, dim3(B), dim3(256), 0, C.s, C.L.inst,
                            C.L.abssum, C.L.q, col_prices, kappa, eps0);
@@ -820,8 +877,8 @@ extern "C" lpr_status lpr_pricenet_train_step(int32_t B, const int32_t *n,
     }
     net::Ctx C;
     LPR_TRY(net::prepare(C, B, n, cost_offset, costs, workspace, workspace_bytes, stream));
-    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1));
-    LPR_TRY(net::run_forward(C, params));
+    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1, true));
+    LPR_TRY(net::run_forward(C, params, true));
     LPR_TRY(net::run_backward(C, params, target_prices));
     if (grad_out)
         LPR_TRY_HIP(hipMemcpyAsync(grad_out, C.L.grad, sizeof(float) * net::N_PARAMS,
