@@ -66,35 +66,36 @@ __device__ inline float from_bf16(__bf16 b) { return (float)b; }
 // ---------------------------------------------------------------------------
 // Feature passes
 // ---------------------------------------------------------------------------
-// Row pass 1: min_y c(x,y) and the instance's sum of |c|.  One wavefront per
-// stacked row index r (row x of instance rinst[r]).
+// Row pass 1: min_y c(x,y) and the instance's sum of |c|.  grid = (row
+// blocks, B): block (i, b) takes rows ROWS1 i .. ROWS1 (i+1) - 1 of instance
+// b, one wavefront per row in turn, and adds its part of the sum with one
+// atomic (the instance's rows then meet in few device-scope atomics).
+constexpr int ROWS1 = 16;
 __global__ __launch_bounds__(256) void k_feat_rows1(const NInst *inst,
-                                                    const int32_t *rinst,
                                                     const int32_t *costs,
-                                                    int32_t sign, int32_t R,
-                                                    int32_t *rowmin,
+                                                    int32_t sign, int32_t *rowmin,
                                                     unsigned long long *abssum) {
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (r >= R) return;
-    const NInst I = inst[rinst[r]];
-    const int x = r - I.row_off;
-    const int32_t *row = costs + I.cost_off + int64_t(x) * I.n;
-    int mn = INT_MAX;
+    const NInst I = inst[blockIdx.y];
+    const int x0 = blockIdx.x * ROWS1;
+    if (x0 >= I.n) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long s = 0;
-    for (int y = lane; y < I.n; y += 64) {
-        const int c = sign * row[y];
-        mn = min(mn, c);
-        s += unsigned(c < 0 ? -c : c);
+    for (int x = x0 + wave; x < min(x0 + ROWS1, I.n); x += 4) {
+        const int32_t *row = costs + I.cost_off + int64_t(x) * I.n;
+        int mn = INT_MAX;
+        for (int y = lane; y < I.n; y += 64) {
+            const int c = sign * row[y];
+            mn = min(mn, c);
+            s += unsigned(c < 0 ? -c : c);
+        }
+        for (int o = 32; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, 64));
+        if (lane == 0) rowmin[I.row_off + x] = mn;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        mn = min(mn, __shfl_xor(mn, o, 64));
-        s += __shfl_xor(s, o, 64);
-    }
-    if (lane == 0) {
-        rowmin[r] = mn;
-        atomicAdd(&abssum[rinst[r]], s);
-    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    __shared__ unsigned long long part[4];
+    if (lane == 0) part[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&abssum[blockIdx.y], part[0] + part[1] + part[2] + part[3]);
 }
 
 __device__ inline float inst_scale(const NInst &I, const unsigned long long *abssum, int b) {
@@ -102,7 +103,9 @@ __device__ inline float inst_scale(const NInst &I, const unsigned long long *abs
     return m > 0 ? float(m) : 1.0f;
 }
 
-constexpr int FEAT_AHEAD = 8;  // rows loaded ahead in the column passes
+// rows loaded ahead in the column passes (one thread per column leaves
+// about one wavefront per SIMD, so the loads in flight set the pace)
+constexpr int FEAT_AHEAD = 32;
 
 // Column pass 1: one thread per stacked column.
 __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
@@ -368,9 +371,10 @@ __global__ __launch_bounds__(POOL_G * WID) void k_pool_fwd(const NInst *inst,
     }
 }
 
-// Z += P[inst]; H = relu(Z) as bf16, row-major and (when HT is not null, for
-// the backward pass) transposed.  Padding rows are zero.  grid = Rp / 64
-// blocks of 256 threads: 64 rows x 128 columns.
+// H = relu(Z + P[inst]) as bf16, row-major; when HT is not null (training)
+// also transposed, with Z + P written back for the backward pass.  Padding
+// rows are zero.  grid = Rp / 64 blocks of 256 threads: 64 rows x 128
+// columns.
 __global__ __launch_bounds__(256) void k_act_fwd(const int32_t *rinst, int32_t R,
                                                  int32_t Rp, float *Z, const float *P,
                                                  __bf16 *H, __bf16 *HT) {
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(256) void k_act_fwd(const int32_t *rinst, int32_t R
         const int r = r0 + i / WID, j = i % WID;
         float z = 0.f;
         if (r < R) z = Z[int64_t(r) * WID + j] + P[int64_t(rinst[r]) * WID + j];
-        Z[int64_t(r) * WID + j] = z;
+        if (HT) Z[int64_t(r) * WID + j] = z;  // pre-activations for the backward pass
         const __bf16 h = to_bf16(z > 0.f ? z : 0.f);
         H[int64_t(r) * WID + j] = h;
         if (HT) HT[int64_t(j) * Rp + r] = h;
@@ -709,9 +713,11 @@ static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign, bool 
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.abssum), 0, C.B, C.s));
     // padding rows of the bf16 input are zero
     LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0), 0, C.Rp * F_PAD / 2, C.s));
-    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0T), 0, C.Rp * F_PAD / 2, C.s));
-    hipLaunchKernelGGL(k_feat_rows1, dim3(ceil_div(R, 4)), dim3(256), 0, C.s,
-                       L.inst, L.rinst, costs, sign, R, L.rowmin, L.abssum);
+    if (train) LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0T), 0, C.Rp * F_PAD / 2, C.s));
+    int nmax = 0;
+    for (const NInst &I : C.insts) nmax = std::max(nmax, int(I.n));
+    hipLaunchKernelGGL(k_feat_rows1, dim3(ceil_div(nmax, ROWS1), C.B), dim3(256), 0, C.s,
+                       L.inst, costs, sign, L.rowmin, L.abssum);
     hipLaunchKernelGGL(k_feat_cols1, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
                        L.inst, L.rinst, costs, sign, R, L.rowmin, L.abssum, L.F, L.sval);
     hipLaunchKernelGGL(k_feat_rows2, dim3(ceil_div(R, 4)), dim3(256), 0, C.s,
