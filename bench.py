@@ -7,8 +7,10 @@ resident in HBM before the timed region; outputs and workspace are
 preallocated.  The JSON line also carries the dense assignment leg (n = 1024,
 weights U{0..1000}, max-weight) and the batched assignment leg (256
 optical-flow-like instances), the roofline of the dominant kernel (the push
-sweep or the global-relabel relaxation, whichever takes more time) and the CPU
-oracle timed on this host.
+sweep or the global-relabel relaxation, whichever takes more time), the push
+update rate against a measured atomic-add ceiling, and the CPU oracles timed
+on this host (FIFO push-relabel for the grid, Hungarian for the assignment
+legs).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -78,8 +80,6 @@ def grid_leg(args, torch, lpr, synth):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = wall * 1e3 / args.steps
-    # The same K solves again with HIP events around every group of push-sweep
-    # launches (on the library's stream) for the dominant kernel's duration.
     # The same K solves again with HIP events around every group of push-sweep
     # and relaxation launches (on the library's stream) for the durations of
     # the two kernels that take the time.
@@ -276,6 +276,61 @@ def assign_leg(args, torch, lpr, synth):
     return out
 
 
+def atomics_leg(torch, lpr, g):
+    """Push updates per second of the 1024 x 1024 solve (four atomic word
+    updates per push in Algorithm 4.5) next to the measured ceiling of
+    non-returning device-scope atomic adds to scattered addresses."""
+    log2, blocks, per = 23, 16384, 16        # 32 MiB of counters, 64 M adds
+    cnt = torch.zeros(1 << log2, dtype=torch.int32, device="cuda")
+    lpr.lpr_atomic_probe(cnt, log2, blocks, per)
+    total = blocks * 256 * per
+    assert int(cnt.sum().item()) == total
+    ms = sorted(lpr.lpr_atomic_probe(cnt, log2, blocks, per) for _ in range(5))[2]
+    ceiling = total / (ms * 1e-3)
+    pushes = g["stats"]["pushes"]
+    rate = 4 * pushes / (g["ms"] * 1e-3)
+    return {"push_updates_per_s": round(rate / 1e9, 3), "unit": "G/s",
+            "pushes_per_solve": pushes,
+            "atomic_add_ceiling_per_s": round(ceiling / 1e9, 3),
+            "frac": round(rate / ceiling, 4),
+            "probe": f"{total} non-returning 32-bit atomic adds over 2^{log2} "
+                     f"int32 counters (xorshift addresses), median of 5: "
+                     f"{ms:.3f} ms"}
+
+
+def cpu_assign_leg(args, synth):
+    """The Hungarian oracle on this host: the n = 1024 instance on one core,
+    and the batched workload over a thread pool (the oracle releases the GIL)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.lib()
+    c = synth.assign_uniform(1024, seed=0)
+    t0 = time.perf_counter()
+    oracle.assign(c, maximize=True)
+    t1024 = time.perf_counter() - t0
+    mats = synth.assign_batch(seed=0)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    per = []
+
+    def one(m):
+        ts = time.perf_counter()
+        oracle.assign(m)
+        return time.perf_counter() - ts
+
+    with ThreadPoolExecutor(cores) as ex:
+        per = list(ex.map(one, mats))
+    tb = time.perf_counter() - t0
+    return {"kind": "oracle", "n1024_solves_per_s": round(1.0 / t1024, 3),
+            "n1024_cores": 1,
+            "batched_solves_per_s": round(len(mats) / tb, 1),
+            "batched_cores": cores,
+            "batched_instance_ms_median": round(float(np.median(per)) * 1e3, 3),
+            "sample": "Hungarian oracle: one solve of the n=1024 instance on "
+                      "one core; the 256 batched instances over a pool of "
+                      f"{cores} threads"}
+
+
 def cpu_leg(args, inst):
     import oracle
     oracle.lib()
@@ -336,11 +391,14 @@ def main():
                    "sweeps_per_relabel": g["stats"]["sweeps_per_relabel"]},
         "roofline": g["roofline"],
         "other_kernels": g["other_kernels"],
+        "atomics": atomics_leg(torch, lpr, g),
     }
     if not args.no_batched_grid:
         out["grid_batched"] = grid_batched_leg(args, torch, lpr, synth)
     if not args.no_assign:
         out["assignment"] = assign_leg(args, torch, lpr, synth)
+        if not args.no_cpu:
+            out["assignment"]["cpu_oracle"] = cpu_assign_leg(args, synth)
     if not args.no_cpu:
         cb, cpu_flow = cpu_leg(args, g["inst"])
         assert cpu_flow == g["flow"], (cpu_flow, g["flow"])

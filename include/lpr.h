@@ -387,6 +387,23 @@ lpr_status lpr_pricenet_train_step(int32_t B, const int32_t *n,
                                    float *loss_out, void *workspace,
                                    size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Measurement helper (not part of the method).  Section 4's pushes each
+ * update four words with atomics; this gives the device's rate for such
+ * updates: `blocks` x 256 threads each add 1 with a non-returning
+ * device-scope 32-bit atomic to `per_thread` counters picked by their own
+ * xorshift32 sequence among 2^log2_counters.
+ *   counters       device int32 [2^log2_counters], caller-owned (zero it to
+ *                  check that the counts sum to blocks * 256 * per_thread).
+ *   log2_counters  6 .. 28;  blocks  1 .. 2^20;  per_thread  1 .. 4096.
+ *   ms             host double [1]: the kernel's time (HIP events).
+ * Returns after completion.  Errors: LPR_EINVAL (argument out of range or
+ * NULL), LPR_EDEVICE.
+ * ------------------------------------------------------------------------- */
+lpr_status lpr_atomic_probe(int32_t *counters, int32_t log2_counters,
+                            int32_t blocks, int32_t per_thread, double *ms,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

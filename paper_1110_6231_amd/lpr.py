@@ -38,6 +38,7 @@ EXPORTED = [
     "lpr_assign_batched_workspace", "lpr_assign_solve_batched",
     "lpr_pricenet_param_count", "lpr_pricenet_workspace",
     "lpr_pricenet_features", "lpr_pricenet_infer", "lpr_pricenet_train_step",
+    "lpr_atomic_probe",
 ]
 PRICENET_FEATURES = 16
 PRICENET_WIDTH = 128
@@ -153,6 +154,8 @@ def lib():
     L.lpr_pricenet_train_step.restype = ctypes.c_int
     L.lpr_pricenet_train_step.argtypes = [i32, i32p, i64p, vp, i32, vp, vp, vp, vp,
                                           vp, i32, ctypes.c_float, vp, vp, sz, vp]
+    L.lpr_atomic_probe.restype = ctypes.c_int
+    L.lpr_atomic_probe.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     _lib = L
     return L
 
@@ -482,3 +485,14 @@ def lpr_pricenet_train_step(packed: PackedAssign, target_prices, params,
         float(lr), _ptr(loss), _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "lpr_pricenet_train_step")
     return float(loss.item()), grad
+
+
+def lpr_atomic_probe(counters, log2_counters, blocks, per_thread, stream=None):
+    """Kernel time (ms) of blocks * 256 * per_thread non-returning atomic adds
+    into the device int32 tensor `counters` (2^log2_counters entries)."""
+    assert counters.numel() == (1 << log2_counters) and counters.dtype.itemsize == 4
+    ms = ctypes.c_double(0)
+    rc = lib().lpr_atomic_probe(_ptr(counters), int(log2_counters), int(blocks),
+                                int(per_thread), ctypes.byref(ms), _stream(stream))
+    _check(rc, "lpr_atomic_probe")
+    return ms.value

@@ -63,3 +63,14 @@ def test_struct_layouts():
     assert ctypes.sizeof(lpr.AssignOpts) == 64
     assert ctypes.sizeof(lpr.GridStats) == 8 * 8 + 4 * 4 + 3 * 8
     assert ctypes.sizeof(lpr.AssignStats) == 8 * 8 + 2 * 8
+
+
+def test_atomic_probe_rejects_bad_arguments():
+    """Argument checks run on the host before anything reaches the device."""
+    import ctypes
+    L = lpr.lib()
+    ms = ctypes.c_double(0)
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below is rejected
+    for args in ((None, 10, 1, 1), (fake, 5, 1, 1), (fake, 29, 1, 1),
+                 (fake, 10, 0, 1), (fake, 10, 1, 0), (fake, 10, 1, 4097)):
+        assert L.lpr_atomic_probe(*args, ctypes.byref(ms), None) == lpr.LPR_EINVAL
