@@ -13,6 +13,8 @@ on this host (FIFO push-relabel for the grid, Hungarian for the assignment
 legs).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       python bench.py --assign-only   (the n = 1024 assignment alone, for
+                                        counter profiles of its kernel)
 """
 from __future__ import annotations
 
@@ -53,6 +55,9 @@ def parse():
     ap.add_argument("--no-assign", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-batched-grid", action="store_true")
+    ap.add_argument("--assign-only", action="store_true",
+                    help="only time the n = 1024 assignment (for counter "
+                         "profiles of the solve kernel) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain copies of a known size (counter "
                          "calibration) and exit")
@@ -212,24 +217,29 @@ def copy_probe(torch, mib=256, reps=5):
                       "launches": reps}), flush=True)
 
 
-def assign_leg(args, torch, lpr, synth):
+def assign_single(torch, lpr, synth, reps=3):
+    """The dense n = 1024 max-weight assignment, mean of `reps` solves."""
     dev = torch.device("cuda:0")
     cost = torch.as_tensor(synth.assign_uniform(1024, seed=0), device=dev)
     ws = torch.empty(lpr.lpr_assign_workspace(1024), dtype=torch.uint8, device=dev)
     lpr.lpr_assign_solve(cost, maximize=True, workspace=ws)
-    reps = 3
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         _, tot, _, st = lpr.lpr_assign_solve(cost, maximize=True, workspace=ws)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    out = {"workload": "dense assignment n=1024, weights U{0..1000}, "
-                       "max-weight, alpha=8, plain start",
-           "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(dt * 1e3, 3),
-           "total": tot, "refines": st["refines"], "phases": st["phases"],
-           "pushes": st["pushes"], "relabels": st["relabels"],
-           "price_updates": st["price_updates"]}
+    return {"workload": "dense assignment n=1024, weights U{0..1000}, "
+                        "max-weight, alpha=8, plain start",
+            "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(dt * 1e3, 3),
+            "total": tot, "refines": st["refines"], "phases": st["phases"],
+            "pushes": st["pushes"], "relabels": st["relabels"],
+            "price_updates": st["price_updates"]}
+
+
+def assign_leg(args, torch, lpr, synth):
+    dev = torch.device("cuda:0")
+    out = assign_single(torch, lpr, synth)
     from paper_1110_6231_amd.train_pricenet import learned_solve, load_weights
     mats = synth.assign_batch(seed=0)
     packed = lpr.PackedAssign.from_matrices(mats, device=dev)
@@ -364,6 +374,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.assign_only:
+        print(json.dumps({"assignment": assign_single(torch, lpr, synth)}), flush=True)
         return
     g = grid_leg(args, torch, lpr, synth)
     out = {
