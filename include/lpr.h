@@ -216,6 +216,21 @@ lpr_status lpr_grid_tune(int32_t B, const int32_t *H, const int32_t *W,
 #define LPR_ASSIGN_NO_START_UPDATE 0x2 /* skip the global price update that
                                           otherwise runs right after each
                                           refine's first push of every row  */
+#define LPR_ASSIGN_ARC_FIXING 0x4 /* arc fixing (Section 5): once
+                                     (4n+2) eps < max|c| S, each refine
+                                     ends by keeping per row only the arcs
+                                     less than (4n+2) eps above the row
+                                     minimum
+                                     (a reduced cost above 2|V| eps never
+                                     carries flow again) and later row
+                                     scans read that list; after the last
+                                     refine every row is checked for
+                                     1-optimality over all arcs, and a
+                                     failure reruns that refine with full
+                                     scans (fixing_reruns).  Off by
+                                     default: on the measured workloads
+                                     the lists stay long until the last
+                                     refines and the solve is not faster */
 
 typedef struct {
     int32_t alpha;                  /* epsilon divisor per refine; 0 -> 8    */
@@ -244,7 +259,13 @@ typedef struct {
                                        running operations back to back once
                                        at most this many rows are active;
                                        0 -> min(32, max(8, 8192 / n))        */
-    int32_t reserved;               /* must be 0                             */
+    int32_t fixing_shift;           /* for tests of the rerun path: divides
+                                       the arc-fixing bound by
+                                       2^fixing_shift (0..63; 0 = the
+                                       bound above, 63 keeps only each
+                                       row's matched arc); a bound that
+                                       drops needed arcs is caught by the
+                                       final check and costs a rerun       */
 } lpr_assign_opts;
 
 typedef struct {
@@ -255,7 +276,9 @@ typedef struct {
     int64_t scans;      /* arc scans of X rows (each reads n costs)       */
     int64_t price_updates; /* global price updates (Algorithm 5.3)        */
     int64_t price_update_us; /* time inside them, summed over instances   */
-    int64_t reserved;
+    int64_t fixing_reruns;   /* last refines rerun with full scans because
+                                the arc-fixed matching failed the
+                                1-optimality check (expected 0)          */
     double kernel_ms;   /* with LPR_ASSIGN_TIME_KERNELS: solve kernel time */
     double total_ms;    /* device time of the whole call (HIP events)      */
 } lpr_assign_stats;

@@ -100,6 +100,11 @@ struct AArgs {
     int64_t pu_period;             // pushes between price updates; 0: n, < 0: never
     int32_t tail_rows;             // serial tail threshold (active rows)
     int32_t pu_start;              // price update after each refine's first push
+    int32_t arc_fixing;            // keep candidate lists of unfixed arcs
+    int32_t fixing_shift;          // the bound divided by 2^fixing_shift
+    int32_t *cand;                 // per row: (y << 16 | c16(x,y)) of the arcs
+                                   // not fixed yet, row stride ld16(n)
+    int32_t *ncand;                // per row: number of them
     uint64_t max_ticks;            // wall-clock budget in wall_clock64 ticks
     unsigned long long *counters;  // refines, phases, pushes, relabels, scans,
                                    // price updates, wall-clock ticks in them
@@ -278,6 +283,34 @@ __device__ inline void row_min(const T *__restrict__ row, const int64_t *py,
     int a = 0, ca = 0;
     // |S*sign| <= 2*2048+1 fits 32 bits
     lane_scan(row, py, n, int32_t(sgnS), lane, b, a, ca);
+    const int64_t m = wave_min64(b);
+    const unsigned long long hit = __ballot(b == m);
+    const int src = __ffsll((long long)hit) - 1;
+    best = m;
+    arg = __builtin_amdgcn_readlane(a, src);
+    carg = __builtin_amdgcn_readlane(ca, src);
+}
+
+// Row minimum over a candidate list: entries (y << 16) | (c(x,y) & 0xffff) of
+// int16 costs, K of them.  Same value as the full scan when the list holds
+// the row's minimising column; ties go to the smallest column of a lane's
+// entries, then to the lowest lane.
+__device__ inline void row_min_list(const int32_t *__restrict__ list, int K,
+                                    const int64_t *py, int64_t sgnS, int lane,
+                                    int64_t &best, int &arg, int &carg) {
+    int64_t b = LLONG_MAX;
+    int a = 0, ca = 0;
+    for (int k = lane; k < K; k += 64) {
+        const int w = list[k];
+        const int y = int(uint32_t(w) >> 16);
+        const int c = int(int16_t(w & 0xffff));
+        const int64_t v = int64_t(__mul24(c, int32_t(sgnS))) - py[y];
+        if (v < b || (v == b && y < a)) {
+            b = v;
+            a = y;
+            ca = c;
+        }
+    }
     const int64_t m = wave_min64(b);
     const unsigned long long hit = __ballot(b == m);
     const int src = __ffsll((long long)hit) - 1;
@@ -507,6 +540,77 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
     __syncthreads();
 }
 
+// Arc fixing (Section 5's second heuristic): for an eps-optimal flow, an arc
+// whose reduced cost exceeds 2 |V| eps never changes its flow again.  At the
+// end of a refine the flow is a perfect matching, eps-optimal with the
+// current prices, and for row x every c_p(x,y) >= -eps, so c_p(x,y) >=
+// r(x,y) - eps with r(x,y) = c'_p(x,y) - min_y' c'_p(x,y').  The row keeps
+// the arcs with r < keep_r = (2 |V| + 2) eps (|V| = 2n) and its
+// matched arc; later row scans read only that list (which holds the row's
+// minimising column whenever the fixed arcs are indeed never used).  Every
+// wavefront compacts its rows in place; called by every thread, no barrier.
+__device__ void fix_arcs(const int16_t *__restrict__ C, int ldc, int32_t *cand,
+                         int32_t *ncand, bool lists, const int64_t *py,
+                         const int32_t *mate, int n, int64_t sgnS, int64_t keep_r,
+                         int wave, int lane) {
+    for (int x = wave; x < n; x += NW) {
+        int32_t *list = cand + int64_t(x) * ldc;
+        const int16_t *row = C + int64_t(x) * ldc;
+        const int K = lists ? ncand[x] : n;
+        const int mx = mate[x];
+        int64_t b = LLONG_MAX;
+        for (int k = lane; k < K; k += 64) {
+            const int w = lists ? list[k] : 0;
+            const int y = lists ? int(uint32_t(w) >> 16) : k;
+            const int c = lists ? int(int16_t(w & 0xffff)) : int(row[k]);
+            const int64_t v = int64_t(__mul24(c, int32_t(sgnS))) - py[y];
+            b = v < b ? v : b;
+        }
+        const int64_t m = wave_min64(b);
+        int out = 0;
+        for (int k0 = 0; k0 < K; k0 += 64) {
+            const int k = k0 + lane;
+            int w = 0;
+            bool keep = false;
+            if (k < K) {
+                const int lw = lists ? list[k] : 0;
+                const int y = lists ? int(uint32_t(lw) >> 16) : k;
+                const int c = lists ? int(int16_t(lw & 0xffff)) : int(row[k]);
+                const int64_t v = int64_t(__mul24(c, int32_t(sgnS))) - py[y];
+                keep = v - m < keep_r || y == mx;
+                w = (y << 16) | (c & 0xffff);
+            }
+            // every lane has read its entry before any lane writes (the
+            // ballot), and the write position never passes k0 + 63
+            const unsigned long long bal = __ballot(keep);
+            if (keep) list[out + __popcll(bal & ((1ull << lane) - 1))] = w;
+            out += __popcll(bal);
+        }
+        if (lane == 0) ncand[x] = out;
+    }
+}
+
+// 1 if some row's matched arc is not within 2 (scaled units) of its row
+// minimum over all columns, i.e. the final matching is not 1-optimal for any
+// row prices; else 0.  Full scans of every row.  Called by every thread.
+template <typename T>
+__device__ bool not_one_optimal(const T *__restrict__ C, int ldc, const int64_t *py,
+                                const int32_t *mate, int n, int64_t sgnS, int wave,
+                                int lane, int *flag) {
+    for (int x = wave; x < n; x += NW) {
+        int64_t best;
+        int arg, carg;
+        row_min(C + int64_t(x) * ldc, py, n, sgnS, lane, best, arg, carg);
+        if (lane == 0) {
+            const int y = mate[x];
+            const int64_t cm = int64_t(C[int64_t(x) * ldc + y]) * sgnS - py[y];
+            if (cm - best > 2) atomicOr(flag, 1);
+        }
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
 constexpr int HOT = 64;  // columns with e(y) >= HOT are resolved by the workgroup
 
 // The same operation as resolve_column for a column with many matched rows
@@ -628,13 +732,13 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     const int tail_exit = max(TAIL_EXIT, 4 * tail_enter);
     __shared__ int s_nx, s_ny, s_stop, s_qh, s_nh;
     __shared__ unsigned long long s_pu_mark;  // pushes at the last price update
-    __shared__ unsigned long long s_cnt[7];
+    __shared__ unsigned long long s_cnt[8];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t t_start = wall_clock64();
     const int64_t S = 2 * int64_t(n) + 1;
     const int64_t sgnS = int64_t(A.sign) * S;
-    if (tid < 7) s_cnt[tid] = 0;
+    if (tid < 8) s_cnt[tid] = 0;
     if (tid == 0) {
         s_nx = 0;
         s_ny = 0;
@@ -651,6 +755,22 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     int64_t eps = A.eps0 > 0 ? A.eps0 : (cmax > 0 ? int64_t(cmax) * S : 1);
     if (A.eps0_inst && A.eps0_inst[slot] > 0) eps = A.eps0_inst[slot];
     const int64_t alpha = A.alpha;
+    // candidate lists of unfixed arcs (int16 costs only); `lists` is the same
+    // in every thread
+    const bool fixing = sizeof(T) == 2 && A.arc_fixing && A.cand;
+    int32_t *cand = fixing ? A.cand + I.c16_off : nullptr;
+    int32_t *ncand = fixing ? A.ncand + I.row_off : nullptr;
+    bool lists = false;
+    __shared__ int s_bad;
+    // the least part-reduced cost of row x over its candidates (all columns
+    // without lists)
+    auto scan = [&](int x, int64_t &best, int &arg, int &carg) {
+        if (lists)
+            row_min_list(cand + int64_t(x) * ldc, ncand[x], py, sgnS, lane, best, arg,
+                         carg);
+        else
+            row_min(C + int64_t(x) * ldc, py, n, sgnS, lane, best, arg, carg);
+    };
 
     for (;;) {
         eps = eps / alpha;
@@ -666,7 +786,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
         for (int x = wave; x < n; x += NW) {
             int64_t best;
             int arg, carg;
-            row_min(C + int64_t(x) * ldc, py, n, sgnS, lane, best, arg, carg);
+            scan(x, best, arg, carg);
             if (lane == 0) {
                 px[x] = -(best + eps);
                 L.mate[x] = arg;
@@ -763,7 +883,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                         --qlen;
                         int64_t best;
                         int arg, carg;
-                        row_min(C + int64_t(x) * ldc, py, n, sgnS, lane, best, arg, carg);
+                        scan(x, best, arg, carg);
                         const int old = L.head[arg], e = L.ey[arg];
                         int64_t pxx = px[x];
                         if (best + pxx >= 0) {
@@ -842,7 +962,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                 const int x = L.xl[qh0 + i < n ? qh0 + i : qh0 + i - n];
                 int64_t best;
                 int arg, carg;
-                row_min(C + int64_t(x) * ldc, py, n, sgnS, lane, best, arg, carg);
+                scan(x, best, arg, carg);
                 if (lane == 0) {
                     if (best + px[x] >= 0) {  // relabel, then the arc is admissible
                         px[x] = -(best + eps);
@@ -862,7 +982,30 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             __syncthreads();
         }
         if (s_stop) break;
-        if (eps == 1) break;
+        if (eps == 1) {
+            if (!lists) break;
+            // the lists rest on arc fixing's bound: confirm 1-optimality over
+            // all arcs, else run the last refine again with full scans
+            if (tid == 0) s_bad = 0;
+            __syncthreads();
+            if (!not_one_optimal(C, ldc, py, L.mate, n, sgnS, wave, lane, &s_bad)) break;
+            lists = false;
+            eps = alpha;  // the next refine runs at eps = 1 again
+            if (tid == 0) atomicAdd(&s_cnt[7], 1ull);
+            __syncthreads();
+            continue;
+        }
+        if constexpr (sizeof(T) == 2) {
+            const int64_t bound = (4 * int64_t(n) + 2) * eps;
+            const int64_t keep_r = bound >> A.fixing_shift;
+            // only once the bound can drop arcs (every r is at most about
+            // 2 max|c| S)
+            if (fixing && bound < int64_t(cmax) * S) {
+                fix_arcs(C, ldc, cand, ncand, lists, py, L.mate, n, sgnS, keep_r, wave,
+                         lane);
+                lists = true;
+            }
+        }
         __syncthreads();
     }
     __syncthreads();
@@ -889,7 +1032,7 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             A.status[slot] = 0;
         }
     }
-    if (tid < 7 && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
+    if (tid < 8 && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
 }
 
 __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
@@ -919,6 +1062,7 @@ struct Layout {
     unsigned *cmax;
     unsigned long long *counters;
     int16_t *c16, *c16t;
+    int32_t *cand, *ncand;
 };
 
 static int64_t c16_elems(int B, const int32_t *n) {
@@ -935,6 +1079,10 @@ static Carver carve(Carver cv, int B, const int32_t *n, Layout *L) {
     L->counters = cv.take<unsigned long long>(8);
     L->c16 = cv.take<int16_t>(size_t(c16_elems(B, n)));
     L->c16t = cv.take<int16_t>(size_t(c16_elems(B, n)));
+    int64_t rows = 0;
+    for (int b = 0; b < B; ++b) rows += n[b];
+    L->cand = cv.take<int32_t>(size_t(c16_elems(B, n)));
+    L->ncand = cv.take<int32_t>(size_t(rows));
     return cv;
 }
 
@@ -987,7 +1135,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     int32_t alpha = 8;
     int64_t eps0 = 0, max_ops = 64 * int64_t(nmax) * nmax + (int64_t(1) << 20);
     int64_t max_ms = 20000, pu_period = 0;
-    int32_t tail_rows = 0, pu_start = 1;
+    int32_t tail_rows = 0, pu_start = 1, arc_fixing = 0, fixing_shift = 0;
     const int64_t *init = nullptr, *eps0_inst = nullptr;
     bool timing = false;
     if (opts) {
@@ -1000,10 +1148,12 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         pu_period = opts->price_update_period;
         tail_rows = opts->tail_rows;
         pu_start = (opts->flags & LPR_ASSIGN_NO_START_UPDATE) == 0;
+        arc_fixing = (opts->flags & LPR_ASSIGN_ARC_FIXING) != 0;
+        fixing_shift = opts->fixing_shift;
         timing = (opts->flags & LPR_ASSIGN_TIME_KERNELS) != 0;
     }
     if (alpha < 2 || eps0 < 0 || max_ops < 0 || max_ms < 0 || tail_rows < 0 ||
-        tail_rows > 4096) {
+        tail_rows > 4096 || fixing_shift < 0 || fixing_shift > 63) {
         set_error("invalid lpr_assign_opts");
         return LPR_EINVAL;
     }
@@ -1054,6 +1204,10 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     A.pu_period = pu_period;
     A.tail_rows = tail_rows;
     A.pu_start = pu_start;
+    A.arc_fixing = arc_fixing;
+    A.fixing_shift = fixing_shift;
+    A.cand = L.cand;
+    A.ncand = L.ncand;
     int khz = 0;  // wall_clock64 ticks per millisecond
     {
         int dev = 0;
@@ -1092,6 +1246,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         stats->scans = int64_t(cnt[4]);
         stats->price_updates = int64_t(cnt[5]);
         stats->price_update_us = int64_t(cnt[6] * 1000 / uint64_t(khz));
+        stats->fixing_reruns = int64_t(cnt[7]);
         stats->kernel_ms = kms;
         stats->total_ms = tms;
     }

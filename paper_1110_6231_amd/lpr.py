@@ -27,6 +27,7 @@ LPR_GRID_TIME_KERNELS = 0x1
 LPR_GRID_NO_GRAPH = 0x2
 LPR_ASSIGN_TIME_KERNELS = 0x1
 LPR_ASSIGN_NO_START_UPDATE = 0x2
+LPR_ASSIGN_ARC_FIXING = 0x4
 
 # Every symbol the header declares (checked by the ABI test).
 EXPORTED = [
@@ -80,7 +81,7 @@ class AssignOpts(ctypes.Structure):
                 ("max_ms", ctypes.c_int64),
                 ("eps0_per_instance", ctypes.c_void_p),
                 ("price_update_period", ctypes.c_int64),
-                ("tail_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tail_rows", ctypes.c_int32), ("fixing_shift", ctypes.c_int32)]
 
 
 class AssignStats(ctypes.Structure):
@@ -88,7 +89,7 @@ class AssignStats(ctypes.Structure):
                 ("pushes", ctypes.c_int64), ("relabels", ctypes.c_int64),
                 ("scans", ctypes.c_int64), ("price_updates", ctypes.c_int64),
                 ("price_update_us", ctypes.c_int64),
-                ("reserved", ctypes.c_int64),
+                ("fixing_reruns", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
@@ -316,11 +317,13 @@ def lpr_grid_tune(Hs, Ws, caps_packed, reps=2, workspace=None, stream=None):
 # ---------------------------------------------------------------------------
 def make_assign_opts(alpha=0, eps0=0, init_col_prices=None, max_ops=0,
                      flags=0, max_ms=0, eps0_per_instance=None,
-                     price_update_period=0, tail_rows=0) -> AssignOpts:
+                     price_update_period=0, tail_rows=0,
+                     fixing_shift=0) -> AssignOpts:
     o = AssignOpts()
     o.max_ms = max_ms
     o.price_update_period = price_update_period
     o.tail_rows = tail_rows
+    o.fixing_shift = fixing_shift
     o.eps0_per_instance = (None if eps0_per_instance is None
                            else eps0_per_instance.data_ptr())
     o.alpha = alpha

@@ -100,6 +100,41 @@ def test_alpha_eps_and_warm_start():
             init_col_prices=torch.as_tensor(edge, device="cuda")))
 
 
+@pytest.mark.parametrize("n", [64, 257, 700])
+def test_arc_fixing_stays_exact(n):
+    """Arc fixing (Section 5) with the bound (4n+2) eps: same optimum, and the
+    final all-arcs check never has to rerun a refine."""
+    fix = lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_ARC_FIXING)
+    st = check(synth.assign_random_small(n, seed=n + 7, lo=0, hi=1000), opts=fix)
+    assert st["fixing_reruns"] == 0
+    st = check(synth.assign_points(n, seed=1, instance=n), opts=fix)
+    assert st["fixing_reruns"] == 0
+    st = check(synth.assign_random_small(n, seed=n, lo=-1000, hi=1000), maximize=True,
+               opts=fix)
+    assert st["fixing_reruns"] == 0
+
+
+def test_arc_fixing_uniform_n1024():
+    fix = lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_ARC_FIXING)
+    st = check(synth.assign_uniform(1024, seed=1), maximize=True, opts=fix)
+    assert st["fixing_reruns"] == 0
+
+
+def test_arc_fixing_rerun_path():
+    """A bound shrunk far below the theorem's drops arcs the optimum needs:
+    the final check must catch it and the rerun with full scans must still
+    return the optimum."""
+    # costs up to 30000: the first lists are built after a refine at an eps
+    # of several cost units, whose matching is not yet optimal; with only
+    # the matched arc kept, the later refines cannot improve it
+    c = synth.assign_random_small(300, seed=11, lo=0, hi=30000)
+    st = check(c, opts=lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_ARC_FIXING,
+                                            fixing_shift=63))
+    assert st["fixing_reruns"] == 1
+    with pytest.raises(lpr.LprError):
+        lpr.lpr_assign_solve(c, opts=lpr.make_assign_opts(fixing_shift=64))
+
+
 @pytest.mark.parametrize("tail,flags,period", [
     (1, 0, 0), (2, lpr.LPR_ASSIGN_NO_START_UPDATE, 0), (64, 0, 1),
     (4096, 0, 0), (8, 0, -1), (0, lpr.LPR_ASSIGN_NO_START_UPDATE, -1),
