@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-assign", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-batched-grid", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the arbitrary-network max-flow leg")
     ap.add_argument("--assign-only", action="store_true",
                     help="only time the n = 1024 assignment (for counter "
                          "profiles of the solve kernel) and print its JSON")
@@ -286,6 +288,44 @@ def assign_leg(args, torch, lpr, synth):
     return out
 
 
+def graph_leg(args, torch, lpr, synth):
+    """Form 1 on arbitrary networks (arc lists in mate pairs): a layered
+    network with long augmenting paths and a 512 x 512 blob graph cut given as
+    an arc list, each solved three times (median)."""
+    out = {}
+    cases = {
+        "layered 64 x 4096, 4 arcs per node": synth.graph_layered(64, 4096, 4, seed=0),
+        "512x512 graph cut as an arc list": synth.grid_to_arcs(synth.grid_blobs(512, 512, seed=0)),
+    }
+    for name, (n, tail, head, cap, s, t) in cases.items():
+        arrs = [torch.as_tensor(a, device="cuda") for a in (tail, head, cap)]
+        ws = torch.empty(lpr.lpr_graph_maxflow_workspace(n, len(tail)), dtype=torch.uint8,
+                         device="cuda")
+        lpr.lpr_graph_maxflow(n, *arrs, s, t, workspace=ws)
+        print(f"[bench] graph warmup done: {name}", file=sys.stderr, flush=True)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v, _, st = lpr.lpr_graph_maxflow(n, *arrs, s, t, workspace=ws)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        dt = float(np.median(ts))
+        out[name] = {"nodes": n, "arcs": len(tail), "flow_value": v,
+                     "ms_per_solve": round(dt * 1e3, 3),
+                     "mvertex_per_s": round(n / dt / 1e6, 3),
+                     "rounds": st["rounds"], "pushes": st["pushes"],
+                     "bfs_levels": st["bfs_levels"]}
+        if not args.no_cpu:
+            # the FIFO push-relabel oracle on one host core, one solve
+            import oracle
+            t0 = time.perf_counter()
+            vc = oracle.graph_maxflow(n, tail, head, cap, s, t)[0]
+            assert vc == v, (vc, v)
+            out[name]["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    return out
+
+
 def atomics_leg(torch, lpr, g):
     """Push updates per second of the 1024 x 1024 solve (four atomic word
     updates per push in Algorithm 4.5) next to the measured ceiling of
@@ -408,6 +448,8 @@ def main():
     }
     if not args.no_batched_grid:
         out["grid_batched"] = grid_batched_leg(args, torch, lpr, synth)
+    if not args.no_graph:
+        out["graph"] = graph_leg(args, torch, lpr, synth)
     if not args.no_assign:
         out["assignment"] = assign_leg(args, torch, lpr, synth)
         if not args.no_cpu:

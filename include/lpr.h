@@ -411,6 +411,56 @@ lpr_status lpr_pricenet_train_step(int32_t B, const int32_t *n,
                                    size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Form 1 on an arbitrary directed graph (Section 4 with the node/adjacency
+ * representation of the paper's implementation).
+ * ------------------------------------------------------------------------- */
+#define LPR_GRAPH_MAX_N (1 << 27)
+
+typedef struct {
+    int32_t cycle;       /* push/relabel operations per node per sweep (the
+                            paper's CYCLE); 0 -> 64                         */
+    int32_t max_rounds;  /* sweeps (each followed by a global relabel);
+                            0 -> 100000                                     */
+    int32_t reserved[2]; /* must be 0                                       */
+} lpr_graph_opts;
+
+typedef struct {
+    int64_t rounds;      /* sweeps                                           */
+    int64_t pushes;      /* push operations                                  */
+    int64_t relabels;    /* relabel operations (in the sweeps)               */
+    int64_t bfs_levels;  /* BFS levels launched (global relabels, closure)   */
+    double total_ms;     /* device time of the whole call (HIP events)       */
+} lpr_graph_stats;
+
+/* Device workspace bytes for lpr_graph_maxflow (0 if n < 2, m < 0 or m odd). */
+size_t lpr_graph_maxflow_workspace(int32_t n, int32_t m);
+
+/*
+ * Maximum s-t flow of a directed network (Section 3's flow network; Section
+ * 4's lock-free push-relabel with global relabel and gap).
+ *   n                nodes 0..n-1 (2 <= n <= LPR_GRAPH_MAX_N); s != t.
+ *   m                arcs, even: arcs a and a^1 are each other's reverse
+ *                    (tail[a^1] == head[a], head[a^1] == tail[a]); an
+ *                    undirected edge or a one-way arc is a pair with the
+ *                    reverse capacity given (0 for one-way).
+ *   tail, head, cap  device int32 [m]; cap >= 0 and cap[a] + cap[a^1] <=
+ *                    2^31 - 1.  Parallel arcs and self-loops are allowed.
+ *   flow_value       host int64 [1]: the maximum flow value.
+ *   source_side      device uint8 [n] or NULL: 1 for the nodes of the
+ *                    minimal source side of a minimum cut (the residual
+ *                    closure of s and of the nodes left with excess).
+ * Errors: LPR_EINVAL (arguments, arcs not in mate pairs or out of range),
+ * LPR_ERANGE (capacity), LPR_ENOMEM (workspace too small), LPR_EBUDGET
+ * (max_rounds), LPR_EDEVICE.  Returns after completion.
+ */
+lpr_status lpr_graph_maxflow(int32_t n, int32_t m, const int32_t *tail,
+                             const int32_t *head, const int32_t *cap, int32_t s,
+                             int32_t t, int64_t *flow_value, uint8_t *source_side,
+                             const lpr_graph_opts *opts, lpr_graph_stats *stats,
+                             void *workspace, size_t workspace_bytes,
+                             void *stream);
+
+/* ---------------------------------------------------------------------------
  * Measurement helper (not part of the method).  Section 4's pushes each
  * update four words with atomics; this gives the device's rate for such
  * updates: `blocks` x 256 threads each add 1 with a non-returning

@@ -1,0 +1,451 @@
+// Form 1 on an arbitrary directed graph: lock-free push-relabel max-flow on
+// an explicit arc list, gfx950.
+//
+// Method (Section 4).  The network is given as arcs in mate pairs (arc a^1 is
+// the reverse of a, as in the node/adjacency design of Section 4.3's
+// implementation): u_f(a) = cap(a) - f(a) with a skew-symmetric pseudoflow.
+// Init (Algorithm 4.7) saturates every arc leaving s and sets h(s) = |V|.
+// The push/relabel operation is Algorithm 4.5 (Hong): an active node u
+// (e(u) > 0, h(u) < |V|) finds the lowest neighbour w over its residual arcs;
+// if h(u) > h(w) it pushes min(e(u), u_f(u,w)) with atomic updates of the two
+// residuals and the two excesses, otherwise it relabels h(u) = h(w) + 1
+// (only u's thread writes h(u)).  Between sweeps, the global relabel of
+// Algorithm 4.4 recomputes h as the exact BFS distance to t over reverse
+// residual arcs; nodes it does not reach get |V| (the gap step).  The solver
+// stops when no node is active right after an exact relabel (Algorithm
+// 4.8's termination, e(s) + e(t) = total): the preflow is then maximum, e(t)
+// is the flow value, and the residual closure of s and of the nodes with
+// excess is the minimal source side of a minimum cut.
+//
+// GPU design.  The arc list is turned into a CSR adjacency by tail on the
+// device (degree count, exclusive scan, scatter).  A sweep is one thread per
+// node running up to `cycle` operations (the paper's CYCLE); stale reads are
+// lower bounds (residuals and excesses shrink only by their owner, heights
+// only grow), the staleness Hong's argument admits.  The BFS runs level by
+// level over a frontier queue (one launch per level over the whole device,
+// frontier sizes kept on the device, the host checking once per batch of
+// levels).
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "lpr_internal.h"
+
+namespace lpr {
+namespace graph {
+
+constexpr int NTB = 256;
+constexpr int LEVEL_BATCH = 16;  // BFS levels launched between host checks
+
+struct G {
+    int n, m, s, t;
+    const int32_t *tail, *head, *cap;
+    int32_t *off;    // [n + 1] CSR offsets over arcs grouped by tail
+    int32_t *adj;    // [m] arc ids
+    int32_t *cur;    // [n] scatter cursors
+    int32_t *res;    // [m] residual capacities
+    int64_t *e;      // [n] excesses
+    int32_t *h;      // [n] heights
+    int32_t *lab;    // [n] BFS labels / closure marks
+    int32_t *q[2];   // frontier queues
+    int32_t *qn;     // [n + 2] frontier size per level
+    unsigned long long *cnt;  // pushes, relabels, active, error bits
+    int32_t *bsum;   // block sums of the scan
+};
+
+// Checks the mate-pair structure and ranges (error bits: 1 range or
+// structure, 2 capacity) and counts out-degrees into off[tail + 1].
+__global__ __launch_bounds__(NTB) void k_validate(G g) {
+    for (int a = blockIdx.x * NTB + threadIdx.x; a < g.m; a += gridDim.x * NTB) {
+        const int u = g.tail[a], v = g.head[a];
+        unsigned bits = 0;
+        if (u < 0 || u >= g.n || v < 0 || v >= g.n) {
+            bits |= 1;
+        } else {
+            if (g.tail[a ^ 1] != v || g.head[a ^ 1] != u) bits |= 1;
+            const int64_t c = g.cap[a], cr = g.cap[a ^ 1];
+            // u_f(a) + u_f(a^1) = cap(a) + cap(a^1) stays below 2^31
+            if (c < 0 || c + cr > int64_t(INT_MAX)) bits |= 2;
+            atomicAdd(&g.off[u + 1], 1);
+        }
+        if (bits) atomicOr(&g.cnt[3], (unsigned long long)bits);
+    }
+}
+
+// Exclusive scan of off[0..n] in place (off[0] = 0 on entry): per-block
+// inclusive scans of 1024 entries, then the block sums, then the offsets.
+__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t *x, int len, int32_t *bsum) {
+    __shared__ int32_t s[1024];
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    s[threadIdx.x] = i < len ? x[i] : 0;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int32_t v = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (i < len) x[i] = s[threadIdx.x];
+    if (threadIdx.x == 1023) bsum[blockIdx.x] = s[1023];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *bsum, int nb) {
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    __shared__ int32_t s[1024];
+    for (int base = 0; base < nb; base += 1024) {
+        const int i = base + threadIdx.x;
+        s[threadIdx.x] = i < nb ? bsum[i] : 0;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int32_t v = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += v;
+            __syncthreads();
+        }
+        // exclusive prefix of the block sums
+        if (i < nb) bsum[i] = carry + s[threadIdx.x] - (i < nb ? bsum[i] : 0);
+        __syncthreads();
+        if (threadIdx.x == 0) carry += s[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_add(int32_t *x, int len, const int32_t *bsum) {
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    if (i < len) x[i] += bsum[blockIdx.x];
+}
+
+__global__ __launch_bounds__(NTB) void k_scatter(G g) {
+    for (int a = blockIdx.x * NTB + threadIdx.x; a < g.m; a += gridDim.x * NTB) {
+        const int u = g.tail[a];
+        g.adj[g.off[u] + atomicAdd(&g.cur[u], 1)] = a;
+    }
+}
+
+// Init (Algorithm 4.7) part 1: u_f = cap, e = 0, h = 0 except h(s) = |V|.
+__global__ __launch_bounds__(NTB) void k_init(G g) {
+    for (int a = blockIdx.x * NTB + threadIdx.x; a < g.m; a += gridDim.x * NTB)
+        g.res[a] = g.cap[a];
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB) {
+        g.e[v] = 0;
+        g.h[v] = v == g.s ? g.n : 0;
+        g.cur[v] = 0;
+    }
+}
+
+// Init part 2: saturate every arc leaving s.
+__global__ __launch_bounds__(NTB) void k_saturate(G g) {
+    const int b = g.off[g.s], en = g.off[g.s + 1];
+    for (int j = b + blockIdx.x * NTB + threadIdx.x; j < en; j += gridDim.x * NTB) {
+        const int a = g.adj[j];
+        const int32_t d = g.res[a];
+        if (d <= 0 || g.head[a] == g.s) continue;
+        g.res[a] = 0;
+        atomicAdd(&g.res[a ^ 1], d);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&g.e[g.head[a]]),
+                  (unsigned long long)d);
+    }
+}
+
+// Algorithm 4.5, up to `cycle` operations per active node, one thread per
+// node.  A node with no residual arc at all cannot reach t: it takes |V|.
+__global__ __launch_bounds__(NTB) void k_push(G g, int cycle) {
+    unsigned long long pushes = 0, relabels = 0;
+    for (int u = blockIdx.x * NTB + threadIdx.x; u < g.n; u += gridDim.x * NTB) {
+        if (u == g.s || u == g.t) continue;
+        const int b = g.off[u], en = g.off[u + 1];
+        int hu = g.h[u];
+        for (int it = 0; it < cycle; ++it) {
+            const int64_t eu = g.e[u];
+            if (eu <= 0 || hu >= g.n) break;
+            int hmin = INT_MAX, amin = -1;
+            for (int j = b; j < en; ++j) {
+                const int a = g.adj[j];
+                const int w = g.head[a];
+                if (w == u || g.res[a] <= 0) continue;
+                const int hw = g.h[w];
+                if (hw < hmin) {
+                    hmin = hw;
+                    amin = a;
+                }
+            }
+            if (amin < 0) {
+                hu = g.n;
+                g.h[u] = hu;
+                ++relabels;
+                break;
+            }
+            if (hu > hmin) {
+                const int32_t r = g.res[amin];
+                const int32_t d = int32_t(eu < int64_t(r) ? eu : int64_t(r));
+                if (d <= 0) continue;
+                atomicSub(&g.res[amin], d);
+                atomicAdd(&g.res[amin ^ 1], d);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&g.e[u]),
+                          (unsigned long long)(-int64_t(d)));
+                atomicAdd(reinterpret_cast<unsigned long long *>(&g.e[g.head[amin]]),
+                          (unsigned long long)d);
+                ++pushes;
+            } else {
+                hu = hmin >= g.n - 1 ? g.n : hmin + 1;
+                g.h[u] = hu;
+                ++relabels;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        pushes += __shfl_xor(pushes, o, 64);
+        relabels += __shfl_xor(relabels, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (pushes) atomicAdd(&g.cnt[0], pushes);
+        if (relabels) atomicAdd(&g.cnt[1], relabels);
+    }
+}
+
+// BFS seeds.  Backward (global relabel): labels |V| except t at 0, frontier
+// {t}.  Forward (cut): marks s and every node with excess, frontier = them.
+__global__ __launch_bounds__(NTB) void k_bfs_seed(G g, int forward) {
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB) {
+        if (!forward) {
+            g.lab[v] = v == g.t ? 0 : g.n;
+            if (v == g.t) g.q[0][0] = v;
+        } else {
+            const bool in = v == g.s || (v != g.t && g.e[v] > 0);
+            g.lab[v] = in ? 1 : 0;
+            if (in) g.q[0][atomicAdd(&g.qn[0], 1)] = v;
+        }
+    }
+    if (!forward && blockIdx.x == 0 && threadIdx.x == 0) g.qn[0] = 1;
+}
+
+// Level L of a BFS over the frontier q[L & 1] (entries wid, wid + nwaves, ...
+// of its `size`): one wavefront per frontier node, its lanes over the node's
+// arcs (s and t, or any hub, can hold most arcs of the network).  Backward:
+// w reaches frontier node u over the residual arc (w,u) = a^1 of u's arc
+// a = (u,w); w gets L + 1 (s keeps |V|).  Forward: u reaches w over its
+// residual arc a; w is marked.  The next frontier goes to q[(L + 1) & 1].
+__device__ inline void bfs_expand(const G &g, int L, int forward, int size, int wid,
+                                  int nwaves, int lane) {
+    const int32_t *front = g.q[L & 1];
+    int32_t *next = g.q[(L + 1) & 1];
+    for (int i = wid; i < size; i += nwaves) {
+        const int u = front[i];
+        for (int j = g.off[u] + lane; j < g.off[u + 1]; j += 64) {
+            const int a = g.adj[j];
+            const int w = g.head[a];
+            if (!forward) {
+                if (w == g.s || g.res[a ^ 1] <= 0 || g.lab[w] != g.n) continue;
+                if (atomicCAS(&g.lab[w], g.n, L + 1) == g.n)
+                    next[atomicAdd(&g.qn[L + 1], 1)] = w;
+            } else {
+                if (g.res[a] <= 0 || g.lab[w] != 0) continue;
+                if (atomicCAS(&g.lab[w], 0, 1) == 0) next[atomicAdd(&g.qn[L + 1], 1)] = w;
+            }
+        }
+    }
+}
+
+// One BFS level L over the whole device.
+__global__ __launch_bounds__(NTB) void k_bfs_level(G g, int L, int forward) {
+    const int size = g.qn[L];
+    if (size == 0) return;
+    bfs_expand(g, L, forward, size, (blockIdx.x * NTB + threadIdx.x) >> 6,
+               (gridDim.x * NTB) >> 6, threadIdx.x & 63);
+}
+
+// Heights from the exact labels (unreached: |V|), and the active count.
+__global__ __launch_bounds__(NTB) void k_labels_count(G g) {
+    unsigned long long act = 0;
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB) {
+        if (v == g.s) continue;
+        const int hv = g.lab[v];
+        g.h[v] = hv;
+        if (v != g.t && hv < g.n && g.e[v] > 0) ++act;
+    }
+    for (int o = 32; o > 0; o >>= 1) act += __shfl_xor(act, o, 64);
+    if ((threadIdx.x & 63) == 0 && act) atomicAdd(&g.cnt[2], act);
+}
+
+__global__ __launch_bounds__(NTB) void k_side(G g, uint8_t *side) {
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB)
+        side[v] = uint8_t(g.lab[v] != 0);
+}
+
+static int blocks_for(int64_t k) {
+    return int(std::max<int64_t>(1, std::min<int64_t>(4096, (k + NTB - 1) / NTB)));
+}
+
+struct Layout {
+    int32_t *off, *adj, *cur, *res, *h, *lab, *q0, *q1, *qn, *bsum;
+    int64_t *e;
+    unsigned long long *cnt;
+};
+
+static Carver carve(Carver cv, int n, int m, Layout *L) {
+    L->off = cv.take<int32_t>(size_t(n) + 1);
+    L->adj = cv.take<int32_t>(size_t(std::max(m, 1)));
+    L->cur = cv.take<int32_t>(size_t(n));
+    L->res = cv.take<int32_t>(size_t(std::max(m, 1)));
+    L->h = cv.take<int32_t>(size_t(n));
+    L->lab = cv.take<int32_t>(size_t(n));
+    L->q0 = cv.take<int32_t>(size_t(n));
+    L->q1 = cv.take<int32_t>(size_t(n));
+    L->qn = cv.take<int32_t>(size_t(n) + 2);
+    L->bsum = cv.take<int32_t>(size_t((n + 1 + 1023) / 1024) + 1);
+    L->e = cv.take<int64_t>(size_t(n));
+    L->cnt = cv.take<unsigned long long>(4);
+    return cv;
+}
+
+// A BFS (backward labels or forward closure) to its end: levels launched in
+// batches, the host reading the frontier size once per batch.
+static lpr_status run_bfs(const G &g, int forward, hipStream_t s, int64_t *levels) {
+    LPR_TRY(fill_i32(g.qn, 0, int64_t(g.n) + 2, s));
+    hipLaunchKernelGGL(k_bfs_seed, dim3(blocks_for(g.n)), dim3(NTB), 0, s, g, forward);
+    LPR_TRY_HIP(hipGetLastError());
+    const int grid = blocks_for(g.n);
+    for (int L0 = 0; L0 <= g.n; L0 += LEVEL_BATCH) {
+        const int L1 = std::min(g.n + 1, L0 + LEVEL_BATCH);
+        for (int L = L0; L < L1; ++L)
+            hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(NTB), 0, s, g, L, forward);
+        LPR_TRY_HIP(hipGetLastError());
+        int32_t last = 0;
+        LPR_TRY_HIP(hipMemcpyAsync(&last, g.qn + L1, sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+        LPR_TRY_HIP(hipStreamSynchronize(s));
+        *levels += L1 - L0;
+        if (last == 0) return LPR_OK;
+    }
+    return LPR_OK;  // every level up to |V| done: the BFS is complete
+}
+
+}  // namespace graph
+}  // namespace lpr
+
+using namespace lpr;
+
+extern "C" size_t lpr_graph_maxflow_workspace(int32_t n, int32_t m) {
+    if (n < 2 || m < 0 || (m & 1)) return 0;
+    graph::Layout L;
+    return graph::carve(Carver(), n, m, &L).used();
+}
+
+extern "C" lpr_status lpr_graph_maxflow(int32_t n, int32_t m, const int32_t *tail,
+                                        const int32_t *head, const int32_t *cap,
+                                        int32_t s, int32_t t, int64_t *flow_value,
+                                        uint8_t *source_side,
+                                        const lpr_graph_opts *opts,
+                                        lpr_graph_stats *stats, void *workspace,
+                                        size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (n < 2 || m < 0 || (m & 1) || s < 0 || s >= n || t < 0 || t >= n || s == t ||
+        !flow_value || !workspace || (m > 0 && (!tail || !head || !cap)) ||
+        n > LPR_GRAPH_MAX_N) {
+        set_error("invalid arguments (n, m, s, t or a NULL pointer)");
+        return LPR_EINVAL;
+    }
+    int cycle = 64, max_rounds = 100000;
+    if (opts) {
+        if (opts->cycle) cycle = opts->cycle;
+        if (opts->max_rounds) max_rounds = opts->max_rounds;
+    }
+    if (cycle < 1 || max_rounds < 1) {
+        set_error("invalid lpr_graph_opts");
+        return LPR_EINVAL;
+    }
+    graph::Layout L;
+    const size_t need = graph::carve(Carver(), n, m, &L).used();
+    if (workspace_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", workspace_bytes, need);
+        return LPR_ENOMEM;
+    }
+    graph::carve(Carver(workspace, workspace_bytes), n, m, &L);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    CallTimer call(st);
+    call.start();
+    graph::G g;
+    g.n = n;
+    g.m = m;
+    g.s = s;
+    g.t = t;
+    g.tail = tail;
+    g.head = head;
+    g.cap = cap;
+    g.off = L.off;
+    g.adj = L.adj;
+    g.cur = L.cur;
+    g.res = L.res;
+    g.e = L.e;
+    g.h = L.h;
+    g.lab = L.lab;
+    g.q[0] = L.q0;
+    g.q[1] = L.q1;
+    g.qn = L.qn;
+    g.cnt = L.cnt;
+    g.bsum = L.bsum;
+    const int ga = graph::blocks_for(m), gn = graph::blocks_for(n);
+    LPR_TRY(fill_i32(L.off, 0, int64_t(n) + 1, st));
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.cnt), 0, 4, st));
+    hipLaunchKernelGGL(graph::k_init, dim3(std::max(ga, gn)), dim3(graph::NTB), 0, st, g);
+    if (m > 0)
+        hipLaunchKernelGGL(graph::k_validate, dim3(ga), dim3(graph::NTB), 0, st, g);
+    LPR_TRY_HIP(hipGetLastError());
+    unsigned long long cnt[4] = {0, 0, 0, 0};
+    LPR_TRY_HIP(hipMemcpyAsync(cnt, L.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    LPR_TRY_HIP(hipStreamSynchronize(st));
+    if (cnt[3]) {
+        if (cnt[3] & 1) {
+            set_error("arcs are not mate pairs (a^1 reverses a) over nodes 0..n-1");
+            return LPR_EINVAL;
+        }
+        set_error("a capacity is negative or a mate pair's sum exceeds 2^31 - 1");
+        return LPR_ERANGE;
+    }
+    // CSR by tail: exclusive scan of the degrees, then the scatter
+    const int len = n + 1, nb = (len + 1023) / 1024;
+    hipLaunchKernelGGL(graph::k_scan_blocks, dim3(nb), dim3(1024), 0, st, L.off, len, L.bsum);
+    hipLaunchKernelGGL(graph::k_scan_sums, dim3(1), dim3(1024), 0, st, L.bsum, nb);
+    hipLaunchKernelGGL(graph::k_scan_add, dim3(nb), dim3(1024), 0, st, L.off, len, L.bsum);
+    if (m > 0) hipLaunchKernelGGL(graph::k_scatter, dim3(ga), dim3(graph::NTB), 0, st, g);
+    hipLaunchKernelGGL(graph::k_saturate, dim3(graph::blocks_for(m)), dim3(graph::NTB), 0,
+                       st, g);
+    LPR_TRY_HIP(hipGetLastError());
+
+    int64_t rounds = 0, levels = 0;
+    for (;;) {
+        LPR_TRY(graph::run_bfs(g, 0, st, &levels));
+        LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.cnt) + 2, 0, 1, st));
+        hipLaunchKernelGGL(graph::k_labels_count, dim3(gn), dim3(graph::NTB), 0, st, g);
+        LPR_TRY_HIP(hipGetLastError());
+        LPR_TRY_HIP(hipMemcpyAsync(cnt, L.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        LPR_TRY_HIP(hipStreamSynchronize(st));
+        if (cnt[2] == 0) break;
+        if (rounds >= max_rounds) {
+            set_error("graph max-flow: round budget (%d) exhausted", max_rounds);
+            return LPR_EBUDGET;
+        }
+        ++rounds;
+        hipLaunchKernelGGL(graph::k_push, dim3(gn), dim3(graph::NTB), 0, st, g, cycle);
+        LPR_TRY_HIP(hipGetLastError());
+    }
+    LPR_TRY_HIP(hipMemcpyAsync(flow_value, L.e + t, sizeof(int64_t), hipMemcpyDeviceToHost,
+                               st));
+    if (source_side) {
+        LPR_TRY(graph::run_bfs(g, 1, st, &levels));
+        hipLaunchKernelGGL(graph::k_side, dim3(gn), dim3(graph::NTB), 0, st, g, source_side);
+        LPR_TRY_HIP(hipGetLastError());
+    }
+    double ms = 0;
+    LPR_TRY(call.stop_ms(&ms));
+    if (stats) {
+        stats->rounds = rounds;
+        stats->pushes = int64_t(cnt[0]);
+        stats->relabels = int64_t(cnt[1]);
+        stats->bfs_levels = levels;
+        stats->total_ms = ms;
+    }
+    return LPR_OK;
+}

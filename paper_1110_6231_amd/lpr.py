@@ -39,6 +39,7 @@ EXPORTED = [
     "lpr_assign_batched_workspace", "lpr_assign_solve_batched",
     "lpr_pricenet_param_count", "lpr_pricenet_workspace",
     "lpr_pricenet_features", "lpr_pricenet_infer", "lpr_pricenet_train_step",
+    "lpr_graph_maxflow_workspace", "lpr_graph_maxflow",
     "lpr_atomic_probe",
 ]
 PRICENET_FEATURES = 16
@@ -91,6 +92,17 @@ class AssignStats(ctypes.Structure):
                 ("price_update_us", ctypes.c_int64),
                 ("fixing_reruns", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
+class GraphOpts(ctypes.Structure):
+    _fields_ = [("cycle", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class GraphStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("pushes", ctypes.c_int64),
+                ("relabels", ctypes.c_int64), ("bfs_levels", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
 
 
 def _struct_dict(s) -> dict:
@@ -155,6 +167,12 @@ def lib():
     L.lpr_pricenet_train_step.restype = ctypes.c_int
     L.lpr_pricenet_train_step.argtypes = [i32, i32p, i64p, vp, i32, vp, vp, vp, vp,
                                           vp, i32, ctypes.c_float, vp, vp, sz, vp]
+    L.lpr_graph_maxflow_workspace.restype = sz
+    L.lpr_graph_maxflow_workspace.argtypes = [i32, i32]
+    L.lpr_graph_maxflow.restype = ctypes.c_int
+    L.lpr_graph_maxflow.argtypes = [i32, i32, vp, vp, vp, i32, i32, i64p, vp,
+                                    ctypes.POINTER(GraphOpts),
+                                    ctypes.POINTER(GraphStats), vp, sz, vp]
     L.lpr_atomic_probe.restype = ctypes.c_int
     L.lpr_atomic_probe.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     _lib = L
@@ -499,3 +517,39 @@ def lpr_atomic_probe(counters, log2_counters, blocks, per_thread, stream=None):
                                 int(per_thread), ctypes.byref(ms), _stream(stream))
     _check(rc, "lpr_atomic_probe")
     return ms.value
+
+
+def lpr_graph_maxflow_workspace(n: int, m: int) -> int:
+    return int(lib().lpr_graph_maxflow_workspace(int(n), int(m)))
+
+
+def make_graph_opts(cycle=0, max_rounds=0) -> GraphOpts:
+    o = GraphOpts()
+    o.cycle = cycle
+    o.max_rounds = max_rounds
+    return o
+
+
+def lpr_graph_maxflow(n, tail, head, cap, s, t, want_cut=True,
+                      opts: GraphOpts | None = None, workspace=None, stream=None,
+                      device="cuda"):
+    """Maximum s-t flow of the network whose arcs come in mate pairs (see
+    lpr_graph_maxflow in include/lpr.h).  tail, head, cap: int32 arrays of m
+    entries (torch CUDA tensors or host arrays).  Returns (flow_value (int),
+    source_side (torch uint8 [n] on the device, or None), stats dict)."""
+    import torch
+    arrs = [_dev_i32(a, device) for a in (tail, head, cap)]
+    m = arrs[0].numel()
+    dev = arrs[0].device
+    side = torch.empty(n, dtype=torch.uint8, device=dev) if want_cut else None
+    need = lpr_graph_maxflow_workspace(n, m)
+    ws = workspace if workspace is not None else _workspace(max(need, 1), dev)
+    flow = ctypes.c_int64(0)
+    st = GraphStats()
+    rc = lib().lpr_graph_maxflow(
+        int(n), int(m), *[_ptr(a) for a in arrs], int(s), int(t),
+        ctypes.byref(flow), _ptr(side),
+        ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+        _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_graph_maxflow")
+    return int(flow.value), side, _struct_dict(st)

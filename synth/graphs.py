@@ -1,0 +1,118 @@
+"""Seeded directed networks as arc lists in mate pairs.
+
+Arc 2k and arc 2k+1 are each other's reverse; cap[2k] is the capacity of the
+edge's direction tail[2k] -> head[2k] and cap[2k+1] that of the opposite
+direction (0 for a one-way arc).  Only random draws and layout live here.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CONFIG_GRAPH_RANDOM = 11
+CONFIG_GRAPH_LAYERED = 12
+CONFIG_GRAPH_BIPARTITE = 13
+
+
+def _rng(config_id: int, instance_id: int, seed: int):
+    return np.random.default_rng(np.random.SeedSequence([config_id, instance_id, seed]))
+
+
+def pairs_to_arcs(u, v, cap_uv, cap_vu):
+    """Edges (u[k], v[k]) with capacities in both directions -> mate-pair arcs."""
+    k = len(u)
+    tail = np.empty(2 * k, np.int32)
+    head = np.empty(2 * k, np.int32)
+    cap = np.empty(2 * k, np.int32)
+    tail[0::2], head[0::2], cap[0::2] = u, v, cap_uv
+    tail[1::2], head[1::2], cap[1::2] = v, u, cap_vu
+    return tail, head, cap
+
+
+def graph_random(n: int, edges: int, seed: int = 0, instance: int = 0,
+                 max_cap: int = 100, two_way: float = 0.3):
+    """Uniform random edges over n nodes (self-loops and parallel edges kept);
+    a fraction `two_way` also gets a reverse capacity.  s = 0, t = n - 1.
+    Returns (n, tail, head, cap, s, t)."""
+    g = _rng(CONFIG_GRAPH_RANDOM, instance, seed)
+    u = g.integers(0, n, edges)
+    v = g.integers(0, n, edges)
+    c = g.integers(0, max_cap + 1, edges)
+    back = g.random(edges) < two_way
+    cr = np.where(back, g.integers(0, max_cap + 1, edges), 0)
+    return (n, *pairs_to_arcs(u, v, c, cr), 0, n - 1)
+
+
+def graph_layered(layers: int, width: int, degree: int, seed: int = 0,
+                  instance: int = 0, max_cap: int = 1000):
+    """s, `layers` layers of `width` nodes, t: s feeds every node of the
+    first layer, every node sends `degree` arcs to random nodes of the next
+    layer, the last layer feeds t (long augmenting paths).  One-way arcs.
+    Returns (n, tail, head, cap, s, t)."""
+    g = _rng(CONFIG_GRAPH_LAYERED, instance, seed)
+    n = layers * width + 2
+    s, t = 0, n - 1
+    us, vs, cs = [], [], []
+    first = 1 + np.arange(width)
+    us.append(np.full(width, s))
+    vs.append(first)
+    cs.append(g.integers(1, max_cap + 1, width))
+    for l in range(layers - 1):
+        src = 1 + l * width + np.repeat(np.arange(width), degree)
+        dst = 1 + (l + 1) * width + g.integers(0, width, width * degree)
+        us.append(src)
+        vs.append(dst)
+        cs.append(g.integers(1, max_cap + 1, width * degree))
+    last = 1 + (layers - 1) * width + np.arange(width)
+    us.append(last)
+    vs.append(np.full(width, t))
+    cs.append(g.integers(1, max_cap + 1, width))
+    u, v, c = (np.concatenate(x) for x in (us, vs, cs))
+    return (n, *pairs_to_arcs(u, v, c, np.zeros_like(c)), s, t)
+
+
+def graph_bipartite(nx: int, ny: int, edges: int, seed: int = 0, instance: int = 0):
+    """Unit-capacity matching network: s -> X, X -> Y (random edges), Y -> t.
+    The flow value is the size of a maximum matching.
+    Returns (n, tail, head, cap, s, t)."""
+    g = _rng(CONFIG_GRAPH_BIPARTITE, instance, seed)
+    n = nx + ny + 2
+    s, t = 0, n - 1
+    xs = 1 + np.arange(nx)
+    ys = 1 + nx + np.arange(ny)
+    eu = 1 + g.integers(0, nx, edges)
+    ev = 1 + nx + g.integers(0, ny, edges)
+    u = np.concatenate([np.full(nx, s), eu, ys])
+    v = np.concatenate([xs, ev, np.full(ny, t)])
+    c = np.ones(len(u), np.int64)
+    return (n, *pairs_to_arcs(u, v, c, np.zeros_like(c)), s, t)
+
+
+def grid_to_arcs(inst):
+    """A grid instance as a mate-pair arc list: pixels 0..HW-1 (row-major),
+    s = HW, t = HW + 1; edges s-p (cap_src, 0), p-t (cap_snk, 0), p-right
+    (cap_right[p], cap_left[p+1]) and p-down (cap_down[p], cap_up[p+W]).
+    Returns (n, tail, head, cap, s, t)."""
+    H, W = inst.H, inst.W
+    HW = H * W
+    s, t = HW, HW + 1
+    pix = np.arange(HW).reshape(H, W)
+    us, vs, cf, cb = [], [], [], []
+    allp = pix.ravel()
+    us += [np.full(HW, s), allp]
+    vs += [allp, np.full(HW, t)]
+    cf += [inst.cap_src, inst.cap_snk]
+    cb += [np.zeros(HW, np.int64), np.zeros(HW, np.int64)]
+    if W > 1:
+        a = pix[:, :-1].ravel()
+        us.append(a)
+        vs.append(a + 1)
+        cf.append(inst.cap_right[a])
+        cb.append(inst.cap_left[a + 1])
+    if H > 1:
+        a = pix[:-1, :].ravel()
+        us.append(a)
+        vs.append(a + W)
+        cf.append(inst.cap_down[a])
+        cb.append(inst.cap_up[a + W])
+    u, v, c1, c2 = (np.concatenate(x) for x in (us, vs, cf, cb))
+    return (HW + 2, *pairs_to_arcs(u, v, c1, c2), s, t)
