@@ -6,7 +6,9 @@ relabels with gap, termination, flow value and the minimal cut.  Inputs are
 resident in HBM before the timed region; outputs and workspace are
 preallocated.  The JSON line also carries the dense assignment leg (n = 1024,
 weights U{0..1000}, max-weight) and the batched assignment leg (256
-optical-flow-like instances), the roofline of the dominant kernel (the push
+optical-flow-like instances), max-flow on two arbitrary networks (a layered
+network and a 512 x 512 cut as an arc list), the roofline of the dominant
+kernel (the push
 sweep or the global-relabel relaxation, whichever takes more time), the push
 update rate against a measured atomic-add ceiling, and the CPU oracles timed
 on this host (FIFO push-relabel for the grid, Hungarian for the assignment
