@@ -417,15 +417,16 @@ lpr_status lpr_pricenet_train_step(int32_t B, const int32_t *n,
 #define LPR_GRAPH_MAX_N (1 << 27)
 
 typedef struct {
-    int32_t cycle;       /* push/relabel operations per node per sweep (the
-                            paper's CYCLE); 0 -> 64                         */
-    int32_t max_rounds;  /* sweeps (each followed by a global relabel);
-                            0 -> 100000                                     */
-    int32_t reserved[2]; /* must be 0                                       */
+    int32_t cycle;       /* push/relabel attempts per node per sweep (the
+                            paper's CYCLE); 0 -> 16                         */
+    int32_t max_rounds;  /* rounds (sweeps_per_relabel sweeps, then a
+                            global relabel); 0 -> 100000                    */
+    int32_t sweeps_per_relabel; /* 1..1024; 0 -> 16                        */
+    int32_t reserved;    /* must be 0                                       */
 } lpr_graph_opts;
 
 typedef struct {
-    int64_t rounds;      /* sweeps                                           */
+    int64_t rounds;      /* rounds (each ends with a global relabel)         */
     int64_t pushes;      /* push operations                                  */
     int64_t relabels;    /* relabel operations (in the sweeps)               */
     int64_t bfs_levels;  /* BFS levels launched (global relabels, closure)   */

@@ -149,8 +149,9 @@ __global__ __launch_bounds__(NTB) void k_saturate(G g) {
     }
 }
 
-// Algorithm 4.5, up to `cycle` operations per active node, one thread per
-// node.  A node with no residual arc at all cannot reach t: it takes |V|.
+// Algorithm 4.5: every node's thread makes `cycle` attempts (the paper's
+// CYCLE loop), each a push or relabel when the node is active at that moment.
+// A node with no residual arc at all cannot reach t: it takes |V|.
 __global__ __launch_bounds__(NTB) void k_push(G g, int cycle) {
     unsigned long long pushes = 0, relabels = 0;
     for (int u = blockIdx.x * NTB + threadIdx.x; u < g.n; u += gridDim.x * NTB) {
@@ -158,8 +159,11 @@ __global__ __launch_bounds__(NTB) void k_push(G g, int cycle) {
         const int b = g.off[u], en = g.off[u + 1];
         int hu = g.h[u];
         for (int it = 0; it < cycle; ++it) {
+            if (hu >= g.n) break;
+            // an idle node keeps polling its excess for the rest of the
+            // sweep: flow pushed into it meanwhile moves on in the same sweep
             const int64_t eu = g.e[u];
-            if (eu <= 0 || hu >= g.n) break;
+            if (eu <= 0) continue;
             int hmin = INT_MAX, amin = -1;
             for (int j = b; j < en; ++j) {
                 const int a = g.adj[j];
@@ -347,12 +351,15 @@ extern "C" lpr_status lpr_graph_maxflow(int32_t n, int32_t m, const int32_t *tai
         set_error("invalid arguments (n, m, s, t or a NULL pointer)");
         return LPR_EINVAL;
     }
-    int cycle = 64, max_rounds = 100000;
+    // defaults measured on layered, grid and random networks of 65 k - 262 k
+    // nodes (16 x 16 against 1 x 64: 3 - 9 times faster)
+    int cycle = 16, max_rounds = 100000, sweeps = 16;
     if (opts) {
         if (opts->cycle) cycle = opts->cycle;
         if (opts->max_rounds) max_rounds = opts->max_rounds;
+        if (opts->sweeps_per_relabel) sweeps = opts->sweeps_per_relabel;
     }
-    if (cycle < 1 || max_rounds < 1) {
+    if (cycle < 1 || max_rounds < 1 || sweeps < 1 || sweeps > 1024) {
         set_error("invalid lpr_graph_opts");
         return LPR_EINVAL;
     }
@@ -428,7 +435,8 @@ extern "C" lpr_status lpr_graph_maxflow(int32_t n, int32_t m, const int32_t *tai
             return LPR_EBUDGET;
         }
         ++rounds;
-        hipLaunchKernelGGL(graph::k_push, dim3(gn), dim3(graph::NTB), 0, st, g, cycle);
+        for (int k = 0; k < sweeps; ++k)
+            hipLaunchKernelGGL(graph::k_push, dim3(gn), dim3(graph::NTB), 0, st, g, cycle);
         LPR_TRY_HIP(hipGetLastError());
     }
     LPR_TRY_HIP(hipMemcpyAsync(flow_value, L.e + t, sizeof(int64_t), hipMemcpyDeviceToHost,

@@ -96,7 +96,7 @@ class AssignStats(ctypes.Structure):
 
 class GraphOpts(ctypes.Structure):
     _fields_ = [("cycle", ctypes.c_int32), ("max_rounds", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("sweeps_per_relabel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GraphStats(ctypes.Structure):
@@ -523,10 +523,11 @@ def lpr_graph_maxflow_workspace(n: int, m: int) -> int:
     return int(lib().lpr_graph_maxflow_workspace(int(n), int(m)))
 
 
-def make_graph_opts(cycle=0, max_rounds=0) -> GraphOpts:
+def make_graph_opts(cycle=0, max_rounds=0, sweeps_per_relabel=0) -> GraphOpts:
     o = GraphOpts()
     o.cycle = cycle
     o.max_rounds = max_rounds
+    o.sweeps_per_relabel = sweeps_per_relabel
     return o
 
 

@@ -93,10 +93,13 @@ def test_edge_cases():
 
 def test_options():
     g = synth.graph_layered(30, 40, 3, seed=4)
-    for cycle in (1, 7, 500):
-        check(g, opts=lpr.make_graph_opts(cycle=cycle))
+    for cycle, sweeps in ((1, 1), (7, 3), (500, 1), (16, 64)):
+        check(g, opts=lpr.make_graph_opts(cycle=cycle, sweeps_per_relabel=sweeps))
     with pytest.raises(lpr.LprError):
-        lpr.lpr_graph_maxflow(*g, opts=lpr.make_graph_opts(max_rounds=1, cycle=1))
+        lpr.lpr_graph_maxflow(*g, opts=lpr.make_graph_opts(max_rounds=1, cycle=1,
+                                                           sweeps_per_relabel=1))
+    with pytest.raises(lpr.LprError):
+        lpr.lpr_graph_maxflow(*g, opts=lpr.make_graph_opts(sweeps_per_relabel=1025))
 
 
 def test_invalid_inputs_are_rejected():
