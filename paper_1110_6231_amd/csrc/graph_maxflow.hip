@@ -27,7 +27,6 @@
 // levels).
 #include <algorithm>
 #include <climits>
-#include <vector>
 
 #include "lpr_internal.h"
 
