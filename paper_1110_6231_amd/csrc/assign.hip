@@ -75,7 +75,7 @@ typedef const __attribute__((address_space(1))) int32_t *gint32_p;
 
 struct AInst {
     int64_t cost_off;  // first cost entry of the instance (int32 input)
-    int64_t c16_off;   // first entry of its int16 copies (n rows of ld16(n))
+    int64_t c16_off;   // sum of n x ld16(n) over the instances before it
     int32_t n;
     int32_t row_off;   // offset of the instance in packed per-row outputs
 };
@@ -84,9 +84,11 @@ struct AArgs {
     const AInst *inst;
     const int32_t *order;
     const int32_t *costs;
+    // Cost copies: instance b owns the 2 n ld16(n) int16 entries from
+    // 2 c16_off.  When max|c| fits int16 they hold the row-major copy, then
+    // the transposed copy (column y contiguous); otherwise a transposed int32
+    // copy fills the same bytes.  Rows are ld16(n) entries apart throughout.
     const int16_t *c16;
-    const int16_t *c16t;  // transposed int16 copy (column y is contiguous)
-                          // both copies have row stride ld16(n)
     const unsigned *cmax;
     int32_t sign;      // +1 minimise c, -1 maximise (solve with c = -w)
     int32_t alpha;
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(256) void k_prep(const AInst *inst,
     unsigned m = 0;
     for (int r = blockIdx.x; r < n; r += gridDim.x) {
         const int32_t *src = costs + I.cost_off + int64_t(r) * n;
-        int16_t *dst = c16 + I.c16_off + int64_t(r) * ld;
+        int16_t *dst = c16 + 2 * I.c16_off + int64_t(r) * ld;
         for (int k = threadIdx.x; k < ld; k += 256) {
             const int32_t c = k < n ? src[k] : 0;
             m = max(m, c < 0 ? 0u - unsigned(c) : unsigned(c));
@@ -139,32 +141,40 @@ __global__ __launch_bounds__(256) void k_prep(const AInst *inst,
     }
 }
 
-// Transposed saturated int16 copy of every instance's costs, through 64 x 64
-// LDS tiles.  grid = (B, tiles, tiles) over the largest instance.
-__global__ __launch_bounds__(256) void k_transpose16(const AInst *inst,
-                                                     const int32_t *costs,
-                                                     int16_t *c16t) {
+// Transposed copy of every instance's costs, through 64 x 64 LDS tiles, in
+// int16 after the row-major copy when max|c| fits int16, else in int32 over
+// both halves of the instance's region (row stride ld16(n) either way).
+// Runs after k_prep, whose max|c| it reads.  grid = (B, tiles, tiles) over
+// the largest instance.
+__global__ __launch_bounds__(256) void k_transpose(const AInst *inst,
+                                                   const int32_t *costs,
+                                                   const unsigned *cmax,
+                                                   int16_t *c16) {
     const AInst I = inst[blockIdx.x];
     const int n = I.n;
     const int c0 = blockIdx.y * 64, r0 = blockIdx.z * 64;  // source column / row
-    if (c0 >= n || r0 >= n) return;
-    __shared__ int16_t tile[64][66];
+    const unsigned cm = cmax[blockIdx.x];
+    if (c0 >= n || r0 >= n || cm > unsigned(LPR_ASSIGN_MAX_COST)) return;
+    __shared__ int32_t tile[64][65];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     for (int r = ty; r < 64; r += 4) {
         const int row = r0 + r, col = c0 + tx;
-        int16_t v = 0;
-        if (row < n && col < n) {
-            const int32_t c = costs[I.cost_off + int64_t(row) * n + col];
-            v = int16_t(max(-32768, min(32767, c)));
-        }
-        tile[r][tx] = v;
+        tile[r][tx] = row < n && col < n ? costs[I.cost_off + int64_t(row) * n + col] : 0;
     }
     __syncthreads();
+    const bool narrow = cm <= C16_MAX;
+    int16_t *t16 = c16 + 2 * I.c16_off + int64_t(n) * ld16(n);
+    int32_t *t32 = reinterpret_cast<int32_t *>(c16 + 2 * I.c16_off);
     for (int r = ty; r < 64; r += 4) {
         const int orow = c0 + r, ocol = r0 + tx;  // destination row = source column
         // padding columns (ocol in [n, ld16(n))) get the tile's zeros
-        if (orow < n && ocol < ld16(n))
-            c16t[I.c16_off + int64_t(orow) * ld16(n) + ocol] = tile[tx][r];
+        if (orow < n && ocol < ld16(n)) {
+            const int64_t o = int64_t(orow) * ld16(n) + ocol;
+            if (narrow)
+                t16[o] = int16_t(tile[tx][r]);
+            else
+                t32[o] = tile[tx][r];
+        }
     }
 }
 
@@ -412,8 +422,9 @@ struct PU {
 // for the nodes not scanned.
 // Called by the whole workgroup between phases; `fl` is n ints of scratch
 // for the column frontier.
+template <typename T>
 __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
-                             const int16_t *__restrict__ CT, int n, int64_t sgnS,
+                             const T *__restrict__ CT, int n, int64_t sgnS,
                              int64_t eps, int tid) {
     // per-level shared values, double-buffered by level parity so that no
     // barrier is spent resetting them and every read precedes the next write:
@@ -478,8 +489,11 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
                     for (int k = 0; k < PU_LOADS; ++k) {
                         if (j0 + k >= nf) break;
                         const int y = fl[j0 + k];
-                        // int16 costs: a 24 x 24-bit product
-                        const int64_t cp = int64_t(__mul24(cv[k], int(sgnS))) + pxx - L.py[y];
+                        // int16 costs take a 24 x 24-bit product, int32 a 64-bit one
+                        const int64_t cs = sizeof(T) == 2
+                                               ? int64_t(__mul24(cv[k], int(sgnS)))
+                                               : int64_t(cv[k]) * sgnS;
+                        const int64_t cp = cs + pxx - L.py[y];
                         if (cp < bound && y != mx) {
                             best = level + D.floor_div(cp) + 1;
                             bound = D.mul_sat(best - level - 1);
@@ -702,7 +716,7 @@ __device__ bool resolve_hot(int y, int64_t eps, const Shared &L, int32_t *idx,
 template <typename T>
 __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                                const T *__restrict__ C,
-                               const int16_t *__restrict__ CT, unsigned cmax,
+                               const T *__restrict__ CT, unsigned cmax,
                                unsigned char *smem) {
     const int n = I.n;
     Shared L;
@@ -1044,11 +1058,13 @@ __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
         if (threadIdx.x == 0) A.status[slot] = 2;
         return;
     }
+    const int16_t *copies = A.c16 + 2 * I.c16_off;
     if (cmax <= C16_MAX)
-        solve_instance<int16_t>(A, I, slot, A.c16 + I.c16_off, A.c16t + I.c16_off,
+        solve_instance<int16_t>(A, I, slot, copies, copies + int64_t(I.n) * ld16(I.n),
                                 cmax, smem);
     else
-        solve_instance<int32_t>(A, I, slot, A.costs + I.cost_off, nullptr, cmax, smem);
+        solve_instance<int32_t>(A, I, slot, A.costs + I.cost_off,
+                                reinterpret_cast<const int32_t *>(copies), cmax, smem);
 }
 
 // py, px, b(x) (int64), e(y), head, next, mate, two lists (int32), two
@@ -1061,7 +1077,7 @@ struct Layout {
     int32_t *order, *status;
     unsigned *cmax;
     unsigned long long *counters;
-    int16_t *c16, *c16t;
+    int16_t *c16;
     int32_t *cand, *ncand;
 };
 
@@ -1077,8 +1093,7 @@ static Carver carve(Carver cv, int B, const int32_t *n, Layout *L) {
     L->status = cv.take<int32_t>(size_t(B));
     L->cmax = cv.take<unsigned>(size_t(B));
     L->counters = cv.take<unsigned long long>(8);
-    L->c16 = cv.take<int16_t>(size_t(c16_elems(B, n)));
-    L->c16t = cv.take<int16_t>(size_t(c16_elems(B, n)));
+    L->c16 = cv.take<int16_t>(size_t(2 * c16_elems(B, n)));
     int64_t rows = 0;
     for (int b = 0; b < B; ++b) rows += n[b];
     L->cand = cv.take<int32_t>(size_t(c16_elems(B, n)));
@@ -1182,15 +1197,14 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     hipLaunchKernelGGL(k_prep, dim3(gx, B), dim3(256), 0, s, L.inst, costs, L.c16, L.cmax);
     LPR_TRY_HIP(hipGetLastError());
     const unsigned tiles = unsigned((nmax + 63) / 64);
-    hipLaunchKernelGGL(k_transpose16, dim3(B, tiles, tiles), dim3(256), 0, s, L.inst,
-                       costs, L.c16t);
+    hipLaunchKernelGGL(k_transpose, dim3(B, tiles, tiles), dim3(256), 0, s, L.inst,
+                       costs, L.cmax, L.c16);
     LPR_TRY_HIP(hipGetLastError());
     AArgs A;
     A.inst = L.inst;
     A.order = L.order;
     A.costs = costs;
     A.c16 = L.c16;
-    A.c16t = L.c16t;
     A.cmax = L.cmax;
     A.sign = maximize ? -1 : 1;
     A.alpha = alpha;

@@ -153,13 +153,48 @@ def test_schedule_options_stay_exact(tail, flags, period):
 
 
 def test_costs_at_the_limit():
-    """|c| up to LPR_ASSIGN_MAX_COST (2^24 - 1): the int32 row scans, scaled
-    costs near 2^36 and prices in int64; totals must match the oracle."""
+    """|c| up to LPR_ASSIGN_MAX_COST (2^24 - 1): the int32 row scans and the
+    price update over the int32 column-major copy, scaled costs near 2^36 and
+    prices in int64; totals must match the oracle."""
     big = lpr.LPR_ASSIGN_MAX_COST
-    for n, seed in ((40, 1), (130, 2)):
+    for n, seed in ((40, 1), (130, 2), (300, 3)):
         c = synth.assign_random_small(n, seed=seed, lo=-big, hi=big)
-        check(c)
+        st = check(c)
+        assert n < 100 or st["price_updates"] > 0, st
         check(c, maximize=True)
+
+
+@pytest.mark.parametrize("period", [1, 37, -1])
+def test_int32_costs_schedules(period):
+    """Price updates after every push, at an odd period and never, on costs
+    that need int32: the same optimum and certificate."""
+    opts = lpr.make_assign_opts(price_update_period=period)
+    c = synth.assign_random_small(257, seed=8, lo=0, hi=1 << 22)
+    st = check(c, maximize=True, opts=opts)
+    assert (st["price_updates"] == 0) == (period < 0), st
+    check(synth.assign_points(200, seed=4, instance=2, scale=5e6), opts=opts)
+
+
+def test_batched_mixed_cost_widths():
+    """Instances whose costs fit int16 next to instances that need int32: the
+    int32 column-major copy fills the instance's whole share of the copy
+    buffer, which must not reach its neighbours."""
+    specs = [(65, 1000), (200, 1 << 23), (64, 300), (129, 40000), (8, 1 << 20),
+             (300, 32767)]
+    mats = [synth.assign_random_small(n, seed=20 + k, lo=-hi, hi=hi)
+            for k, (n, hi) in enumerate(specs)]
+    packed = lpr.PackedAssign.from_matrices(mats)
+    print("[assign] batched mixed widths", packed.ns, flush=True)
+    for flags in (0, lpr.LPR_ASSIGN_ARC_FIXING):
+        opts = lpr.make_assign_opts(flags=flags)
+        r2c, tots, prices, _ = lpr.lpr_assign_solve_batched(packed, opts=opts)
+        r2c, prices, tots = (r2c.cpu().numpy(), prices.cpu().numpy(),
+                             tots.cpu().numpy())
+        for k, m in enumerate(mats):
+            a, b = packed.row_offset[k], packed.row_offset[k + 1]
+            assert tots[k] == oracle.assign(m)[1], (k, flags)
+            assert is_permutation(r2c[a:b], m.shape[0])
+            assert scaled_eps_certificate(m, r2c[a:b], prices[a:b])
 
 
 def test_maximum_size_n2048():
@@ -185,7 +220,7 @@ def test_maximum_size_n2048():
     assert is_permutation(r2c, n)
     assert int(c[np.arange(n), r2c].astype(np.int64).sum()) == tot
     assert scaled_eps_certificate(-c.astype(np.int64), r2c, prices.cpu().numpy())
-    # int32 costs (|c| >= 2^15 takes the int32 row scans, no price update)
+    # int32 costs (|c| >= 2^15 takes the int32 row scans and column copy)
     c = synth.assign_random_small(n, seed=13, lo=0, hi=1 << 20)
     print("[assign] n=2048 int32 costs", flush=True)
     r2c, tot, prices, _ = lpr.lpr_assign_solve(c)
