@@ -292,12 +292,14 @@ def assign_leg(args, torch, lpr, synth):
 
 def graph_leg(args, torch, lpr, synth):
     """Form 1 on arbitrary networks (arc lists in mate pairs): a layered
-    network with long augmenting paths and a 512 x 512 blob graph cut given as
-    an arc list, each solved three times (median)."""
+    network with long augmenting paths, a 512 x 512 blob graph cut given as
+    an arc list and a 64^3 6-connected volume, each solved three times
+    (median)."""
     out = {}
     cases = {
         "layered 64 x 4096, 4 arcs per node": synth.graph_layered(64, 4096, 4, seed=0),
         "512x512 graph cut as an arc list": synth.grid_to_arcs(synth.grid_blobs(512, 512, seed=0)),
+        "64x64x64 6-connected volume": synth.grid3d_arcs(64, 64, 64, seed=0),
     }
     for name, (n, tail, head, cap, s, t) in cases.items():
         arrs = [torch.as_tensor(a, device="cuda") for a in (tail, head, cap)]

@@ -35,6 +35,8 @@ namespace graph {
 
 constexpr int NTB = 256;
 constexpr int LEVEL_BATCH = 16;  // BFS levels launched between host checks
+constexpr int CHUNK = 64;        // arcs per frontier entry
+constexpr int GROUP = 8;         // lanes per frontier entry
 
 struct G {
     int n, m, s, t;
@@ -46,8 +48,8 @@ struct G {
     int64_t *e;      // [n] excesses
     int32_t *h;      // [n] heights
     int32_t *lab;    // [n] BFS labels / closure marks
-    int32_t *q[2];   // frontier queues
-    int32_t *qn;     // [n + 2] frontier size per level
+    int64_t *q[2];   // frontier queues: entries (chunk << 32) | node
+    int32_t *qn;     // [n + 2] frontier entries per level
     unsigned long long *cnt;  // pushes, relabels, active, error bits
     int32_t *bsum;   // block sums of the scan
 };
@@ -208,44 +210,68 @@ __global__ __launch_bounds__(NTB) void k_push(G g, int cycle) {
     }
 }
 
+// Frontier entries: a node's arcs in chunks of CHUNK, one entry per chunk
+// (at least one), so that a hub's arcs spread over many wavefronts.  A node
+// has at most max(1, ceil(d / CHUNK)) entries, and a queue at most
+// n + m / CHUNK + 1.
+__device__ inline int chunks_of(const G &g, int v) {
+    const int d = g.off[v + 1] - g.off[v];
+    return d > CHUNK ? (d + CHUNK - 1) / CHUNK : 1;
+}
+
+__device__ inline void enqueue(const G &g, int64_t *q, int32_t *count, int v) {
+    const int k = chunks_of(g, v);
+    const int base = atomicAdd(count, k);
+    for (int c = 0; c < k; ++c) q[base + c] = (int64_t(c) << 32) | uint32_t(v);
+}
+
 // BFS seeds.  Backward (global relabel): labels |V| except t at 0, frontier
 // {t}.  Forward (cut): marks s and every node with excess, frontier = them.
 __global__ __launch_bounds__(NTB) void k_bfs_seed(G g, int forward) {
-    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB) {
+    const int tid = blockIdx.x * NTB + threadIdx.x, nth = gridDim.x * NTB;
+    for (int v = tid; v < g.n; v += nth) {
         if (!forward) {
             g.lab[v] = v == g.t ? 0 : g.n;
-            if (v == g.t) g.q[0][0] = v;
         } else {
             const bool in = v == g.s || (v != g.t && g.e[v] > 0);
             g.lab[v] = in ? 1 : 0;
-            if (in) g.q[0][atomicAdd(&g.qn[0], 1)] = v;
+            if (in) enqueue(g, g.q[0], &g.qn[0], v);
         }
     }
-    if (!forward && blockIdx.x == 0 && threadIdx.x == 0) g.qn[0] = 1;
+    if (!forward) {  // t's entries, one per thread
+        const int k = chunks_of(g, g.t);
+        for (int c = tid; c < k; c += nth) g.q[0][c] = (int64_t(c) << 32) | uint32_t(g.t);
+        if (tid == 0) g.qn[0] = k;
+    }
 }
 
-// Level L of a BFS over the frontier q[L & 1] (entries wid, wid + nwaves, ...
-// of its `size`): one wavefront per frontier node, its lanes over the node's
-// arcs (s and t, or any hub, can hold most arcs of the network).  Backward:
-// w reaches frontier node u over the residual arc (w,u) = a^1 of u's arc
-// a = (u,w); w gets L + 1 (s keeps |V|).  Forward: u reaches w over its
-// residual arc a; w is marked.  The next frontier goes to q[(L + 1) & 1].
+// Level L of a BFS over the frontier q[L & 1] (`size` entries): GROUP lanes
+// per entry over its chunk of the node's arcs, 64 / GROUP entries per
+// wavefront at a time.  Backward: w reaches frontier node u over the
+// residual arc (w,u) = a^1 of u's arc a = (u,w); w gets L + 1 (s keeps |V|).
+// Forward: u reaches w over its residual arc a; w is marked.  The next
+// frontier goes to q[(L + 1) & 1].
 __device__ inline void bfs_expand(const G &g, int L, int forward, int size, int wid,
                                   int nwaves, int lane) {
-    const int32_t *front = g.q[L & 1];
-    int32_t *next = g.q[(L + 1) & 1];
-    for (int i = wid; i < size; i += nwaves) {
-        const int u = front[i];
-        for (int j = g.off[u] + lane; j < g.off[u + 1]; j += 64) {
+    const int64_t *front = g.q[L & 1];
+    int64_t *next = g.q[(L + 1) & 1];
+    constexpr int PER = 64 / GROUP;
+    const int sub = lane % GROUP;
+    for (int i = wid * PER + lane / GROUP; i < size; i += nwaves * PER) {
+        const int64_t ent = front[i];
+        const int u = int(uint32_t(ent));
+        const int b = g.off[u] + int(ent >> 32) * CHUNK;
+        const int e = min(g.off[u + 1], b + CHUNK);
+        for (int j = b + sub; j < e; j += GROUP) {
             const int a = g.adj[j];
             const int w = g.head[a];
             if (!forward) {
                 if (w == g.s || g.res[a ^ 1] <= 0 || g.lab[w] != g.n) continue;
                 if (atomicCAS(&g.lab[w], g.n, L + 1) == g.n)
-                    next[atomicAdd(&g.qn[L + 1], 1)] = w;
+                    enqueue(g, next, &g.qn[L + 1], w);
             } else {
                 if (g.res[a] <= 0 || g.lab[w] != 0) continue;
-                if (atomicCAS(&g.lab[w], 0, 1) == 0) next[atomicAdd(&g.qn[L + 1], 1)] = w;
+                if (atomicCAS(&g.lab[w], 0, 1) == 0) enqueue(g, next, &g.qn[L + 1], w);
             }
         }
     }
@@ -282,7 +308,8 @@ static int blocks_for(int64_t k) {
 }
 
 struct Layout {
-    int32_t *off, *adj, *cur, *res, *h, *lab, *q0, *q1, *qn, *bsum;
+    int32_t *off, *adj, *cur, *res, *h, *lab, *qn, *bsum;
+    int64_t *q0, *q1;
     int64_t *e;
     unsigned long long *cnt;
 };
@@ -294,8 +321,9 @@ static Carver carve(Carver cv, int n, int m, Layout *L) {
     L->res = cv.take<int32_t>(size_t(std::max(m, 1)));
     L->h = cv.take<int32_t>(size_t(n));
     L->lab = cv.take<int32_t>(size_t(n));
-    L->q0 = cv.take<int32_t>(size_t(n));
-    L->q1 = cv.take<int32_t>(size_t(n));
+    const size_t qcap = size_t(n) + size_t(m) / CHUNK + 1;
+    L->q0 = cv.take<int64_t>(qcap);
+    L->q1 = cv.take<int64_t>(qcap);
     L->qn = cv.take<int32_t>(size_t(n) + 2);
     L->bsum = cv.take<int32_t>(size_t((n + 1 + 1023) / 1024) + 1);
     L->e = cv.take<int64_t>(size_t(n));

@@ -13,7 +13,7 @@ from .grids import (GridInstance, grid_uniform, grid_blobs, grid_batch,
 from .assign import (assign_uniform, assign_points, assign_batch,
                      assign_random_small, TRAIN_BRANCH)
 from .graphs import (graph_random, graph_layered, graph_bipartite, pairs_to_arcs,
-                     grid_to_arcs)
+                     grid_to_arcs, grid3d_arcs, grid8_arcs)
 
 __all__ = [
     "GridInstance", "grid_uniform", "grid_blobs", "grid_batch",
@@ -21,5 +21,5 @@ __all__ = [
     "assign_uniform", "assign_points", "assign_batch", "assign_random_small",
     "TRAIN_BRANCH",
     "graph_random", "graph_layered", "graph_bipartite", "pairs_to_arcs",
-    "grid_to_arcs",
+    "grid_to_arcs", "grid3d_arcs", "grid8_arcs",
 ]

@@ -116,3 +116,65 @@ def grid_to_arcs(inst):
         cb.append(inst.cap_up[a + W])
     u, v, c1, c2 = (np.concatenate(x) for x in (us, vs, cf, cb))
     return (HW + 2, *pairs_to_arcs(u, v, c1, c2), s, t)
+
+
+CONFIG_GRID_3D = 14
+CONFIG_GRID_8 = 15
+
+
+def _terminals(g, npix, tmax):
+    """Terminal arcs drawn as in the 64 x 64 grid workload: t uniform in
+    [-tmax, tmax]; t > 0 is a source arc of capacity t, else a sink arc of
+    capacity -t."""
+    tt = g.integers(-tmax, tmax + 1, npix)
+    return np.where(tt > 0, tt, 0), np.where(tt < 0, -tt, 0)
+
+
+def grid3d_arcs(D: int, H: int, W: int, seed: int = 0, instance: int = 0,
+                tmax: int = 100, pmax: int = 50):
+    """6-connected D x H x W volume as a mate-pair arc list: voxels
+    0..DHW-1 (z-major, then rows), s = DHW, t = DHW + 1; every neighbour
+    pair gets one capacity drawn uniformly from [0, pmax], the same in both
+    directions.  Returns (n, tail, head, cap, s, t)."""
+    g = _rng(CONFIG_GRID_3D, instance, seed)
+    N = D * H * W
+    s, t = N, N + 1
+    vox = np.arange(N).reshape(D, H, W)
+    src, snk = _terminals(g, N, tmax)
+    us, vs, cs = [np.full(N, s), vox.ravel()], [vox.ravel(), np.full(N, t)], [src, snk]
+    backs = [np.zeros(N, np.int64), np.zeros(N, np.int64)]
+    for a, b in ((vox[:, :, :-1], vox[:, :, 1:]), (vox[:, :-1, :], vox[:, 1:, :]),
+                 (vox[:-1, :, :], vox[1:, :, :])):
+        a, b = a.ravel(), b.ravel()
+        c = g.integers(0, pmax + 1, len(a))
+        us.append(a)
+        vs.append(b)
+        cs.append(c)
+        backs.append(c)
+    u, v, c1, c2 = (np.concatenate(x) for x in (us, vs, cs, backs))
+    return (N + 2, *pairs_to_arcs(u, v, c1, c2), s, t)
+
+
+def grid8_arcs(H: int, W: int, seed: int = 0, instance: int = 0,
+               tmax: int = 100, pmax: int = 50):
+    """8-connected H x W grid (the 4 axis neighbours and the 4 diagonals) as
+    a mate-pair arc list: pixels row-major, s = HW, t = HW + 1; every
+    neighbour pair gets one capacity drawn uniformly from [0, pmax], the
+    same in both directions.  Returns (n, tail, head, cap, s, t)."""
+    g = _rng(CONFIG_GRID_8, instance, seed)
+    N = H * W
+    s, t = N, N + 1
+    pix = np.arange(N).reshape(H, W)
+    src, snk = _terminals(g, N, tmax)
+    us, vs, cs = [np.full(N, s), pix.ravel()], [pix.ravel(), np.full(N, t)], [src, snk]
+    backs = [np.zeros(N, np.int64), np.zeros(N, np.int64)]
+    for a, b in ((pix[:, :-1], pix[:, 1:]), (pix[:-1, :], pix[1:, :]),
+                 (pix[:-1, :-1], pix[1:, 1:]), (pix[:-1, 1:], pix[1:, :-1])):
+        a, b = a.ravel(), b.ravel()
+        c = g.integers(0, pmax + 1, len(a))
+        us.append(a)
+        vs.append(b)
+        cs.append(c)
+        backs.append(c)
+    u, v, c1, c2 = (np.concatenate(x) for x in (us, vs, cs, backs))
+    return (N + 2, *pairs_to_arcs(u, v, c1, c2), s, t)

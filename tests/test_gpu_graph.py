@@ -74,6 +74,20 @@ def test_grid_as_a_graph_matches_the_grid_solver():
     assert st["pushes"] > 0
 
 
+@pytest.mark.parametrize("gen,args", [(synth.grid3d_arcs, (1, 1, 1)),
+                                      (synth.grid3d_arcs, (3, 4, 5)),
+                                      (synth.grid3d_arcs, (16, 24, 20)),
+                                      (synth.grid3d_arcs, (40, 40, 40)),
+                                      (synth.grid8_arcs, (1, 7)),
+                                      (synth.grid8_arcs, (64, 64)),
+                                      (synth.grid8_arcs, (150, 170))])
+def test_volume_and_8_connected_grids(gen, args):
+    """Neighbourhood systems other than the 4-connected grid (6-connected
+    volumes, 8-connected images) through the arc-list solver."""
+    for seed in range(2):
+        check(gen(*args, seed=seed))
+
+
 def test_edge_cases():
     # no arcs
     v, side, _ = lpr.lpr_graph_maxflow(5, [], [], [], 0, 4)

@@ -203,3 +203,53 @@ def test_golden_file_consistent_with_oracle():
         v, side = oracle.grid_maxflow(inst, "fifo")
         assert rec["name"] == inst.name and rec["flow"] == v
         assert rec["source_side_sha256"] == hashlib.sha256(side.tobytes()).hexdigest()
+
+
+def _arc_min_cut_bruteforce(n, tail, head, cap, s, t):
+    """Minimum s-t cut of an arc list by enumerating every source side (the
+    definition of Section 3); returns (value, the minimal source side, which
+    is the intersection of all minimum ones)."""
+    others = [v for v in range(n) if v not in (s, t)]
+    tail, head, cap = np.asarray(tail), np.asarray(head), np.asarray(cap, np.int64)
+    best, sides = None, []
+    for mask in range(1 << len(others)):
+        side = np.zeros(n, np.uint8)
+        side[s] = 1
+        for k, v in enumerate(others):
+            if mask >> k & 1:
+                side[v] = 1
+        val = int(cap[(side[tail] == 1) & (side[head] == 0)].sum())
+        if best is None or val < best:
+            best, sides = val, [side]
+        elif val == best:
+            sides.append(side)
+    return best, np.minimum.reduce(sides)
+
+
+@pytest.mark.parametrize("gen,args", [
+    (synth.grid3d_arcs, (2, 2, 2)), (synth.grid3d_arcs, (1, 2, 5)),
+    (synth.grid3d_arcs, (2, 3, 2)), (synth.grid8_arcs, (3, 3)),
+    (synth.grid8_arcs, (2, 5))])
+def test_volume_and_8_connected_grids_bruteforce(gen, args):
+    """6-connected volumes and 8-connected grids (Section 4.3's neighbourhood
+    systems beyond the 4-connected one) as arc lists: both oracle methods
+    against every cut."""
+    for seed in range(4):
+        n, tail, head, cap, s, t = gen(*args, seed=seed, tmax=20, pmax=10)
+        want, wside = _arc_min_cut_bruteforce(n, tail, head, cap, s, t)
+        for method in ("ek", "fifo"):
+            v, side, _ = oracle.graph_maxflow(n, tail, head, cap, s, t, method)
+            assert v == want, (gen.__name__, args, seed, method)
+            np.testing.assert_array_equal(side, wside)
+
+
+@pytest.mark.parametrize("gen,args", [(synth.grid3d_arcs, (8, 12, 10)),
+                                      (synth.grid8_arcs, (30, 40))])
+def test_volume_and_8_connected_grids_match_scipy(gen, args):
+    n, tail, head, cap, s, t = gen(*args, seed=1)
+    keep = cap > 0
+    m = csr_matrix((cap[keep].astype(np.int32), (tail[keep], head[keep])),
+                   shape=(n, n))
+    v, side, _ = oracle.graph_maxflow(n, tail, head, cap, s, t)
+    assert v == int(maximum_flow(m, s, t).flow_value)
+    assert int(cap[(side[tail] == 1) & (side[head] == 0)].sum()) == v
