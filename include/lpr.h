@@ -49,7 +49,8 @@ typedef enum {
     LPR_ERANGE = -2,  /* a value too large for the fixed-width arithmetic  */
     LPR_ENOMEM = -3,  /* workspace smaller than required                   */
     LPR_EDEVICE = -4, /* a HIP runtime error (text in lpr_last_error)      */
-    LPR_EBUDGET = -5  /* the round / operation budget ran out              */
+    LPR_EBUDGET = -5, /* the round / operation budget ran out              */
+    LPR_ENOMATCH = -6 /* a sparse assignment has no perfect matching       */
 } lpr_status;
 
 /* Thread-local, NUL-terminated description of the most recent failure of a
@@ -337,6 +338,42 @@ lpr_status lpr_assign_solve_batched(int32_t B, const int32_t *n,
                                     const lpr_assign_opts *opts,
                                     lpr_assign_stats *stats, void *workspace,
                                     size_t workspace_bytes, void *stream);
+
+/* Most arcs a sparse assignment instance may list (parallel arcs included). */
+#define LPR_ASSIGN_SPARSE_MAX_ARCS (1 << 26)
+
+/* Device workspace bytes for lpr_assign_sparse_solve (0 for bad n or m). */
+size_t lpr_assign_sparse_workspace(int32_t n, int32_t m);
+
+/*
+ * Optimal assignment on a sparse bipartite graph X x Y, |X| = |Y| = n
+ * (Section 3's problem on a graph with fewer arcs than the complete one),
+ * by the same cost scaling (Section 5).  The arcs are given in CSR by row,
+ * all device int32:
+ *   row_ptr [n+1]  row_ptr[0] = 0, non-decreasing, row_ptr[n] = m;
+ *   col     [m]    the columns of row x are col[row_ptr[x] .. row_ptr[x+1]);
+ *   cost    [m]    |cost| <= 32767.
+ * Parallel arcs are allowed; the best of them (least cost to minimise,
+ * largest weight to maximise) is the arc.  Every row scan of every refine
+ * reads the row's arcs only.  The price update (Algorithm 5.3) runs over a
+ * dense copy in which a missing arc costs as much as the costliest arc and
+ * has a length of at least 0; labels over a graph with such extra arcs
+ * still bound every real arc, so the update stays valid.  Before the refines, a unit-capacity max-flow on
+ * the arbitrary-network solver checks that a perfect matching exists.
+ * Outputs as for lpr_assign_solve (total: the given costs of the chosen
+ * arcs).  opts as for lpr_assign_solve; LPR_ASSIGN_ARC_FIXING is ignored.
+ * Errors: LPR_EINVAL (n outside [1, LPR_ASSIGN_MAX_N], m outside
+ * [0, LPR_ASSIGN_SPARSE_MAX_ARCS], a bad row_ptr, a column outside [0, n),
+ * NULL pointers), LPR_ERANGE (|cost| > 32767), LPR_ENOMATCH (no perfect
+ * matching), LPR_ENOMEM, LPR_EBUDGET, LPR_EDEVICE.
+ */
+lpr_status lpr_assign_sparse_solve(int32_t n, int32_t m, const int32_t *row_ptr,
+                                   const int32_t *col, const int32_t *cost,
+                                   int32_t maximize, int32_t *row_to_col,
+                                   int64_t *total, int64_t *col_prices,
+                                   const lpr_assign_opts *opts,
+                                   lpr_assign_stats *stats, void *workspace,
+                                   size_t workspace_bytes, void *stream);
 
 /* ======================================================================== */
 /* Learned warm start for cost scaling (not part of the paper's method)     */

@@ -20,6 +20,9 @@ Max-flow (Section 3 definitions; Sections 4.1-4.2 algorithms):
 
 Assignment (Section 3 definition; Section 5 method):
   * ``hungarian(cost)`` -- O(n^3) Hungarian method with integer duals.
+  * ``assign_sparse(n, row_ptr, col, cost)`` -- the same problem on listed
+    arcs only (CSR by row): the Hungarian method on the complete matrix with
+    missing arcs at a prohibitive cost.
   * ``cost_scaling(cost, ...)`` -- the paper's refine (Algorithm 5.2) with the
     push/relabel operation of Algorithm 5.4, run sequentially in FIFO order.
 
@@ -186,6 +189,36 @@ def assign(cost, maximize=False):
     maximize=True the weights are negated and minimised (Section 3 states
     the problem as maximum weight)."""
     r2c, tot, _, _ = hungarian(_oriented(cost, maximize))
+    return r2c, (-tot if maximize else tot)
+
+
+def assign_sparse(n, row_ptr, col, cost, maximize=False):
+    """Optimal assignment on a sparse bipartite graph given in CSR by row
+    (Section 3's problem restricted to the listed arcs; of parallel arcs the
+    best one counts).  Returns (row_to_col, total) or None when no perfect
+    matching exists.
+
+    By definition: the complete matrix with every missing arc at a cost M
+    larger than n times the spread of the real costs, so that any perfect
+    matching of real arcs is cheaper than every assignment using an M arc;
+    the Hungarian method then finds the optimum, which uses an M arc exactly
+    when no perfect matching of real arcs exists."""
+    row_ptr = np.asarray(row_ptr, np.int64)
+    col = np.asarray(col, np.int64)
+    w = np.asarray(cost, np.int64)
+    c = -w if maximize else w
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    spread = int(c.max() - c.min()) if len(c) else 0
+    big = int(c.max() if len(c) else 0) + n * (spread + 1) + 1
+    dense = np.full((n, n), big, np.int64)
+    np.minimum.at(dense, (rows, col), c)
+    real = np.zeros((n, n), bool)
+    real[rows, col] = True
+    assert big < 2**31, "costs too large for the int32 Hungarian oracle"
+    r2c, _, _, _ = hungarian(dense)
+    if not real[np.arange(n), r2c].all():
+        return None
+    tot = int(dense[np.arange(n), r2c].sum())
     return r2c, (-tot if maximize else tot)
 
 

@@ -104,6 +104,8 @@ struct AArgs {
     int32_t pu_start;              // price update after each refine's first push
     int32_t arc_fixing;            // keep candidate lists of unfixed arcs
     int32_t fixing_shift;          // the bound divided by 2^fixing_shift
+    int32_t sparse;                // the lists hold the instance's arcs: the
+                                   // row scans read only them, always
     int32_t *cand;                 // per row: (y << 16 | c16(x,y)) of the arcs
                                    // not fixed yet, row stride ld16(n)
     int32_t *ncand;                // per row: number of them
@@ -495,7 +497,12 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
                                                : int64_t(cv[k]) * sgnS;
                         const int64_t cp = cs + pxx - L.py[y];
                         if (cp < bound && y != mx) {
-                            best = level + D.floor_div(cp) + 1;
+                            // c_p >= -eps on every arc of an eps-optimal
+                            // pseudoflow, so the clamp only acts on the
+                            // missing arcs of a sparse instance (which are
+                            // not kept eps-optimal): Dial's buckets need
+                            // lengths >= 0
+                            best = level + max(int64_t(0), D.floor_div(cp) + 1);
                             bound = D.mul_sat(best - level - 1);
                         }
                     }
@@ -772,9 +779,10 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     // candidate lists of unfixed arcs (int16 costs only); `lists` is the same
     // in every thread
     const bool fixing = sizeof(T) == 2 && A.arc_fixing && A.cand;
-    int32_t *cand = fixing ? A.cand + I.c16_off : nullptr;
-    int32_t *ncand = fixing ? A.ncand + I.row_off : nullptr;
-    bool lists = false;
+    const bool sparse = sizeof(T) == 2 && A.sparse;
+    int32_t *cand = fixing || sparse ? A.cand + I.c16_off : nullptr;
+    int32_t *ncand = fixing || sparse ? A.ncand + I.row_off : nullptr;
+    bool lists = sparse;
     __shared__ int s_bad;
     // the least part-reduced cost of row x over its candidates (all columns
     // without lists)
@@ -997,7 +1005,8 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
         }
         if (s_stop) break;
         if (eps == 1) {
-            if (!lists) break;
+            // a sparse instance's lists are its arcs: nothing else to check
+            if (!lists || sparse) break;
             // the lists rest on arc fixing's bound: confirm 1-optimality over
             // all arcs, else run the last refine again with full scans
             if (tid == 0) s_bad = 0;
@@ -1054,7 +1063,7 @@ __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
     const AInst I = A.inst[slot];
     extern __shared__ __align__(16) unsigned char smem[];
     const unsigned cmax = A.cmax[slot];
-    if (cmax > unsigned(LPR_ASSIGN_MAX_COST)) {
+    if (cmax > unsigned(LPR_ASSIGN_MAX_COST) || (A.sparse && cmax > C16_MAX)) {
         if (threadIdx.x == 0) A.status[slot] = 2;
         return;
     }
@@ -1110,8 +1119,9 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
                       const int32_t *costs, int32_t maximize,
                       int32_t *row_to_col, int64_t *totals, int64_t *col_prices,
                       const lpr_assign_opts *opts, lpr_assign_stats *stats,
-                      void *workspace, size_t ws_bytes, void *stream) {
-    clear_error();
+                      void *workspace, size_t ws_bytes, void *stream,
+                      int32_t sparse = 0) {
+    if (!sparse) clear_error();
     if (B < 1 || !n || !cost_offset || !costs || !row_to_col || !totals ||
         !workspace) {
         set_error("invalid arguments (NULL pointer or B < 1)");
@@ -1220,6 +1230,8 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     A.pu_start = pu_start;
     A.arc_fixing = arc_fixing;
     A.fixing_shift = fixing_shift;
+    A.sparse = sparse;
+    if (sparse) A.arc_fixing = 0;
     A.cand = L.cand;
     A.ncand = L.ncand;
     int khz = 0;  // wall_clock64 ticks per millisecond
@@ -1327,4 +1339,228 @@ extern "C" lpr_status lpr_assign_solve_batched(
     return assign::run(B, n, cost_offset, costs, maximize, row_to_col, totals,
                        col_prices, opts, stats, workspace, workspace_bytes,
                        stream);
+}
+
+// ---------------------------------------------------------------------------
+// Sparse assignment: the bipartite graph is given by its arcs (CSR by row).
+// The arcs become the row lists that every row scan of the refine reads.
+// The price update keeps a dense column-major copy; there every missing arc
+// carries the largest cost of the instance.  Missing arcs are not kept
+// eps-optimal, so their length floor(c_p / eps) + 1 is clamped at 0 (Dial's
+// buckets need lengths >= 0; real arcs are never clamped).  Labels computed
+// over a graph with extra arcs of length >= 0 still satisfy
+// d(u) <= d(v) + length(u,v) on every real residual arc, so their price
+// change keeps the pseudoflow eps-optimal and the update stays valid.  A refine terminates only when a perfect matching exists, so that
+// is checked first, as a unit-capacity max-flow on the arbitrary-network
+// solver (Section 3: a maximum matching is a maximum flow).
+// ---------------------------------------------------------------------------
+namespace lpr {
+namespace assign {
+
+// error bits: 1 structure (row_ptr, column range), 2 |cost| > C16_MAX
+__global__ __launch_bounds__(256) void k_sp_check(int n, int m, const int32_t *row_ptr,
+                                                  const int32_t *col,
+                                                  const int32_t *cost, unsigned *err,
+                                                  unsigned *cmax) {
+    const int tid = blockIdx.x * 256 + threadIdx.x, nth = gridDim.x * 256;
+    unsigned bits = 0, cm = 0;
+    for (int x = tid; x <= n; x += nth) {
+        const int a = row_ptr[x];
+        if (x == 0 && a != 0) bits |= 1;
+        if (x == n && a != m) bits |= 1;
+        if (x < n && row_ptr[x + 1] < a) bits |= 1;
+    }
+    for (int k = tid; k < m; k += nth) {
+        const int y = col[k], c = cost[k];
+        if (y < 0 || y >= n) bits |= 1;
+        const unsigned a = c < 0 ? 0u - unsigned(c) : unsigned(c);
+        if (a > C16_MAX) bits |= 2;
+        cm = max(cm, a);
+    }
+    if (bits) atomicOr(err, bits);
+    for (int o = 32; o > 0; o >>= 1) cm = max(cm, unsigned(__shfl_xor(int(cm), o, 64)));
+    if ((threadIdx.x & 63) == 0 && cm) atomicMax(cmax, cm);
+}
+
+// Dense matrix of the missing-arc cost (max|c| to minimise, -max|c| to
+// maximise: the worst value either way) and an empty arc bitmap.
+__global__ __launch_bounds__(256) void k_sp_fill(int n, int32_t *D, uint32_t *mask,
+                                                 int words, const unsigned *cmax,
+                                                 int sign) {
+    const int32_t fake = sign > 0 ? int32_t(*cmax) : -int32_t(*cmax);
+    const int64_t nn = int64_t(n) * n, nm = int64_t(n) * words;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < nn; i += gridDim.x * 256ll) {
+        D[i] = fake;
+        if (i < nm) mask[i] = 0;
+    }
+}
+
+// One wavefront per row: each arc lowers (raises, to maximise) its matrix
+// entry -- of parallel arcs only the best one matters -- and sets its bit;
+// the flow network gets the arc X(x) -> Y(y) of capacity 1, plus s -> X(x)
+// and Y(x) -> t.  Nodes: X = 0..n-1, Y = n..2n-1, s = 2n, t = 2n + 1.
+__global__ __launch_bounds__(256) void k_sp_scatter(int n, int m, const int32_t *row_ptr,
+                                                    const int32_t *col,
+                                                    const int32_t *cost, int sign,
+                                                    int32_t *D, uint32_t *mask, int words,
+                                                    int32_t *tail, int32_t *head,
+                                                    int32_t *cap) {
+    const int lane = threadIdx.x & 63;
+    const int x = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (x >= n) return;
+    for (int k = row_ptr[x] + lane; k < row_ptr[x + 1]; k += 64) {
+        const int y = col[k], c = cost[k];
+        int32_t *d = D + int64_t(x) * n + y;
+        if (sign > 0) atomicMin(d, c);
+        else atomicMax(d, c);
+        atomicOr(&mask[int64_t(x) * words + (y >> 5)], 1u << (y & 31));
+        tail[2 * k] = x;
+        head[2 * k] = n + y;
+        cap[2 * k] = 1;
+        tail[2 * k + 1] = n + y;
+        head[2 * k + 1] = x;
+        cap[2 * k + 1] = 0;
+    }
+    if (lane == 0) {
+        const int64_t a = 2 * (int64_t(m) + x), b = 2 * (int64_t(m) + n + x);
+        tail[a] = 2 * n;
+        head[a] = x;
+        cap[a] = 1;
+        tail[a + 1] = x;
+        head[a + 1] = 2 * n;
+        cap[a + 1] = 0;
+        tail[b] = n + x;
+        head[b] = 2 * n + 1;
+        cap[b] = 1;
+        tail[b + 1] = 2 * n + 1;
+        head[b + 1] = n + x;
+        cap[b + 1] = 0;
+    }
+}
+
+// One wavefront per row: the row's distinct arcs in column order as list
+// entries (y << 16) | (c(x,y) & 0xffff), their number in ncand[x].
+__global__ __launch_bounds__(256) void k_sp_lists(int n, const int32_t *D,
+                                                  const uint32_t *mask, int words,
+                                                  int32_t *cand, int32_t *ncand) {
+    const int lane = threadIdx.x & 63;
+    const int x = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (x >= n) return;
+    int32_t *list = cand + int64_t(x) * ld16(n);
+    int out = 0;
+    for (int y0 = 0; y0 < n; y0 += 64) {
+        const int y = y0 + lane;
+        const bool real =
+            y < n && (mask[int64_t(x) * words + (y >> 5)] >> (y & 31) & 1u) != 0;
+        const unsigned long long bal = __ballot(real);
+        if (real)
+            list[out + __popcll(bal & ((1ull << lane) - 1))] =
+                (y << 16) | (D[int64_t(x) * n + y] & 0xffff);
+        out += __popcll(bal);
+    }
+    if (lane == 0) ncand[x] = out;
+}
+
+struct SparseLayout {
+    unsigned char *assign_ws, *graph_ws;
+    size_t assign_bytes, graph_bytes;
+    int32_t *D, *tail, *head, *cap;
+    uint32_t *mask;
+    unsigned *words;  // error bits, max|c|
+};
+
+static Carver sparse_carve(Carver cv, int n, int m, SparseLayout *S) {
+    const int words = (n + 31) / 32;
+    const int64_t arcs = 2 * (int64_t(m) + 2 * n);
+    S->assign_bytes = workspace_bytes(1, &n);
+    S->graph_bytes = lpr_graph_maxflow_workspace(2 * n + 2, int32_t(arcs));
+    S->assign_ws = cv.take<unsigned char>(S->assign_bytes);
+    S->graph_ws = cv.take<unsigned char>(S->graph_bytes);
+    S->D = cv.take<int32_t>(size_t(n) * n);
+    S->mask = cv.take<uint32_t>(size_t(n) * words);
+    S->tail = cv.take<int32_t>(size_t(arcs));
+    S->head = cv.take<int32_t>(size_t(arcs));
+    S->cap = cv.take<int32_t>(size_t(arcs));
+    S->words = cv.take<unsigned>(2);
+    return cv;
+}
+
+static bool sparse_args_ok(int32_t n, int32_t m) {
+    return n >= 1 && n <= LPR_ASSIGN_MAX_N && m >= 0 && m <= LPR_ASSIGN_SPARSE_MAX_ARCS;
+}
+
+}  // namespace assign
+}  // namespace lpr
+
+extern "C" size_t lpr_assign_sparse_workspace(int32_t n, int32_t m) {
+    if (!assign::sparse_args_ok(n, m)) return 0;
+    assign::SparseLayout S;
+    return assign::sparse_carve(Carver(), n, m, &S).used();
+}
+
+extern "C" lpr_status lpr_assign_sparse_solve(int32_t n, int32_t m, const int32_t *row_ptr,
+                                              const int32_t *col, const int32_t *cost,
+                                              int32_t maximize, int32_t *row_to_col,
+                                              int64_t *total, int64_t *col_prices,
+                                              const lpr_assign_opts *opts,
+                                              lpr_assign_stats *stats, void *workspace,
+                                              size_t workspace_bytes, void *stream) {
+    using namespace assign;
+    clear_error();
+    if (!sparse_args_ok(n, m) || !row_ptr || (m > 0 && (!col || !cost)) || !row_to_col ||
+        !total || !workspace) {
+        set_error("invalid arguments (n = %d, m = %d, or a NULL pointer)", n, m);
+        return LPR_EINVAL;
+    }
+    const size_t need = lpr_assign_sparse_workspace(n, m);
+    if (workspace_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", workspace_bytes, need);
+        return LPR_ENOMEM;
+    }
+    SparseLayout S;
+    sparse_carve(Carver(workspace, workspace_bytes), n, m, &S);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int words = (n + 31) / 32, sign = maximize ? -1 : 1;
+    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(S.words), 0, 2, s));
+    const int gc = int(std::min<int64_t>(1024, (int64_t(m) + n + 256) / 256));
+    hipLaunchKernelGGL(k_sp_check, dim3(gc), dim3(256), 0, s, n, m, row_ptr, col, cost,
+                       S.words, S.words + 1);
+    LPR_TRY_HIP(hipGetLastError());
+    unsigned w[2] = {0, 0};
+    LPR_TRY_HIP(hipMemcpyAsync(w, S.words, sizeof(w), hipMemcpyDeviceToHost, s));
+    LPR_TRY_HIP(hipStreamSynchronize(s));
+    if (w[0] & 1) {
+        set_error("row_ptr is not a CSR offset array of m arcs, or a column is outside [0, n)");
+        return LPR_EINVAL;
+    }
+    if (w[0] & 2) {
+        set_error("|cost| > 32767 in a sparse instance");
+        return LPR_ERANGE;
+    }
+    const int gf = int(std::min<int64_t>(4096, (int64_t(n) * n + 255) / 256));
+    hipLaunchKernelGGL(k_sp_fill, dim3(gf), dim3(256), 0, s, n, S.D, S.mask, words,
+                       S.words + 1, sign);
+    const int gw = (n + 3) / 4;  // four wavefronts per block, one per row
+    hipLaunchKernelGGL(k_sp_scatter, dim3(gw), dim3(256), 0, s, n, m, row_ptr, col, cost,
+                       sign, S.D, S.mask, words, S.tail, S.head, S.cap);
+    LPR_TRY_HIP(hipGetLastError());
+    // a perfect matching must exist, else no refine ends
+    int64_t matched = 0;
+    const lpr_status fs = lpr_graph_maxflow(
+        2 * n + 2, int32_t(2 * (int64_t(m) + 2 * n)), S.tail, S.head, S.cap, 2 * n,
+        2 * n + 1, &matched, nullptr, nullptr, nullptr, S.graph_ws, S.graph_bytes, stream);
+    if (fs != LPR_OK) return fs;
+    if (matched < n) {
+        set_error("no perfect matching: at most %lld of %d rows can be matched",
+                  (long long)matched, n);
+        return LPR_ENOMATCH;
+    }
+    Layout L;
+    carve(Carver(S.assign_ws, S.assign_bytes), 1, &n, &L);
+    hipLaunchKernelGGL(k_sp_lists, dim3(gw), dim3(256), 0, s, n, S.D, S.mask, words,
+                       L.cand, L.ncand);
+    LPR_TRY_HIP(hipGetLastError());
+    const int64_t off[2] = {0, int64_t(n) * n};
+    return run(1, &n, off, S.D, maximize, row_to_col, total, col_prices, opts, stats,
+               S.assign_ws, S.assign_bytes, stream, 1);
 }

@@ -18,11 +18,14 @@ LIB_PATH = os.path.join(HERE, "liblpr.so")
 
 LPR_OK, LPR_EINVAL, LPR_ERANGE, LPR_ENOMEM, LPR_EDEVICE, LPR_EBUDGET = (
     0, -1, -2, -3, -4, -5)
+LPR_ENOMATCH = -6
 STATUS_NAMES = {0: "LPR_OK", -1: "LPR_EINVAL", -2: "LPR_ERANGE",
-                -3: "LPR_ENOMEM", -4: "LPR_EDEVICE", -5: "LPR_EBUDGET"}
+                -3: "LPR_ENOMEM", -4: "LPR_EDEVICE", -5: "LPR_EBUDGET",
+                -6: "LPR_ENOMATCH"}
 LPR_GRID_MAX_CAP = (1 << 26) - 1
 LPR_ASSIGN_MAX_COST = (1 << 24) - 1
 LPR_ASSIGN_MAX_N = 2048
+LPR_ASSIGN_SPARSE_MAX_ARCS = 1 << 26
 LPR_GRID_TIME_KERNELS = 0x1
 LPR_GRID_NO_GRAPH = 0x2
 LPR_ASSIGN_TIME_KERNELS = 0x1
@@ -37,6 +40,7 @@ EXPORTED = [
     "lpr_grid_tune",
     "lpr_assign_workspace", "lpr_assign_solve",
     "lpr_assign_batched_workspace", "lpr_assign_solve_batched",
+    "lpr_assign_sparse_workspace", "lpr_assign_sparse_solve",
     "lpr_pricenet_param_count", "lpr_pricenet_workspace",
     "lpr_pricenet_features", "lpr_pricenet_infer", "lpr_pricenet_train_step",
     "lpr_graph_maxflow_workspace", "lpr_graph_maxflow",
@@ -155,6 +159,12 @@ def lib():
                                            ctypes.POINTER(AssignOpts),
                                            ctypes.POINTER(AssignStats), vp, sz,
                                            vp]
+    L.lpr_assign_sparse_workspace.restype = sz
+    L.lpr_assign_sparse_workspace.argtypes = [i32, i32]
+    L.lpr_assign_sparse_solve.restype = ctypes.c_int
+    L.lpr_assign_sparse_solve.argtypes = [i32, i32, vp, vp, vp, i32, vp, vp, vp,
+                                          ctypes.POINTER(AssignOpts),
+                                          ctypes.POINTER(AssignStats), vp, sz, vp]
     L.lpr_pricenet_param_count.restype = sz
     L.lpr_pricenet_param_count.argtypes = []
     L.lpr_pricenet_workspace.restype = sz
@@ -379,6 +389,40 @@ def lpr_assign_solve(cost, maximize=False, opts: AssignOpts | None = None,
         _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "lpr_assign_solve")
     return r2c, int(tot.item()), prices, _struct_dict(st)
+
+
+def lpr_assign_sparse_workspace(n: int, m: int) -> int:
+    return int(lib().lpr_assign_sparse_workspace(n, m))
+
+
+def lpr_assign_sparse_solve(n, row_ptr, col, cost, maximize=False,
+                            opts: AssignOpts | None = None, want_prices=True,
+                            workspace=None, stream=None, device="cuda"):
+    """Solve one sparse assignment given in CSR by row
+    (lpr_assign_sparse_solve).  Returns (row_to_col int32 tensor, total (int),
+    col_prices int64 tensor or None, stats)."""
+    import torch
+    rp = _dev_i32(row_ptr, device)
+    cl = _dev_i32(col, device)
+    cs = _dev_i32(cost, device)
+    m = int(cl.numel())
+    assert rp.numel() == n + 1 and cs.numel() == m
+    dev = rp.device
+    r2c = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    tot = torch.zeros(1, dtype=torch.int64, device=dev)
+    prices = (torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+              if want_prices else None)
+    ws = (workspace if workspace is not None
+          else _workspace(lpr_assign_sparse_workspace(n, m), dev))
+    st = AssignStats()
+    rc = lib().lpr_assign_sparse_solve(
+        n, m, _ptr(rp), _ptr(cl if m else None), _ptr(cs if m else None),
+        int(bool(maximize)), _ptr(r2c), _ptr(tot), _ptr(prices),
+        ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+        _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_assign_sparse_solve")
+    return r2c[:n], int(tot.item()), None if prices is None else prices[:n], \
+        _struct_dict(st)
 
 
 def lpr_assign_batched_workspace(ns) -> int:

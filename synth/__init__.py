@@ -11,7 +11,7 @@ row-major and part of the definition of each workload.
 from .grids import (GridInstance, grid_uniform, grid_blobs, grid_batch,
                     grid_random_small, grid_from_pairs)
 from .assign import (assign_uniform, assign_points, assign_batch,
-                     assign_random_small, TRAIN_BRANCH)
+                     assign_random_small, assign_sparse, TRAIN_BRANCH)
 from .graphs import (graph_random, graph_layered, graph_bipartite, pairs_to_arcs,
                      grid_to_arcs, grid3d_arcs, grid8_arcs)
 
@@ -19,6 +19,7 @@ __all__ = [
     "GridInstance", "grid_uniform", "grid_blobs", "grid_batch",
     "grid_random_small", "grid_from_pairs",
     "assign_uniform", "assign_points", "assign_batch", "assign_random_small",
+    "assign_sparse",
     "TRAIN_BRANCH",
     "graph_random", "graph_layered", "graph_bipartite", "pairs_to_arcs",
     "grid_to_arcs", "grid3d_arcs", "grid8_arcs",

@@ -55,3 +55,35 @@ def assign_random_small(n: int, seed: int, lo: int = -50, hi: int = 50):
     """Small general cost matrix for pins (negative entries allowed)."""
     g = np.random.default_rng(np.random.SeedSequence([901, n, seed]))
     return np.ascontiguousarray(g.integers(lo, hi + 1, (n, n)).astype(np.int32))
+
+
+CONFIG_ASSIGN_SPARSE = 16
+
+
+def assign_sparse(n: int, degree: int, seed: int = 0, instance: int = 0,
+                  lo: int = 0, hi: int = 1000, planted: bool = True,
+                  parallel: float = 0.0):
+    """Sparse bipartite instance in CSR by row: every row gets `degree`
+    uniform random columns (repeats possible) and, with `planted`, the column
+    of a random permutation, so that a perfect matching exists; a fraction
+    `parallel` of the arcs is listed twice with another cost.  Costs uniform
+    in {lo..hi}.  Returns (row_ptr, col, cost), int32."""
+    g = _rng(CONFIG_ASSIGN_SPARSE, instance, seed)
+    perm = g.permutation(n)
+    cols = [g.integers(0, n, (n, degree))]
+    if planted:
+        cols.append(perm[:, None])
+    c = np.concatenate(cols, axis=1) if n else np.zeros((0, 0), np.int64)
+    rows = [list(r) for r in c]
+    if parallel > 0:
+        for r in rows:
+            extra = [y for y in r if g.random() < parallel]
+            r.extend(extra)
+    for r in rows:
+        g.shuffle(r)
+    deg = np.array([len(r) for r in rows], np.int64)
+    row_ptr = np.zeros(n + 1, np.int64)
+    row_ptr[1:] = np.cumsum(deg)
+    col = np.array([y for r in rows for y in r], np.int64)
+    cost = g.integers(lo, hi + 1, len(col))
+    return row_ptr.astype(np.int32), col.astype(np.int32), cost.astype(np.int32)

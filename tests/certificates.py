@@ -68,3 +68,32 @@ def scaled_eps_certificate(cost_min, row_to_col, col_prices, eps=1) -> bool:
     if n == 1:
         return True
     return bool(np.all(gm >= g.max(axis=1) - 2 * eps))
+
+
+def scaled_eps_certificate_sparse(n, row_ptr, col, cost_min, row_to_col,
+                                  col_prices, eps=1) -> bool:
+    """scaled_eps_certificate on a sparse graph: only listed arcs are
+    residual arcs (of parallel arcs, the cheapest), so the condition is
+    g(x,M(x)) >= max over the row's other listed columns of g(x,y) - 2 eps.
+    A residual cycle still has at most 2n arcs, so eps = 1 certifies
+    optimality among the perfect matchings of the listed arcs."""
+    S = 2 * n + 1
+    row_ptr = np.asarray(row_ptr, np.int64)
+    col = np.asarray(col, np.int64)
+    c = np.asarray(cost_min, np.int64)
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    best = np.full((n, n), np.iinfo(np.int64).max, np.int64)
+    np.minimum.at(best, (rows, col), c)
+    listed = best != np.iinfo(np.int64).max
+    m = np.asarray(row_to_col, np.int64)
+    r = np.arange(n)
+    if not listed[r, m].all():
+        return False
+    p = np.asarray(col_prices, np.int64)
+    g = np.where(listed, p[None, :] - S * np.where(listed, best, 0),
+                 np.iinfo(np.int64).min)
+    gm = g[r, m].copy()
+    g[r, m] = np.iinfo(np.int64).min
+    other = g.max(axis=1)
+    alone = other == np.iinfo(np.int64).min  # the row lists one column only
+    return bool(np.all(alone | (gm >= np.where(alone, 0, other) - 2 * eps)))

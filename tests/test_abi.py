@@ -74,3 +74,29 @@ def test_atomic_probe_rejects_bad_arguments():
     for args in ((None, 10, 1, 1), (fake, 5, 1, 1), (fake, 29, 1, 1),
                  (fake, 10, 0, 1), (fake, 10, 1, 0), (fake, 10, 1, 4097)):
         assert L.lpr_atomic_probe(*args, ctypes.byref(ms), None) == lpr.LPR_EINVAL
+
+
+def test_sparse_assignment_host_checks():
+    """Sizes and argument checks of the sparse assignment entry point, all
+    decided on the host before anything reaches the device."""
+    import ctypes
+    assert lpr.lpr_assign_sparse_workspace(0, 5) == 0
+    assert lpr.lpr_assign_sparse_workspace(lpr.LPR_ASSIGN_MAX_N + 1, 5) == 0
+    assert lpr.lpr_assign_sparse_workspace(8, -1) == 0
+    assert lpr.lpr_assign_sparse_workspace(8, lpr.LPR_ASSIGN_SPARSE_MAX_ARCS + 1) == 0
+    w = lpr.lpr_assign_sparse_workspace(1024, 32 * 1024)
+    # the dense copy and the assignment workspace at least
+    assert w >= 4 * 1024 * 1024 + lpr.lpr_assign_workspace(1024)
+    assert "#define LPR_ASSIGN_SPARSE_MAX_ARCS (1 << 26)" in open(HEADER).read()
+    assert "LPR_ENOMATCH = -6" in open(HEADER).read()
+    L = lpr.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below is rejected
+    f = L.lpr_assign_sparse_solve
+    common = (0, fake, fake, None, None, None, fake)
+    assert f(0, 4, fake, fake, fake, *common, 1 << 30, None) == lpr.LPR_EINVAL
+    assert f(4, -1, fake, fake, fake, *common, 1 << 30, None) == lpr.LPR_EINVAL
+    assert f(4, 4, None, fake, fake, *common, 1 << 30, None) == lpr.LPR_EINVAL
+    assert f(4, 4, fake, None, fake, *common, 1 << 30, None) == lpr.LPR_EINVAL
+    assert f(4, 4, fake, fake, fake, 0, None, fake, None, None, None, fake,
+             1 << 30, None) == lpr.LPR_EINVAL  # row_to_col NULL
+    assert f(4, 4, fake, fake, fake, *common, 16, None) == lpr.LPR_ENOMEM

@@ -156,3 +156,58 @@ def test_certificate_rejects_suboptimal():
     bad[[0, 1]] = bad[[1, 0]]
     if int(c[np.arange(12), bad].sum()) > tot:
         assert not scaled_eps_certificate(c, bad, prices)
+
+
+def _sparse_bruteforce(n, row_ptr, col, cost, maximize):
+    """Every permutation that uses listed arcs only, each pair at the best of
+    its parallel arcs; None when there is none."""
+    import itertools
+    best_arc = {}
+    for x in range(n):
+        for k in range(row_ptr[x], row_ptr[x + 1]):
+            y, c = int(col[k]), int(cost[k])
+            key = (x, y)
+            if key not in best_arc or (c > best_arc[key] if maximize else c < best_arc[key]):
+                best_arc[key] = c
+    best = None
+    for p in itertools.permutations(range(n)):
+        if all((x, p[x]) in best_arc for x in range(n)):
+            t = sum(best_arc[(x, p[x])] for x in range(n))
+            if best is None or (t > best if maximize else t < best):
+                best = t
+    return best
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
+def test_sparse_oracle_bruteforce(n):
+    """Section 3's problem on listed arcs: the oracle against every
+    permutation, with parallel arcs, with and without a planted perfect
+    matching (so that some instances have none), both senses."""
+    infeasible = 0
+    for seed in range(12):
+        planted = seed % 3 != 0
+        inst = synth.assign_sparse(n, 1 + seed % 3, seed=seed, lo=-40, hi=40,
+                                   planted=planted, parallel=0.3)
+        for maximize in (False, True):
+            want = _sparse_bruteforce(n, *inst, maximize)
+            got = oracle.assign_sparse(n, *inst, maximize=maximize)
+            if want is None:
+                assert got is None
+                infeasible += 1
+            else:
+                r2c, tot = got
+                assert tot == want
+                assert sorted(r2c.tolist()) == list(range(n))
+    if n >= 3:
+        assert infeasible > 0  # the no-matching branch is exercised
+
+
+def test_sparse_oracle_complete_graph_is_dense():
+    """Listing every arc of the complete graph gives the dense problem."""
+    for n, seed in ((7, 1), (40, 2)):
+        c = synth.assign_random_small(n, seed, lo=-500, hi=500)
+        row_ptr = (np.arange(n + 1) * n).astype(np.int32)
+        col = np.tile(np.arange(n), n).astype(np.int32)
+        for maximize in (False, True):
+            _, tot = oracle.assign_sparse(n, row_ptr, col, c.ravel(), maximize)
+            assert tot == oracle.assign(c, maximize)[1]
