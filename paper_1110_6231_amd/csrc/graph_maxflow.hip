@@ -56,20 +56,58 @@ struct G {
 
 // Checks the mate-pair structure and ranges (error bits: 1 range or
 // structure, 2 capacity) and counts out-degrees into off[tail + 1].
-__global__ __launch_bounds__(NTB) void k_validate(G g) {
-    for (int a = blockIdx.x * NTB + threadIdx.x; a < g.m; a += gridDim.x * NTB) {
-        const int u = g.tail[a], v = g.head[a];
-        unsigned bits = 0;
-        if (u < 0 || u >= g.n || v < 0 || v >= g.n) {
-            bits |= 1;
-        } else {
-            if (g.tail[a ^ 1] != v || g.head[a ^ 1] != u) bits |= 1;
-            const int64_t c = g.cap[a], cr = g.cap[a ^ 1];
-            // u_f(a) + u_f(a^1) = cap(a) + cap(a^1) stays below 2^31
-            if (c < 0 || c + cr > int64_t(INT_MAX)) bits |= 2;
-            atomicAdd(&g.off[u + 1], 1);
+// counter[key] += 1 for every lane with `active`, returning the lane's
+// ticket (the old value plus its rank among the lanes of the same key).
+// Lanes sharing the key of the first lane still waiting are served by one
+// atomic, for two rounds, the rest by one atomic each: s and t can be the
+// tail of half of all arcs, and one address taking an atomic per arc
+// serialises the whole pass.  Called by every lane of the wavefront that
+// runs the loop iteration.
+__device__ inline int wave_ticket(int32_t *counter, int key, bool active) {
+    const int lane = threadIdx.x & 63;
+    bool done = !active;
+    int ticket = 0;
+    for (int r = 0; r < 2; ++r) {
+        const unsigned long long left = __ballot(!done);
+        if (!left) break;
+        const int leader = __ffsll((long long)left) - 1;
+        const int k0 = __shfl(key, leader, 64);
+        const bool mine = !done && key == k0;
+        const unsigned long long same = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&counter[k0], __popcll(same));
+        base = __shfl(base, leader, 64);
+        if (mine) {
+            ticket = base + __popcll(same & ((1ull << lane) - 1));
+            done = true;
         }
-        if (bits) atomicOr(&g.cnt[3], (unsigned long long)bits);
+    }
+    if (!done) ticket = atomicAdd(&counter[key], 1);
+    return ticket;
+}
+
+__global__ __launch_bounds__(NTB) void k_validate(G g) {
+    // wavefront-uniform trip count (wave_ticket needs every lane)
+    for (int a0 = blockIdx.x * NTB; a0 < g.m; a0 += gridDim.x * NTB) {
+        const int a = a0 + int(threadIdx.x);
+        bool ok = false;
+        int u = 0;
+        if (a < g.m) {
+            u = g.tail[a];
+            const int v = g.head[a];
+            unsigned bits = 0;
+            if (u < 0 || u >= g.n || v < 0 || v >= g.n) {
+                bits |= 1;
+            } else {
+                if (g.tail[a ^ 1] != v || g.head[a ^ 1] != u) bits |= 1;
+                const int64_t c = g.cap[a], cr = g.cap[a ^ 1];
+                // u_f(a) + u_f(a^1) = cap(a) + cap(a^1) stays below 2^31
+                if (c < 0 || c + cr > int64_t(INT_MAX)) bits |= 2;
+                ok = true;
+            }
+            if (bits) atomicOr(&g.cnt[3], (unsigned long long)bits);
+        }
+        wave_ticket(g.off, u + 1, ok);
     }
 }
 
@@ -119,9 +157,12 @@ __global__ __launch_bounds__(1024) void k_scan_add(int32_t *x, int len, const in
 }
 
 __global__ __launch_bounds__(NTB) void k_scatter(G g) {
-    for (int a = blockIdx.x * NTB + threadIdx.x; a < g.m; a += gridDim.x * NTB) {
-        const int u = g.tail[a];
-        g.adj[g.off[u] + atomicAdd(&g.cur[u], 1)] = a;
+    for (int a0 = blockIdx.x * NTB; a0 < g.m; a0 += gridDim.x * NTB) {
+        const int a = a0 + int(threadIdx.x);
+        const bool in = a < g.m;
+        const int u = in ? g.tail[a] : 0;
+        const int k = wave_ticket(g.cur, u, in);
+        if (in) g.adj[g.off[u] + k] = a;
     }
 }
 
