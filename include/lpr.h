@@ -50,7 +50,8 @@ typedef enum {
     LPR_ENOMEM = -3,  /* workspace smaller than required                   */
     LPR_EDEVICE = -4, /* a HIP runtime error (text in lpr_last_error)      */
     LPR_EBUDGET = -5, /* the round / operation budget ran out              */
-    LPR_ENOMATCH = -6 /* a sparse assignment has no perfect matching       */
+    LPR_ENOMATCH = -6,   /* a sparse assignment has no perfect matching    */
+    LPR_EINFEASIBLE = -7 /* no flow meets the supplies                     */
 } lpr_status;
 
 /* Thread-local, NUL-terminated description of the most recent failure of a
@@ -497,6 +498,74 @@ lpr_status lpr_graph_maxflow(int32_t n, int32_t m, const int32_t *tail,
                              const lpr_graph_opts *opts, lpr_graph_stats *stats,
                              void *workspace, size_t workspace_bytes,
                              void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Minimum-cost flow with node supplies (Section 5, Algorithm 5.0: the cost
+ * scaling Min-Cost loop with the generic Refine, push and relabel) on a
+ * directed network given as arcs in mate pairs, as for lpr_graph_maxflow.
+ * ------------------------------------------------------------------------- */
+
+#define LPR_MCF_MAX_N (1 << 20)
+#define LPR_MCF_MAX_COST ((1 << 16) - 1)
+#define LPR_MCF_MAX_SUPPLY (1 << 30)
+
+typedef struct {
+    int32_t alpha;           /* eps divisor per refine (0: 8; >= 2)          */
+    int32_t iters_per_check; /* push + relabel passes between host checks of
+                                the active count (0: 8)                      */
+    int64_t max_iters;       /* budget of passes over all refines (0: 2^20)  */
+} lpr_mcf_opts;
+
+typedef struct {
+    int64_t refines;    /* Refine calls                                      */
+    int64_t iterations; /* push + relabel passes launched                    */
+    int64_t pushes;     /* push operations                                   */
+    int64_t relabels;   /* relabel operations                                */
+    double total_ms;    /* device time of the whole call (HIP events)        */
+} lpr_mcf_stats;
+
+/* Device workspace bytes for lpr_mincost_flow (0 for bad n or m). */
+size_t lpr_mincost_flow_workspace(int32_t n, int32_t m);
+
+/*
+ * A flow meeting every node's supply (out-flow minus in-flow = supply[v])
+ * within the arc capacities, of least total cost.
+ *   n       nodes 0..n-1, 1 <= n <= LPR_MCF_MAX_N.
+ *   m       arcs, even: arc a ^ 1 reverses arc a (as for lpr_graph_maxflow).
+ *   tail, head, cap  device int32 [m] as for lpr_graph_maxflow; cap[a] bounds
+ *           the flow along a, so a pair carries a net flow in
+ *           [-cap[a ^ 1], cap[a]].
+ *   cost    device int32 [m], cost[a ^ 1] = -cost[a], |cost| <=
+ *           LPR_MCF_MAX_COST.
+ *   supply  device int32 [n], |supply| <= LPR_MCF_MAX_SUPPLY, summing to 0.
+ * Method: costs scaled by S = n + 1; eps starts at max|cost| x S and each
+ * Refine divides it by alpha (at least 1) until a refine at eps = 1 (i.e.
+ * 1/(n+1) < 1/n in cost units) has ended, which makes the flow optimal.
+ * Refine saturates every arc of negative reduced cost, then alternates a
+ * push pass (every node with excess pushes along its admissible arcs, with
+ * atomic updates of residuals and excesses, prices fixed) and a relabel
+ * pass (every node with excess and no admissible arc relabels, reading its
+ * neighbours' prices, which only fall) until no node has excess.  A
+ * maximum flow from the supplies to the demands on the arbitrary-network
+ * solver first checks that a feasible flow exists.
+ * Outputs: *total_cost (host) = sum over pairs of net flow x cost[a], in
+ * int64 (callers keep it in range); residual (device int32 [m] or NULL):
+ * final residual capacities, net flow along a = cap[a] - residual[a];
+ * prices (device int64 [n] or NULL): final prices for the scaled costs,
+ * with cost[a] S + p[tail] - p[head] >= -1 on every residual arc (the
+ * optimality certificate).
+ * Errors: LPR_EINVAL (n, m, pairs, nodes out of range, supplies not summing
+ * to 0, costs not antisymmetric, NULL pointers), LPR_ERANGE (capacity, cost
+ * or supply out of range), LPR_EINFEASIBLE (no flow meets the supplies),
+ * LPR_ENOMEM, LPR_EBUDGET (max_iters), LPR_EDEVICE.
+ */
+lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail,
+                            const int32_t *head, const int32_t *cap,
+                            const int32_t *cost, const int32_t *supply,
+                            int64_t *total_cost, int32_t *residual,
+                            int64_t *prices, const lpr_mcf_opts *opts,
+                            lpr_mcf_stats *stats, void *workspace,
+                            size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Measurement helper (not part of the method).  Section 4's pushes each

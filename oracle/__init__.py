@@ -23,6 +23,9 @@ Assignment (Section 3 definition; Section 5 method):
   * ``assign_sparse(n, row_ptr, col, cost)`` -- the same problem on listed
     arcs only (CSR by row): the Hungarian method on the complete matrix with
     missing arcs at a prohibitive cost.
+  * ``mincost_flow(n, tail, head, cap, cost, supply)`` -- minimum-cost flow
+    with node supplies (the problem Algorithm 5.0 solves) by successive
+    shortest paths.
   * ``cost_scaling(cost, ...)`` -- the paper's refine (Algorithm 5.2) with the
     push/relabel operation of Algorithm 5.4, run sequentially in FIFO order.
 
@@ -74,8 +77,12 @@ def lib():
             ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_void_p,
             ctypes.c_int64, _i32p, ctypes.POINTER(ctypes.c_int64), _i64p,
             _i64p]
+        L.oracle_mincost_flow.argtypes = [
+            ctypes.c_int, ctypes.c_int, _i32p, _i32p, _i64p, _i64p, _i64p,
+            _i64p, ctypes.POINTER(ctypes.c_int64), _i64p]
         for f in (L.oracle_maxflow_ek, L.oracle_maxflow_fifo,
-                  L.oracle_hungarian, L.oracle_cost_scaling):
+                  L.oracle_hungarian, L.oracle_cost_scaling,
+                  L.oracle_mincost_flow):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -190,6 +197,30 @@ def assign(cost, maximize=False):
     the problem as maximum weight)."""
     r2c, tot, _, _ = hungarian(_oriented(cost, maximize))
     return r2c, (-tot if maximize else tot)
+
+
+def mincost_flow(n, tail, head, cap, cost, supply):
+    """Minimum-cost flow meeting node supplies on mate-pair arcs (arc a^1
+    reverses a, cost[a^1] = -cost[a]) by successive shortest paths.
+
+    Returns (total cost, residual capacities int64[m], potentials int64[n])
+    or None when no flow meets the supplies."""
+    tail = np.ascontiguousarray(tail, np.int32)
+    head = np.ascontiguousarray(head, np.int32)
+    cap = np.ascontiguousarray(cap, np.int64)
+    cost = np.ascontiguousarray(cost, np.int64)
+    supply = np.ascontiguousarray(supply, np.int64)
+    m = len(tail)
+    res = np.zeros(max(m, 1), np.int64)
+    pi = np.zeros(n, np.int64)
+    tot = ctypes.c_int64(0)
+    rc = lib().oracle_mincost_flow(n, m, tail, head, cap, cost, supply, res,
+                                   ctypes.byref(tot), pi)
+    if rc < 0:
+        raise ValueError("oracle min-cost flow rejected its input")
+    if rc == 1:
+        return None
+    return int(tot.value), res[:m], pi
 
 
 def assign_sparse(n, row_ptr, col, cost, maximize=False):

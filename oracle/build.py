@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["maxflow.c", "assignment.c"]
+SOURCES = ["maxflow.c", "assignment.c", "mincost.c"]
 TARGET = os.path.join(HERE, "liboracle.so")
 
 

@@ -394,6 +394,60 @@ static lpr_status run_bfs(const G &g, int forward, hipStream_t s, int64_t *level
     return LPR_OK;  // every level up to |V| done: the BFS is complete
 }
 
+// The state of a network on its workspace: u_f = cap, e = 0, and the CSR of
+// arc ids by tail (degree count with the mate-pair and capacity checks, an
+// exclusive scan, the scatter).
+static lpr_status build_csr(int n, int m, int s, int t, const int32_t *tail,
+                            const int32_t *head, const int32_t *cap, const Layout &L,
+                            hipStream_t st, G *out) {
+    G g;
+    g.n = n;
+    g.m = m;
+    g.s = s;
+    g.t = t;
+    g.tail = tail;
+    g.head = head;
+    g.cap = cap;
+    g.off = L.off;
+    g.adj = L.adj;
+    g.cur = L.cur;
+    g.res = L.res;
+    g.e = L.e;
+    g.h = L.h;
+    g.lab = L.lab;
+    g.q[0] = L.q0;
+    g.q[1] = L.q1;
+    g.qn = L.qn;
+    g.cnt = L.cnt;
+    g.bsum = L.bsum;
+    *out = g;
+    const int ga = blocks_for(m), gn = blocks_for(n);
+    LPR_TRY(fill_i32(L.off, 0, int64_t(n) + 1, st));
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.cnt), 0, 4, st));
+    hipLaunchKernelGGL(k_init, dim3(std::max(ga, gn)), dim3(NTB), 0, st, g);
+    if (m > 0) hipLaunchKernelGGL(k_validate, dim3(ga), dim3(NTB), 0, st, g);
+    LPR_TRY_HIP(hipGetLastError());
+    unsigned long long cnt[4] = {0, 0, 0, 0};
+    LPR_TRY_HIP(hipMemcpyAsync(cnt, L.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    LPR_TRY_HIP(hipStreamSynchronize(st));
+    if (cnt[3]) {
+        if (cnt[3] & 1) {
+            set_error("arcs are not mate pairs (a^1 reverses a) over nodes 0..n-1");
+            return LPR_EINVAL;
+        }
+        set_error("a capacity is negative or a mate pair's sum exceeds 2^31 - 1");
+        return LPR_ERANGE;
+    }
+    // CSR by tail: exclusive scan of the degrees, then the scatter
+    const int len = n + 1, nb = (len + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, st, L.off, len, L.bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, L.bsum, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, st, L.off, len, L.bsum);
+    if (m > 0) hipLaunchKernelGGL(k_scatter, dim3(ga), dim3(NTB), 0, st, g);
+    LPR_TRY_HIP(hipGetLastError());
+    return LPR_OK;
+}
+
 }  // namespace graph
 }  // namespace lpr
 
@@ -442,49 +496,9 @@ extern "C" lpr_status lpr_graph_maxflow(int32_t n, int32_t m, const int32_t *tai
     CallTimer call(st);
     call.start();
     graph::G g;
-    g.n = n;
-    g.m = m;
-    g.s = s;
-    g.t = t;
-    g.tail = tail;
-    g.head = head;
-    g.cap = cap;
-    g.off = L.off;
-    g.adj = L.adj;
-    g.cur = L.cur;
-    g.res = L.res;
-    g.e = L.e;
-    g.h = L.h;
-    g.lab = L.lab;
-    g.q[0] = L.q0;
-    g.q[1] = L.q1;
-    g.qn = L.qn;
-    g.cnt = L.cnt;
-    g.bsum = L.bsum;
-    const int ga = graph::blocks_for(m), gn = graph::blocks_for(n);
-    LPR_TRY(fill_i32(L.off, 0, int64_t(n) + 1, st));
-    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.cnt), 0, 4, st));
-    hipLaunchKernelGGL(graph::k_init, dim3(std::max(ga, gn)), dim3(graph::NTB), 0, st, g);
-    if (m > 0)
-        hipLaunchKernelGGL(graph::k_validate, dim3(ga), dim3(graph::NTB), 0, st, g);
-    LPR_TRY_HIP(hipGetLastError());
+    LPR_TRY(graph::build_csr(n, m, s, t, tail, head, cap, L, st, &g));
+    const int gn = graph::blocks_for(n);
     unsigned long long cnt[4] = {0, 0, 0, 0};
-    LPR_TRY_HIP(hipMemcpyAsync(cnt, L.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
-    LPR_TRY_HIP(hipStreamSynchronize(st));
-    if (cnt[3]) {
-        if (cnt[3] & 1) {
-            set_error("arcs are not mate pairs (a^1 reverses a) over nodes 0..n-1");
-            return LPR_EINVAL;
-        }
-        set_error("a capacity is negative or a mate pair's sum exceeds 2^31 - 1");
-        return LPR_ERANGE;
-    }
-    // CSR by tail: exclusive scan of the degrees, then the scatter
-    const int len = n + 1, nb = (len + 1023) / 1024;
-    hipLaunchKernelGGL(graph::k_scan_blocks, dim3(nb), dim3(1024), 0, st, L.off, len, L.bsum);
-    hipLaunchKernelGGL(graph::k_scan_sums, dim3(1), dim3(1024), 0, st, L.bsum, nb);
-    hipLaunchKernelGGL(graph::k_scan_add, dim3(nb), dim3(1024), 0, st, L.off, len, L.bsum);
-    if (m > 0) hipLaunchKernelGGL(graph::k_scatter, dim3(ga), dim3(graph::NTB), 0, st, g);
     hipLaunchKernelGGL(graph::k_saturate, dim3(graph::blocks_for(m)), dim3(graph::NTB), 0,
                        st, g);
     LPR_TRY_HIP(hipGetLastError());
@@ -521,6 +535,403 @@ extern "C" lpr_status lpr_graph_maxflow(int32_t n, int32_t m, const int32_t *tai
         stats->pushes = int64_t(cnt[0]);
         stats->relabels = int64_t(cnt[1]);
         stats->bfs_levels = levels;
+        stats->total_ms = ms;
+    }
+    return LPR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Minimum-cost flow with supplies by cost scaling (Section 5, Algorithm 5.0:
+// Min-Cost, the generic Refine, push, relabel), on the same CSR.  Reduced
+// cost c_p(a) = cost(a) S + p(tail) - p(head) with S = n + 1; an arc is
+// admissible when residual with c_p < 0.
+// ---------------------------------------------------------------------------
+namespace lpr {
+namespace graph {
+
+struct Mcf {
+    const int32_t *cost;    // [m], cost[a ^ 1] = -cost[a]
+    const int32_t *supply;  // [n]
+    int64_t *p;             // [n] prices of the scaled costs
+    int64_t S;              // n + 1
+    unsigned long long *w;  // [4]: error bits, max |cost|, supply sum, positive supply sum
+};
+
+// error bits: 1 costs not antisymmetric, 2 |cost| or |supply| out of range
+__global__ __launch_bounds__(NTB) void k_mcf_check(G g, Mcf q) {
+    const int tid = blockIdx.x * NTB + threadIdx.x, nth = gridDim.x * NTB;
+    unsigned bits = 0, cm = 0;
+    long long sum = 0, pos = 0;
+    for (int a = tid; a < g.m; a += nth) {
+        const int c = q.cost[a];
+        if (q.cost[a ^ 1] != -c) bits |= 1;
+        const unsigned u = c < 0 ? 0u - unsigned(c) : unsigned(c);
+        if (u > unsigned(LPR_MCF_MAX_COST)) bits |= 2;
+        cm = max(cm, u);
+    }
+    for (int v = tid; v < g.n; v += nth) {
+        const int d = q.supply[v];
+        if (d > LPR_MCF_MAX_SUPPLY || d < -LPR_MCF_MAX_SUPPLY) bits |= 2;
+        sum += d;
+        pos += d > 0 ? d : 0;
+    }
+    if (bits) atomicOr(&q.w[0], (unsigned long long)bits);
+    if (cm) atomicMax(&q.w[1], (unsigned long long)cm);
+    if (sum) atomicAdd(&q.w[2], (unsigned long long)sum);
+    if (pos) atomicAdd(&q.w[3], (unsigned long long)pos);
+}
+
+// The feasibility network: the arcs as given, then per node v the pairs
+// s* -> v (capacity max(d, 0)) and v -> t* (capacity max(-d, 0));
+// s* = n, t* = n + 1.
+__global__ __launch_bounds__(NTB) void k_mcf_feas_arcs(G g, Mcf q, int32_t *ft, int32_t *fh,
+                                                       int32_t *fc) {
+    const int tid = blockIdx.x * NTB + threadIdx.x, nth = gridDim.x * NTB;
+    for (int a = tid; a < g.m; a += nth) {
+        ft[a] = g.tail[a];
+        fh[a] = g.head[a];
+        fc[a] = g.cap[a];
+    }
+    for (int v = tid; v < g.n; v += nth) {
+        const int d = q.supply[v];
+        const int64_t b = int64_t(g.m) + 4 * int64_t(v);
+        ft[b] = g.n;
+        fh[b] = v;
+        fc[b] = d > 0 ? d : 0;
+        ft[b + 1] = v;
+        fh[b + 1] = g.n;
+        fc[b + 1] = 0;
+        ft[b + 2] = v;
+        fh[b + 2] = g.n + 1;
+        fc[b + 2] = d < 0 ? -d : 0;
+        ft[b + 3] = g.n + 1;
+        fh[b + 3] = v;
+        fc[b + 3] = 0;
+    }
+}
+
+__device__ inline int64_t reduced(const G &g, const Mcf &q, int a, int64_t pu) {
+    return int64_t(q.cost[a]) * q.S + pu - q.p[g.head[a]];
+}
+
+// Refine's start: every arc of negative reduced cost is saturated (one
+// thread per mate pair: c_p(a ^ 1) = -c_p(a), so at most one of the two).
+__global__ __launch_bounds__(NTB) void k_mcf_saturate(G g, Mcf q) {
+    for (int a = 2 * (blockIdx.x * NTB + threadIdx.x); a < g.m; a += 2 * gridDim.x * NTB) {
+        const int64_t cp = reduced(g, q, a, q.p[g.tail[a]]);
+        const int r = g.res[a], rr = g.res[a ^ 1];
+        if (cp < 0 && r > 0) {
+            g.res[a] = 0;
+            g.res[a ^ 1] = rr + r;
+        } else if (cp > 0 && rr > 0) {
+            g.res[a] = r + rr;
+            g.res[a ^ 1] = 0;
+        }
+    }
+}
+
+// e(v) = supply(v) - sum of the net flow out of v; nodes with e > 0 counted.
+__global__ __launch_bounds__(NTB) void k_mcf_excess(G g, Mcf q) {
+    unsigned long long act = 0;
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB) {
+        int64_t e = q.supply[v];
+        for (int k = g.off[v]; k < g.off[v + 1]; ++k) {
+            const int a = g.adj[k];
+            e -= int64_t(g.cap[a]) - g.res[a];
+        }
+        g.e[v] = e;
+        act += e > 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) act += __shfl_xor(act, o, 64);
+    if ((threadIdx.x & 63) == 0 && act) atomicAdd(&g.cnt[2], act);
+}
+
+__device__ inline int64_t shfl_up64(int64_t v, int d) {
+    const int lo = __shfl_up(int(uint32_t(v)), d, 64);
+    const int hi = __shfl_up(int(v >> 32), d, 64);
+    return int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+
+__device__ inline int64_t shfl_xor64(int64_t v, int d) {
+    const int lo = __shfl_xor(int(uint32_t(v)), d, 64);
+    const int hi = __shfl_xor(int(v >> 32), d, 64);
+    return int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+
+// Push pass, one wavefront per node, its lanes over 64 arcs at a time:
+// prices are fixed; a node with excess sends min(e, u_f) along its
+// admissible arcs in CSR order (an inclusive scan of the admissible
+// residuals gives every lane its share of what is left).  Only v lowers
+// res(a) for its own arcs and only v lowers e(v); others only raise them,
+// so every amount read stays available.
+__global__ __launch_bounds__(NTB) void k_mcf_push(G g, Mcf q) {
+    const int lane = threadIdx.x & 63;
+    const int nwaves = (gridDim.x * NTB) >> 6;
+    unsigned long long pushes = 0;
+    for (int v = (blockIdx.x * NTB + threadIdx.x) >> 6; v < g.n; v += nwaves) {
+        // others add to e(v) meanwhile: every lane takes lane 0's reading
+        int64_t e0 = g.e[v];
+        {
+            const int lo = __shfl(int(uint32_t(e0)), 0, 64);
+            const int hi = __shfl(int(e0 >> 32), 0, 64);
+            e0 = int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+        }
+        if (e0 <= 0) continue;
+        int64_t left = e0;
+        const int64_t pv = q.p[v];
+        const int end = g.off[v + 1];
+        for (int k0 = g.off[v]; k0 < end && left > 0; k0 += 64) {
+            const int k = k0 + lane;
+            int a = 0;
+            int64_t r = 0;
+            if (k < end) {
+                a = g.adj[k];
+                const int rr = g.res[a];
+                if (rr > 0 && reduced(g, q, a, pv) < 0) r = rr;
+            }
+            int64_t incl = r;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int64_t t = shfl_up64(incl, o);
+                if (lane >= o) incl += t;
+            }
+            const int64_t before = incl - r;
+            const int64_t d = min(r, max(int64_t(0), left - before));
+            if (d > 0) {
+                atomicSub(&g.res[a], int(d));
+                atomicAdd(&g.res[a ^ 1], int(d));
+                atomicAdd(reinterpret_cast<unsigned long long *>(&g.e[g.head[a]]),
+                          (unsigned long long)d);
+                ++pushes;
+            }
+            // the wave sent min(left, sum of the admissible residuals)
+            const int lo = __shfl(int(uint32_t(incl)), 63, 64);
+            const int hi = __shfl(int(incl >> 32), 63, 64);
+            left -= min(left, int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+        }
+        if (lane == 0 && left != e0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&g.e[v]),
+                      (unsigned long long)(left - e0));
+    }
+    for (int o = 32; o > 0; o >>= 1) pushes += __shfl_xor(pushes, o, 64);
+    if (lane == 0 && pushes) atomicAdd(&g.cnt[0], pushes);
+}
+
+// Relabel pass, one wavefront per node: a node with excess and no
+// admissible arc takes p(v) = max over residual arcs (v,w) of
+// p(w) - cost S - eps.  Neighbours relabelling at the same time only lower
+// their prices, and a value read before such a change gives a price that is
+// still eps-optimal on both directions of every arc.
+__global__ __launch_bounds__(NTB) void k_mcf_relabel(G g, Mcf q, int64_t eps) {
+    const int lane = threadIdx.x & 63;
+    const int nwaves = (gridDim.x * NTB) >> 6;
+    unsigned long long relabels = 0;
+    for (int v = (blockIdx.x * NTB + threadIdx.x) >> 6; v < g.n; v += nwaves) {
+        if (g.e[v] <= 0) continue;
+        const int64_t pv = q.p[v];
+        int64_t best = LLONG_MIN;
+        bool admissible = false;
+        for (int k = g.off[v] + lane; k < g.off[v + 1]; k += 64) {
+            const int a = g.adj[k];
+            if (g.res[a] <= 0) continue;
+            const int64_t val = q.p[g.head[a]] - int64_t(q.cost[a]) * q.S;
+            admissible |= val > pv;  // c_p(a) < 0
+            best = max(best, val);
+        }
+        for (int o = 32; o > 0; o >>= 1) best = max(best, shfl_xor64(best, o));
+        if (__ballot(admissible) == 0 && best != LLONG_MIN) {
+            if (lane == 0) q.p[v] = best - eps;
+            ++relabels;
+        }
+    }
+    if (lane == 0 && relabels) atomicAdd(&g.cnt[1], relabels);
+}
+
+__global__ __launch_bounds__(NTB) void k_mcf_count(G g) {
+    unsigned long long act = 0;
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB)
+        act += g.e[v] > 0;
+    for (int o = 32; o > 0; o >>= 1) act += __shfl_xor(act, o, 64);
+    if ((threadIdx.x & 63) == 0 && act) atomicAdd(&g.cnt[2], act);
+}
+
+// sum over pairs of net flow x cost
+__global__ __launch_bounds__(NTB) void k_mcf_total(G g, Mcf q, unsigned long long *tot) {
+    long long t = 0;
+    for (int a = 2 * (blockIdx.x * NTB + threadIdx.x); a < g.m; a += 2 * gridDim.x * NTB)
+        t += (long long)(int64_t(g.cap[a]) - g.res[a]) * q.cost[a];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(tot, (unsigned long long)t);
+}
+
+struct McfLayout {
+    Layout L;
+    int64_t *p;
+    unsigned long long *w;
+    int32_t *ft, *fh, *fc;
+    unsigned char *fws;
+    size_t fbytes;
+};
+
+static Carver mcf_carve(Carver cv, int n, int m, McfLayout *M) {
+    cv = carve(cv, n, m, &M->L);
+    const int64_t fm = int64_t(m) + 4 * int64_t(n);
+    M->p = cv.take<int64_t>(size_t(n));
+    M->w = cv.take<unsigned long long>(8);
+    M->ft = cv.take<int32_t>(size_t(fm));
+    M->fh = cv.take<int32_t>(size_t(fm));
+    M->fc = cv.take<int32_t>(size_t(fm));
+    M->fbytes = lpr_graph_maxflow_workspace(n + 2, int32_t(fm));
+    M->fws = cv.take<unsigned char>(M->fbytes);
+    return cv;
+}
+
+static bool mcf_args_ok(int32_t n, int32_t m) {
+    return n >= 1 && n <= LPR_MCF_MAX_N && m >= 0 && (m & 1) == 0 &&
+           int64_t(m) + 4 * int64_t(n) <= int64_t(INT_MAX) - 1;
+}
+
+}  // namespace graph
+}  // namespace lpr
+
+extern "C" size_t lpr_mincost_flow_workspace(int32_t n, int32_t m) {
+    if (!graph::mcf_args_ok(n, m)) return 0;
+    graph::McfLayout M;
+    return graph::mcf_carve(Carver(), n, m, &M).used();
+}
+
+extern "C" lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail,
+                                       const int32_t *head, const int32_t *cap,
+                                       const int32_t *cost, const int32_t *supply,
+                                       int64_t *total_cost, int32_t *residual,
+                                       int64_t *prices, const lpr_mcf_opts *opts,
+                                       lpr_mcf_stats *stats, void *workspace,
+                                       size_t workspace_bytes, void *stream) {
+    using namespace graph;
+    clear_error();
+    if (!mcf_args_ok(n, m) || !supply || !total_cost || !workspace ||
+        (m > 0 && (!tail || !head || !cap || !cost))) {
+        set_error("invalid arguments (n = %d, m = %d, or a NULL pointer)", n, m);
+        return LPR_EINVAL;
+    }
+    int32_t alpha = 8, per_check = 8;
+    int64_t max_iters = int64_t(1) << 20;
+    if (opts) {
+        if (opts->alpha) alpha = opts->alpha;
+        if (opts->iters_per_check) per_check = opts->iters_per_check;
+        if (opts->max_iters) max_iters = opts->max_iters;
+    }
+    if (alpha < 2 || per_check < 1 || per_check > 1024 || max_iters < 1) {
+        set_error("invalid lpr_mcf_opts");
+        return LPR_EINVAL;
+    }
+    const size_t need = lpr_mincost_flow_workspace(n, m);
+    if (workspace_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", workspace_bytes, need);
+        return LPR_ENOMEM;
+    }
+    McfLayout M;
+    mcf_carve(Carver(workspace, workspace_bytes), n, m, &M);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    CallTimer call(st);
+    call.start();
+    G g;
+    LPR_TRY(build_csr(n, m, 0, 0, tail, head, cap, M.L, st, &g));
+    Mcf q;
+    q.cost = cost;
+    q.supply = supply;
+    q.p = M.p;
+    q.S = int64_t(n) + 1;
+    q.w = M.w;
+    const int ga = blocks_for(std::max(m, n)), gn = blocks_for(n);
+    const int gp = blocks_for(std::max(m / 2, 1));
+    // one wavefront per node: NTB / 64 nodes per block
+    const int gw = int(std::min<int64_t>(4096, (int64_t(n) + NTB / 64 - 1) / (NTB / 64)));
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.w), 0, 8, st));
+    hipLaunchKernelGGL(k_mcf_check, dim3(ga), dim3(NTB), 0, st, g, q);
+    LPR_TRY_HIP(hipGetLastError());
+    unsigned long long w[4];
+    LPR_TRY_HIP(hipMemcpyAsync(w, M.w, sizeof(w), hipMemcpyDeviceToHost, st));
+    LPR_TRY_HIP(hipStreamSynchronize(st));
+    if (w[0] & 1) {
+        set_error("cost[a ^ 1] != -cost[a] for some arc");
+        return LPR_EINVAL;
+    }
+    if (w[0] & 2) {
+        set_error("a cost above LPR_MCF_MAX_COST or a supply above LPR_MCF_MAX_SUPPLY");
+        return LPR_ERANGE;
+    }
+    if (int64_t(w[2]) != 0) {
+        set_error("supplies sum to %lld, not 0", (long long)int64_t(w[2]));
+        return LPR_EINVAL;
+    }
+    // a feasible flow exists iff the supplies can all reach the demands
+    if (w[3] > 0) {
+        const int64_t fm = int64_t(m) + 4 * int64_t(n);
+        hipLaunchKernelGGL(k_mcf_feas_arcs, dim3(blocks_for(std::max<int64_t>(m, n))),
+                           dim3(NTB), 0, st, g, q, M.ft, M.fh, M.fc);
+        LPR_TRY_HIP(hipGetLastError());
+        int64_t routed = 0;
+        const lpr_status fs =
+            lpr_graph_maxflow(n + 2, int32_t(fm), M.ft, M.fh, M.fc, n, n + 1, &routed,
+                              nullptr, nullptr, nullptr, M.fws, M.fbytes, stream);
+        if (fs != LPR_OK) return fs;
+        if (routed < int64_t(w[3])) {
+            set_error("no feasible flow: %lld of %llu supply units can be routed",
+                      (long long)routed, w[3]);
+            return LPR_EINFEASIBLE;
+        }
+    }
+    // Min-Cost: p = 0, eps = C (scaled), Refine until one at eps = 1 ends
+    LPR_TRY(fill_i64(M.p, 0, n, st));
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.L.cnt), 0, 4, st));
+    int64_t eps = int64_t(std::max<unsigned long long>(w[1], 1)) * q.S;
+    int64_t refines = 0, iters = 0;
+    unsigned long long cnt[4] = {0, 0, 0, 0};
+    for (;;) {
+        eps = std::max<int64_t>(1, eps / alpha);
+        hipLaunchKernelGGL(k_mcf_saturate, dim3(gp), dim3(NTB), 0, st, g, q);
+        LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.L.cnt) + 2, 0, 1, st));
+        hipLaunchKernelGGL(k_mcf_excess, dim3(gn), dim3(NTB), 0, st, g, q);
+        LPR_TRY_HIP(hipGetLastError());
+        for (;;) {
+            LPR_TRY_HIP(hipMemcpyAsync(cnt, M.L.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
+            LPR_TRY_HIP(hipStreamSynchronize(st));
+            if (cnt[2] == 0) break;
+            if (iters >= max_iters) {
+                set_error("min-cost flow: pass budget (%lld) exhausted", (long long)max_iters);
+                return LPR_EBUDGET;
+            }
+            for (int k = 0; k < per_check; ++k) {
+                hipLaunchKernelGGL(k_mcf_push, dim3(gw), dim3(NTB), 0, st, g, q);
+                hipLaunchKernelGGL(k_mcf_relabel, dim3(gw), dim3(NTB), 0, st, g, q, eps);
+            }
+            iters += per_check;
+            LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.L.cnt) + 2, 0, 1, st));
+            hipLaunchKernelGGL(k_mcf_count, dim3(gn), dim3(NTB), 0, st, g);
+            LPR_TRY_HIP(hipGetLastError());
+        }
+        ++refines;
+        if (eps == 1) break;
+    }
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.w), 0, 1, st));
+    hipLaunchKernelGGL(k_mcf_total, dim3(gp), dim3(NTB), 0, st, g, q, M.w);
+    LPR_TRY_HIP(hipGetLastError());
+    unsigned long long tot = 0;
+    LPR_TRY_HIP(hipMemcpyAsync(&tot, M.w, sizeof(tot), hipMemcpyDeviceToHost, st));
+    if (residual && m > 0)
+        LPR_TRY_HIP(hipMemcpyAsync(residual, M.L.res, sizeof(int32_t) * size_t(m),
+                                   hipMemcpyDeviceToDevice, st));
+    if (prices)
+        LPR_TRY_HIP(hipMemcpyAsync(prices, M.p, sizeof(int64_t) * size_t(n),
+                                   hipMemcpyDeviceToDevice, st));
+    double ms = 0;
+    LPR_TRY(call.stop_ms(&ms));
+    *total_cost = int64_t(tot);
+    if (stats) {
+        stats->refines = refines;
+        stats->iterations = iters;
+        stats->pushes = int64_t(cnt[0]);
+        stats->relabels = int64_t(cnt[1]);
         stats->total_ms = ms;
     }
     return LPR_OK;

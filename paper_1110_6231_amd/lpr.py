@@ -19,9 +19,13 @@ LIB_PATH = os.path.join(HERE, "liblpr.so")
 LPR_OK, LPR_EINVAL, LPR_ERANGE, LPR_ENOMEM, LPR_EDEVICE, LPR_EBUDGET = (
     0, -1, -2, -3, -4, -5)
 LPR_ENOMATCH = -6
+LPR_EINFEASIBLE = -7
 STATUS_NAMES = {0: "LPR_OK", -1: "LPR_EINVAL", -2: "LPR_ERANGE",
                 -3: "LPR_ENOMEM", -4: "LPR_EDEVICE", -5: "LPR_EBUDGET",
-                -6: "LPR_ENOMATCH"}
+                -6: "LPR_ENOMATCH", -7: "LPR_EINFEASIBLE"}
+LPR_MCF_MAX_N = 1 << 20
+LPR_MCF_MAX_COST = (1 << 16) - 1
+LPR_MCF_MAX_SUPPLY = 1 << 30
 LPR_GRID_MAX_CAP = (1 << 26) - 1
 LPR_ASSIGN_MAX_COST = (1 << 24) - 1
 LPR_ASSIGN_MAX_N = 2048
@@ -44,6 +48,7 @@ EXPORTED = [
     "lpr_pricenet_param_count", "lpr_pricenet_workspace",
     "lpr_pricenet_features", "lpr_pricenet_infer", "lpr_pricenet_train_step",
     "lpr_graph_maxflow_workspace", "lpr_graph_maxflow",
+    "lpr_mincost_flow_workspace", "lpr_mincost_flow",
     "lpr_atomic_probe",
 ]
 PRICENET_FEATURES = 16
@@ -106,6 +111,17 @@ class GraphOpts(ctypes.Structure):
 class GraphStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("pushes", ctypes.c_int64),
                 ("relabels", ctypes.c_int64), ("bfs_levels", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+class McfOpts(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_int32), ("iters_per_check", ctypes.c_int32),
+                ("max_iters", ctypes.c_int64)]
+
+
+class McfStats(ctypes.Structure):
+    _fields_ = [("refines", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("pushes", ctypes.c_int64), ("relabels", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
 
 
@@ -183,6 +199,12 @@ def lib():
     L.lpr_graph_maxflow.argtypes = [i32, i32, vp, vp, vp, i32, i32, i64p, vp,
                                     ctypes.POINTER(GraphOpts),
                                     ctypes.POINTER(GraphStats), vp, sz, vp]
+    L.lpr_mincost_flow_workspace.restype = sz
+    L.lpr_mincost_flow_workspace.argtypes = [i32, i32]
+    L.lpr_mincost_flow.restype = ctypes.c_int
+    L.lpr_mincost_flow.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64p, vp, vp,
+                                   ctypes.POINTER(McfOpts), ctypes.POINTER(McfStats),
+                                   vp, sz, vp]
     L.lpr_atomic_probe.restype = ctypes.c_int
     L.lpr_atomic_probe.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     _lib = L
@@ -598,3 +620,40 @@ def lpr_graph_maxflow(n, tail, head, cap, s, t, want_cut=True,
         _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "lpr_graph_maxflow")
     return int(flow.value), side, _struct_dict(st)
+
+
+def make_mcf_opts(alpha=0, iters_per_check=0, max_iters=0) -> McfOpts:
+    o = McfOpts()
+    o.alpha, o.iters_per_check, o.max_iters = alpha, iters_per_check, max_iters
+    return o
+
+
+def lpr_mincost_flow_workspace(n: int, m: int) -> int:
+    return int(lib().lpr_mincost_flow_workspace(n, m))
+
+
+def lpr_mincost_flow(n, tail, head, cap, cost, supply, want_residual=True,
+                     want_prices=True, opts: McfOpts | None = None,
+                     workspace=None, stream=None, device="cuda"):
+    """Minimum-cost flow meeting the supplies (lpr_mincost_flow).  Arrays are
+    int32 (torch CUDA tensors or host arrays).  Returns (total cost (int),
+    residual int32 tensor [m] or None, prices int64 tensor [n] or None,
+    stats dict)."""
+    import torch
+    arrs = [_dev_i32(a, device) for a in (tail, head, cap, cost)]
+    sup = _dev_i32(supply, device)
+    m = arrs[0].numel()
+    dev = sup.device
+    res = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if want_residual else None
+    pr = torch.empty(n, dtype=torch.int64, device=dev) if want_prices else None
+    ws = (workspace if workspace is not None
+          else _workspace(lpr_mincost_flow_workspace(n, m), dev))
+    tot = ctypes.c_int64(0)
+    st = McfStats()
+    rc = lib().lpr_mincost_flow(
+        int(n), int(m), *[_ptr(a if m else None) for a in arrs], _ptr(sup),
+        ctypes.byref(tot), _ptr(res if m else None), _ptr(pr),
+        ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+        _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_mincost_flow")
+    return int(tot.value), None if res is None else res[:m], pr, _struct_dict(st)

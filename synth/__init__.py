@@ -13,7 +13,8 @@ from .grids import (GridInstance, grid_uniform, grid_blobs, grid_batch,
 from .assign import (assign_uniform, assign_points, assign_batch,
                      assign_random_small, assign_sparse, TRAIN_BRANCH)
 from .graphs import (graph_random, graph_layered, graph_bipartite, pairs_to_arcs,
-                     grid_to_arcs, grid3d_arcs, grid8_arcs)
+                     grid_to_arcs, grid3d_arcs, grid8_arcs, mcf_random,
+                     mcf_transport)
 
 __all__ = [
     "GridInstance", "grid_uniform", "grid_blobs", "grid_batch",
@@ -22,5 +23,5 @@ __all__ = [
     "assign_sparse",
     "TRAIN_BRANCH",
     "graph_random", "graph_layered", "graph_bipartite", "pairs_to_arcs",
-    "grid_to_arcs", "grid3d_arcs", "grid8_arcs",
+    "grid_to_arcs", "grid3d_arcs", "grid8_arcs", "mcf_random", "mcf_transport",
 ]

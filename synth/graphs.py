@@ -178,3 +178,54 @@ def grid8_arcs(H: int, W: int, seed: int = 0, instance: int = 0,
         backs.append(c)
     u, v, c1, c2 = (np.concatenate(x) for x in (us, vs, cs, backs))
     return (N + 2, *pairs_to_arcs(u, v, c1, c2), s, t)
+
+
+CONFIG_MCF_RANDOM = 17
+CONFIG_MCF_TRANSPORT = 18
+
+
+def mcf_random(n: int, edges: int, seed: int = 0, instance: int = 0,
+               max_cap: int = 50, max_cost: int = 100, two_way: float = 0.3):
+    """Random network with costs and supplies met by a planted flow: uniform
+    random edges (self-loops and parallel edges kept), forward capacity
+    U{0..max_cap}, a share `two_way` also with a reverse capacity, cost
+    U{-max_cost..max_cost} along the edge (its reverse the negative); a flow
+    drawn uniformly in [-reverse cap, forward cap] on every edge defines the
+    supplies (out-flow minus in-flow), so a feasible flow exists.
+    Returns (n, tail, head, cap, cost, supply)."""
+    g = _rng(CONFIG_MCF_RANDOM, instance, seed)
+    u = g.integers(0, n, edges)
+    v = g.integers(0, n, edges)
+    c = g.integers(0, max_cap + 1, edges)
+    back = g.random(edges) < two_way
+    cr = np.where(back, g.integers(0, max_cap + 1, edges), 0)
+    w = g.integers(-max_cost, max_cost + 1, edges)
+    f = np.floor(g.random(edges) * (c + cr + 1)).astype(np.int64) - cr
+    supply = np.zeros(n, np.int64)
+    np.add.at(supply, u, f)
+    np.add.at(supply, v, -f)
+    tail, head, cap = pairs_to_arcs(u, v, c, cr)
+    cost = np.empty(2 * edges, np.int32)
+    cost[0::2], cost[1::2] = w, -w
+    return n, tail, head, cap, cost, supply.astype(np.int32)
+
+
+def mcf_transport(sources: int, sinks: int, seed: int = 0, instance: int = 0,
+                  max_cost: int = 1000, max_supply: int = 100, cap: int = 1 << 20):
+    """Transportation problem: every source (nodes 0..sources-1) joined to
+    every sink (the rest) by an arc of capacity `cap` and cost
+    U{0..max_cost}; source supplies U{1..max_supply}, their total split over
+    the sinks uniformly at random as demands.
+    Returns (n, tail, head, cap, cost, supply)."""
+    g = _rng(CONFIG_MCF_TRANSPORT, instance, seed)
+    n = sources + sinks
+    s = g.integers(1, max_supply + 1, sources)
+    demand = np.bincount(g.integers(0, sinks, int(s.sum())), minlength=sinks)
+    supply = np.concatenate([s, -demand]).astype(np.int32)
+    u = np.repeat(np.arange(sources), sinks)
+    v = sources + np.tile(np.arange(sinks), sources)
+    w = g.integers(0, max_cost + 1, len(u))
+    tail, head, caps = pairs_to_arcs(u, v, np.full(len(u), cap), np.zeros(len(u), np.int64))
+    cost = np.empty(2 * len(u), np.int32)
+    cost[0::2], cost[1::2] = w, -w
+    return n, tail, head, caps, cost, supply

@@ -100,3 +100,35 @@ def test_sparse_assignment_host_checks():
     assert f(4, 4, fake, fake, fake, 0, None, fake, None, None, None, fake,
              1 << 30, None) == lpr.LPR_EINVAL  # row_to_col NULL
     assert f(4, 4, fake, fake, fake, *common, 16, None) == lpr.LPR_ENOMEM
+
+
+def test_mincost_flow_host_checks():
+    """Sizes and argument checks of the min-cost flow entry point, decided on
+    the host before anything reaches the device."""
+    import ctypes
+    assert lpr.lpr_mincost_flow_workspace(0, 4) == 0
+    assert lpr.lpr_mincost_flow_workspace(4, 3) == 0
+    assert lpr.lpr_mincost_flow_workspace(lpr.LPR_MCF_MAX_N + 1, 4) == 0
+    assert lpr.lpr_mincost_flow_workspace(100, 400) >= lpr.lpr_graph_maxflow_workspace(100, 400)
+    text = open(HEADER).read()
+    assert "#define LPR_MCF_MAX_N (1 << 20)" in text
+    assert "#define LPR_MCF_MAX_COST ((1 << 16) - 1)" in text
+    assert "LPR_EINFEASIBLE = -7" in text
+    assert ctypes.sizeof(lpr.McfOpts) == 16
+    assert ctypes.sizeof(lpr.McfStats) == 5 * 8
+    L = lpr.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below is rejected
+    tot = ctypes.c_int64(0)
+    f = L.lpr_mincost_flow
+    arcs = (fake, fake, fake, fake, fake)
+    assert f(0, 2, *arcs, ctypes.byref(tot), None, None, None, None, fake, 1 << 30,
+             None) == lpr.LPR_EINVAL
+    assert f(4, 3, *arcs, ctypes.byref(tot), None, None, None, None, fake, 1 << 30,
+             None) == lpr.LPR_EINVAL
+    assert f(4, 2, fake, fake, fake, fake, None, ctypes.byref(tot), None, None, None,
+             None, fake, 1 << 30, None) == lpr.LPR_EINVAL  # supply NULL
+    bad = lpr.make_mcf_opts(alpha=1)
+    assert f(4, 2, *arcs, ctypes.byref(tot), None, None, ctypes.byref(bad), None, fake,
+             1 << 30, None) == lpr.LPR_EINVAL
+    assert f(4, 2, *arcs, ctypes.byref(tot), None, None, None, None, fake, 16,
+             None) == lpr.LPR_ENOMEM
