@@ -512,7 +512,7 @@ lpr_status lpr_graph_maxflow(int32_t n, int32_t m, const int32_t *tail,
 typedef struct {
     int32_t alpha;           /* eps divisor per refine (0: 8; >= 2)          */
     int32_t iters_per_check; /* push + relabel passes between host checks of
-                                the active count (0: 8)                      */
+                                the active count (0: 32)                     */
     int64_t max_iters;       /* budget of passes over all refines (0: 2^20)  */
 } lpr_mcf_opts;
 

@@ -554,7 +554,8 @@ struct Mcf {
     const int32_t *supply;  // [n]
     int64_t *p;             // [n] prices of the scaled costs
     int64_t S;              // n + 1
-    unsigned long long *w;  // [4]: error bits, max |cost|, supply sum, positive supply sum
+    unsigned long long *w;  // [8]: error bits, max |cost|, supply sum, positive
+                            // supply sum, -, eps of the current refine
 };
 
 // error bits: 1 costs not antisymmetric, 2 |cost| or |supply| out of range
@@ -721,7 +722,8 @@ __global__ __launch_bounds__(NTB) void k_mcf_push(G g, Mcf q) {
 // p(w) - cost S - eps.  Neighbours relabelling at the same time only lower
 // their prices, and a value read before such a change gives a price that is
 // still eps-optimal on both directions of every arc.
-__global__ __launch_bounds__(NTB) void k_mcf_relabel(G g, Mcf q, int64_t eps) {
+__global__ __launch_bounds__(NTB) void k_mcf_relabel(G g, Mcf q) {
+    const int64_t eps = int64_t(q.w[5]);
     const int lane = threadIdx.x & 63;
     const int nwaves = (gridDim.x * NTB) >> 6;
     unsigned long long relabels = 0;
@@ -785,6 +787,48 @@ static Carver mcf_carve(Carver cv, int n, int m, McfLayout *M) {
     return cv;
 }
 
+// The passes between two host checks (push and relabel passes, then the
+// active count) captured once per call and replayed: the long tail of a
+// refine has few active nodes, and each pass there costs little more than
+// its launches.  eps is read from the device, so one graph serves every
+// refine.
+struct McfPasses {
+    hipStream_t cs = nullptr;
+    hipGraphExec_t ex = nullptr;
+    ~McfPasses() {
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    lpr_status capture(const G &g, const Mcf &q, int gw, int gn, int passes) {
+        LPR_TRY_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        LPR_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < passes; ++k) {
+            hipLaunchKernelGGL(k_mcf_push, dim3(gw), dim3(NTB), 0, cs, g, q);
+            hipLaunchKernelGGL(k_mcf_relabel, dim3(gw), dim3(NTB), 0, cs, g, q);
+        }
+        hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, cs,
+                           reinterpret_cast<int64_t *>(g.cnt) + 2, int64_t(0), int64_t(1));
+        hipLaunchKernelGGL(k_mcf_count, dim3(gn), dim3(NTB), 0, cs, g);
+        hipGraph_t gr = nullptr;
+        const hipError_t le = hipGetLastError();
+        const hipError_t ce = hipStreamEndCapture(cs, &gr);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            set_error("capturing the min-cost passes failed: %s",
+                      hipGetErrorString(le != hipSuccess ? le : ce));
+            return LPR_EDEVICE;
+        }
+        const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ie != hipSuccess) {
+            ex = nullptr;
+            set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+            return LPR_EDEVICE;
+        }
+        return LPR_OK;
+    }
+};
+
 static bool mcf_args_ok(int32_t n, int32_t m) {
     return n >= 1 && n <= LPR_MCF_MAX_N && m >= 0 && (m & 1) == 0 &&
            int64_t(m) + 4 * int64_t(n) <= int64_t(INT_MAX) - 1;
@@ -813,7 +857,7 @@ extern "C" lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail
         set_error("invalid arguments (n = %d, m = %d, or a NULL pointer)", n, m);
         return LPR_EINVAL;
     }
-    int32_t alpha = 8, per_check = 8;
+    int32_t alpha = 8, per_check = 32;
     int64_t max_iters = int64_t(1) << 20;
     if (opts) {
         if (opts->alpha) alpha = opts->alpha;
@@ -887,8 +931,11 @@ extern "C" lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail
     int64_t eps = int64_t(std::max<unsigned long long>(w[1], 1)) * q.S;
     int64_t refines = 0, iters = 0;
     unsigned long long cnt[4] = {0, 0, 0, 0};
+    McfPasses passes;
+    LPR_TRY(passes.capture(g, q, gw, gn, per_check));
     for (;;) {
         eps = std::max<int64_t>(1, eps / alpha);
+        LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.w) + 5, eps, 1, st));
         hipLaunchKernelGGL(k_mcf_saturate, dim3(gp), dim3(NTB), 0, st, g, q);
         LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.L.cnt) + 2, 0, 1, st));
         hipLaunchKernelGGL(k_mcf_excess, dim3(gn), dim3(NTB), 0, st, g, q);
@@ -901,14 +948,8 @@ extern "C" lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail
                 set_error("min-cost flow: pass budget (%lld) exhausted", (long long)max_iters);
                 return LPR_EBUDGET;
             }
-            for (int k = 0; k < per_check; ++k) {
-                hipLaunchKernelGGL(k_mcf_push, dim3(gw), dim3(NTB), 0, st, g, q);
-                hipLaunchKernelGGL(k_mcf_relabel, dim3(gw), dim3(NTB), 0, st, g, q, eps);
-            }
+            LPR_TRY_HIP(hipGraphLaunch(passes.ex, st));
             iters += per_check;
-            LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.L.cnt) + 2, 0, 1, st));
-            hipLaunchKernelGGL(k_mcf_count, dim3(gn), dim3(NTB), 0, st, g);
-            LPR_TRY_HIP(hipGetLastError());
         }
         ++refines;
         if (eps == 1) break;
