@@ -659,19 +659,24 @@ __device__ inline int64_t shfl_xor64(int64_t v, int d) {
     return int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
 }
 
+constexpr int MCF_CYCLE = 8;  // times a push pass visits each node
+
 // Push pass, one wavefront per node, its lanes over 64 arcs at a time:
 // prices are fixed; a node with excess sends min(e, u_f) along its
 // admissible arcs in CSR order (an inclusive scan of the admissible
 // residuals gives every lane its share of what is left).  Only v lowers
 // res(a) for its own arcs and only v lowers e(v); others only raise them,
-// so every amount read stays available.
+// so every amount read stays available.  Each node is visited MCF_CYCLE
+// times per pass, reading its excess from the device-coherent level each
+// time, so flow pushed into it meanwhile moves on in the same pass.
 __global__ __launch_bounds__(NTB) void k_mcf_push(G g, Mcf q) {
     const int lane = threadIdx.x & 63;
     const int nwaves = (gridDim.x * NTB) >> 6;
     unsigned long long pushes = 0;
+    for (int it = 0; it < MCF_CYCLE; ++it)
     for (int v = (blockIdx.x * NTB + threadIdx.x) >> 6; v < g.n; v += nwaves) {
         // others add to e(v) meanwhile: every lane takes lane 0's reading
-        int64_t e0 = g.e[v];
+        int64_t e0 = __hip_atomic_load(&g.e[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         {
             const int lo = __shfl(int(uint32_t(e0)), 0, 64);
             const int hi = __shfl(int(e0 >> 32), 0, 64);
