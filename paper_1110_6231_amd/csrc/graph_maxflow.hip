@@ -753,6 +753,65 @@ __global__ __launch_bounds__(NTB) void k_mcf_relabel(G g, Mcf q) {
     if (lane == 0 && relabels) atomicAdd(&g.cnt[1], relabels);
 }
 
+// Global price update (Algorithm 5.3 on the general network): labels d(v)
+// = least sum of lengths floor(c_p(a) / eps) + 1 over residual paths from v
+// to a node with a deficit (d = 0 there), capped at LCAP; then
+// p(v) -= eps d(v), nodes that reach no deficit taking the largest label
+// found.  Any labels with d(v) <= d(w) + length(v,w) on every residual arc
+// keep the pseudoflow eps-optimal, and both the cap and a Bellman-Ford
+// pass reading labels that are still falling keep that inequality.
+// Labels are relaxed to their fixpoint one wavefront per node.
+__global__ __launch_bounds__(NTB) void k_mcf_pu_init(G g, int32_t *d, int32_t cap) {
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB)
+        d[v] = g.e[v] < 0 ? 0 : cap;
+}
+
+__global__ __launch_bounds__(NTB) void k_mcf_pu_relax(G g, Mcf q, int32_t *d, int32_t cap,
+                                                      int32_t *changed) {
+    const int lane = threadIdx.x & 63;
+    const int nwaves = (gridDim.x * NTB) >> 6;
+    const int64_t eps = int64_t(q.w[5]);
+    for (int v = (blockIdx.x * NTB + threadIdx.x) >> 6; v < g.n; v += nwaves) {
+        const int dv = d[v];
+        if (dv == 0) continue;
+        const int64_t pv = q.p[v];
+        int best = cap;
+        for (int k = g.off[v] + lane; k < g.off[v + 1]; k += 64) {
+            const int a = g.adj[k];
+            if (g.res[a] <= 0) continue;
+            const int dw = d[g.head[a]];
+            if (dw >= cap) continue;
+            // c_p >= -eps on residual arcs, so the length is >= 0
+            const int64_t cp = reduced(g, q, a, pv);
+            const int64_t len = cp < 0 ? 0 : cp / eps + 1;
+            best = int(min(int64_t(best), int64_t(dw) + len));
+        }
+        for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+        if (lane == 0 && best < dv) {
+            d[v] = best;
+            *changed = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(NTB) void k_mcf_pu_max(G g, const int32_t *d, int32_t cap,
+                                                    int32_t *dmax) {
+    int m = 0;
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB)
+        if (d[v] < cap) m = max(m, d[v]);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(dmax, m);
+}
+
+__global__ __launch_bounds__(NTB) void k_mcf_pu_apply(G g, Mcf q, const int32_t *d,
+                                                      int32_t cap, const int32_t *dmax) {
+    const int64_t eps = int64_t(q.w[5]);
+    for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB) {
+        const int dv = d[v] < cap ? d[v] : *dmax;
+        if (dv) q.p[v] -= eps * dv;
+    }
+}
+
 __global__ __launch_bounds__(NTB) void k_mcf_count(G g) {
     unsigned long long act = 0;
     for (int v = blockIdx.x * NTB + threadIdx.x; v < g.n; v += gridDim.x * NTB)
@@ -772,6 +831,7 @@ __global__ __launch_bounds__(NTB) void k_mcf_total(G g, Mcf q, unsigned long lon
 
 struct McfLayout {
     Layout L;
+    int32_t *d, *flags;  // price-update labels [n]; changed, max label
     int64_t *p;
     unsigned long long *w;
     int32_t *ft, *fh, *fc;
@@ -783,6 +843,8 @@ static Carver mcf_carve(Carver cv, int n, int m, McfLayout *M) {
     cv = carve(cv, n, m, &M->L);
     const int64_t fm = int64_t(m) + 4 * int64_t(n);
     M->p = cv.take<int64_t>(size_t(n));
+    M->d = cv.take<int32_t>(size_t(n));
+    M->flags = cv.take<int32_t>(2);
     M->w = cv.take<unsigned long long>(8);
     M->ft = cv.take<int32_t>(size_t(fm));
     M->fh = cv.take<int32_t>(size_t(fm));
@@ -938,13 +1000,44 @@ extern "C" lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail
     unsigned long long cnt[4] = {0, 0, 0, 0};
     McfPasses passes;
     LPR_TRY(passes.capture(g, q, gw, gn, per_check));
+    // A refine runs at most PU_MAX updates, each lowering a price by at most
+    // eps x lcap; lcap (any positive cap keeps the labels valid) is 4n + 4
+    // unless eps is so large that the drift could pass 2^50.
+    constexpr int PU_MAX = 64, PU_EVERY = 2;  // updates per refine, checks between
+    int32_t lcap = 4 * n + 4;
+    auto price_update = [&]() -> lpr_status {
+        hipLaunchKernelGGL(k_mcf_pu_init, dim3(gn), dim3(NTB), 0, st, g, M.d, lcap);
+        int32_t fl[2] = {0, 0};
+        bool fixpoint = false;
+        // Bellman-Ford reaches its fixpoint within n rounds
+        for (int64_t r = 0; r <= int64_t(n) + 8 && !fixpoint; r += 8) {
+            LPR_TRY(fill_i32(M.flags, 0, 2, st));
+            for (int k = 0; k < 8; ++k)
+                hipLaunchKernelGGL(k_mcf_pu_relax, dim3(gw), dim3(NTB), 0, st, g, q, M.d,
+                                   lcap, M.flags);
+            LPR_TRY_HIP(hipGetLastError());
+            LPR_TRY_HIP(hipMemcpyAsync(fl, M.flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+            LPR_TRY_HIP(hipStreamSynchronize(st));
+            fixpoint = fl[0] == 0;
+        }
+        if (!fixpoint) return LPR_OK;  // labels not final: leave the prices
+        hipLaunchKernelGGL(k_mcf_pu_max, dim3(gn), dim3(NTB), 0, st, g, M.d, lcap,
+                           M.flags + 1);
+        hipLaunchKernelGGL(k_mcf_pu_apply, dim3(gn), dim3(NTB), 0, st, g, q, M.d, lcap,
+                           M.flags + 1);
+        LPR_TRY_HIP(hipGetLastError());
+        return LPR_OK;
+    };
     for (;;) {
         eps = std::max<int64_t>(1, eps / alpha);
+        lcap = int32_t(std::max<int64_t>(
+            1, std::min<int64_t>(4 * int64_t(n) + 4, (int64_t(1) << 50) / (eps * PU_MAX))));
         LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.w) + 5, eps, 1, st));
         hipLaunchKernelGGL(k_mcf_saturate, dim3(gp), dim3(NTB), 0, st, g, q);
         LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(M.L.cnt) + 2, 0, 1, st));
         hipLaunchKernelGGL(k_mcf_excess, dim3(gn), dim3(NTB), 0, st, g, q);
         LPR_TRY_HIP(hipGetLastError());
+        int pu_done = 0, checks = 0;
         for (;;) {
             LPR_TRY_HIP(hipMemcpyAsync(cnt, M.L.cnt, sizeof(cnt), hipMemcpyDeviceToHost, st));
             LPR_TRY_HIP(hipStreamSynchronize(st));
@@ -953,6 +1046,11 @@ extern "C" lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail
                 set_error("min-cost flow: pass budget (%lld) exhausted", (long long)max_iters);
                 return LPR_EBUDGET;
             }
+            if (pu_done < PU_MAX && checks % PU_EVERY == 0) {
+                LPR_TRY(price_update());
+                ++pu_done;
+            }
+            ++checks;
             LPR_TRY_HIP(hipGraphLaunch(passes.ex, st));
             iters += per_check;
         }
