@@ -545,9 +545,11 @@ size_t lpr_mincost_flow_workspace(int32_t n, int32_t m);
  * push pass (every node with excess pushes along its admissible arcs, with
  * atomic updates of residuals and excesses, prices fixed) and a relabel
  * pass (every node with excess and no admissible arc relabels, reading its
- * neighbours' prices, which only fall) until no node has excess.  A
- * maximum flow from the supplies to the demands on the arbitrary-network
- * solver first checks that a feasible flow exists.
+ * neighbours' prices, which only fall) until no node has excess; a global
+ * price update (Algorithm 5.3: distances in units of eps over residual arcs
+ * to the nodes with a deficit) runs at the start of a refine and between
+ * batches of passes.  A maximum flow from the supplies to the demands on
+ * the arbitrary-network solver first checks that a feasible flow exists.
  * Outputs: *total_cost (host) = sum over pairs of net flow x cost[a], in
  * int64 (callers keep it in range); residual (device int32 [m] or NULL):
  * final residual capacities, net flow along a = cap[a] - residual[a];

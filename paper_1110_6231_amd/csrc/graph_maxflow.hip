@@ -1003,7 +1003,7 @@ extern "C" lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail
     // A refine runs at most PU_MAX updates, each lowering a price by at most
     // eps x lcap; lcap (any positive cap keeps the labels valid) is 4n + 4
     // unless eps is so large that the drift could pass 2^50.
-    constexpr int PU_MAX = 64, PU_EVERY = 2;  // updates per refine, checks between
+    constexpr int PU_MAX = 256, PU_EVERY = 1;  // updates per refine, checks between
     int32_t lcap = 4 * n + 4;
     auto price_update = [&]() -> lpr_status {
         hipLaunchKernelGGL(k_mcf_pu_init, dim3(gn), dim3(NTB), 0, st, g, M.d, lcap);
