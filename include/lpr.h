@@ -13,6 +13,12 @@
  *      to min-cost flow, the Min-Cost loop of Algorithm 5.0, the Refine of
  *      Algorithm 5.2 and the lock-free push/relabel of Algorithm 5.4).
  *
+ * Built on the same machinery: form 1 on any directed network given as an
+ * arc list (lpr_graph_maxflow), assignment on a sparse bipartite graph
+ * (lpr_assign_sparse_solve) and min-cost flow with node supplies on any
+ * capacitated network (lpr_mincost_flow, Algorithm 5.0 with the generic
+ * Refine).
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - Pointers documented as "device" must be device memory of the current HIP
@@ -22,7 +28,10 @@
  *  - `workspace` is a caller-owned device buffer of at least the size the
  *    matching *_workspace() function returns (any alignment is accepted; the
  *    library aligns internally).  The solve entry points allocate no device
- *    memory of their own.
+ *    memory of their own; the grid solvers keep instantiated HIP graphs of
+ *    their round loops in a process-wide cache, and lpr_mincost_flow
+ *    creates a stream and a HIP graph for its passes, released before it
+ *    returns.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Work is enqueued on it and every solve call RETURNS AFTER COMPLETION
  *    (it synchronises the stream), so the status covers convergence.
