@@ -1010,9 +1010,10 @@ extern "C" lpr_status lpr_mincost_flow(int32_t n, int32_t m, const int32_t *tail
         int32_t fl[2] = {0, 0};
         bool fixpoint = false;
         // Bellman-Ford reaches its fixpoint within n rounds
-        for (int64_t r = 0; r <= int64_t(n) + 8 && !fixpoint; r += 8) {
+        constexpr int ROUNDS = 16;  // relaxation rounds between host checks
+        for (int64_t r = 0; r <= int64_t(n) + ROUNDS && !fixpoint; r += ROUNDS) {
             LPR_TRY(fill_i32(M.flags, 0, 2, st));
-            for (int k = 0; k < 8; ++k)
+            for (int k = 0; k < ROUNDS; ++k)
                 hipLaunchKernelGGL(k_mcf_pu_relax, dim3(gw), dim3(NTB), 0, st, g, q, M.d,
                                    lcap, M.flags);
             LPR_TRY_HIP(hipGetLastError());
