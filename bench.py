@@ -366,15 +366,18 @@ def sparse_assign_leg(args, torch, lpr, synth):
 
 def mincost_leg(args, torch, lpr, synth):
     """Minimum-cost flow with supplies (Algorithm 5.0 on a capacitated
-    network): a 200 x 300 transportation problem and a random network of
-    2000 nodes and 8000 edges with planted supplies; three solves (median),
-    the successive-shortest-path oracle once on one host core."""
+    network): a 200 x 300 transportation problem and random networks of
+    2000 and 100000 nodes with planted supplies; three solves (median), the
+    successive-shortest-path oracle once on one host core for the two
+    smaller ones."""
     out = {}
     cases = {
         "transportation 200 x 300, supplies U{1..1000}, costs U{0..1000}":
             synth.mcf_transport(200, 300, seed=0, max_supply=1000),
         "random network 2000 nodes, 8000 edges, costs U{-100..100}":
             synth.mcf_random(2000, 8000, seed=0),
+        "random network 100000 nodes, 400000 edges, costs U{-100..100}":
+            synth.mcf_random(100000, 400000, seed=0),
     }
     for name, g in cases.items():
         n = g[0]
@@ -395,7 +398,7 @@ def mincost_leg(args, torch, lpr, synth):
                      "ms_per_solve": round(dt * 1e3, 3), "refines": st["refines"],
                      "passes": st["iterations"], "pushes": st["pushes"],
                      "relabels": st["relabels"]}
-        if not args.no_cpu:
+        if not args.no_cpu and n <= 10000:  # the oracle takes minutes beyond
             import oracle
             t0 = time.perf_counter()
             want = oracle.mincost_flow(*g)[0]

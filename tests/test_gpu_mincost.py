@@ -128,3 +128,26 @@ def test_infeasible_and_errors():
     with pytest.raises(lpr.LprError) as e:
         lpr.lpr_mincost_flow(n, tail, wrong, cap, cost, supply)
     assert e.value.status == lpr.LPR_EINVAL
+
+
+def test_large_network_by_certificate():
+    """20 000 nodes, 80 000 edges: too large for the oracle in a test, so the
+    checks are the ones that need none: the flow conserves every supply
+    within the capacities, and the prices certify it optimal (every
+    residual arc has scaled reduced cost >= -1, and a residual cycle has at
+    most n arcs, so none has negative cost)."""
+    n, tail, head, cap, cost, supply = synth.mcf_random(20000, 80000, seed=3)
+    print(f"[mcf] n={n} m={len(tail)} certificate only", flush=True)
+    tot, res, prices, st = lpr.lpr_mincost_flow(n, tail, head, cap, cost, supply)
+    res = res.cpu().numpy().astype(np.int64)
+    p = prices.cpu().numpy()
+    f = cap.astype(np.int64) - res
+    assert np.all(res >= 0) and np.all(f[0::2] == -f[1::2])
+    out = np.zeros(n, np.int64)
+    np.add.at(out, tail[0::2], f[0::2])
+    np.add.at(out, head[0::2], -f[0::2])
+    assert np.array_equal(out, supply.astype(np.int64))
+    assert int((f[0::2] * cost[0::2].astype(np.int64)).sum()) == tot
+    red = cost.astype(np.int64) * (n + 1) + p[tail] - p[head]
+    assert np.all(red[res > 0] >= -1)
+    print("[mcf] large network stats", st, flush=True)
