@@ -1,6 +1,7 @@
 /*
  * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.  Not part of the GPU library and
- * shares no code with it.
+ * shares no code with it: only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this code.
  *
  *   oracle_mincost_flow -- minimum-cost flow with node supplies: the problem
  *       the cost-scaling method of Section 5 (Algorithm 5.0) solves, where
