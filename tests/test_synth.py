@@ -50,3 +50,42 @@ def test_assign_generators():
     assert not np.array_equal(p, pt)
     ns = [x.shape[0] for x in synth.assign_batch(seed=0, count=6)]
     assert all(64 <= n <= 512 for n in ns)
+
+
+def _check_pairs(n, tail, head, cap):
+    tail, head, cap = np.asarray(tail), np.asarray(head), np.asarray(cap)
+    assert len(tail) % 2 == 0
+    assert np.array_equal(tail[0::2], head[1::2]) and np.array_equal(head[0::2], tail[1::2])
+    assert tail.min(initial=0) >= 0 and max(tail.max(initial=0), head.max(initial=0)) < n
+    assert np.all(cap >= 0)
+
+
+def test_volume_and_8_connected_generators():
+    n, tail, head, cap, s, t = synth.grid3d_arcs(3, 4, 5, seed=1)
+    _check_pairs(n, tail, head, cap)
+    inner = 3 * 4 * 5
+    # terminal pairs + (D(H)(W-1) + D(H-1)W + (D-1)HW) neighbour pairs
+    assert len(tail) == 2 * (2 * inner + 3 * 4 * 4 + 3 * 3 * 5 + 2 * 4 * 5)
+    assert np.array_equal(cap[4 * inner::2], cap[4 * inner + 1::2])  # symmetric
+    n8, t8, h8, c8, _, _ = synth.grid8_arcs(4, 6, seed=1)
+    _check_pairs(n8, t8, h8, c8)
+    assert len(t8) == 2 * (2 * 24 + 4 * 5 + 3 * 6 + 2 * 3 * 5)
+    assert np.array_equal(synth.grid8_arcs(4, 6, seed=1)[3], c8)    # seeded
+
+
+def test_mincost_generators_are_feasible_by_construction():
+    for g in (synth.mcf_random(40, 150, seed=2), synth.mcf_transport(5, 7, seed=3)):
+        n, tail, head, cap, cost, supply = g
+        _check_pairs(n, tail, head, cap)
+        assert np.array_equal(cost[0::2], -cost[1::2])
+        assert int(np.asarray(supply, np.int64).sum()) == 0
+    n, tail, head, cap, cost, supply = synth.mcf_transport(5, 7, seed=3)
+    assert np.all(supply[:5] > 0) and np.all(supply[5:] <= 0)
+
+
+def test_sparse_assignment_generator():
+    row_ptr, col, cost = synth.assign_sparse(50, 3, seed=4, parallel=0.5, lo=-9, hi=9)
+    assert row_ptr[0] == 0 and row_ptr[-1] == len(col) and np.all(np.diff(row_ptr) >= 4)
+    assert col.min() >= 0 and col.max() < 50 and cost.min() >= -9 and cost.max() <= 9
+    rp2, c2, _ = synth.assign_sparse(50, 0, seed=4)
+    assert np.array_equal(np.sort(c2), np.arange(50))  # the planted permutation
