@@ -1,26 +1,32 @@
 """Benchmark: lock-free push-relabel on one MI355X.
 
-One step = one complete solve of the 1024 x 1024 graph-cut grid (32 Gaussian
-blobs plus N(0, 0.1^2) noise, int32 capacities): init, push sweeps, global
-relabels with gap, termination, flow value and the minimal cut.  Inputs are
-resident in HBM before the timed region; outputs and workspace are
-preallocated.  The JSON line also carries the dense assignment leg (n = 1024,
-weights U{0..1000}, max-weight) and the batched assignment leg (256
-optical-flow-like instances), max-flow on two arbitrary networks (a layered
-network and a 512 x 512 cut as an arc list), the roofline of the dominant
-kernel (the push
-sweep or the global-relabel relaxation, whichever takes more time), the push
-update rate against a measured atomic-add ceiling, and the CPU oracles timed
-on this host (FIFO push-relabel for the grid, Hungarian for the assignment
-legs).
+One step = one batched solve of the batched graph-cut workload: 64 blob
+graph cuts with H, W ~ U{128..512} plus one 2048 x 2048 blob graph cut with
+pair weights x4 (10.5 M pixels), all in one lpr_grid_maxflow_batched call --
+init, push sweeps, global relabels with gap, termination, the flow value and
+the minimal cut of every grid.  Inputs are resident in HBM before the timed
+region; every flow value and cut is checked against the oracle's stored
+values (tests/golden/grid_golden.json).
+
+The JSON line also carries: the roofline of the dominant grid kernel (push
+sweep or global-relabel relaxation, whichever takes more time) with HIP
+events over the timed steps, the device-atomic rate against a measured
+atomic-add ceiling, the FIFO push-relabel oracle on the same workload pooled
+over this host's cores (cpu_baseline); the 2048 x 2048 grid and the
+1024 x 1024 graph cut solved alone; the dense n = 1024 assignment and the
+batched assignment workload (plain and learned start), each with its
+roofline and checked against the Hungarian oracle; max-flow on arbitrary
+networks, sparse assignment and min-cost flow.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       python bench.py --assign-only   (the n = 1024 assignment alone, for
-                                        counter profiles of its kernel)
+       python bench.py --grid-only   (the batched grid workload alone, for
+                                      kernel traces and counters)
+       python bench.py --assign-only (the n = 1024 assignment alone)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,124 +47,66 @@ HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_PER_PIXEL = 28
 SWEEP_BYTES_PER_RELABEL = 4
 SWEEP_BYTES_PER_PUSH = 16
-# Bytes one pass of the global-relabel relaxation must move per pixel of a
-# relaxed tile: the height and the four neighbour residuals read, the height
-# written.
+# Bytes one pass of the global-relabel relaxation moves per pixel of a
+# relaxed tile: the label and the four neighbour residuals read, the label
+# written.  (A whole global relabel also reads the sink residual once, in the
+# seed kernel, which makes the 28 B per pixel of one work-efficient BFS.)
 RELAX_BYTES_PER_PIXEL = 24
+# Bytes per cost entry a row scan of the refine reads (the int32 cost row).
+ASSIGN_BYTES_PER_ENTRY = 4
+GRID_SRC = os.path.join(ROOT, "paper_1110_6231_amd", "csrc", "grid_maxflow.hip")
+
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB
+# per dispatch, averaged over the dispatches of the named workload), scaled
+# by what the same counters read for a plain copy of known size (FETCH_SIZE
+# x 2.0, WRITE_SIZE x 1.0).  Each entry holds the sha256 of the kernel's
+# source file at measurement time; a changed source reports null.
+MEASURED_TRAFFIC = {}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true",
-                    help="skip the CPU oracle baseline")
+                    help="skip the CPU oracle legs (the golden check stays)")
     ap.add_argument("--no-assign", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-batched-grid", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
-                    help="skip the arbitrary-network max-flow leg")
+                    help="skip the arbitrary-network, sparse assignment and "
+                         "min-cost flow legs")
+    ap.add_argument("--grid-only", action="store_true",
+                    help="only the batched grid workload (for kernel traces "
+                         "and counter runs)")
     ap.add_argument("--assign-only", action="store_true",
-                    help="only time the n = 1024 assignment (for counter "
-                         "profiles of the solve kernel) and print its JSON")
+                    help="only the n = 1024 assignment (for counter profiles "
+                         "of its kernel)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain copies of a known size (counter "
                          "calibration) and exit")
     return ap.parse_args()
 
 
-def grid_leg(args, torch, lpr, synth):
-    inst = synth.grid_blobs(1024, 1024, seed=0)
-    dev = torch.device("cuda:0")
-    caps = [torch.as_tensor(a, device=dev) for a in inst.arrays()]
-    HW = inst.H * inst.W
-    ws = torch.empty(lpr.lpr_grid_maxflow_workspace(inst.H, inst.W),
-                     dtype=torch.uint8, device=dev)
-    opts = lpr.make_grid_opts()
-    for _ in range(args.warmup):
-        v, _, _ = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=opts,
-                                       workspace=ws)
-    print(f"[bench] grid warmup done, flow={v}", file=sys.stderr, flush=True)
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        v, side, st = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=opts,
-                                           workspace=ws, stream=stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = wall * 1e3 / args.steps
-    # The same K solves again with HIP events around every group of push-sweep
-    # and relaxation launches (on the library's stream) for the durations of
-    # the two kernels that take the time.
-    timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
-    acc = dict(sweep_ms=0.0, bfs_ms=0.0, tiles_swept=0, tiles_relaxed=0,
-               sweeps=0, bfs_passes=0, pushes=0, relabels=0)
-    for _ in range(args.steps):
-        v, side, st = lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=timed,
-                                           workspace=ws, stream=stream)
-        for k in acc:
-            acc[k] += st[k]
-    torch.cuda.synchronize()
-    tile_px = st["tile_rows"] * 64
-    legs = {
-        f"k_sweep<{st['tile_rows']}>": kernel_roofline(
-            acc["sweep_ms"], acc["sweeps"], sweep_bytes(acc, tile_px)),
-        "k_relax4<false>": kernel_roofline(
-            acc["bfs_ms"], acc["bfs_passes"],
-            acc["tiles_relaxed"] * st["relax_tile_rows"] * 64 * RELAX_BYTES_PER_PIXEL),
-    }
-    dominant = max(legs, key=lambda k: legs[k]["total_ms"])
-    for name, leg in legs.items():
-        leg["traffic"] = traffic_for(name, st["tile_rows"])  # HBM bytes per launch
-        leg["traffic_GBps"] = (None if leg["traffic"] is None else
-                               round(leg["traffic"] / (leg["avg_launch_us"] * 1e-6) / 1e9, 1))
-    roof = dict(legs[dominant])
-    roof["kernel"] = dominant
-    others = {name: leg for name, leg in legs.items() if name != dominant}
-    return dict(inst=inst, flow=v, ms=ms, HW=HW, stats=st, roofline=roof,
-                other_kernels=others)
-
-
-# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
-# dispatch, averaged over the dispatches of the 1024 x 1024 solve), scaled by
-# what the same counters read for a plain copy of known size (FETCH_SIZE
-# x 2.0, WRITE_SIZE x 1.0).  Each entry holds the sha256 of the kernel's
-# source file at measurement time; a changed source reports null.
-MEASURED_TRAFFIC = {
-    "k_relax4<false>": {"source_sha256": "101a8f1994ebf72dd6d0b262b2808c23b1c1313a9047be203267bcda5252409d",
-                  "bytes_per_launch": 5231326},  # FETCH 2476.6 KiB, WRITE 156.0 KiB
-    "k_sweep<8>": {"source_sha256": "101a8f1994ebf72dd6d0b262b2808c23b1c1313a9047be203267bcda5252409d",
-                  "bytes_per_launch": 12638952},  # FETCH 3612.6 KiB, WRITE 5118.2 KiB
-}
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def source_sha(path):
-    import hashlib
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def traffic_for(kernel, tile_rows):
-    rec = MEASURED_TRAFFIC.get(kernel)
-    if not rec:
-        return None
-    src = os.path.join(ROOT, "paper_1110_6231_amd", "csrc", "grid_maxflow.hip")
-    if source_sha(src) != rec["source_sha256"]:
+def traffic_for(kernel, workload):
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
+    if not rec or source_sha(GRID_SRC) != rec["source_sha256"]:
         return None
     return rec["bytes_per_launch"]
 
 
-def sweep_bytes(st, tile_px):
-    return (st["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL
-            + st["relabels"] * SWEEP_BYTES_PER_RELABEL
-            + st["pushes"] * SWEEP_BYTES_PER_PUSH)
-
-
 def kernel_roofline(total_ms, launches, algo_bytes):
-    """Algorithmic bytes per launch / average launch duration (HIP events)."""
-    launches = max(launches, 1)
+    """Algorithmic bytes per launch / average launch duration (HIP events on
+    the library's stream around each group of launches of the kernel)."""
+    launches = max(int(launches), 1)
     avg_ms = total_ms / launches
     achieved = (algo_bytes / launches) / max(avg_ms * 1e-3, 1e-12) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1),
@@ -169,43 +117,119 @@ def kernel_roofline(total_ms, launches, algo_bytes):
             "launches": launches, "total_ms": round(total_ms, 3)}
 
 
+def grid_kernels(acc, workload):
+    """Roofline entries of the push sweep and the BFS relaxation from
+    accumulated solve statistics; returns (dominant name, {name: entry})."""
+    tile_px = acc["tile_rows"] * 64
+    sweep_bytes = (acc["tiles_swept"] * tile_px * SWEEP_BYTES_PER_PIXEL
+                   + acc["relabels"] * SWEEP_BYTES_PER_RELABEL
+                   + acc["pushes"] * SWEEP_BYTES_PER_PUSH)
+    relax_bytes = (acc["tiles_relaxed"] * acc["relax_tile_rows"] * 64
+                   * RELAX_BYTES_PER_PIXEL)
+    legs = {f"k_sweep<{acc['tile_rows']}>": kernel_roofline(acc["sweep_ms"], acc["sweeps"],
+                                                            sweep_bytes),
+            "k_relax4<false>": kernel_roofline(acc["bfs_ms"], acc["bfs_passes"],
+                                               relax_bytes)}
+    for name, leg in legs.items():
+        leg["traffic"] = traffic_for(name, workload)
+    dominant = max(legs, key=lambda k: legs[k]["total_ms"])
+    return dominant, legs
+
+
+SUM_KEYS = ("sweep_ms", "bfs_ms", "tiles_swept", "tiles_relaxed", "sweeps",
+            "bfs_passes", "pushes", "relabels", "device_atomics", "rounds")
+
+
+def time_grid(solve, steps, torch, lpr):
+    """Wall time per solve over `steps` solves, then the same solves with
+    HIP events around every group of sweep and relaxation launches."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = solve(None)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    acc = {k: 0 for k in SUM_KEYS}
+    timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
+    for _ in range(steps):
+        _, _, st = solve(timed)
+        for k in SUM_KEYS:
+            acc[k] += st[k]
+    acc["tile_rows"] = st["tile_rows"]
+    acc["relax_tile_rows"] = st["relax_tile_rows"]
+    return ms, out, acc, st
+
+
+def pack_grids(insts, torch):
+    return [torch.as_tensor(np.concatenate([getattr(i, f) for i in insts]),
+                            device="cuda")
+            for f in ("cap_src", "cap_snk", "cap_right", "cap_left",
+                      "cap_down", "cap_up")]
+
+
+def check_golden(insts, flows, side, golden):
+    flows = flows.cpu().numpy()
+    side = side.cpu().numpy()
+    off = 0
+    for k, (inst, rec) in enumerate(zip(insts, golden)):
+        assert rec["name"] == inst.name, (k, rec["name"], inst.name)
+        assert flows[k] == rec["flow"], ("flow value differs from the oracle", k,
+                                         int(flows[k]), rec["flow"])
+        s = side[off:off + inst.n_pixels]
+        assert hashlib.sha256(s.tobytes()).hexdigest() == rec["source_side_sha256"], \
+            ("minimal cut differs from the oracle", k)
+        off += inst.n_pixels
+
+
 def grid_batched_leg(args, torch, lpr, synth):
-    """The batched graph-cut workload (64 grids, H, W in [128, 512], plus one
-    2048 x 2048 grid with pair weights x4) solved by one batched call."""
+    """The headline: 64 blob graph cuts (H, W ~ U{128..512}) plus the
+    2048 x 2048 grid with pair weights x4, one batched call per step."""
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden",
+                                       "grid_golden.json")))["batch_seed0"]
     insts = synth.grid_batch(seed=0)
     Hs = [i.H for i in insts]
     Ws = [i.W for i in insts]
-    dev = torch.device("cuda:0")
-    caps = [torch.as_tensor(np.concatenate([getattr(i, f) for i in insts]),
-                            device=dev)
-            for f in ("cap_src", "cap_snk", "cap_right", "cap_left",
-                      "cap_down", "cap_up")]
+    caps = pack_grids(insts, torch)
     ws = torch.empty(lpr.lpr_grid_maxflow_batched_workspace(Hs, Ws),
-                     dtype=torch.uint8, device=dev)
+                     dtype=torch.uint8, device="cuda")
     px = sum(i.n_pixels for i in insts)
-    lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, workspace=ws)
-    reps = 3
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        flows, _, st = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, workspace=ws)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    timed = lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS)
-    _, _, sti = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, opts=timed, workspace=ws)
-    tile_px = sti["tile_rows"] * 64
-    sweep = kernel_roofline(sti["sweep_ms"], sti["sweeps"], sweep_bytes(sti, tile_px))
-    relax = kernel_roofline(sti["bfs_ms"], sti["bfs_passes"],
-                            sti["tiles_relaxed"] * sti["relax_tile_rows"] * 64
-                            * RELAX_BYTES_PER_PIXEL)
-    return {"workload": "64 blob graph cuts (H, W ~ U{128..512}) + one 2048x2048 "
-                        "graph cut with pair weights x4, one batched call",
-            "pixels": px, "ms_per_batch": round(dt * 1e3, 3),
-            "mvertex_per_s": round(px / dt / 1e6, 2),
-            "flow_2048": int(flows[-1].item()),
+
+    def solve(opts):
+        return lpr.lpr_grid_maxflow_batched(Hs, Ws, caps, opts=opts, workspace=ws)
+
+    for _ in range(max(args.warmup, 1)):
+        flows, side, _ = solve(None)
+    check_golden(insts, flows, side, gold)
+    log(f"batched grids: warm-up done, {len(insts)} flow values and cuts equal "
+        "the oracle's")
+    ms, (flows, side, _), acc, st = time_grid(solve, args.steps, torch, lpr)
+    check_golden(insts, flows, side, gold)
+    dominant, legs = grid_kernels(acc, "batched")
+    return dict(insts=insts, px=px, ms=ms, acc=acc, st=st, dominant=dominant,
+                legs=legs, flows=flows.cpu().numpy().tolist())
+
+
+def grid_single_leg(args, torch, lpr, inst, want_flow=None, reps=5):
+    """One grid solved alone (lpr_grid_maxflow), median-free mean of `reps`
+    solves, and the kernels' rooflines."""
+    caps = [torch.as_tensor(a, device="cuda") for a in inst.arrays()]
+    ws = torch.empty(lpr.lpr_grid_maxflow_workspace(inst.H, inst.W),
+                     dtype=torch.uint8, device="cuda")
+
+    def solve(opts):
+        return lpr.lpr_grid_maxflow(inst.H, inst.W, *caps, opts=opts, workspace=ws)
+
+    v, _, _ = solve(None)
+    if want_flow is not None:
+        assert v == want_flow, ("flow value differs from the oracle", v, want_flow)
+    ms, (v2, _, _), acc, st = time_grid(solve, reps, torch, lpr)
+    assert v2 == v
+    dominant, legs = grid_kernels(acc, f"{inst.H}x{inst.W}")
+    return {"pixels": inst.n_pixels, "flow_value": v, "ms_per_solve": round(ms, 3),
+            "mvertex_per_s": round(inst.n_pixels / ms / 1e3, 2),
             "global_relabels": st["rounds"], "sweeps": st["sweeps"],
-            f"k_sweep<{sti['tile_rows']}>": sweep,
-            "k_relax4<false>": relax}
+            "bfs_passes": st["bfs_passes"], "tile": f"64x{st['tile_rows']}",
+            "dominant_kernel": dominant, "kernels": legs}
 
 
 def copy_probe(torch, mib=256, reps=5):
@@ -221,10 +245,18 @@ def copy_probe(torch, mib=256, reps=5):
                       "launches": reps}), flush=True)
 
 
+def assign_roofline(st):
+    """The solve kernel's algorithmic bytes: 4 bytes per cost entry its row
+    scans read (the refine inits included), over the kernel's duration."""
+    return kernel_roofline(st["kernel_ms"], 1,
+                           st["scan_entries"] * ASSIGN_BYTES_PER_ENTRY)
+
+
 def assign_single(torch, lpr, synth, reps=3):
     """The dense n = 1024 max-weight assignment, mean of `reps` solves."""
     dev = torch.device("cuda:0")
-    cost = torch.as_tensor(synth.assign_uniform(1024, seed=0), device=dev)
+    cost_np = synth.assign_uniform(1024, seed=0)
+    cost = torch.as_tensor(cost_np, device=dev)
     ws = torch.empty(lpr.lpr_assign_workspace(1024), dtype=torch.uint8, device=dev)
     lpr.lpr_assign_solve(cost, maximize=True, workspace=ws)
     torch.cuda.synchronize()
@@ -233,17 +265,22 @@ def assign_single(torch, lpr, synth, reps=3):
         _, tot, _, st = lpr.lpr_assign_solve(cost, maximize=True, workspace=ws)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    _, tot2, _, sti = lpr.lpr_assign_solve(
+        cost, maximize=True, workspace=ws,
+        opts=lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_TIME_KERNELS))
+    assert tot2 == tot
     return {"workload": "dense assignment n=1024, weights U{0..1000}, "
                         "max-weight, alpha=8, plain start",
             "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(dt * 1e3, 3),
             "total": tot, "refines": st["refines"], "phases": st["phases"],
             "pushes": st["pushes"], "relabels": st["relabels"],
-            "price_updates": st["price_updates"]}
+            "price_updates": st["price_updates"],
+            "roofline": assign_roofline(sti)}, cost_np
 
 
 def assign_leg(args, torch, lpr, synth):
     dev = torch.device("cuda:0")
-    out = assign_single(torch, lpr, synth)
+    out, cost1024 = assign_single(torch, lpr, synth)
     from paper_1110_6231_amd.train_pricenet import learned_solve, load_weights
     mats = synth.assign_batch(seed=0)
     packed = lpr.PackedAssign.from_matrices(mats, device=dev)
@@ -253,9 +290,10 @@ def assign_leg(args, torch, lpr, synth):
                       device=dev)
     theta, kappa, _ = load_weights()
     params = torch.as_tensor(theta, device=dev)
+    timed = lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_TIME_KERNELS)
 
-    def plain():
-        return lpr.lpr_assign_solve_batched(packed, workspace=wsb)
+    def plain(opts=None):
+        return lpr.lpr_assign_solve_batched(packed, opts=opts, workspace=wsb)
 
     def learned():
         return learned_solve(packed, params, kappa, lpr, ws_net=wsn, ws_solve=wsb)
@@ -274,20 +312,64 @@ def assign_leg(args, torch, lpr, synth):
     tp, (_, tot_p, _, stp) = median_time(plain)
     tl, (_, tot_l, _, stl) = median_time(learned)
     assert torch.equal(tot_p, tot_l), "learned start changed an optimum"
+    sti = plain(timed)[3]
     out["batched"] = {"workload": "256 optical-flow-like instances, "
                                   "n ~ U{64..512}, min-cost",
                       "plain": {"solves_per_s": round(len(mats) / tp, 1),
                                 "ms_per_batch": round(tp * 1e3, 3),
-                                "ops": stp["pushes"] + stp["relabels"]},
+                                "ops": stp["pushes"] + stp["relabels"],
+                                "roofline": assign_roofline(sti)},
                       "learned": {"solves_per_s": round(len(mats) / tl, 1),
                                   "ms_per_batch": round(tl * 1e3, 3),
                                   "ops": stl["pushes"] + stl["relabels"],
+                                  "warm_restarts": stl["warm_restarts"],
                                   "kappa": kappa},
                       "time_to_optimal_plain_over_learned": round(tp / tl, 3),
                       "ops_plain_over_learned": round(
                           (stp["pushes"] + stp["relabels"]) /
                           (stl["pushes"] + stl["relabels"]), 3)}
+    if not args.no_cpu:
+        cpu, want1024, want_batch = cpu_assign_leg(cost1024, mats)
+        assert out["total"] == want1024, ("n=1024 total differs from the oracle",
+                                          out["total"], want1024)
+        got = tot_p.cpu().numpy()
+        assert np.array_equal(got, want_batch), "batched totals differ from the oracle"
+        out["cpu_oracle"] = cpu
+        out["checked_against_oracle"] = True
     return out
+
+
+def cpu_assign_leg(cost1024, mats):
+    """The Hungarian oracle on this host: the n = 1024 instance on one core,
+    and the batched workload over a thread pool (the oracle releases the GIL).
+    Returns the timings and the optimal totals."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.lib()
+    t0 = time.perf_counter()
+    want1024 = oracle.assign(cost1024, maximize=True)[1]
+    t1024 = time.perf_counter() - t0
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def one(m):
+        ts = time.perf_counter()
+        tot = oracle.assign(m)[1]
+        return tot, time.perf_counter() - ts
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        res = list(ex.map(one, mats))
+    tb = time.perf_counter() - t0
+    per = [r[1] for r in res]
+    return ({"kind": "oracle", "n1024_solves_per_s": round(1.0 / t1024, 3),
+             "n1024_cores": 1,
+             "batched_solves_per_s": round(len(mats) / tb, 1),
+             "batched_cores": cores,
+             "batched_instance_ms_median": round(float(np.median(per)) * 1e3, 3),
+             "sample": "Hungarian oracle: one solve of the n=1024 instance on "
+                       "one core; the 256 batched instances over a pool of "
+                       f"{cores} threads"},
+            want1024, np.array([r[0] for r in res]))
 
 
 def graph_leg(args, torch, lpr, synth):
@@ -306,7 +388,7 @@ def graph_leg(args, torch, lpr, synth):
         ws = torch.empty(lpr.lpr_graph_maxflow_workspace(n, len(tail)), dtype=torch.uint8,
                          device="cuda")
         lpr.lpr_graph_maxflow(n, *arrs, s, t, workspace=ws)
-        print(f"[bench] graph warmup done: {name}", file=sys.stderr, flush=True)
+        log(f"graph warmup done: {name}")
         ts = []
         for _ in range(3):
             torch.cuda.synchronize()
@@ -340,7 +422,7 @@ def sparse_assign_leg(args, torch, lpr, synth):
     ws = torch.empty(lpr.lpr_assign_sparse_workspace(n, cl.numel()), dtype=torch.uint8,
                      device="cuda")
     lpr.lpr_assign_sparse_solve(n, rp, cl, cs, maximize=True, workspace=ws)
-    print("[bench] sparse assignment warmup done", file=sys.stderr, flush=True)
+    log("sparse assignment warmup done")
     ts = []
     for _ in range(3):
         torch.cuda.synchronize()
@@ -385,7 +467,7 @@ def mincost_leg(args, torch, lpr, synth):
         ws = torch.empty(lpr.lpr_mincost_flow_workspace(n, arrs[0].numel()),
                          dtype=torch.uint8, device="cuda")
         lpr.lpr_mincost_flow(n, *arrs, workspace=ws)
-        print(f"[bench] min-cost flow warmup done: {name}", file=sys.stderr, flush=True)
+        log(f"min-cost flow warmup done: {name}")
         ts = []
         for _ in range(3):
             torch.cuda.synchronize()
@@ -408,9 +490,12 @@ def mincost_leg(args, torch, lpr, synth):
 
 
 def atomics_leg(torch, lpr, g):
-    """Push updates per second of the 1024 x 1024 solve (four atomic word
-    updates per push in Algorithm 4.5) next to the measured ceiling of
-    non-returning device-scope atomic adds to scattered addresses."""
+    """Device-scope atomic updates per second of the batched grid solve (the
+    tile-edge excess deltas and the three words of every push across a tile
+    edge; pushes inside a tile update registers) next to the measured
+    ceiling of non-returning device-scope atomic adds to scattered
+    addresses, and the push rate as Algorithm 4.5 counts it (four word
+    updates per push)."""
     log2, blocks, per = 23, 16384, 16        # 32 MiB of counters, 64 M adds
     cnt = torch.zeros(1 << log2, dtype=torch.int32, device="cuda")
     lpr.lpr_atomic_probe(cnt, log2, blocks, per)
@@ -418,65 +503,42 @@ def atomics_leg(torch, lpr, g):
     assert int(cnt.sum().item()) == total
     ms = sorted(lpr.lpr_atomic_probe(cnt, log2, blocks, per) for _ in range(5))[2]
     ceiling = total / (ms * 1e-3)
-    pushes = g["stats"]["pushes"]
-    rate = 4 * pushes / (g["ms"] * 1e-3)
-    return {"push_updates_per_s": round(rate / 1e9, 3), "unit": "G/s",
-            "pushes_per_solve": pushes,
+    st = g["st"]
+    solve_s = g["ms"] * 1e-3
+    dev_rate = st["device_atomics"] / solve_s
+    return {"device_atomics_per_s": round(dev_rate / 1e9, 3), "unit": "G/s",
+            "device_atomics_per_solve": st["device_atomics"],
             "atomic_add_ceiling_per_s": round(ceiling / 1e9, 3),
-            "frac": round(rate / ceiling, 4),
+            "frac": round(dev_rate / ceiling, 4),
+            "pushes_per_solve": st["pushes"],
+            "push_word_updates_per_s": round(4 * st["pushes"] / solve_s / 1e9, 3),
             "probe": f"{total} non-returning 32-bit atomic adds over 2^{log2} "
                      f"int32 counters (xorshift addresses), median of 5: "
                      f"{ms:.3f} ms"}
 
 
-def cpu_assign_leg(args, synth):
-    """The Hungarian oracle on this host: the n = 1024 instance on one core,
-    and the batched workload over a thread pool (the oracle releases the GIL)."""
+def cpu_grid_leg(insts):
+    """The FIFO push-relabel oracle (global and gap relabels) on the batched
+    grid workload: every instance one task of a pool of this host's threads
+    (the oracle is a C library called through ctypes, which releases the
+    GIL); the 2048 x 2048 grid alone takes most of the wall time."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
     oracle.lib()
-    c = synth.assign_uniform(1024, seed=0)
-    t0 = time.perf_counter()
-    oracle.assign(c, maximize=True)
-    t1024 = time.perf_counter() - t0
-    mats = synth.assign_batch(seed=0)
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    order = sorted(range(len(insts)), key=lambda k: -insts[k].n_pixels)
     t0 = time.perf_counter()
-    per = []
-
-    def one(m):
-        ts = time.perf_counter()
-        oracle.assign(m)
-        return time.perf_counter() - ts
-
     with ThreadPoolExecutor(cores) as ex:
-        per = list(ex.map(one, mats))
-    tb = time.perf_counter() - t0
-    return {"kind": "oracle", "n1024_solves_per_s": round(1.0 / t1024, 3),
-            "n1024_cores": 1,
-            "batched_solves_per_s": round(len(mats) / tb, 1),
-            "batched_cores": cores,
-            "batched_instance_ms_median": round(float(np.median(per)) * 1e3, 3),
-            "sample": "Hungarian oracle: one solve of the n=1024 instance on "
-                      "one core; the 256 batched instances over a pool of "
-                      f"{cores} threads"}
-
-
-def cpu_leg(args, inst):
-    import oracle
-    oracle.lib()
-    reps, t_used = 0, 0.0
-    t0 = time.perf_counter()
-    while t_used < args.cpu_seconds and reps < 50:
-        v, _ = oracle.grid_maxflow(inst, "fifo")
-        reps += 1
-        t_used = time.perf_counter() - t0
-    mv = inst.H * inst.W * reps / t_used / 1e6
-    return {"value": round(mv, 4), "unit": "Mvertex/s", "cores": 1,
+        res = dict(zip(order, ex.map(lambda k: oracle.grid_maxflow(insts[k], "fifo")[0],
+                                     order)))
+    wall = time.perf_counter() - t0
+    px = sum(i.n_pixels for i in insts)
+    return {"value": round(px / wall / 1e6, 4), "unit": "Mvertex/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{reps} full solves of the same 1024x1024 graph cut by "
-                      f"the FIFO push-relabel oracle (global + gap relabel, "
-                      f"single thread), {t_used:.1f} s"}, v
+            "sample": f"one full solve of the whole batched workload ({len(insts)} grids, "
+                      f"{px} pixels) by the FIFO push-relabel oracle, one instance "
+                      f"per task on a pool of {cores} threads, largest first: "
+                      f"{wall:.1f} s"}, [res[k] for k in range(len(insts))]
 
 
 def main():
@@ -497,12 +559,15 @@ def main():
         copy_probe(torch)
         return
     if args.assign_only:
-        print(json.dumps({"assignment": assign_single(torch, lpr, synth)}), flush=True)
+        print(json.dumps({"assignment": assign_single(torch, lpr, synth)[0]}), flush=True)
         return
-    g = grid_leg(args, torch, lpr, synth)
+    g = grid_batched_leg(args, torch, lpr, synth)
+    acc, st = g["acc"], g["st"]
+    roof = dict(g["legs"][g["dominant"]])
+    roof["kernel"] = g["dominant"]
     out = {
         "metric": METRIC,
-        "value": round(g["HW"] / (g["ms"] * 1e-3) / 1e6, 3),
+        "value": round(g["px"] / (g["ms"] * 1e-3) / 1e6, 3),
         "unit": "Mvertex/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -513,34 +578,57 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "4-connected grid graph cut 1024x1024, int32: "
-                               "32 Gaussian blobs + N(0,0.1) noise; terminals "
-                               "rint(100|I-0.5|), pairs rint(50 exp(-dI^2/"
-                               "(2*0.05^2))); seed 0",
-                   "pixels": g["HW"], "flow_value": g["flow"],
-                   "global_relabels": g["stats"]["rounds"],
-                   "sweeps": g["stats"]["sweeps"],
-                   "tile": f"64x{g['stats']['tile_rows']}",
-                   "local_iters": g["stats"]["local_iters"],
-                   "sweeps_per_relabel": g["stats"]["sweeps_per_relabel"]},
-        "roofline": g["roofline"],
-        "other_kernels": g["other_kernels"],
+        "config": {"workload": "batched 4-connected grid graph cuts, int32, one "
+                               "lpr_grid_maxflow_batched call: 64 grids H, W ~ "
+                               "U{128..512} (32 Gaussian blobs + N(0,0.1) noise; "
+                               "terminals rint(100|I-0.5|), pairs rint(50 exp(-dI^2/"
+                               "(2*0.05^2)))) + one 2048x2048 grid with pair weights "
+                               "x4; seed 0; flow values and minimal cuts checked "
+                               "against the oracle",
+                   "grids": len(g["insts"]), "pixels": g["px"],
+                   "global_relabels": st["rounds"], "sweeps": st["sweeps"],
+                   "bfs_passes": st["bfs_passes"],
+                   "tile": f"64x{st['tile_rows']}",
+                   "local_iters": st["local_iters"],
+                   "sweeps_per_relabel": st["sweeps_per_relabel"]},
+        "roofline": roof,
+        "other_kernels": {k: v for k, v in g["legs"].items() if k != g["dominant"]},
         "atomics": atomics_leg(torch, lpr, g),
     }
-    if not args.no_batched_grid:
-        out["grid_batched"] = grid_batched_leg(args, torch, lpr, synth)
+    if not args.no_cpu:
+        cb, cpu_flows = cpu_grid_leg(g["insts"])
+        assert cpu_flows == [int(f) for f in g["flows"]], \
+            "the oracle's flow values differ from the GPU's"
+        out["cpu_baseline"] = cb
+    big = g["insts"][-1]
+    out["grid_2048"] = dict(workload="the 2048x2048 graph cut with pair weights x4 "
+                                     "alone (lpr_grid_maxflow)",
+                            **grid_single_leg(args, torch, lpr, big,
+                                              want_flow=cpu_flows[-1] if not args.no_cpu
+                                              else None, reps=3))
+    if args.grid_only:
+        print(json.dumps(out), flush=True)
+        return
+    import oracle
+    w2 = synth.grid_blobs(1024, 1024, seed=0)
+    want2 = None
+    if not args.no_cpu:
+        oracle.lib()
+        t0 = time.perf_counter()
+        want2 = oracle.grid_maxflow(w2, "fifo")[0]
+        cpu1024 = time.perf_counter() - t0
+    out["grid_1024"] = dict(workload="4-connected grid graph cut 1024x1024 alone",
+                            **grid_single_leg(args, torch, lpr, w2, want_flow=want2))
+    if not args.no_cpu:
+        out["grid_1024"]["cpu_oracle_mvertex_per_s_1core"] = round(
+            w2.n_pixels / cpu1024 / 1e6, 3)
     if not args.no_graph:
         out["graph"] = graph_leg(args, torch, lpr, synth)
         out["mincost_flow"] = mincost_leg(args, torch, lpr, synth)
     if not args.no_assign:
         out["assignment"] = assign_leg(args, torch, lpr, synth)
-        if not args.no_cpu:
-            out["assignment"]["cpu_oracle"] = cpu_assign_leg(args, synth)
-        out["assignment"]["sparse"] = sparse_assign_leg(args, torch, lpr, synth)
-    if not args.no_cpu:
-        cb, cpu_flow = cpu_leg(args, g["inst"])
-        assert cpu_flow == g["flow"], (cpu_flow, g["flow"])
-        out["cpu_baseline"] = cb
+        if not args.no_graph:
+            out["assignment"]["sparse"] = sparse_assign_leg(args, torch, lpr, synth)
     print(json.dumps(out), flush=True)
 
 

@@ -111,6 +111,10 @@ typedef struct {
     int64_t relabels;        /* relabel operations                          */
     int64_t cut_passes;      /* tile-relaxation launches of the cut closure */
     int64_t tiles_relaxed;   /* tiles processed by the BFS relaxation       */
+    int64_t device_atomics;  /* device-scope atomic updates the push sweeps
+                                made (edge-pixel excess deltas and the three
+                                words of every push across a tile edge);
+                                pushes inside a tile update registers      */
     int32_t tile_rows;       /* push-sweep tile height actually used        */
     int32_t local_iters;     /* local iterations actually used              */
     int32_t sweeps_per_relabel;
@@ -195,7 +199,7 @@ lpr_status lpr_grid_maxflow_batched(int32_t B, const int32_t *H,
 /*
  * Schedule autotuner for the grid solver.  Solves the given batch (same
  * arguments as lpr_grid_maxflow_batched; flow_values device int64 [B]
- * receives the flow values) under every schedule of tile rows {8,16,32} x
+ * receives the flow values) under every schedule of tile rows {4,8,16,32} x
  * local iterations {4,8,16,32} x sweeps per relabel {2,4,8}, each `reps`
  * times after one warm-up run (1 <= reps <= 100), timed with HIP events, and
  * returns the fastest in `best` (host, may be NULL) with its time in ms
@@ -277,6 +281,17 @@ typedef struct {
                                        row's matched arc); a bound that
                                        drops needed arcs is caught by the
                                        final check and costs a rerun       */
+    int64_t warm_max_ops;           /* fallback of a warm start: an
+                                       instance started from given prices
+                                       (init_col_prices) or a given epsilon
+                                       (eps0, eps0_per_instance) that has
+                                       spent this many push+relabel
+                                       operations without finishing
+                                       restarts once from the plain start
+                                       of Algorithm 5.0 (prices 0, epsilon
+                                       max|c| (2n+1)); max_ops still bounds
+                                       the whole solve.  0 -> 2 n^2 + 2^16,
+                                       -1 -> never                         */
 } lpr_assign_opts;
 
 typedef struct {
@@ -290,6 +305,11 @@ typedef struct {
     int64_t fixing_reruns;   /* last refines rerun with full scans because
                                 the arc-fixed matching failed the
                                 1-optimality check (expected 0)          */
+    int64_t warm_restarts;   /* instances whose warm start ran past
+                                warm_max_ops and restarted from the plain
+                                start                                     */
+    int64_t scan_entries;    /* cost entries read by row scans: scans x n,
+                                summed over instances                     */
     double kernel_ms;   /* with LPR_ASSIGN_TIME_KERNELS: solve kernel time */
     double total_ms;    /* device time of the whole call (HIP events)      */
 } lpr_assign_stats;

@@ -30,7 +30,8 @@ W3, U3 [128,128], b3, w_o [128], b_o [1] -- each row-major, concatenated.
 
 Loss over a batch of instances with centred targets t (normalised prices):
   L = (1 / sum_i n_i) sum_i sum_y ((q_y - mean_i q) - t_y)^2
-Scaled integer start prices for the solver: p(y) = rint(q_y * sc * (2n+1)).
+Scaled integer start prices for the solver: p(y) = rint((q_y - mean q) sc
+(2n+1)), and the starting epsilon max(1, rint(kappa sc (2n+1))).
 """
 from __future__ import annotations
 
@@ -155,12 +156,23 @@ def loss_and_grad(theta, feats_list, targets):
 
 
 def predict_prices(theta, cost, maximize=False):
-    """Integer scaled start prices for one instance."""
+    """Integer scaled start prices for one instance: the centred network
+    output in units of sc, scaled by the solver's cost scale S = 2n+1 and
+    rounded half to even."""
     f, sc = features(cost, maximize)
     q = forward(theta, [f])[0][0]
     q = q - q.mean()
     n = f.shape[0]
     return np.rint(q * sc * (2 * n + 1)).astype(np.int64)
+
+
+def start_epsilon(cost, kappa, maximize=False):
+    """Starting epsilon of a warm-started solve, in the solver's scaled
+    units: kappa (the network's error in units of sc) times sc (2n+1),
+    rounded half to even, at least 1."""
+    f, sc = features(cost, maximize)
+    n = f.shape[0]
+    return max(1, int(np.rint(kappa * sc * (2 * n + 1))))
 
 
 def bf16_round(a):

@@ -59,6 +59,7 @@ constexpr int NW = NT / 64;
 constexpr int TAIL_EXIT = 8;   // back to phases when the queue grows past
                                // max(this, 4 x the entry threshold)
 constexpr unsigned C16_MAX = 32767;
+constexpr int NCNT = 16;       // statistics counters per solve
 // Row stride of the int16 copies: rows padded to a multiple of 8 entries so
 // that every row starts 16-byte aligned and is read with 16-byte loads.
 __host__ __device__ inline int ld16(int n) { return (n + 7) & ~7; }
@@ -99,6 +100,9 @@ struct AArgs {
     int64_t *totals;
     int64_t *col_prices;
     int64_t max_ops;
+    int64_t warm_max_ops;          // > 0: budget of a warm start before it
+                                   // restarts from the plain start; 0: the
+                                   // default 2 n^2 + 2^16; < 0: never
     int64_t pu_period;             // pushes between price updates; 0: n, < 0: never
     int32_t tail_rows;             // serial tail threshold (active rows)
     int32_t pu_start;              // price update after each refine's first push
@@ -111,7 +115,9 @@ struct AArgs {
     int32_t *ncand;                // per row: number of them
     uint64_t max_ticks;            // wall-clock budget in wall_clock64 ticks
     unsigned long long *counters;  // refines, phases, pushes, relabels, scans,
-                                   // price updates, wall-clock ticks in them
+                                   // price updates, wall-clock ticks in them,
+                                   // fixing reruns, warm-start restarts,
+                                   // cost entries read by row scans
     int32_t *status;  // per instance: 0 ok, 1 budget, 2 range, 3 internal
 };
 
@@ -379,7 +385,11 @@ __device__ inline bool resolve_column(int y, int64_t eps, const Shared &L,
 // Division by a fixed eps >= 1 without a 64-bit integer divide per call
 // (a software sequence of ~100 instructions on this hardware): the quotient
 // is estimated through a double reciprocal and corrected to the exact floor
-// by its integer remainder.  Exact for |a| < 2^62.
+// by its integer remainder.  Exact for |a| < 2^62: double(a) is within 2^9 of
+// a there, so the first estimate is within 2^9 / eps + 2 of the quotient and
+// leaves a remainder below 2^9 + 3 eps in magnitude; a second estimate on that
+// remainder has a relative error near 2^-52, so it is off by at most one, and
+// each correction loop below runs at most one step.
 struct EpsDiv {
     int64_t eps, kmax;  // kmax = floor(LLONG_MAX / eps)
     double inv;
@@ -388,6 +398,8 @@ struct EpsDiv {
     __device__ int64_t floor_div(int64_t a) const {
         int64_t q = int64_t(floor(double(a) * inv));
         int64_t r = a - q * eps;
+        q += int64_t(floor(double(r) * inv));
+        r = a - q * eps;
         while (r < 0) {
             --q;
             r += eps;
@@ -753,13 +765,13 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     const int tail_exit = max(TAIL_EXIT, 4 * tail_enter);
     __shared__ int s_nx, s_ny, s_stop, s_qh, s_nh;
     __shared__ unsigned long long s_pu_mark;  // pushes at the last price update
-    __shared__ unsigned long long s_cnt[8];
+    __shared__ unsigned long long s_cnt[NCNT];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t t_start = wall_clock64();
     const int64_t S = 2 * int64_t(n) + 1;
     const int64_t sgnS = int64_t(A.sign) * S;
-    if (tid < 8) s_cnt[tid] = 0;
+    if (tid < NCNT) s_cnt[tid] = 0;
     if (tid == 0) {
         s_nx = 0;
         s_ny = 0;
@@ -773,8 +785,21 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     if (tid < ld16(n) - n) py[n + tid] = PAD_PRICE;
     __syncthreads();
     // Algorithm 5.0 starts at eps = C (largest |cost|), here in scaled units
-    int64_t eps = A.eps0 > 0 ? A.eps0 : (cmax > 0 ? int64_t(cmax) * S : 1);
+    const int64_t eps_plain = cmax > 0 ? int64_t(cmax) * S : 1;
+    int64_t eps = A.eps0 > 0 ? A.eps0 : eps_plain;
     if (A.eps0_inst && A.eps0_inst[slot] > 0) eps = A.eps0_inst[slot];
+    // A start from given prices or a given epsilon is a guess: exactness
+    // never depends on it (every refine recomputes p(X) from p(Y), Algorithm
+    // 5.2), but a poor guess can cost far more operations than the plain
+    // start.  Past its budget the instance restarts once from the plain
+    // start (p = 0, eps = max|c| S), which is thus both the fallback and the
+    // judge of the guess.  `on_warm` is the same in every thread.
+    bool on_warm = A.warm_max_ops >= 0 &&
+                   (A.init_prices != nullptr || A.eps0 > 0 ||
+                    (A.eps0_inst && A.eps0_inst[slot] > 0));
+    const long long warm_budget =
+        A.warm_max_ops > 0 ? (long long)A.warm_max_ops
+                           : 2ll * n * n + (1ll << 16);
     const int64_t alpha = A.alpha;
     // candidate lists of unfixed arcs (int16 costs only); `lists` is the same
     // in every thread
@@ -869,9 +894,11 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                 s_ny = 0;
                 s_qh = 0;
                 atomicAdd(&s_cnt[1], 1ull);
-                if ((long long)(s_cnt[2] + s_cnt[3]) > A.max_ops ||
-                    wall_clock64() - t_start > A.max_ticks)
+                const long long ops = (long long)(s_cnt[2] + s_cnt[3]);
+                if (ops > A.max_ops || wall_clock64() - t_start > A.max_ticks)
                     atomicOr(&s_stop, 1);
+                else if (on_warm && ops > warm_budget)
+                    atomicOr(&s_stop, 4);
             }
             __syncthreads();
             int nx = s_nx;
@@ -954,11 +981,16 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                                 break;
                             }
                         }
-                        if ((ts & 127) == 0 &&
-                            ((long long)(s_cnt[2] + s_cnt[3] + tp + tr) > A.max_ops ||
-                             wall_clock64() - t_start > A.max_ticks)) {
-                            stop = 1;
-                            break;
+                        if ((ts & 127) == 0) {
+                            const long long ops = (long long)(s_cnt[2] + s_cnt[3] + tp + tr);
+                            if (ops > A.max_ops || wall_clock64() - t_start > A.max_ticks) {
+                                stop = 1;
+                                break;
+                            }
+                            if (on_warm && ops > warm_budget) {
+                                stop = 4;
+                                break;
+                            }
                         }
                     }
                     if (lane == 0) {
@@ -1002,6 +1034,27 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
                 if (x_rel) atomicAdd(&s_cnt[3], x_rel);
             }
             __syncthreads();
+        }
+        if (s_stop == 4) {
+            // The warm start ran past its budget: back to the plain start of
+            // Algorithm 5.0.  Every thread has read s_stop before the
+            // barrier below; the refine init rebuilds the matching state.
+            __syncthreads();
+            for (int y = tid; y < n; y += NT) py[y] = 0;
+            if (tid == 0) {
+                s_stop = 0;
+                s_nx = 0;
+                s_ny = 0;
+                s_qh = 0;
+                s_nh = 0;
+                s_pu_mark = s_cnt[2];
+                atomicAdd(&s_cnt[8], 1ull);
+            }
+            on_warm = false;
+            lists = sparse;
+            eps = eps_plain;  // the loop divides it first, as for a plain start
+            __syncthreads();
+            continue;
         }
         if (s_stop) break;
         if (eps == 1) {
@@ -1055,7 +1108,9 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             A.status[slot] = 0;
         }
     }
-    if (tid < 8 && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
+    if (tid == 0) s_cnt[9] = s_cnt[4] * (unsigned long long)n;  // cost entries scanned
+    __syncthreads();
+    if (tid < NCNT && s_cnt[tid]) atomicAdd(&A.counters[tid], s_cnt[tid]);
 }
 
 __global__ __launch_bounds__(NT) void k_assign(AArgs A) {
@@ -1101,7 +1156,7 @@ static Carver carve(Carver cv, int B, const int32_t *n, Layout *L) {
     L->order = cv.take<int32_t>(size_t(B));
     L->status = cv.take<int32_t>(size_t(B));
     L->cmax = cv.take<unsigned>(size_t(B));
-    L->counters = cv.take<unsigned long long>(8);
+    L->counters = cv.take<unsigned long long>(NCNT);
     L->c16 = cv.take<int16_t>(size_t(2 * c16_elems(B, n)));
     int64_t rows = 0;
     for (int b = 0; b < B; ++b) rows += n[b];
@@ -1159,7 +1214,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     }
     int32_t alpha = 8;
     int64_t eps0 = 0, max_ops = 64 * int64_t(nmax) * nmax + (int64_t(1) << 20);
-    int64_t max_ms = 20000, pu_period = 0;
+    int64_t max_ms = 20000, pu_period = 0, warm_max_ops = 0;
     int32_t tail_rows = 0, pu_start = 1, arc_fixing = 0, fixing_shift = 0;
     const int64_t *init = nullptr, *eps0_inst = nullptr;
     bool timing = false;
@@ -1175,10 +1230,11 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         pu_start = (opts->flags & LPR_ASSIGN_NO_START_UPDATE) == 0;
         arc_fixing = (opts->flags & LPR_ASSIGN_ARC_FIXING) != 0;
         fixing_shift = opts->fixing_shift;
+        warm_max_ops = opts->warm_max_ops;
         timing = (opts->flags & LPR_ASSIGN_TIME_KERNELS) != 0;
     }
     if (alpha < 2 || eps0 < 0 || max_ops < 0 || max_ms < 0 || tail_rows < 0 ||
-        tail_rows > 4096 || fixing_shift < 0 || fixing_shift > 63) {
+        tail_rows > 4096 || fixing_shift < 0 || fixing_shift > 63 || warm_max_ops < -1) {
         set_error("invalid lpr_assign_opts");
         return LPR_EINVAL;
     }
@@ -1200,7 +1256,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
                                hipMemcpyHostToDevice, s));
     LPR_TRY_HIP(hipMemcpyAsync(L.order, order.data(), sizeof(int32_t) * B,
                                hipMemcpyHostToDevice, s));
-    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.counters), 0, 8, s));
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.counters), 0, NCNT, s));
     LPR_TRY(fill_i32(L.status, -1, B, s));
     LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.cmax), 0, B, s));
     const int gx = int(std::min<int64_t>(512, std::max<int64_t>(1, (nnmax + 4095) / 4096)));
@@ -1225,6 +1281,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     A.totals = totals;
     A.col_prices = col_prices;
     A.max_ops = max_ops;
+    A.warm_max_ops = warm_max_ops;
     A.pu_period = pu_period;
     A.tail_rows = tail_rows;
     A.pu_start = pu_start;
@@ -1255,7 +1312,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     tk.end(ev);
     LPR_TRY_HIP(hipGetLastError());
     std::vector<int32_t> status(B);
-    unsigned long long cnt[8];
+    unsigned long long cnt[NCNT];
     LPR_TRY_HIP(hipMemcpyAsync(status.data(), L.status, sizeof(int32_t) * B,
                                hipMemcpyDeviceToHost, s));
     LPR_TRY_HIP(hipMemcpyAsync(cnt, L.counters, sizeof(cnt),
@@ -1273,6 +1330,8 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         stats->price_updates = int64_t(cnt[5]);
         stats->price_update_us = int64_t(cnt[6] * 1000 / uint64_t(khz));
         stats->fixing_reruns = int64_t(cnt[7]);
+        stats->warm_restarts = int64_t(cnt[8]);
+        stats->scan_entries = int64_t(cnt[9]);
         stats->kernel_ms = kms;
         stats->total_ms = tms;
     }

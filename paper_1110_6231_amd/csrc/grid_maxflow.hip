@@ -143,7 +143,8 @@ struct Dev {
     unsigned long long *inst_active;  // per-instance active pixels (last count)
     int32_t *done;                    // per-instance: no active pixel left
     unsigned long long *counters;     // pushes, relabels, tiles swept,
-                                      // tiles relaxed (BFS), tiles relaxed (cut)
+                                      // tiles relaxed (BFS), tiles relaxed (cut),
+                                      // device-scope atomics of the sweeps
     Scalars *sc;
     int32_t ntiles, ntiles_r;
     int32_t ninst;
@@ -704,6 +705,7 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
                              uint32_t(from_right(int32_t(acted), 0));
     bool active_end = false, touch_l = false, touch_r = false;
     bool touch_u = false, touch_d = false;
+    uint32_t n_atomic = 0;                     // device-scope atomics of this lane
 #pragma unroll
     for (int r = 0; r < TH; ++r) {
         if (!((valid >> r) & 1u)) continue;
@@ -714,7 +716,10 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
         const bool edge = (lane == 63 && x + 1 < g.W) || (lane == 0 && x > 0) ||
                           (r == TH - 1 && y + 1 < g.H) || (r == 0 && y > 0);
         if (edge) {
-            if (e[r] != e0[r]) atomicAdd(&at(D.e, o), e[r] - e0[r]);
+            if (e[r] != e0[r]) {
+                atomicAdd(&at(D.e, o), e[r] - e0[r]);
+                ++n_atomic;
+            }
         } else {
             at(D.e, o) = e[r];
         }
@@ -731,6 +736,7 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
                 atomicAdd(&at(D.rl, o + 4), out);
                 atomicAdd(&at(D.e, o + 4), out);
                 touch_r = true;
+                n_atomic += 3;
             }
         }
         if (lane == 0) {
@@ -740,6 +746,7 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
                 atomicAdd(&at(D.rr, o - 4), out);
                 atomicAdd(&at(D.e, o - 4), out);
                 touch_l = true;
+                n_atomic += 3;
             }
         }
         if (r == 0) {
@@ -749,6 +756,7 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
                 atomicAdd(&at(D.rd, o - ow), out);
                 atomicAdd(&at(D.e, o - ow), out);
                 touch_u = true;
+                n_atomic += 3;
             }
         }
         if (r == TH - 1) {
@@ -758,9 +766,11 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
                 atomicAdd(&at(D.ru, o + ow), out);
                 atomicAdd(&at(D.e, o + ow), out);
                 touch_d = true;
+                n_atomic += 3;
             }
         }
     }
+    for (int o = 32; o > 0; o >>= 1) n_atomic += __shfl_xor(n_atomic, o, 64);
     const bool a_end = __any(active_end);
     const bool a_l = __any(touch_l), a_r = __any(touch_r);
     const bool a_u = __any(touch_u), a_d = __any(touch_d);
@@ -773,6 +783,7 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
         if (pushes) atomicAdd(&D.counters[0], pushes);
         if (relabels) atomicAdd(&D.counters[1], relabels);
         atomicAdd(&D.counters[2], 1ull);
+        if (n_atomic) atomicAdd(&D.counters[5], (unsigned long long)n_atomic);
     }
 }
 
@@ -948,16 +959,24 @@ static lpr_status enqueue_round(hipStream_t s, const Dev &D, Layout &Lw, dim3 gr
 // Round graphs: the kernels of one round captured once per (buffers, shape,
 // schedule) and replayed with a single launch per round.
 // ---------------------------------------------------------------------------
+// A captured round bakes in every kernel argument (the Dev struct with its
+// tile counts, the carved workspace pointers, which follow from the
+// workspace base, N, B and both tile counts) and every grid size (T sweep
+// tiles, TR relaxation tiles).  The key holds all of them, so two batches
+// with the same pixel count but other shapes (e.g. 32 x 64 and 16 x 128:
+// the same N and T but TR 1 against 2) never share a graph.  The per-tile
+// and per-instance tables are read from the workspace at run time and are
+// rewritten by every solve, so their contents need no key.
 struct GraphKey {
     int device;
     const void *ws;
     const void *caps[6];
     int64_t N;
-    int B, T, TH, K, L, P;
+    int B, T, TR, TH, K, L, P;
     bool operator==(const GraphKey &o) const {
         return device == o.device && ws == o.ws && N == o.N && B == o.B &&
-               T == o.T && TH == o.TH && K == o.K && L == o.L && P == o.P &&
-               std::equal(caps, caps + 6, o.caps);
+               T == o.T && TR == o.TR && TH == o.TH && K == o.K && L == o.L &&
+               P == o.P && std::equal(caps, caps + 6, o.caps);
     }
 };
 
@@ -1181,6 +1200,7 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
         stats->relabels = int64_t(cnt[1]);
         stats->tiles_swept = int64_t(cnt[2]);
         stats->tiles_relaxed = int64_t(cnt[3]);
+        stats->device_atomics = int64_t(cnt[5]);
         stats->tile_rows = TH;
         stats->local_iters = P.L;
         stats->sweeps_per_relabel = P.K;
@@ -1383,6 +1403,7 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     key.N = N;
     key.B = B;
     key.T = int(T);
+    key.TR = int(TR);
     key.TH = P.TH;
     CallTimer call(s);
     call.start();

@@ -76,6 +76,7 @@ class GridStats(ctypes.Structure):
                 ("tiles_swept", ctypes.c_int64), ("pushes", ctypes.c_int64),
                 ("relabels", ctypes.c_int64), ("cut_passes", ctypes.c_int64),
                 ("tiles_relaxed", ctypes.c_int64),
+                ("device_atomics", ctypes.c_int64),
                 ("tile_rows", ctypes.c_int32), ("local_iters", ctypes.c_int32),
                 ("sweeps_per_relabel", ctypes.c_int32),
                 ("relax_tile_rows", ctypes.c_int32),
@@ -91,7 +92,8 @@ class AssignOpts(ctypes.Structure):
                 ("max_ms", ctypes.c_int64),
                 ("eps0_per_instance", ctypes.c_void_p),
                 ("price_update_period", ctypes.c_int64),
-                ("tail_rows", ctypes.c_int32), ("fixing_shift", ctypes.c_int32)]
+                ("tail_rows", ctypes.c_int32), ("fixing_shift", ctypes.c_int32),
+                ("warm_max_ops", ctypes.c_int64)]
 
 
 class AssignStats(ctypes.Structure):
@@ -100,6 +102,8 @@ class AssignStats(ctypes.Structure):
                 ("scans", ctypes.c_int64), ("price_updates", ctypes.c_int64),
                 ("price_update_us", ctypes.c_int64),
                 ("fixing_reruns", ctypes.c_int64),
+                ("warm_restarts", ctypes.c_int64),
+                ("scan_entries", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
@@ -368,8 +372,9 @@ def lpr_grid_tune(Hs, Ws, caps_packed, reps=2, workspace=None, stream=None):
 def make_assign_opts(alpha=0, eps0=0, init_col_prices=None, max_ops=0,
                      flags=0, max_ms=0, eps0_per_instance=None,
                      price_update_period=0, tail_rows=0,
-                     fixing_shift=0) -> AssignOpts:
+                     fixing_shift=0, warm_max_ops=0) -> AssignOpts:
     o = AssignOpts()
+    o.warm_max_ops = warm_max_ops
     o.max_ms = max_ms
     o.price_update_period = price_update_period
     o.tail_rows = tail_rows

@@ -57,12 +57,43 @@ def test_workspace_sizes():
     assert lpr.lpr_assign_batched_workspace([64, 128, 512]) > 0
 
 
-def test_struct_layouts():
+STRUCTS = {
+    "lpr_grid_opts": "GridOpts", "lpr_grid_stats": "GridStats",
+    "lpr_assign_opts": "AssignOpts", "lpr_assign_stats": "AssignStats",
+    "lpr_graph_opts": "GraphOpts", "lpr_graph_stats": "GraphStats",
+    "lpr_mcf_opts": "McfOpts", "lpr_mcf_stats": "McfStats",
+}
+
+
+def test_struct_layouts(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors in the
+    binding equals what the C compiler makes of include/lpr.h."""
     import ctypes
-    assert ctypes.sizeof(lpr.GridOpts) == 32
-    assert ctypes.sizeof(lpr.AssignOpts) == 64
-    assert ctypes.sizeof(lpr.GridStats) == 8 * 8 + 4 * 4 + 3 * 8
-    assert ctypes.sizeof(lpr.AssignStats) == 8 * 8 + 2 * 8
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lpr.h"',
+             "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(lpr, pyname)
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}",
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True,
+                         text=True).stdout.split()
+    got = {(out[i], out[i + 1]): int(out[i + 2]) for i in range(0, len(out), 3)}
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(lpr, pyname)
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
 
 
 def test_atomic_probe_rejects_bad_arguments():

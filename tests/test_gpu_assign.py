@@ -245,6 +245,44 @@ def test_batched():
         assert scaled_eps_certificate(m, r2c[a:b], prices[a:b])
 
 
+def test_warm_start_fallback():
+    """A start that costs more than its budget restarts from the plain start
+    (p = 0, eps = max|c| (2n+1)) and still ends at the optimum.  eps0 = 1 on
+    an n = 300 instance and garbage prices with eps0 = 1 both exhaust even the
+    whole-solve budget (64 n^2 + 2^20 operations) without the fallback."""
+    c = synth.assign_points(300, seed=4, instance=9)
+    st = check(c, opts=lpr.make_assign_opts(eps0=1))
+    print("[assign] eps0=1 fallback", st, flush=True)
+    assert st["warm_restarts"] == 1
+    g = np.random.default_rng(5)
+    garbage = torch.as_tensor(g.integers(-10**9, 10**9, 300), device="cuda")
+    st = check(c, opts=lpr.make_assign_opts(init_col_prices=garbage, eps0=1))
+    assert st["warm_restarts"] == 1
+    # a plain start never restarts; neither does a warm start within budget
+    assert check(c)["warm_restarts"] == 0
+    assert check(c, opts=lpr.make_assign_opts(eps0=5000))["warm_restarts"] == 0
+    # without the fallback the same start runs into the whole-solve budget
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_assign_solve(c, opts=lpr.make_assign_opts(eps0=1, warm_max_ops=-1,
+                                                          max_ops=400000))
+    assert e.value.status == lpr.LPR_EBUDGET
+    # in a batch, only the instances with a bad start restart
+    mats = [synth.assign_points(n, seed=6, instance=k + 1)
+            for k, n in enumerate([200, 96, 300, 150])]
+    packed = lpr.PackedAssign.from_matrices(mats)
+    eps = torch.tensor([1, 0, 1, 0], dtype=torch.int64, device="cuda")
+    r2c, tots, prices, st = lpr.lpr_assign_solve_batched(
+        packed, opts=lpr.make_assign_opts(eps0_per_instance=eps))
+    print("[assign] batched fallback", st, flush=True)
+    assert 1 <= st["warm_restarts"] <= 2
+    r2c, tots, prices = r2c.cpu().numpy(), tots.cpu().numpy(), prices.cpu().numpy()
+    for k, m in enumerate(mats):
+        a, b = packed.row_offset[k], packed.row_offset[k + 1]
+        assert tots[k] == oracle.assign(m)[1]
+        assert is_permutation(r2c[a:b], m.shape[0])
+        assert scaled_eps_certificate(m, r2c[a:b], prices[a:b])
+
+
 def test_errors():
     c = synth.assign_random_small(20, 0)
     big = c.copy()

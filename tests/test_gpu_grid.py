@@ -244,3 +244,27 @@ def test_autotuner_is_exact_and_sets_default():
                                                     sched["local_iters"])
     k = sched["sweeps_per_relabel"]
     assert st["sweeps_per_relabel"] == k
+
+
+def test_same_pixel_count_other_shape_reuses_buffers():
+    """Grids with the same pixel count and sweep-tile count but another
+    relaxation tiling (32 x 64, 8 x 256 and 16 x 128: 1, 4 and 2 relaxation
+    tiles of 64 x 32, against 4 sweep tiles of the default 64 x 8 each),
+    solved back to back through the same capacity tensors and workspace with
+    round graphs replayed: each must match the oracle, so no captured round
+    of one shape is replayed for the other."""
+    shapes = [(32, 64), (8, 256), (16, 128), (32, 64), (8, 256)]
+    N = 2048
+    need = max(lpr.lpr_grid_maxflow_workspace(H, W) for H, W in shapes)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    caps = [torch.empty(N, dtype=torch.int32, device="cuda") for _ in range(6)]
+    for k, (H, W) in enumerate(shapes):
+        inst = synth.grid_random_small(H, W, seed=50 + k, max_cap=30, max_term=60)
+        for dst, src in zip(caps, inst.arrays()):
+            dst.copy_(torch.as_tensor(src))
+        print(f"[grid] shared buffers {H}x{W}", flush=True)
+        v, side, st = lpr.lpr_grid_maxflow(H, W, *caps, workspace=ws)
+        want_v, want_side = oracle.grid_maxflow(inst, "fifo")
+        assert v == want_v, (H, W, v, want_v, st)
+        np.testing.assert_array_equal(side.cpu().numpy(), want_side)
+        assert st["rounds"] >= 2, st   # at least one replayed round

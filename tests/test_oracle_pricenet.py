@@ -118,3 +118,67 @@ def test_bf16_rounding_matches_torch():
     x = np.random.default_rng(0).normal(0, 3, 1000).astype(np.float32)
     ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(P.bf16_round(x), ref)
+
+
+def _one_hot_net(feature, sign_in=1.0, sign_out=1.0):
+    """Parameters of a network whose output is sign_out * relu(sign_in *
+    f_feature): unit 0 of every layer carries the feature, every other
+    weight is 0 (all values exact in bf16)."""
+    theta = np.zeros(P.param_count(), np.float32)
+    parts = P.unpack(theta.astype(np.float64))
+    offs, off = [], 0
+    for p in parts:
+        offs.append(off)
+        off += p.size
+    W1 = offs[0]
+    theta[W1 + feature * P.WIDTH + 0] = sign_in
+    for l in (1, 2):
+        theta[offs[3 * l] + 0] = 1.0      # W_l[0, 0]
+    theta[offs[9] + 0] = sign_out         # w_o[0]
+    return theta
+
+
+def _exact_round(fr):
+    """Round a Fraction half to even."""
+    from fractions import Fraction
+    fl = fr.numerator // fr.denominator
+    rem = fr - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return fl
+
+
+def test_predict_prices_closed_forms():
+    """Start prices of hand-set networks against closed forms in exact
+    rational arithmetic: a zero head gives all-zero prices whatever the
+    bias; a network passing the column mean of z = c / sc gives
+    p(y) = round((colmean(y) - mean) (2n+1)); maximising negates the costs,
+    and the same network read through -f gives the negated closed form."""
+    from fractions import Fraction
+    c = synth.assign_random_small(13, 5, lo=0, hi=400)
+    n = c.shape[0]
+    theta = P.init_params(3)
+    theta[-129:-1] = 0.0                  # w_o = 0
+    theta[-1] = 7.25                      # b_o
+    np.testing.assert_array_equal(P.predict_prices(theta, c), np.zeros(n, np.int64))
+    colsum = [int(v) for v in c.astype(np.int64).sum(axis=0)]
+    total = sum(colsum)
+    want = np.array([_exact_round(Fraction((n * cs - total) * (2 * n + 1), n * n))
+                     for cs in colsum], np.int64)
+    got = P.predict_prices(_one_hot_net(8), c)
+    np.testing.assert_array_equal(got, want)
+    # maximise: z = -c / sc, f8 = -colmean / sc; relu(-f8) then a head of -1
+    got = P.predict_prices(_one_hot_net(8, -1.0, -1.0), c, maximize=True)
+    want_max = np.array([_exact_round(Fraction(-(n * cs - total) * (2 * n + 1), n * n))
+                         for cs in colsum], np.int64)
+    np.testing.assert_array_equal(got, want_max)
+    # a different feature index would be caught: f0 (column minimum) differs
+    assert not np.array_equal(P.predict_prices(_one_hot_net(0), c), want)
+
+
+def test_start_epsilon_closed_form():
+    c = np.full((10, 10), 7)
+    assert P.start_epsilon(c, 1.0) == 7 * 21
+    assert P.start_epsilon(c, 0.5) == 74          # 73.5 rounds to even 74
+    assert P.start_epsilon(c, 1e-9) == 1
+    assert P.start_epsilon(-c, 2.0, maximize=True) == 2 * 7 * 21
