@@ -147,9 +147,15 @@ def test_forward_and_gradient_match_oracle():
 
 def test_gradient_with_uncorrelated_targets():
     """The backward pass on targets the network's output does not track
-    (unit normal prices): the residual's contributions do not cancel, so the
-    gradient's error is that of bf16 operands, about 2^-8 per product, and
-    the fixed bound is tight (float64 oracle fed the same bf16 inputs)."""
+    (unit normal prices).  The gradient of the column-centred loss sums
+    residuals that add up to zero against activations that share a large
+    common part, so the bf16 rounding of the activations alone moves the
+    float64 gradient by about a quarter here (0.26 for this seed, measured on
+    the CPU by the emulation below); no bf16 implementation can be held to a
+    fixed bound against the exact float64 gradient on such inputs.  The GPU
+    is held instead to the oracle fed the same bf16-rounded operands: it must
+    agree with that to the error of fp32 accumulation in another order and of
+    the rounded transposed copies (2e-2 overall, 4e-2 per block)."""
     mats = [synth.assign_points(n, seed=8, instance=k + 1)
             for k, n in enumerate([80, 211])]
     packed = _packed(mats)
@@ -171,16 +177,20 @@ def test_gradient_with_uncorrelated_targets():
     loss, grad = lpr.lpr_pricenet_train_step(packed, torch.cat(tp), params, step=0,
                                              want_grad=True)
     L_cpu, g_cpu = P.loss_and_grad(th, feats, targets)
+    g_emu = _loss_and_grad_bf16_operands(th, feats, targets)
     g_gpu = grad.cpu().numpy().astype(np.float64)
-    print(f"[net] loss {loss:.5f} / {L_cpu:.5f}, gradient rel {rel(g_gpu, g_cpu):.4f}",
-          flush=True)
+    r_emu = rel(g_gpu, g_emu)
+    print(f"[net] loss {loss:.5f} / {L_cpu:.5f}, gradient rel to float64 "
+          f"{rel(g_gpu, g_cpu):.4f} (emulation {rel(g_emu, g_cpu):.4f}), "
+          f"rel to bf16-operand emulation {r_emu:.4f}", flush=True)
     assert abs(loss - L_cpu) <= 1e-2 * L_cpu
-    assert rel(g_gpu, g_cpu) < 2e-2
+    assert r_emu < 2e-2
     off = 0
     for name, shape in P.param_shapes():
         size = int(np.prod(shape))
-        if name != "bo":
-            assert rel(g_gpu[off:off + size], g_cpu[off:off + size]) < 4e-2, (name, off)
+        if name != "bo":  # its true value is 0 (the residual sums to zero)
+            rb = rel(g_gpu[off:off + size], g_emu[off:off + size])
+            assert rb < 4e-2, (name, off, rb)
         off += size
 
 
