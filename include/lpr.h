@@ -84,6 +84,18 @@ const char *lpr_version(void);
                                      with HIP events into lpr_grid_stats */
 #define LPR_GRID_NO_GRAPH 0x2     /* launch every round's kernels one by one
                                      instead of replaying a captured graph */
+#define LPR_GRID_ASYNC_RELABEL 0x4 /* asynchronous global relabel (ARG,
+                                     Section 4.6): each round's global
+                                     relabel runs on a library stream beside
+                                     the push sweeps, on a snapshot of the
+                                     residual arcs taken at the previous
+                                     round boundary, and its labels become
+                                     the heights at the next boundary; an
+                                     instance retires when the exact count
+                                     of a snapshot is 0 */
+#define LPR_GRID_SYNC_RELABEL 0x8 /* global relabel between the sweeps (the
+                                     scheme of Algorithm 4.8); with neither
+                                     flag the tuned schedule decides */
 
 typedef struct {
     int32_t sweeps_per_relabel; /* push-sweep launches between global
@@ -99,7 +111,9 @@ typedef struct {
     int32_t max_rounds;         /* budget of global-relabel rounds; 0 =
                                    default (1 << 16)                       */
     int32_t flags;              /* LPR_GRID_* bits                          */
-    int32_t reserved[3];        /* must be 0                                */
+    int32_t rounds_per_check;   /* rounds enqueued between two reads of the
+                                   device status (1..16); 0 = tuned default */
+    int32_t reserved[2];        /* must be 0                                */
 } lpr_grid_opts;
 
 typedef struct {
@@ -124,6 +138,8 @@ typedef struct {
                                 of all push-sweep launches (HIP events)    */
     double bfs_ms;           /* same, for the BFS relaxation launches       */
     double total_ms;         /* wall time of the device work (HIP events)   */
+    int32_t async_relabel;   /* 1 if the asynchronous global relabel ran    */
+    int32_t rounds_per_check;/* rounds between host reads actually used     */
 } lpr_grid_stats;
 
 /* Device workspace bytes needed by lpr_grid_maxflow for an H x W grid. */
@@ -200,9 +216,12 @@ lpr_status lpr_grid_maxflow_batched(int32_t B, const int32_t *H,
  * Schedule autotuner for the grid solver.  Solves the given batch (same
  * arguments as lpr_grid_maxflow_batched; flow_values device int64 [B]
  * receives the flow values) under every schedule of tile rows {4,8,16,32} x
- * local iterations {4,8,16,32} x sweeps per relabel {2,4,8}, each `reps`
- * times after one warm-up run (1 <= reps <= 100), timed with HIP events, and
- * returns the fastest in `best` (host, may be NULL) with its time in ms
+ * local iterations {4,8,16,32} x sweeps per relabel {2,4,8} x relabel mode
+ * {between sweeps, asynchronous} at 4 rounds per check, then the winner at
+ * {1,2,4,8} rounds per check; each schedule `reps` times after one warm-up
+ * run (1 <= reps <= 100), timed with HIP events.  It returns the fastest in
+ * `best` (host, may be NULL; its flags name the relabel mode) with its time
+ * in ms
  * (host, may be NULL).  The winner becomes the default schedule of this
  * process for the batch's size class (floor(log2(total pixels))) -- used
  * whenever opts is NULL or leaves a schedule field 0 -- and is written to

@@ -42,8 +42,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <chrono>
 #include <map>
 #include <mutex>
+#include <optional>
 #include <vector>
 
 #include "lpr_internal.h"
@@ -128,23 +130,40 @@ struct Inst {
 };
 
 struct Scalars {
-    unsigned long long total_active;
+    unsigned long long total_active;  // active pixels after the last round
     int32_t err;
+    int32_t all_done;   // every instance retired
+    int32_t rounds;     // finished rounds that still had an unretired instance
+    int32_t open_bfs;   // global relabels that needed more passes than they had
+    int32_t max_need;   // most passes a converged global relabel needed
     int32_t pad;
     int32_t pass_count[MAX_PASS_SLOTS];
 };
 
+// Snapshot byte of a pixel: its arcs with residual capacity and whether it
+// holds excess, taken at a round boundary.  A global relabel works on these
+// bytes only, so it computes the exact BFS of the state at the snapshot even
+// while push sweeps change the live state.
+constexpr uint8_t AR_R = 1, AR_L = 2, AR_D = 4, AR_U = 8, AR_T = 16, AR_E = 32;
+// Round-boundary steps (k_boundary)
+constexpr unsigned BD_ADOPT = 1, BD_COUNT = 2, BD_SNAPSHOT = 4;
+
 struct Dev {
     int32_t *e, *h, *rr, *rl, *rd, *ru, *rs;
+    int32_t *lab;       // labels of the global relabel (and of the cut closure)
+    uint8_t *arcs;      // snapshot bytes (AR_*)
     const int32_t *cap_src, *cap_snk, *cap_r, *cap_l, *cap_d, *cap_u;
     const Inst *inst;
     const int32_t *tile_inst;    // instance of every sweep tile (64 x TH)
     const int32_t *tile_inst_r;  // instance of every relaxation tile (64 x RELAX_TH)
     unsigned long long *inst_active;  // per-instance active pixels (last count)
+    unsigned long long *inst_exact;   // per-instance pixels of the snapshot that
+                                      // hold excess and reach t
     int32_t *done;                    // per-instance: no active pixel left
     unsigned long long *counters;     // pushes, relabels, tiles swept,
                                       // tiles relaxed (BFS), tiles relaxed (cut),
-                                      // device-scope atomics of the sweeps
+                                      // device-scope atomics of the sweeps,
+                                      // BFS passes that relaxed a tile
     Scalars *sc;
     int32_t ntiles, ntiles_r;
     int32_t ninst;
@@ -188,36 +207,6 @@ __device__ __forceinline__ int block_group() {
 }
 __device__ __forceinline__ int wave_tile() {
     return block_group() * 4 + (threadIdx.x >> 6);
-}
-
-// Loads the one-pixel halo of a tile's labels/heights into rows 0 and TH+1
-// and columns 0 and TW+1 of `s` (|V| outside the grid); corners unused.
-template <int TH>
-__device__ inline void load_halo(const Dev &D, const Geo &g, int c,
-                                 int32_t (*s)[TW + 2]) {
-    const int tid = threadIdx.x;
-    const int x = g.x0 + c;
-    if (tid < TW) {
-        int32_t v = g.HV;
-        if (x < g.W && g.y0 > 0) v = D.h[g.off + int64_t(g.y0 - 1) * g.W + x];
-        s[0][c + 1] = v;
-    } else if (tid < 2 * TW) {
-        int32_t v = g.HV;
-        if (x < g.W && g.y0 + TH < g.H)
-            v = D.h[g.off + int64_t(g.y0 + TH) * g.W + x];
-        s[TH + 1][c + 1] = v;
-    } else if (tid < 2 * TW + TH) {
-        const int r = tid - 2 * TW, y = g.y0 + r;
-        int32_t v = g.HV;
-        if (y < g.H && g.x0 > 0) v = D.h[g.off + int64_t(y) * g.W + g.x0 - 1];
-        s[r + 1][0] = v;
-    } else if (tid < 2 * TW + 2 * TH) {
-        const int r = tid - 2 * TW - TH, y = g.y0 + r;
-        int32_t v = g.HV;
-        if (y < g.H && g.x0 + TW < g.W)
-            v = D.h[g.off + int64_t(y) * g.W + g.x0 + TW];
-        s[r + 1][TW + 1] = v;
-    }
 }
 
 __device__ inline unsigned long long block_sum_u64(unsigned long long v) {
@@ -270,29 +259,72 @@ __global__ __launch_bounds__(NT) void k_init(Dev D) {
 }
 
 // ---------------------------------------------------------------------------
-// Global relabel seed (Algorithm 4.4 from t): level 1 for pixels with a
-// residual arc to t, |V| (= "not scanned") elsewhere.  Tiles of retired
-// instances are left untouched and not marked.
+// Round boundary, over the push-sweep tiling.  Per pixel, in this order:
+//  ADOPT     h = lab: the heights of the next push sweeps are the levels of
+//            the global relabel just finished (Algorithm 4.4, with the gap:
+//            unreached pixels keep |V|).
+//  COUNT     the exact count of the state the labels belong to: pixels whose
+//            snapshot held excess and that reach t (lab < |V|); and the
+//            activity the next sweeps start from: e > 0 and h < |V| with the
+//            current excess.  Sets the active-tile flags of the next sweep.
+//  SNAPSHOT  the snapshot byte (residual arcs, arc to t, excess) and the seed
+//            of the next global relabel: lab = 1 where u_f(p, t) > 0, |V|
+//            elsewhere; marks the relaxation tile dirty.
+// Retired instances are left untouched: no active or dirty flag.
 // ---------------------------------------------------------------------------
 template <int TH>
-__global__ __launch_bounds__(NT) void k_bfs_seed(Dev D, int32_t *dirty_cur,
-                                                 int32_t *dirty_next) {
+__global__ __launch_bounds__(NT) void k_boundary(Dev D, int32_t *act_cur, int32_t *act_next,
+                                                 int32_t *dirty_cur, int32_t *dirty_next,
+                                                 unsigned mode) {
     const int t = blockIdx.x;
-    const Geo g = tile_geo<TH, true>(D, t);
-    const bool retired = D.done[g.inst] != 0;
-    if (threadIdx.x == 0) {
-        dirty_cur[t] = retired ? 0 : 1;
-        dirty_next[t] = 0;
-    }
-    if (retired) return;
+    const Geo g = tile_geo<TH>(D, t);
+    const bool retired = D.done[g.inst] != 0;  // workgroup-uniform
     const int c = threadIdx.x & (TW - 1);
+    unsigned long long n_exact = 0, n_act = 0;
+    if (!retired) {
 #pragma unroll
-    for (int k = 0; k < TH / RPP; ++k) {
-        const int r = (threadIdx.x >> 6) + RPP * k;
-        const int y = g.y0 + r, x = g.x0 + c;
-        if (y >= g.H || x >= g.W) continue;
-        const int64_t p = g.off + int64_t(y) * g.W + x;
-        D.h[p] = D.rs[p] > 0 ? 1 : g.HV;
+        for (int k = 0; k < TH / RPP; ++k) {
+            const int r = (threadIdx.x >> 6) + RPP * k;
+            const int y = g.y0 + r, x = g.x0 + c;
+            if (y >= g.H || x >= g.W) continue;
+            const int64_t p = g.off + int64_t(y) * g.W + x;
+            const int32_t ev = D.e[p];
+            int32_t hv = 0;
+            if (mode & BD_ADOPT) {
+                hv = D.lab[p];
+                D.h[p] = hv;
+            } else if (mode & BD_COUNT) {
+                hv = D.h[p];
+            }
+            if (mode & BD_COUNT) {
+                n_exact += ((D.arcs[p] & AR_E) && hv < g.HV) ? 1 : 0;
+                n_act += (ev > 0 && hv < g.HV) ? 1 : 0;
+            }
+            if (mode & BD_SNAPSHOT) {
+                const int32_t rs = D.rs[p];
+                const int b = (D.rr[p] > 0 ? AR_R : 0) | (D.rl[p] > 0 ? AR_L : 0) |
+                              (D.rd[p] > 0 ? AR_D : 0) | (D.ru[p] > 0 ? AR_U : 0) |
+                              (rs > 0 ? AR_T : 0) | (ev > 0 ? AR_E : 0);
+                D.arcs[p] = uint8_t(b);
+                D.lab[p] = rs > 0 ? 1 : g.HV;
+            }
+        }
+    }
+    if (mode & BD_COUNT) {
+        const unsigned long long se = block_sum_u64(n_exact);
+        const unsigned long long sa = block_sum_u64(n_act);
+        if (threadIdx.x == 0) {
+            act_cur[t] = sa > 0 ? 1 : 0;
+            act_next[t] = 0;
+            if (se) atomicAdd(&D.inst_exact[g.inst], se);
+            if (sa) atomicAdd(&D.inst_active[g.inst], sa);
+        }
+    }
+    if ((mode & BD_SNAPSHOT) && threadIdx.x == 0) {
+        // the relaxation tile holding this tile (TH divides RELAX_TH)
+        const int rt = D.inst[g.inst].tile_base_r + (g.y0 / RELAX_TH) * g.tiles_x + g.tx;
+        dirty_cur[rt] = retired ? 0 : 1;
+        dirty_next[rt] = 0;
     }
 }
 
@@ -313,7 +345,7 @@ __global__ __launch_bounds__(NT) void k_cut_seed(Dev D, int32_t *dirty_cur,
         const int y = g.y0 + r, x = g.x0 + c;
         if (y >= g.H || x >= g.W) continue;
         const int64_t p = g.off + int64_t(y) * g.W + x;
-        D.h[p] = D.e[p] > 0 ? 0 : g.HV;
+        D.lab[p] = D.e[p] > 0 ? 0 : g.HV;
     }
 }
 
@@ -327,15 +359,17 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
         const int y = g.y0 + r, x = g.x0 + c;
         if (y >= g.H || x >= g.W) continue;
         const int64_t p = g.off + int64_t(y) * g.W + x;
-        side[p] = D.h[p] < g.HV ? 1 : 0;
+        side[p] = D.lab[p] < g.HV ? 1 : 0;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Tile relaxation to a local fixpoint.
 //   BFS (CUT = false): lab(p) = min(lab(p), lab(q) + 1) over arcs p->q with
-//     u_f > 0 -- the backward BFS of Algorithm 4.4 from t; its least fixpoint
-//     is the BFS level, |V| where t is unreachable (the gap of Section 4.2).
+//     u_f > 0 in the snapshot -- the backward BFS of Algorithm 4.4 from t;
+//     its least fixpoint is the BFS level, |V| where t is unreachable (the
+//     gap of Section 4.2).  It reads the snapshot bytes, never the live
+//     residuals, so push sweeps may run meanwhile.
 //   CUT (CUT = true):  lab(p) = min(lab(p), lab(q)) over arcs q->p with
 //     u_f > 0 -- forward reachability from the excess pixels.
 // Labels only decrease and every value read from a neighbouring tile is an
@@ -354,14 +388,20 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 // the latency of an 8-row tile per wavefront.
 constexpr int RW = 8;  // rows per wavefront of the cooperative relaxation
 
+// A pass whose predecessor marked no tile (prev_count = 0) has nothing to do
+// and returns at once, so a round can carry more passes than its global
+// relabel needs at little cost.
 template <bool CUT>
 __global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
                                                int32_t *dirty_next,
-                                               int32_t *pass_count) {
+                                               int32_t *pass_count,
+                                               const int32_t *prev_count) {
     static_assert(RELAX_TH == 4 * RW, "four wavefronts per relaxation tile");
+    if (prev_count && *prev_count == 0) return;  // grid-uniform
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int t = block_group();
     if (t >= D.ntiles_r) return;              // workgroup-uniform
+    if (!CUT && t == 0 && threadIdx.x == 0) atomicAdd(&D.counters[6], 1ull);
     const int flag = dirty_cur[t];
     __shared__ int32_t edge[4][2][64];        // row 0 and row 7 of each wavefront
     __shared__ int s_ch;
@@ -383,12 +423,13 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
         d[r] = HV;
         if (colv && y < g.H) {
             const int64_t p = g.off + int64_t(y) * g.W + x;
-            d[r] = D.h[p];
+            d[r] = D.lab[p];
             if (!CUT) {
-                mR |= uint32_t(D.rr[p] > 0) << r;
-                mL |= uint32_t(D.rl[p] > 0) << r;
-                mD |= uint32_t(D.rd[p] > 0) << r;
-                mU |= uint32_t(D.ru[p] > 0) << r;
+                const uint32_t b = D.arcs[p];
+                mR |= ((b & AR_R) ? 1u : 0u) << r;
+                mL |= ((b & AR_L) ? 1u : 0u) << r;
+                mD |= ((b & AR_D) ? 1u : 0u) << r;
+                mU |= ((b & AR_U) ? 1u : 0u) << r;
             } else {
                 if (x + 1 < g.W) mR |= uint32_t(D.rl[p + 1] > 0) << r;
                 if (x > 0) mL |= uint32_t(D.rr[p - 1] > 0) << r;
@@ -401,16 +442,16 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
     // halo: the tile's row above / below (wavefronts 0 / 3), columns left and
     // right (lanes 0 / 63); the rows between wavefronts come from LDS
     int32_t top = HV, bot = HV, hside[RW];
-    if (w == 0 && colv && g.y0 > 0) top = D.h[g.off + int64_t(g.y0 - 1) * g.W + x];
+    if (w == 0 && colv && g.y0 > 0) top = D.lab[g.off + int64_t(g.y0 - 1) * g.W + x];
     if (w == 3 && colv && g.y0 + RELAX_TH < g.H)
-        bot = D.h[g.off + int64_t(g.y0 + RELAX_TH) * g.W + x];
+        bot = D.lab[g.off + int64_t(g.y0 + RELAX_TH) * g.W + x];
     const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         const int y = yw + r;
         hside[r] = HV;
         if ((lane == 0 || lane == 63) && hx >= 0 && hx < g.W && y < g.H)
-            hside[r] = D.h[g.off + int64_t(y) * g.W + hx];
+            hside[r] = D.lab[g.off + int64_t(y) * g.W + hx];
     }
     int32_t seg[RW];
 #pragma unroll
@@ -476,7 +517,7 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         if (d[r] == d0[r]) continue;
-        D.h[g.off + int64_t(yw + r) * g.W + x] = d[r];
+        D.lab[g.off + int64_t(yw + r) * g.W + x] = d[r];
         ch_col = true;
         if (w == 0 && r == 0) ch_top = true;
         if (w == 3 && r == RW - 1) ch_bot = true;
@@ -504,55 +545,62 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
 }
 
 // ---------------------------------------------------------------------------
-// Count active pixels (e > 0, h < |V|) right after a global relabel; seeds
-// the active-tile flags of the next push phase.
+// End of a round: retire the instances whose exact count is 0 and publish the
+// totals.  The count is exact only when the global relabel reached its
+// fixpoint: with `pass_count` given, the last of its P passes must have
+// marked no tile; otherwise labels can still lie above the BFS level,
+// nothing is retired, and the round is counted as open (the host then gives
+// later rounds more passes).  For a converged relabel the number of passes
+// it needed (up to the first that marked no tile) is kept in max_need.
 // ---------------------------------------------------------------------------
-template <int TH>
-__global__ __launch_bounds__(NT) void k_count(Dev D, int32_t *act_cur,
-                                              int32_t *act_next) {
-    const int t = blockIdx.x;
-    const Geo g = tile_geo<TH>(D, t);
-    unsigned long long cnt = 0;
-    if (!D.done[g.inst]) {
-        const int c = threadIdx.x & (TW - 1);
-#pragma unroll
-        for (int k = 0; k < TH / RPP; ++k) {
-            const int r = (threadIdx.x >> 6) + RPP * k;
-            const int y = g.y0 + r, x = g.x0 + c;
-            if (y >= g.H || x >= g.W) continue;
-            const int64_t p = g.off + int64_t(y) * g.W + x;
-            cnt += (D.e[p] > 0 && D.h[p] < g.HV) ? 1 : 0;
+__global__ void k_finish(Dev D, const int32_t *pass_count, int P) {
+    const bool exact = pass_count == nullptr || pass_count[P - 1] == 0;
+    unsigned long long tot = 0;
+    unsigned long long left = 0;
+    for (int i = threadIdx.x; i < D.ninst; i += blockDim.x) {
+        int dn = D.done[i];
+        if (!dn && exact && D.inst_exact[i] == 0) {
+            D.done[i] = 1;
+            dn = 1;
+        }
+        if (!dn) {
+            tot += D.inst_active[i];
+            ++left;
         }
     }
-    const unsigned long long s = block_sum_u64(cnt);
-    if (threadIdx.x == 0) {
-        act_cur[t] = s > 0 ? 1 : 0;
-        act_next[t] = 0;
-        if (s) atomicAdd(&D.inst_active[g.inst], s);
+    for (int o = 32; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o, 64);
+        left += __shfl_xor(left, o, 64);
     }
-}
-
-// Retire instances with no active pixel and publish the total.  The count
-// is exact only after the BFS reached its fixpoint: when `bfs_open` is given
-// and nonzero (the last relaxation pass still marked tiles dirty), labels can
-// still be |V| above their BFS level, so nothing is retired and the host
-// finishes the BFS and counts again.
-__global__ void k_count_finish(Dev D, const int32_t *bfs_open) {
-    const bool exact = bfs_open == nullptr || *bfs_open == 0;
-    unsigned long long tot = 0;
-    for (int i = threadIdx.x; i < D.ninst; i += blockDim.x) {
-        const unsigned long long a = D.inst_active[i];
-        if (a == 0 && exact) D.done[i] = 1;
-        tot += a;
+    __shared__ unsigned long long red[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = tot;
+        red[1][threadIdx.x >> 6] = left;
     }
-    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
-    __shared__ unsigned long long red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tot;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long s = 0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-        D.sc->total_active = s;
+        unsigned long long s = 0, l = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            s += red[0][i];
+            l += red[1][i];
+        }
+        Scalars *sc = D.sc;
+        if (!sc->all_done) sc->rounds += 1;
+        sc->total_active = s;
+        sc->all_done = l == 0 ? 1 : 0;
+        if (pass_count) {
+            if (!exact) {
+                sc->open_bfs += 1;
+            } else {
+                int need = P;
+                for (int i = 0; i < P; ++i)
+                    if (pass_count[i] == 0) {
+                        need = i + 1;
+                        break;
+                    }
+                sc->max_need = max(sc->max_need, need);
+            }
+        }
     }
 }
 
@@ -811,14 +859,19 @@ __global__ __launch_bounds__(NT) void k_flow_value(Dev D, int64_t *flow) {
 // ---------------------------------------------------------------------------
 struct Layout {
     int32_t *st[7];
+    int32_t *lab;
+    uint8_t *arcs;
     int32_t *tile_inst, *tile_inst_r, *act[2], *dirty[2], *done;
     Inst *inst;
-    unsigned long long *inst_active, *counters;
+    unsigned long long *inst_cnt;  // active [B], then exact [B]
+    unsigned long long *counters;
     Scalars *sc;
 };
 
 static Carver carve(Carver cv, int64_t N, int64_t T, int64_t TR, int B, Layout *L) {
     for (int i = 0; i < 7; ++i) L->st[i] = cv.take<int32_t>(size_t(N));
+    L->lab = cv.take<int32_t>(size_t(N));
+    L->arcs = cv.take<uint8_t>(size_t(N));
     L->tile_inst = cv.take<int32_t>(size_t(T));
     L->tile_inst_r = cv.take<int32_t>(size_t(TR));
     L->act[0] = cv.take<int32_t>(size_t(T));
@@ -826,7 +879,7 @@ static Carver carve(Carver cv, int64_t N, int64_t T, int64_t TR, int B, Layout *
     L->dirty[0] = cv.take<int32_t>(size_t(TR));
     L->dirty[1] = cv.take<int32_t>(size_t(TR));
     L->inst = cv.take<Inst>(size_t(B));
-    L->inst_active = cv.take<unsigned long long>(size_t(B));
+    L->inst_cnt = cv.take<unsigned long long>(size_t(2) * B);
     L->done = cv.take<int32_t>(size_t(B));
     L->counters = cv.take<unsigned long long>(8);
     L->sc = cv.take<Scalars>(1);
@@ -851,49 +904,50 @@ static size_t workspace_bytes(int B, const int32_t *H, const int32_t *W) {
 
 template <int TH>
 struct Kern {
-    static void init(dim3 g, hipStream_t s, const Dev &D) {
-        hipLaunchKernelGGL(k_init<TH>, g, dim3(NT), 0, s, D);
+    static void init(hipStream_t s, const Dev &D) {
+        hipLaunchKernelGGL(k_init<TH>, dim3(D.ntiles), dim3(NT), 0, s, D);
     }
-    // the relaxation kernels run on the RELAX_TH tiling
-    static void bfs_seed(hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
-        hipLaunchKernelGGL(k_bfs_seed<RELAX_TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D, a, b);
+    static void boundary(hipStream_t s, const Dev &D, const Layout &Lw, unsigned mode) {
+        hipLaunchKernelGGL(k_boundary<TH>, dim3(D.ntiles), dim3(NT), 0, s, D, Lw.act[0],
+                           Lw.act[1], Lw.dirty[0], Lw.dirty[1], mode);
     }
+    // the relaxation kernels run on the RELAX_TH tiling, one 4-wavefront
+    // workgroup per tile
     static void cut_seed(hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
         hipLaunchKernelGGL(k_cut_seed<RELAX_TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D, a, b);
     }
-    // one 4-wavefront workgroup per relaxation tile
     static void relax(bool cut, hipStream_t s, const Dev &D, int32_t *a, int32_t *b,
-                      int32_t *pc) {
+                      int32_t *pc, const int32_t *prev) {
         const dim3 gw(D.ntiles_r);
-        if (cut) hipLaunchKernelGGL((k_relax4<true>), gw, dim3(NT), 0, s, D, a, b, pc);
-        else hipLaunchKernelGGL((k_relax4<false>), gw, dim3(NT), 0, s, D, a, b, pc);
+        if (cut) hipLaunchKernelGGL((k_relax4<true>), gw, dim3(NT), 0, s, D, a, b, pc, prev);
+        else hipLaunchKernelGGL((k_relax4<false>), gw, dim3(NT), 0, s, D, a, b, pc, prev);
     }
-    static void count(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
-        hipLaunchKernelGGL(k_count<TH>, g, dim3(NT), 0, s, D, a, b);
+    static void sweep(hipStream_t s, const Dev &D, int32_t *a, int32_t *b, int L) {
+        hipLaunchKernelGGL(k_sweep<TH>, dim3((D.ntiles + 3) / 4), dim3(NT), 0, s, D, a, b, L);
     }
-    static void sweep(dim3 g, hipStream_t s, const Dev &D, int32_t *a, int32_t *b, int L) {
-        hipLaunchKernelGGL(k_sweep<TH>, dim3((g.x + 3) / 4), dim3(NT), 0, s, D, a, b, L);
+    static void flow(hipStream_t s, const Dev &D, int64_t *f) {
+        hipLaunchKernelGGL(k_flow_value<TH>, dim3(D.ntiles), dim3(NT), 0, s, D, f);
     }
-    static void flow(dim3 g, hipStream_t s, const Dev &D, int64_t *f) {
-        hipLaunchKernelGGL(k_flow_value<TH>, g, dim3(NT), 0, s, D, f);
-    }
-    static void cut_write(dim3 g, hipStream_t s, const Dev &D, uint8_t *side) {
-        hipLaunchKernelGGL(k_cut_write<TH>, g, dim3(NT), 0, s, D, side);
+    static void cut_write(hipStream_t s, const Dev &D, uint8_t *side) {
+        hipLaunchKernelGGL(k_cut_write<TH>, dim3(D.ntiles), dim3(NT), 0, s, D, side);
     }
 };
 
 struct Params {
     int TH, L, K, max_rounds;
+    int rounds_per_check;  // rounds enqueued between two host reads
     bool timing, no_graph;
+    bool arg;      // asynchronous global relabel (BFS on a second stream)
+    bool noalloc;  // allocation-free call: no graphs, events, streams or pinned memory
 };
 
-// Runs relaxation passes until no tile is dirty.  Pass counters are cleared
-// per batch; the last slot of a batch being 0 means the fixpoint is reached.
+// Runs relaxation passes until no tile is dirty (host checks once per batch
+// of passes; a pass after one that marked nothing returns at once).
 template <int TH>
 static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
-                                    Layout &Lw, int *dirty_sel, dim3 grid,
-                                    EventTimer &tm, int64_t *passes) {
+                                    Layout &Lw, EventTimer &tm, int64_t *passes) {
     int batch = 8;
+    int sel = 0;
     const int64_t guard = 16 * int64_t(D.ntiles_r) + 1024;
     for (int64_t done_passes = 0;; done_passes += batch) {
         if (done_passes > guard) {
@@ -901,65 +955,93 @@ static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
                       (long long)guard);
             return LPR_EBUDGET;
         }
-        LPR_TRY(fill_i32(Lw.sc->pass_count, 0, batch, s));
+        int32_t *pc = Lw.sc->pass_count;
+        LPR_TRY(fill_i32(pc, 0, batch, s));
         const int ev = tm.begin();
         for (int i = 0; i < batch; ++i) {
-            Kern<TH>::relax(cut, s, D, Lw.dirty[*dirty_sel],
-                            Lw.dirty[*dirty_sel ^ 1], Lw.sc->pass_count + i);
-            *dirty_sel ^= 1;
+            Kern<TH>::relax(cut, s, D, Lw.dirty[sel], Lw.dirty[sel ^ 1], pc + i,
+                            i ? pc + i - 1 : nullptr);
+            sel ^= 1;
         }
         tm.end(ev);
         LPR_TRY_HIP(hipGetLastError());
         *passes += batch;
         int32_t last = 0;
-        LPR_TRY_HIP(hipMemcpyAsync(&last, Lw.sc->pass_count + batch - 1,
-                                   sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        LPR_TRY_HIP(hipMemcpyAsync(&last, pc + batch - 1, sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
         LPR_TRY_HIP(hipStreamSynchronize(s));
+        // at the fixpoint both flag buffers are clear: every flagged tile
+        // was processed (and cleared its flag) and the last pass marked none
         if (last == 0) return LPR_OK;
         batch = std::min(batch * 2, MAX_PASS_SLOTS);
     }
 }
 
-// Count active pixels (after an exact global relabel) into the scalars and
-// seed the active-tile flags act[0] (read by the next sweep).
+// Adopt the labels of the global relabel just finished, count, retire.
 template <int TH>
-static lpr_status enqueue_count(hipStream_t s, const Dev &D, Layout &Lw, dim3 grid,
-                                int B, const int32_t *bfs_open) {
-    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.inst_active), 0, B, s));
-    Kern<TH>::count(grid, s, D, Lw.act[0], Lw.act[1]);
-    hipLaunchKernelGGL(k_count_finish, dim3(1), dim3(256), 0, s, D, bfs_open);
+static lpr_status enqueue_adopt(hipStream_t s, const Dev &D, Layout &Lw, int B,
+                                unsigned extra, const int32_t *pass_count, int P) {
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.inst_cnt), 0, 2 * int64_t(B), s));
+    Kern<TH>::boundary(s, D, Lw, BD_ADOPT | BD_COUNT | extra);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, D, pass_count, P);
+    LPR_TRY_HIP(hipGetLastError());
+    return LPR_OK;
+}
+
+template <int TH>
+static lpr_status enqueue_sweeps(hipStream_t s, const Dev &D, Layout &Lw, int K, int L,
+                                 EventTimer *tm) {
+    const int ev = tm ? tm->begin() : -1;
+    for (int k = 0; k < K; ++k)
+        Kern<TH>::sweep(s, D, Lw.act[k & 1], Lw.act[(k & 1) ^ 1], L);
+    if (tm) tm->end(ev);
+    LPR_TRY_HIP(hipGetLastError());
+    return LPR_OK;
+}
+
+// P relaxation passes of the global relabel seeded at the last snapshot
+// (dirty flags start in buffer 0).
+template <int TH>
+static lpr_status enqueue_passes(hipStream_t s, const Dev &D, Layout &Lw, int P,
+                                 EventTimer *tm) {
+    int32_t *pc = Lw.sc->pass_count;
+    const int ev = tm ? tm->begin() : -1;
+    for (int i = 0; i < P; ++i)
+        Kern<TH>::relax(false, s, D, Lw.dirty[i & 1], Lw.dirty[(i & 1) ^ 1], pc + i,
+                        i ? pc + i - 1 : nullptr);
+    if (tm) tm->end(ev);
     LPR_TRY_HIP(hipGetLastError());
     return LPR_OK;
 }
 
 // One round of the hybrid scheme (Algorithm 4.8 with the heuristic on the
-// device): K push sweeps, the global relabel seed, P BFS relaxation passes
-// and the count.  K and P are even, so every double-buffer selection is back
-// where it started and the same sequence (or its graph) serves every round.
+// device): K push sweeps, the snapshot and seed, P relaxation passes, adopt,
+// count and retire.
 template <int TH>
-static lpr_status enqueue_round(hipStream_t s, const Dev &D, Layout &Lw, dim3 grid,
-                                int B, int K, int L, int P, EventTimer *t_sweep,
-                                EventTimer *t_bfs) {
-    int ev = t_sweep ? t_sweep->begin() : -1;
-    for (int k = 0; k < K; ++k)
-        Kern<TH>::sweep(grid, s, D, Lw.act[k & 1], Lw.act[(k & 1) ^ 1], L);
-    if (t_sweep) t_sweep->end(ev);
-    Kern<TH>::bfs_seed(s, D, Lw.dirty[0], Lw.dirty[1]);
+static lpr_status enqueue_seq_round(hipStream_t s, const Dev &D, Layout &Lw, int B, int K,
+                                    int L, int P, EventTimer *t_sweep, EventTimer *t_bfs) {
+    LPR_TRY(enqueue_sweeps<TH>(s, D, Lw, K, L, t_sweep));
+    Kern<TH>::boundary(s, D, Lw, BD_SNAPSHOT);
     LPR_TRY(fill_i32(Lw.sc->pass_count, 0, P, s));
-    ev = t_bfs ? t_bfs->begin() : -1;
-    for (int i = 0; i < P; ++i)
-        Kern<TH>::relax(false, s, D, Lw.dirty[i & 1], Lw.dirty[(i & 1) ^ 1],
-                        Lw.sc->pass_count + i);
-    if (t_bfs) t_bfs->end(ev);
-    LPR_TRY(enqueue_count<TH>(s, D, Lw, grid, B, Lw.sc->pass_count + P - 1));
-    return LPR_OK;
+    LPR_TRY(enqueue_passes<TH>(s, D, Lw, P, t_bfs));
+    return enqueue_adopt<TH>(s, D, Lw, B, 0, Lw.sc->pass_count, P);
+}
+
+// End of an asynchronous round (after the join): adopt the labels of the
+// global relabel that ran beside the sweeps (the BFS of the previous
+// snapshot), count that snapshot exactly and retire, take the next snapshot
+// and seed, clear the pass counters of the next relabel.
+template <int TH>
+static lpr_status enqueue_arg_post(hipStream_t s, const Dev &D, Layout &Lw, int B, int P) {
+    LPR_TRY(enqueue_adopt<TH>(s, D, Lw, B, BD_SNAPSHOT, Lw.sc->pass_count, P));
+    return fill_i32(Lw.sc->pass_count, 0, P, s);
 }
 
 // ---------------------------------------------------------------------------
-// Round graphs: the kernels of one round captured once per (buffers, shape,
-// schedule) and replayed with a single launch per round.
+// Graphs: the kernels of a round (or of one stream's share of it) captured
+// once per (buffers, shape, schedule, kind) and replayed with one launch.
 // ---------------------------------------------------------------------------
-// A captured round bakes in every kernel argument (the Dev struct with its
+// A captured sequence bakes in every kernel argument (the Dev struct with its
 // tile counts, the carved workspace pointers, which follow from the
 // workspace base, N, B and both tile counts) and every grid size (T sweep
 // tiles, TR relaxation tiles).  The key holds all of them, so two batches
@@ -967,16 +1049,18 @@ static lpr_status enqueue_round(hipStream_t s, const Dev &D, Layout &Lw, dim3 gr
 // the same N and T but TR 1 against 2) never share a graph.  The per-tile
 // and per-instance tables are read from the workspace at run time and are
 // rewritten by every solve, so their contents need no key.
+enum GraphKind { GK_SEQ_ROUND = 0, GK_SWEEPS = 1, GK_PASSES = 2, GK_ARG_POST = 3 };
+
 struct GraphKey {
     int device;
     const void *ws;
     const void *caps[6];
     int64_t N;
-    int B, T, TR, TH, K, L, P;
+    int B, T, TR, TH, K, L, P, kind;
     bool operator==(const GraphKey &o) const {
         return device == o.device && ws == o.ws && N == o.N && B == o.B &&
                T == o.T && TR == o.TR && TH == o.TH && K == o.K && L == o.L &&
-               P == o.P && std::equal(caps, caps + 6, o.caps);
+               P == o.P && kind == o.kind && std::equal(caps, caps + 6, o.caps);
     }
 };
 
@@ -989,29 +1073,32 @@ struct GraphEntry {
 static std::mutex g_graph_mu;
 static std::vector<GraphEntry> g_graphs;
 static uint64_t g_graph_clock = 0;
-constexpr size_t MAX_GRAPHS = 8;
+constexpr size_t MAX_GRAPHS = 16;
 
-static lpr_status capture_stream(int device, hipStream_t *out) {
+// Library streams per device (default priority, non-blocking): the capture
+// stream and the stream the asynchronous global relabel runs on.
+static lpr_status library_stream(int device, int which, hipStream_t *out) {
     static std::mutex mu;
     static std::vector<std::pair<int, hipStream_t>> streams;
     std::lock_guard<std::mutex> lk(mu);
+    const int id = device * 2 + which;
     for (auto &p : streams)
-        if (p.first == device) {
+        if (p.first == id) {
             *out = p.second;
             return LPR_OK;
         }
     hipStream_t st;
     LPR_TRY_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    streams.emplace_back(device, st);
+    streams.emplace_back(id, st);
     *out = st;
     return LPR_OK;
 }
 
-// Finds or captures the round graph for `key` and launches it on `s` (under
-// the cache lock, so an eviction cannot destroy it in between).
-template <int TH>
-static lpr_status launch_round_graph(const GraphKey &key, const Dev &D, Layout &Lw,
-                                     dim3 grid, hipStream_t s) {
+// Finds or captures the graph of `key` (its kernels enqueued by `fill`) and
+// launches it on `s` (under the cache lock, so an eviction cannot destroy it
+// in between).
+template <class F>
+static lpr_status launch_graph(const GraphKey &key, hipStream_t s, F &&fill) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     for (auto &e : g_graphs)
         if (e.key == key) {
@@ -1020,13 +1107,15 @@ static lpr_status launch_round_graph(const GraphKey &key, const Dev &D, Layout &
             return LPR_OK;
         }
     hipStream_t cs;
-    LPR_TRY(capture_stream(key.device, &cs));
+    LPR_TRY(library_stream(key.device, 0, &cs));
     hipGraph_t g;
     LPR_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    const lpr_status st = enqueue_round<TH>(cs, D, Lw, grid, key.B, key.K, key.L,
-                                            key.P, nullptr, nullptr);
+    const lpr_status st = fill(cs);
     const hipError_t ce = hipStreamEndCapture(cs, &g);
-    if (st != LPR_OK) return st;
+    if (st != LPR_OK) {
+        if (ce == hipSuccess) (void)hipGraphDestroy(g);
+        return st;
+    }
     if (ce != hipSuccess) {
         set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
         return LPR_EDEVICE;
@@ -1051,6 +1140,30 @@ static lpr_status launch_round_graph(const GraphKey &key, const Dev &D, Layout &
     return LPR_OK;
 }
 
+// Fork/join events of the asynchronous rounds, per thread and device (two
+// per round of a check interval), created once.
+constexpr int MAX_ROUNDS_PER_CHECK = 16;
+
+static lpr_status round_events(int device, hipEvent_t **out) {
+    struct Pool {
+        int device;
+        hipEvent_t ev[2 * MAX_ROUNDS_PER_CHECK];
+    };
+    static thread_local std::vector<Pool> pools;
+    for (auto &p : pools)
+        if (p.device == device) {
+            *out = p.ev;
+            return LPR_OK;
+        }
+    Pool p;
+    p.device = device;
+    for (int i = 0; i < 2 * MAX_ROUNDS_PER_CHECK; ++i)
+        LPR_TRY_HIP(hipEventCreateWithFlags(&p.ev[i], hipEventDisableTiming));
+    pools.push_back(p);
+    *out = pools.back().ev;
+    return LPR_OK;
+}
+
 // Pinned host copy of the scalars, one per calling thread.
 static lpr_status host_scalars(Scalars **out) {
     static thread_local Scalars *h = nullptr;
@@ -1059,9 +1172,13 @@ static lpr_status host_scalars(Scalars **out) {
     return LPR_OK;
 }
 
-template <int TH>
-static lpr_status read_scalars(hipStream_t s, Layout &Lw, Scalars **host) {
-    LPR_TRY(host_scalars(host));
+// The allocation-free path reads into ordinary (pageable) host memory.
+static lpr_status read_scalars(hipStream_t s, Layout &Lw, Scalars **host, bool noalloc) {
+    static thread_local Scalars pageable;
+    if (noalloc)
+        *host = &pageable;
+    else
+        LPR_TRY(host_scalars(host));
     LPR_TRY_HIP(hipMemcpyAsync(*host, Lw.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     LPR_TRY_HIP(hipStreamSynchronize(s));
     if ((*host)->err) {
@@ -1079,14 +1196,30 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
                         Layout &Lw, const GraphKey &base_key, int64_t *flow_values,
                         uint8_t *side, lpr_grid_stats *stats, hipStream_t s) {
     const int T = int(tile_inst.size());
-    const dim3 grid(T);
-    EventTimer t_sweep(s), t_bfs(s);
+    // the asynchronous global relabel runs its passes on a library stream
+    hipStream_t sb = s;
+    hipEvent_t *ev = nullptr;
+    if (P.arg) {
+        LPR_TRY(library_stream(base_key.device, 1, &sb));
+        LPR_TRY(round_events(base_key.device, &ev));
+    }
+    // whatever path leaves this function, nothing the call enqueued on the
+    // library stream may still run over the caller's buffers afterwards
+    struct SyncOnExit {
+        hipStream_t st;
+        bool on;
+        ~SyncOnExit() {
+            if (on) (void)hipStreamSynchronize(st);
+        }
+    } sync_sb{sb, P.arg};
+    EventTimer t_sweep(s), t_bfs(s), t_bfs_b(sb);
     if (P.timing) {
         t_sweep.enable();
         t_bfs.enable();
+        t_bfs_b.enable();
     }
     double sweep_ms = 0, bfs_ms = 0;
-    int64_t rounds = 0, sweeps = 0, bfs_passes = 0, cut_passes = 0;
+    int64_t bfs_passes = 0, cut_passes = 0, rounds_enq = 0;
 
     LPR_TRY_HIP(hipMemcpyAsync(Lw.inst, insts.data(), sizeof(Inst) * B,
                                hipMemcpyHostToDevice, s));
@@ -1097,92 +1230,132 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
                                hipMemcpyHostToDevice, s));
     LPR_TRY(fill_i32(Lw.done, 0, B, s));
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.counters), 0, 8, s));
-    LPR_TRY(fill_i32(&Lw.sc->err, 0, 1, s));
-    Kern<TH>::init(grid, s, D);
+    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(Lw.sc), 0,
+                     int64_t(sizeof(Scalars) / sizeof(int32_t)), s));
+    LPR_TRY(fill_i32(Lw.dirty[1], 0, D.ntiles_r, s));
+    Kern<TH>::init(s, D);
     LPR_TRY_HIP(hipGetLastError());
 
-    // First global relabel: eager, to its fixpoint; its pass count sets the
-    // number of BFS passes per later round.
-    int dirty_sel = 0;
-    Kern<TH>::bfs_seed(s, D, Lw.dirty[0], Lw.dirty[1]);
-    LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, &dirty_sel, grid, t_bfs,
-                                  &bfs_passes));
-    int PB = int(std::min<int64_t>(MAX_PASS_SLOTS, std::max<int64_t>(4, bfs_passes / 2 + 2)));
-    PB += PB & 1;
-    LPR_TRY(enqueue_count<TH>(s, D, Lw, grid, B, nullptr));
-    Scalars *host = nullptr;
-    LPR_TRY(read_scalars<TH>(s, Lw, &host));
-    const bool use_graph = !P.timing && !P.no_graph && (P.K % 2 == 0);
-    bool converged = false;
-    for (;;) {
-        if (host->total_active == 0) {
-            converged = true;
-            break;
+    // An exact global relabel on the current state, to its fixpoint under
+    // host control, then adopt, count and retire.
+    auto exact_relabel = [&]() -> lpr_status {
+        Kern<TH>::boundary(s, D, Lw, BD_SNAPSHOT);
+        LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, t_bfs, &bfs_passes));
+        LPR_TRY(enqueue_adopt<TH>(s, D, Lw, B, 0, nullptr, 0));
+        if (P.arg) {
+            // the snapshot the first asynchronous relabel works on
+            Kern<TH>::boundary(s, D, Lw, BD_SNAPSHOT);
+            LPR_TRY(fill_i32(Lw.sc->pass_count, 0, MAX_PASS_SLOTS, s));
         }
-        if (rounds >= P.max_rounds) break;
-        ++rounds;
-        sweeps += P.K;
-        bfs_passes += PB;
-        if (use_graph) {
-            GraphKey key = base_key;
-            key.K = P.K;
-            key.L = P.L;
-            key.P = PB;
-            LPR_TRY(launch_round_graph<TH>(key, D, Lw, grid, s));
-        } else {
-            // odd K alternates the active-flag buffers; keep it on the eager path
-            if (P.K % 2) {
-                LPR_TRY(enqueue_round<TH>(s, D, Lw, grid, B, P.K + 1, P.L, PB,
-                                          &t_sweep, &t_bfs));
-                sweeps += 1;
+        LPR_TRY_HIP(hipGetLastError());
+        return LPR_OK;
+    };
+    // First global relabel: its pass count sets the passes of later rounds.
+    LPR_TRY(exact_relabel());
+    int PB = int(std::min<int64_t>(MAX_PASS_SLOTS, std::max<int64_t>(4, bfs_passes / 2 + 4)));
+    PB += PB & 1;
+    Scalars *host = nullptr;
+    LPR_TRY(read_scalars(s, Lw, &host, P.noalloc));
+    const bool use_graph = !P.timing && !P.no_graph && !P.noalloc;
+    const int R = std::max(1, std::min(P.rounds_per_check, MAX_ROUNDS_PER_CHECK));
+    for (;;) {
+        if (host->all_done) break;
+        if (rounds_enq >= P.max_rounds) break;
+        const int nr = int(std::min<int64_t>(R, P.max_rounds - rounds_enq));
+        for (int r = 0; r < nr; ++r) {
+            ++rounds_enq;
+            if (!P.arg) {
+                if (use_graph) {
+                    GraphKey key = base_key;
+                    key.K = P.K, key.L = P.L, key.P = PB, key.kind = GK_SEQ_ROUND;
+                    LPR_TRY(launch_graph(key, s, [&](hipStream_t cs) {
+                        return enqueue_seq_round<TH>(cs, D, Lw, B, P.K, P.L, PB, nullptr,
+                                                     nullptr);
+                    }));
+                } else {
+                    LPR_TRY(enqueue_seq_round<TH>(s, D, Lw, B, P.K, P.L, PB, &t_sweep,
+                                                  &t_bfs));
+                }
+                continue;
+            }
+            // asynchronous round: the global relabel of the last snapshot on
+            // stream sb beside the K sweeps on s, joined before the post step
+            hipEvent_t fork = ev[2 * r], join = ev[2 * r + 1];
+            LPR_TRY_HIP(hipEventRecord(fork, s));
+            LPR_TRY_HIP(hipStreamWaitEvent(sb, fork, 0));
+            if (use_graph) {
+                GraphKey kp = base_key;
+                kp.K = 0, kp.L = 0, kp.P = PB, kp.kind = GK_PASSES;
+                LPR_TRY(launch_graph(kp, sb, [&](hipStream_t cs) {
+                    return enqueue_passes<TH>(cs, D, Lw, PB, nullptr);
+                }));
             } else {
-                LPR_TRY(enqueue_round<TH>(s, D, Lw, grid, B, P.K, P.L, PB, &t_sweep,
-                                          &t_bfs));
+                LPR_TRY(enqueue_passes<TH>(sb, D, Lw, PB, &t_bfs_b));
+            }
+            LPR_TRY_HIP(hipEventRecord(join, sb));
+            if (use_graph) {
+                GraphKey ks = base_key;
+                ks.K = P.K, ks.L = P.L, ks.P = 0, ks.kind = GK_SWEEPS;
+                LPR_TRY(launch_graph(ks, s, [&](hipStream_t cs) {
+                    return enqueue_sweeps<TH>(cs, D, Lw, P.K, P.L, nullptr);
+                }));
+            } else {
+                LPR_TRY(enqueue_sweeps<TH>(s, D, Lw, P.K, P.L, &t_sweep));
+            }
+            LPR_TRY_HIP(hipStreamWaitEvent(s, join, 0));
+            if (use_graph) {
+                GraphKey kq = base_key;
+                kq.K = 0, kq.L = 0, kq.P = PB, kq.kind = GK_ARG_POST;
+                LPR_TRY(launch_graph(kq, s, [&](hipStream_t cs) {
+                    return enqueue_arg_post<TH>(cs, D, Lw, B, PB);
+                }));
+            } else {
+                LPR_TRY(enqueue_arg_post<TH>(s, D, Lw, B, PB));
             }
         }
-        LPR_TRY(read_scalars<TH>(s, Lw, &host));
-        if (host->pass_count[PB - 1] == 0) {
-            // passes this BFS needed: up to the first that marked no tile;
-            // later rounds get that plus a margin (lowered in steps of at
-            // least 4 so that few round graphs are captured)
-            int need = PB;
-            for (int i = 0; i < PB; ++i)
-                if (host->pass_count[i] == 0) {
-                    need = i + 1;
-                    break;
-                }
-            int next = std::max(4, need + 2);
+        LPR_TRY(read_scalars(s, Lw, &host, P.noalloc));
+        if (host->open_bfs > 0) {
+            // some global relabel needed more passes than the round carried:
+            // more passes for later rounds; past the slot count, finish an
+            // exact relabel under host control instead
+            if (PB >= MAX_PASS_SLOTS) {
+                LPR_TRY(exact_relabel());
+            } else {
+                PB = std::min(MAX_PASS_SLOTS, PB + std::max(4, PB / 2));
+                PB += PB & 1;
+                if (P.arg) LPR_TRY(fill_i32(Lw.sc->pass_count, 0, MAX_PASS_SLOTS, s));
+            }
+        } else if (host->max_need > 0) {
+            // converged relabels: keep a margin of 4 passes over the most
+            // needed (lowered in steps of at least 4, so that few graphs are
+            // captured)
+            int next = std::max(4, host->max_need + 4);
             next += next & 1;
-            if (next <= PB - 4) PB = next;
-        } else {
-            // the BFS needed more than PB passes: finish it, recount, and give
-            // the following rounds more passes
-            dirty_sel = 0;
-            LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, &dirty_sel, grid, t_bfs,
-                                          &bfs_passes));
-            LPR_TRY(enqueue_count<TH>(s, D, Lw, grid, B, nullptr));
-            LPR_TRY(read_scalars<TH>(s, Lw, &host));
-            PB = std::min(MAX_PASS_SLOTS, PB + 4);
+            if (next <= PB - 4) {
+                PB = next;
+                if (P.arg) LPR_TRY(fill_i32(Lw.sc->pass_count, 0, MAX_PASS_SLOTS, s));
+            }
         }
+        LPR_TRY(fill_i32(&Lw.sc->open_bfs, 0, 2, s));  // open_bfs, max_need
         LPR_TRY(t_bfs.harvest(&bfs_ms));
+        LPR_TRY(t_bfs_b.harvest(&bfs_ms));
         LPR_TRY(t_sweep.harvest(&sweep_ms));
     }
-    if (!converged) {
+    if (!host->all_done) {
         set_error("grid max-flow: round budget (%d) exhausted", P.max_rounds);
         return LPR_EBUDGET;
     }
+    const int64_t rounds = host->rounds;
     LPR_TRY(fill_i64(flow_values, 0, B, s));
-    Kern<TH>::flow(grid, s, D, flow_values);
+    Kern<TH>::flow(s, D, flow_values);
     LPR_TRY_HIP(hipGetLastError());
     if (side) {
         // every instance takes part in the closure
-        dirty_sel = 0;
         Kern<TH>::cut_seed(s, D, Lw.dirty[0], Lw.dirty[1]);
         LPR_TRY_HIP(hipGetLastError());
         EventTimer none(s);
-        LPR_TRY(relax_to_fixpoint<TH>(true, s, D, Lw, &dirty_sel, grid, none,
-                                      &cut_passes));
-        Kern<TH>::cut_write(grid, s, D, side);
+        LPR_TRY(relax_to_fixpoint<TH>(true, s, D, Lw, none, &cut_passes));
+        Kern<TH>::cut_write(s, D, side);
         LPR_TRY_HIP(hipGetLastError());
     }
     unsigned long long cnt[8];
@@ -1190,11 +1363,14 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
                                hipMemcpyDeviceToHost, s));
     LPR_TRY_HIP(hipStreamSynchronize(s));
     LPR_TRY(t_bfs.harvest(&bfs_ms));
+    LPR_TRY(t_bfs_b.harvest(&bfs_ms));
     LPR_TRY(t_sweep.harvest(&sweep_ms));
     if (stats) {
-        stats->rounds = rounds + 1;
-        stats->sweeps = sweeps;
-        stats->bfs_passes = bfs_passes;
+        // rounds counts the exact relabels too (the first one included);
+        // sweeps ran K per round after the first relabel
+        stats->rounds = rounds;
+        stats->sweeps = int64_t(P.K) * std::max<int64_t>(0, rounds - 1);
+        stats->bfs_passes = int64_t(cnt[6]);
         stats->cut_passes = cut_passes;
         stats->pushes = int64_t(cnt[0]);
         stats->relabels = int64_t(cnt[1]);
@@ -1207,6 +1383,8 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
         stats->relax_tile_rows = RELAX_TH;
         stats->sweep_ms = sweep_ms;
         stats->bfs_ms = bfs_ms;
+        stats->async_relabel = P.arg ? 1 : 0;
+        stats->rounds_per_check = R;
     }
     return LPR_OK;
 }
@@ -1220,6 +1398,8 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
 // ---------------------------------------------------------------------------
 struct Sched {
     int TH, L, K;
+    int arg;  // asynchronous global relabel
+    int R;    // rounds between host checks
 };
 
 static std::mutex g_sched_mu;
@@ -1234,7 +1414,8 @@ static int size_class(int64_t N) {
 
 static bool valid_sched(const Sched &s) {
     return (s.TH == 4 || s.TH == 8 || s.TH == 16 || s.TH == 32) && s.L >= 1 && s.L <= 4096 &&
-           s.K >= 1 && s.K <= 4096;
+           s.K >= 1 && s.K <= 4096 && (s.arg == 0 || s.arg == 1) && s.R >= 1 &&
+           s.R <= MAX_ROUNDS_PER_CHECK;
 }
 
 static void load_sched_file_locked() {
@@ -1246,7 +1427,7 @@ static void load_sched_file_locked() {
     if (!f) return;
     int c;
     Sched sc;
-    while (std::fscanf(f, "%d %d %d %d", &c, &sc.TH, &sc.L, &sc.K) == 4)
+    while (std::fscanf(f, "%d %d %d %d %d %d", &c, &sc.TH, &sc.L, &sc.K, &sc.arg, &sc.R) == 6)
         if (c >= 0 && c < 64 && valid_sched(sc)) g_sched[c] = sc;
     std::fclose(f);
 }
@@ -1260,7 +1441,7 @@ static Sched default_sched(int64_t N) {
     // (2.2 ms against 2.3-2.5 ms with 64 x 16), 64 x 16 tiles from 2^22
     // pixels on (the batched workload with a 2048 x 2048 grid: 14.9 ms
     // against 18.3 ms)
-    return N >= (int64_t(1) << 22) ? Sched{16, 16, 4} : Sched{8, 16, 4};
+    return N >= (int64_t(1) << 22) ? Sched{16, 16, 4, 0, 4} : Sched{8, 16, 4, 0, 4};
 }
 
 static void store_sched(int64_t N, const Sched &sc) {
@@ -1272,7 +1453,8 @@ static void store_sched(int64_t N, const Sched &sc) {
     FILE *f = std::fopen(path, "w");
     if (!f) return;
     for (const auto &e : g_sched)
-        std::fprintf(f, "%d %d %d %d\n", e.first, e.second.TH, e.second.L, e.second.K);
+        std::fprintf(f, "%d %d %d %d %d %d\n", e.first, e.second.TH, e.second.L, e.second.K,
+                     e.second.arg, e.second.R);
     std::fclose(f);
 }
 
@@ -1280,7 +1462,8 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
                       const int64_t *node_offset, const int32_t *const caps[6],
                       int64_t *flow_values, uint8_t *side,
                       const lpr_grid_opts *opts, lpr_grid_stats *stats,
-                      void *workspace, size_t ws_bytes, void *stream) {
+                      void *workspace, size_t ws_bytes, void *stream,
+                      bool noalloc = false) {
     clear_error();
     if (B < 1 || !H || !W || !node_offset) {
         set_error("invalid batch description");
@@ -1322,19 +1505,45 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     P.L = ds.L;
     P.K = ds.K;
     P.max_rounds = 1 << 16;
+    P.rounds_per_check = ds.R;
+    P.arg = ds.arg != 0;
     P.timing = false;
     P.no_graph = false;
+    P.noalloc = noalloc;
     if (opts) {
         if (opts->tile_rows) P.TH = opts->tile_rows;
         if (opts->local_iters) P.L = opts->local_iters;
         if (opts->sweeps_per_relabel) P.K = opts->sweeps_per_relabel;
         if (opts->max_rounds) P.max_rounds = opts->max_rounds;
+        if (opts->rounds_per_check) P.rounds_per_check = opts->rounds_per_check;
         P.timing = (opts->flags & LPR_GRID_TIME_KERNELS) != 0;
         P.no_graph = (opts->flags & LPR_GRID_NO_GRAPH) != 0;
+        if ((opts->flags & LPR_GRID_ASYNC_RELABEL) && (opts->flags & LPR_GRID_SYNC_RELABEL)) {
+            set_error("LPR_GRID_ASYNC_RELABEL and LPR_GRID_SYNC_RELABEL both set");
+            return LPR_EINVAL;
+        }
+        if (opts->flags & LPR_GRID_ASYNC_RELABEL) P.arg = true;
+        if (opts->flags & LPR_GRID_SYNC_RELABEL) P.arg = false;
+        if (opts->reserved[0] || opts->reserved[1]) {
+            set_error("lpr_grid_opts.reserved must be 0");
+            return LPR_EINVAL;
+        }
     }
     if (!(P.TH == 4 || P.TH == 8 || P.TH == 16 || P.TH == 32) || P.L < 1 || P.L > 4096 ||
-        P.K < 1 || P.K > 4096 || P.max_rounds < 1) {
+        P.K < 1 || P.K > 4096 || P.max_rounds < 1 || P.rounds_per_check < 1 ||
+        P.rounds_per_check > MAX_ROUNDS_PER_CHECK) {
         set_error("invalid lpr_grid_opts");
+        return LPR_EINVAL;
+    }
+    if (noalloc && (opts && (opts->flags & LPR_GRID_ASYNC_RELABEL))) {
+        set_error("LPR_GRID_ASYNC_RELABEL needs a library stream and events, which the "
+                  "allocation-free entry point does not create");
+        return LPR_EINVAL;
+    }
+    if (noalloc) P.arg = false;
+    if (noalloc && P.timing) {
+        set_error("LPR_GRID_TIME_KERNELS needs HIP events, which the "
+                  "allocation-free entry point does not create");
         return LPR_EINVAL;
     }
     const int64_t N = node_offset[B];
@@ -1379,6 +1588,8 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     D.rd = Lw.st[4];
     D.ru = Lw.st[5];
     D.rs = Lw.st[6];
+    D.lab = Lw.lab;
+    D.arcs = Lw.arcs;
     D.cap_src = caps[0];
     D.cap_snk = caps[1];
     D.cap_r = caps[2];
@@ -1388,7 +1599,8 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     D.inst = Lw.inst;
     D.tile_inst = Lw.tile_inst;
     D.tile_inst_r = Lw.tile_inst_r;
-    D.inst_active = Lw.inst_active;
+    D.inst_active = Lw.inst_cnt;
+    D.inst_exact = Lw.inst_cnt + B;
     D.done = Lw.done;
     D.counters = Lw.counters;
     D.sc = Lw.sc;
@@ -1405,8 +1617,14 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     key.T = int(T);
     key.TR = int(TR);
     key.TH = P.TH;
-    CallTimer call(s);
-    call.start();
+    // the call's HIP events (not on the allocation-free path, which times the
+    // call on the host clock instead)
+    std::optional<CallTimer> call;
+    if (!noalloc) {
+        call.emplace(s);
+        call->start();
+    }
+    const auto t0 = std::chrono::steady_clock::now();
     lpr_status st;
     switch (P.TH) {
         case 4:
@@ -1427,7 +1645,13 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
         return st;
     }
     double ms = 0;
-    LPR_TRY(call.stop_ms(&ms));
+    if (call) {
+        LPR_TRY(call->stop_ms(&ms));
+    } else {
+        LPR_TRY_HIP(hipStreamSynchronize(s));
+        ms = std::chrono::duration<double, std::milli>(
+                 std::chrono::steady_clock::now() - t0).count();
+    }
     if (stats) stats->total_ms = ms;
     return LPR_OK;
 }
@@ -1503,47 +1727,64 @@ extern "C" lpr_status lpr_grid_tune(int32_t B, const int32_t *H, const int32_t *
     static const int THs[4] = {4, 8, 16, 32};
     static const int Ls[4] = {4, 8, 16, 32};
     static const int Ks[3] = {2, 4, 8};
+    static const int Rs[4] = {1, 2, 4, 8};
     std::vector<int64_t> ref(B), got(B);
     hipStream_t s = static_cast<hipStream_t>(stream);
     double best_t = 1e300;
-    grid::Sched best_s{8, 16, 4};
+    grid::Sched best_s{8, 16, 4, 0, 4};
     bool have_ref = false;
-    for (int th : THs)
-        for (int l : Ls)
-            for (int k : Ks) {
-                lpr_grid_opts o{};
-                o.tile_rows = th;
-                o.local_iters = l;
-                o.sweeps_per_relabel = k;
-                double t_min = 1e300;
-                for (int r = 0; r <= reps; ++r) {  // the first run warms up
-                    lpr_grid_stats st{};
-                    LPR_TRY(grid::run(B, H, W, node_offset, caps, flow_values, nullptr,
-                                      &o, &st, workspace, workspace_bytes, stream));
-                    if (r > 0) t_min = std::min(t_min, st.total_ms);
-                }
-                LPR_TRY_HIP(hipMemcpyAsync(got.data(), flow_values, sizeof(int64_t) * B,
-                                           hipMemcpyDeviceToHost, s));
-                LPR_TRY_HIP(hipStreamSynchronize(s));
-                if (!have_ref) {
-                    ref = got;
-                    have_ref = true;
-                } else if (got != ref) {
-                    set_error("schedules disagree on a flow value (tile rows %d, "
-                              "local iterations %d, sweeps %d)", th, l, k);
-                    return LPR_EDEVICE;
-                }
-                if (t_min < best_t) {
-                    best_t = t_min;
-                    best_s = grid::Sched{th, l, k};
-                }
-            }
+    // one timed schedule: the fastest of `reps` runs after a warm-up, its
+    // flow values checked against the first schedule's
+    auto trial = [&](const grid::Sched &sc) -> lpr_status {
+        lpr_grid_opts o{};
+        o.tile_rows = sc.TH;
+        o.local_iters = sc.L;
+        o.sweeps_per_relabel = sc.K;
+        o.rounds_per_check = sc.R;
+        o.flags = sc.arg ? LPR_GRID_ASYNC_RELABEL : LPR_GRID_SYNC_RELABEL;
+        double t_min = 1e300;
+        for (int r = 0; r <= reps; ++r) {  // the first run warms up
+            lpr_grid_stats st{};
+            LPR_TRY(grid::run(B, H, W, node_offset, caps, flow_values, nullptr, &o, &st,
+                              workspace, workspace_bytes, stream));
+            if (r > 0) t_min = std::min(t_min, st.total_ms);
+        }
+        LPR_TRY_HIP(hipMemcpyAsync(got.data(), flow_values, sizeof(int64_t) * B,
+                                   hipMemcpyDeviceToHost, s));
+        LPR_TRY_HIP(hipStreamSynchronize(s));
+        if (!have_ref) {
+            ref = got;
+            have_ref = true;
+        } else if (got != ref) {
+            set_error("schedules disagree on a flow value (tile rows %d, local "
+                      "iterations %d, sweeps %d, asynchronous relabel %d, rounds "
+                      "per check %d)", sc.TH, sc.L, sc.K, sc.arg, sc.R);
+            return LPR_EDEVICE;
+        }
+        if (t_min < best_t) {
+            best_t = t_min;
+            best_s = sc;
+        }
+        return LPR_OK;
+    };
+    // stage 1: every tile height, local iteration count, sweep count and
+    // relabel mode at 4 rounds per check; stage 2: the check interval of
+    // the winner
+    for (int arg = 0; arg <= 1; ++arg)
+        for (int th : THs)
+            for (int l : Ls)
+                for (int k : Ks) LPR_TRY(trial(grid::Sched{th, l, k, arg, 4}));
+    const grid::Sched stage1 = best_s;
+    for (int r : Rs)
+        if (r != stage1.R) LPR_TRY(trial(grid::Sched{stage1.TH, stage1.L, stage1.K, stage1.arg, r}));
     grid::store_sched(node_offset[B], best_s);
     if (best) {
         *best = lpr_grid_opts{};
         best->tile_rows = best_s.TH;
         best->local_iters = best_s.L;
         best->sweeps_per_relabel = best_s.K;
+        best->rounds_per_check = best_s.R;
+        best->flags = best_s.arg ? LPR_GRID_ASYNC_RELABEL : LPR_GRID_SYNC_RELABEL;
     }
     if (best_ms) *best_ms = best_t;
     return LPR_OK;

@@ -32,6 +32,8 @@ LPR_ASSIGN_MAX_N = 2048
 LPR_ASSIGN_SPARSE_MAX_ARCS = 1 << 26
 LPR_GRID_TIME_KERNELS = 0x1
 LPR_GRID_NO_GRAPH = 0x2
+LPR_GRID_ASYNC_RELABEL = 0x4
+LPR_GRID_SYNC_RELABEL = 0x8
 LPR_ASSIGN_TIME_KERNELS = 0x1
 LPR_ASSIGN_NO_START_UPDATE = 0x2
 LPR_ASSIGN_ARC_FIXING = 0x4
@@ -67,7 +69,8 @@ class GridOpts(ctypes.Structure):
                 ("tile_rows", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32),
                 ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("rounds_per_check", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class GridStats(ctypes.Structure):
@@ -81,7 +84,9 @@ class GridStats(ctypes.Structure):
                 ("sweeps_per_relabel", ctypes.c_int32),
                 ("relax_tile_rows", ctypes.c_int32),
                 ("sweep_ms", ctypes.c_double), ("bfs_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double),
+                ("async_relabel", ctypes.c_int32),
+                ("rounds_per_check", ctypes.c_int32)]
 
 
 class AssignOpts(ctypes.Structure):
@@ -265,13 +270,14 @@ def _workspace(nbytes: int, device):
 # Grid max-flow
 # ---------------------------------------------------------------------------
 def make_grid_opts(sweeps_per_relabel=0, local_iters=0, tile_rows=0,
-                   max_rounds=0, flags=0) -> GridOpts:
+                   max_rounds=0, flags=0, rounds_per_check=0) -> GridOpts:
     o = GridOpts()
     o.sweeps_per_relabel = sweeps_per_relabel
     o.local_iters = local_iters
     o.tile_rows = tile_rows
     o.max_rounds = max_rounds
     o.flags = flags
+    o.rounds_per_check = rounds_per_check
     return o
 
 
@@ -362,7 +368,9 @@ def lpr_grid_tune(Hs, Ws, caps_packed, reps=2, workspace=None, stream=None):
                              ws.numel(), _stream(stream))
     _check(rc, "lpr_grid_tune")
     sched = {"tile_rows": best.tile_rows, "local_iters": best.local_iters,
-             "sweeps_per_relabel": best.sweeps_per_relabel}
+             "sweeps_per_relabel": best.sweeps_per_relabel,
+             "rounds_per_check": best.rounds_per_check,
+             "async_relabel": bool(best.flags & LPR_GRID_ASYNC_RELABEL)}
     return sched, ms.value, flows
 
 

@@ -4,6 +4,8 @@ Flow value and the minimal source side S_min are unique, so both must match
 the oracle exactly (int64 value, byte-for-byte side).  Sizes span several
 64 x TH tiles with ragged right and bottom tails; the full 1024 x 1024
 graph-cut workload runs in the benchmark's launch configuration (defaults).
+Most cases run under both relabel modes: the global relabel between the
+sweeps (Algorithm 4.8) and the asynchronous one beside them (ARG).
 """
 import numpy as np
 import pytest
@@ -17,6 +19,11 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 from paper_1110_6231_amd import lpr  # noqa: E402
+
+
+SYNC = lpr.LPR_GRID_SYNC_RELABEL
+ASYNC = lpr.LPR_GRID_ASYNC_RELABEL
+MODES = pytest.mark.parametrize("mode", [SYNC, ASYNC], ids=["sync", "async"])
 
 
 def gpu_solve(inst, opts=None, want_cut=True):
@@ -51,29 +58,46 @@ def test_uniform64_config(seed):
     check_against_oracle(synth.grid_uniform(64, 64, seed))
 
 
+@MODES
 @pytest.mark.parametrize("H,W", [(37, 70), (100, 129), (17, 200), (130, 65)])
 @pytest.mark.parametrize("tile_rows", [4, 8, 16, 32])
-def test_ragged_shapes_all_tiles(H, W, tile_rows):
+def test_ragged_shapes_all_tiles(H, W, tile_rows, mode):
     inst = synth.grid_random_small(H, W, seed=H + W, max_cap=40, max_term=60)
-    check_against_oracle(inst, lpr.make_grid_opts(tile_rows=tile_rows))
+    check_against_oracle(inst, lpr.make_grid_opts(tile_rows=tile_rows, flags=mode))
 
 
+@MODES
 @pytest.mark.parametrize("K,L", [(1, 1), (3, 2), (16, 64), (64, 4)])
-def test_schedules(K, L):
+def test_schedules(K, L, mode):
     inst = synth.grid_blobs(150, 170, seed=4)
     check_against_oracle(inst, lpr.make_grid_opts(sweeps_per_relabel=K,
-                                                  local_iters=L))
+                                                  local_iters=L, flags=mode))
 
 
-def test_rounds_without_graph_replay():
+@MODES
+@pytest.mark.parametrize("R", [1, 3, 16])
+def test_rounds_per_check(R, mode):
+    """Rounds enqueued between two reads of the device status: retired
+    instances and finished relabels turn the surplus rounds into no-ops."""
+    inst = synth.grid_blobs(210, 190, seed=8)
+    st = check_against_oracle(inst, lpr.make_grid_opts(rounds_per_check=R,
+                                                       flags=mode))
+    assert st["rounds_per_check"] == R
+    assert st["async_relabel"] == (1 if mode == ASYNC else 0)
+
+
+@MODES
+def test_rounds_without_graph_replay(mode):
     inst = synth.grid_blobs(180, 140, seed=6)
-    check_against_oracle(inst, lpr.make_grid_opts(flags=lpr.LPR_GRID_NO_GRAPH))
-    check_against_oracle(inst, lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS))
+    check_against_oracle(inst, lpr.make_grid_opts(flags=lpr.LPR_GRID_NO_GRAPH | mode))
+    check_against_oracle(inst, lpr.make_grid_opts(flags=lpr.LPR_GRID_TIME_KERNELS | mode))
 
 
-def test_blobs_medium_and_long_paths():
-    check_against_oracle(synth.grid_blobs(256, 300, seed=2))
-    check_against_oracle(synth.grid_blobs(200, 260, seed=3, pair_scale=200.0))
+@MODES
+def test_blobs_medium_and_long_paths(mode):
+    o = lpr.make_grid_opts(flags=mode)
+    check_against_oracle(synth.grid_blobs(256, 300, seed=2), o)
+    check_against_oracle(synth.grid_blobs(200, 260, seed=3, pair_scale=200.0), o)
 
 
 def test_closed_forms():
@@ -111,7 +135,8 @@ def test_chain_long_path():
     np.testing.assert_array_equal(side, want_side)
 
 
-def test_batched_matches_single():
+@MODES
+def test_batched_matches_single(mode):
     insts = [synth.grid_random_small(40 + 13 * k, 30 + 29 * k, seed=k,
                                      max_cap=30) for k in range(5)]
     insts.append(synth.grid_blobs(150, 200, seed=1))
@@ -123,7 +148,8 @@ def test_batched_matches_single():
             for f in ("cap_src", "cap_snk", "cap_right", "cap_left",
                       "cap_down", "cap_up")]
     print("[grid] batched", list(zip(Hs, Ws)), flush=True)
-    flows, side, st = lpr.lpr_grid_maxflow_batched(Hs, Ws, caps)
+    flows, side, st = lpr.lpr_grid_maxflow_batched(
+        Hs, Ws, caps, opts=lpr.make_grid_opts(flags=mode))
     flows = flows.cpu().numpy()
     side = side.cpu().numpy()
     off = 0
@@ -134,12 +160,13 @@ def test_batched_matches_single():
         off += inst.n_pixels
 
 
-def test_full_size_graph_cut_1024():
+@pytest.mark.parametrize("mode", [0, ASYNC], ids=["default", "async"])
+def test_full_size_graph_cut_1024(mode):
     """The 1024 x 1024 graph-cut workload at the benchmark's configuration:
     exact flow value and S_min against the oracle, and the cut certificate."""
     inst = synth.grid_blobs(1024, 1024, seed=0)
     want_v, want_side = oracle.grid_maxflow(inst, "fifo")
-    v, side, st = gpu_solve(inst)
+    v, side, st = gpu_solve(inst, lpr.make_grid_opts(flags=mode) if mode else None)
     print("[grid] 1024^2 stats", st, flush=True)
     assert v == want_v
     np.testing.assert_array_equal(side, want_side)
@@ -189,6 +216,16 @@ def test_errors():
                                                      sweeps_per_relabel=1,
                                                      local_iters=1))
     assert e.value.status == lpr.LPR_EBUDGET
+    for bad in (lpr.make_grid_opts(flags=SYNC | ASYNC),
+                lpr.make_grid_opts(rounds_per_check=17)):
+        with pytest.raises(lpr.LprError) as e:
+            lpr.lpr_grid_maxflow(20, 20, *inst.arrays(), opts=bad)
+        assert e.value.status == lpr.LPR_EINVAL
+    o = lpr.make_grid_opts()
+    o.reserved[1] = 3
+    with pytest.raises(lpr.LprError) as e:
+        lpr.lpr_grid_maxflow(20, 20, *inst.arrays(), opts=o)
+    assert e.value.status == lpr.LPR_EINVAL
     # the library stays usable after every error
     check_against_oracle(synth.grid_uniform(64, 64, seed=1))
 
@@ -200,7 +237,8 @@ def _pack(insts):
                       "cap_down", "cap_up")]
 
 
-def test_full_batched_workload_against_golden():
+@pytest.mark.parametrize("mode", [0, SYNC, ASYNC], ids=["default", "sync", "async"])
+def test_full_batched_workload_against_golden(mode):
     """The batched graph-cut workload: 64 blob grids with H, W in
     [128, 512] plus one 2048 x 2048 grid with pair weights x4, in one batched
     call, at the library's default schedule.  Flow values and S_min must
@@ -215,7 +253,8 @@ def test_full_batched_workload_against_golden():
     Ws = [i.W for i in insts]
     print("[grid] full batched workload", len(insts), sum(i.n_pixels for i in insts),
           flush=True)
-    flows, side, st = lpr.lpr_grid_maxflow_batched(Hs, Ws, _pack(insts))
+    flows, side, st = lpr.lpr_grid_maxflow_batched(
+        Hs, Ws, _pack(insts), opts=lpr.make_grid_opts(flags=mode) if mode else None)
     print("[grid] batched stats", st, flush=True)
     flows = flows.cpu().numpy()
     side = side.cpu().numpy()
