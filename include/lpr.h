@@ -179,6 +179,32 @@ lpr_status lpr_grid_maxflow(int32_t H, int32_t W,
                             void *workspace, size_t workspace_bytes,
                             void *stream);
 
+/*
+ * Allocation-free variant of lpr_grid_maxflow, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same network, arguments, outputs and errors as
+ * lpr_grid_maxflow, without the workspace: the solve's state lives in a
+ * device array of the library (lpr_grid_maxflow_noalloc_max_bytes() bytes,
+ * 40 MiB; one copy per GPU the library runs on, held until the process
+ * ends).  The call allocates no device or pinned host memory and creates no
+ * graph, stream or event; it still synchronises `stream` before it returns.
+ * It runs the global relabel between the sweeps (LPR_GRID_ASYNC_RELABEL and
+ * LPR_GRID_TIME_KERNELS give LPR_EINVAL: they need a stream or events).
+ * Limit: grids whose lpr_grid_maxflow_workspace(H, W) exceeds that size
+ * (about 1.25 M pixels; 1024 x 1024 fits) give LPR_ENOMEM.
+ * Concurrency: all calls on one GPU share its array; calls that overlap on
+ * one GPU (other threads or streams) race and give unspecified results.  A
+ * call needs nothing from the previous call's contents.
+ */
+size_t lpr_grid_maxflow_noalloc_max_bytes(void);
+lpr_status lpr_grid_maxflow_noalloc(int32_t H, int32_t W,
+                                    const int32_t *cap_src, const int32_t *cap_snk,
+                                    const int32_t *cap_right, const int32_t *cap_left,
+                                    const int32_t *cap_down, const int32_t *cap_up,
+                                    int64_t *flow_value, uint8_t *source_side,
+                                    const lpr_grid_opts *opts, lpr_grid_stats *stats,
+                                    void *stream);
+
 /* Device workspace bytes for lpr_grid_maxflow_batched (H, W: host [B]). */
 size_t lpr_grid_maxflow_batched_workspace(int32_t B, const int32_t *H,
                                           const int32_t *W);

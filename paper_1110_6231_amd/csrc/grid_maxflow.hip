@@ -1656,6 +1656,46 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     return LPR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free entry point: the workspace of one grid lives in `scratch`,
+// a device array of the library, so the call needs no caller workspace and
+// allocates nothing (no device or pinned memory, no graph, no event).  Every
+// GPU the library runs on holds its own copy until the process ends; calls
+// that overlap on one GPU share it and race.  Everything a solve reads is
+// written by that solve first (state, tables, flags, counters), so the
+// previous call's contents do no harm.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = size_t(40) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int MAX_SCRATCH_DEVICES = 64;
+
+// Device address of the calling device's `scratch` (looked up once per
+// device, with that device current; the array's name is a host-side stand-in
+// and is never passed to a kernel).
+static lpr_status scratch_ptr(void **out) {
+    static std::mutex mu;
+    static void *ptrs[MAX_SCRATCH_DEVICES] = {};
+    int dev = -1;
+    LPR_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_SCRATCH_DEVICES) {
+        set_error("device %d out of range for the allocation-free entry point", dev);
+        return LPR_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[dev]) {
+        void *p = nullptr;
+        LPR_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("hipGetSymbolAddress returned NULL for the scratch array");
+            return LPR_EDEVICE;
+        }
+        ptrs[dev] = p;
+    }
+    *out = ptrs[dev];
+    return LPR_OK;
+}
+
 }  // namespace grid
 }  // namespace lpr
 
@@ -1695,6 +1735,41 @@ extern "C" lpr_status lpr_grid_maxflow(int32_t H, int32_t W,
     }
     return grid::run(1, &H, &W, off, caps, flow_value, source_side, opts, stats,
                      workspace, workspace_bytes, stream);
+}
+
+extern "C" size_t lpr_grid_maxflow_noalloc_max_bytes(void) {
+    return grid::SCRATCH_BYTES;
+}
+
+extern "C" lpr_status lpr_grid_maxflow_noalloc(int32_t H, int32_t W,
+                                               const int32_t *cap_src,
+                                               const int32_t *cap_snk,
+                                               const int32_t *cap_right,
+                                               const int32_t *cap_left,
+                                               const int32_t *cap_down,
+                                               const int32_t *cap_up,
+                                               int64_t *flow_value,
+                                               uint8_t *source_side,
+                                               const lpr_grid_opts *opts,
+                                               lpr_grid_stats *stats, void *stream) {
+    const int32_t *caps[6] = {cap_src, cap_snk, cap_right, cap_left, cap_down, cap_up};
+    const int64_t off[2] = {0, int64_t(H) * W};
+    clear_error();
+    if (H < 1 || W < 1) {
+        set_error("bad shape %d x %d", H, W);
+        return LPR_EINVAL;
+    }
+    const size_t need = grid::workspace_bytes(1, &H, &W);
+    if (need > grid::SCRATCH_BYTES) {
+        set_error("a %d x %d grid needs %zu bytes of scratch; the allocation-free "
+                  "entry point holds %zu (grids of up to about 1.25 M pixels)",
+                  H, W, need, grid::SCRATCH_BYTES);
+        return LPR_ENOMEM;
+    }
+    void *ws = nullptr;
+    LPR_TRY(grid::scratch_ptr(&ws));
+    return grid::run(1, &H, &W, off, caps, flow_value, source_side, opts, stats, ws,
+                     grid::SCRATCH_BYTES, stream, /*noalloc=*/true);
 }
 
 extern "C" lpr_status lpr_grid_maxflow_batched(

@@ -42,6 +42,7 @@ LPR_ASSIGN_ARC_FIXING = 0x4
 EXPORTED = [
     "lpr_last_error", "lpr_version",
     "lpr_grid_maxflow_workspace", "lpr_grid_maxflow",
+    "lpr_grid_maxflow_noalloc_max_bytes", "lpr_grid_maxflow_noalloc",
     "lpr_grid_maxflow_batched_workspace", "lpr_grid_maxflow_batched",
     "lpr_grid_tune",
     "lpr_assign_workspace", "lpr_assign_solve",
@@ -163,6 +164,11 @@ def lib():
     L.lpr_grid_maxflow.restype = ctypes.c_int
     L.lpr_grid_maxflow.argtypes = [i32, i32] + [vp] * 6 + [
         vp, vp, ctypes.POINTER(GridOpts), ctypes.POINTER(GridStats), vp, sz, vp]
+    L.lpr_grid_maxflow_noalloc_max_bytes.restype = sz
+    L.lpr_grid_maxflow_noalloc_max_bytes.argtypes = []
+    L.lpr_grid_maxflow_noalloc.restype = ctypes.c_int
+    L.lpr_grid_maxflow_noalloc.argtypes = [i32, i32] + [vp] * 6 + [
+        vp, vp, ctypes.POINTER(GridOpts), ctypes.POINTER(GridStats), vp]
     L.lpr_grid_maxflow_batched_workspace.restype = sz
     L.lpr_grid_maxflow_batched_workspace.argtypes = [i32, i32p, i32p]
     L.lpr_grid_maxflow_batched.restype = ctypes.c_int
@@ -310,6 +316,27 @@ def lpr_grid_maxflow(H, W, cap_src, cap_snk, cap_right, cap_left, cap_down,
         _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "lpr_grid_maxflow")
     return int(flow.item()), side, _struct_dict(st)
+
+
+def lpr_grid_maxflow_noalloc_max_bytes() -> int:
+    return int(lib().lpr_grid_maxflow_noalloc_max_bytes())
+
+
+def lpr_grid_maxflow_noalloc(H, W, caps, flow, side, opts: GridOpts | None = None,
+                             stream=None):
+    """The allocation-free entry point (lpr_grid_maxflow_noalloc).  The
+    caller passes the six int32 capacity tensors and the outputs already on
+    the device (flow: int64 [1]; side: uint8 [H*W] or None); nothing is
+    allocated here.  Returns the stats dict."""
+    for c in caps:
+        assert c.numel() == H * W and c.is_contiguous()
+    st = GridStats()
+    rc = lib().lpr_grid_maxflow_noalloc(
+        H, W, *[_ptr(c) for c in caps], _ptr(flow), _ptr(side),
+        ctypes.byref(opts) if opts is not None else None, ctypes.byref(st),
+        _stream(stream))
+    _check(rc, "lpr_grid_maxflow_noalloc")
+    return _struct_dict(st)
 
 
 def lpr_grid_maxflow_batched_workspace(Hs, Ws) -> int:
