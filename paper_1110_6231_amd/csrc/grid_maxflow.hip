@@ -136,22 +136,26 @@ struct Scalars {
     int32_t rounds;     // finished rounds that still had an unretired instance
     int32_t open_bfs;   // global relabels that needed more passes than they had
     int32_t max_need;   // most passes a converged global relabel needed
-    int32_t pad;
-    int32_t pass_count[MAX_PASS_SLOTS];
+    int32_t seed_count; // entries of the first relaxation list of a relabel
+    int32_t act_cnt[3]; // entries of the three active-tile lists of the sweeps
+    int32_t pass_count[MAX_PASS_SLOTS];  // entries each relaxation pass listed
 };
 
-// Snapshot byte of a pixel: its arcs with residual capacity and whether it
-// holds excess, taken at a round boundary.  A global relabel works on these
-// bytes only, so it computes the exact BFS of the state at the snapshot even
-// while push sweeps change the live state.
-constexpr uint8_t AR_R = 1, AR_L = 2, AR_D = 4, AR_U = 8, AR_T = 16, AR_E = 32;
+// Snapshot of the residual network taken at a round boundary, as bit masks:
+// for every 64 x 32 relaxation tile and every column c of it, one 32-bit word
+// per mask (bit r = row r of the tile): arc to the right, left, down and up
+// neighbour with residual capacity, arc to t, and excess.  A global relabel
+// reads only these words, so it computes the exact BFS of the state at the
+// snapshot even while push sweeps change the live state.
+constexpr int NMASK = 6;
+constexpr int MK_R = 0, MK_L = 1, MK_D = 2, MK_U = 3, MK_T = 4, MK_E = 5;
 // Round-boundary steps (k_boundary)
 constexpr unsigned BD_ADOPT = 1, BD_COUNT = 2, BD_SNAPSHOT = 4;
 
 struct Dev {
     int32_t *e, *h, *rr, *rl, *rd, *ru, *rs;
     int32_t *lab;       // labels of the global relabel (and of the cut closure)
-    uint8_t *arcs;      // snapshot bytes (AR_*)
+    uint32_t *amask;    // snapshot masks: [relaxation tile][NMASK][64 columns]
     const int32_t *cap_src, *cap_snk, *cap_r, *cap_l, *cap_d, *cap_u;
     const Inst *inst;
     const int32_t *tile_inst;    // instance of every sweep tile (64 x TH)
@@ -165,9 +169,16 @@ struct Dev {
                                       // device-scope atomics of the sweeps,
                                       // BFS passes that relaxed a tile
     Scalars *sc;
+    // Work lists, three of each (a launch reads one, appends to the next and
+    // may clear the third): a flag per tile (listed or not) and the list.
+    int32_t *act[3], *alist[3];    // sweep tiles with work
+    int32_t *dirty[3], *dlist[3];  // relaxation tiles to relax
     int32_t ntiles, ntiles_r;
     int32_t ninst;
 };
+
+__device__ __forceinline__ int next3(int i) { return i == 2 ? 0 : i + 1; }
+__device__ __forceinline__ int prev3(int i) { return i == 0 ? 2 : i - 1; }
 
 struct Geo {
     int inst, H, W, HV, y0, x0, tx, ty, tiles_x, tiles_y;
@@ -193,20 +204,6 @@ __device__ inline Geo tile_geo(const Dev &D, int t) {
     g.y0 = g.ty * TH;
     g.x0 = g.tx * TW;
     return g;
-}
-
-// Tile of the calling wavefront in the wave-per-tile kernels (four tiles per
-// 256-thread workgroup).  Workgroups are dispatched to the eight XCDs round
-// robin, so workgroup b takes tile group (its XCD's first group + b / 8): each
-// XCD gets one contiguous band of tiles, whose vertical neighbours share that
-// XCD's L2.
-__device__ __forceinline__ int block_group() {
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int q = nb >> 3, rem = nb & 7, xcd = b & 7;
-    return xcd * q + min(xcd, rem) + (b >> 3);
-}
-__device__ __forceinline__ int wave_tile() {
-    return block_group() * 4 + (threadIdx.x >> 6);
 }
 
 __device__ inline unsigned long long block_sum_u64(unsigned long long v) {
@@ -259,34 +256,48 @@ __global__ __launch_bounds__(NT) void k_init(Dev D) {
 }
 
 // ---------------------------------------------------------------------------
-// Round boundary, over the push-sweep tiling.  Per pixel, in this order:
+// Round boundary, over the relaxation tiling (64 x 32, four wavefronts of
+// eight rows).  Per pixel, in this order:
 //  ADOPT     h = lab: the heights of the next push sweeps are the levels of
 //            the global relabel just finished (Algorithm 4.4, with the gap:
 //            unreached pixels keep |V|).
 //  COUNT     the exact count of the state the labels belong to: pixels whose
 //            snapshot held excess and that reach t (lab < |V|); and the
-//            activity the next sweeps start from: e > 0 and h < |V| with the
-//            current excess.  Sets the active-tile flags of the next sweep.
-//  SNAPSHOT  the snapshot byte (residual arcs, arc to t, excess) and the seed
-//            of the next global relabel: lab = 1 where u_f(p, t) > 0, |V|
-//            elsewhere; marks the relaxation tile dirty.
+//            activity the next push sweeps start from: e > 0 and h < |V| with
+//            the current excess.  Lists every sweep tile (64 x TH) with an
+//            active pixel as the sweeps' first list (buffer 0; the three
+//            counts are 0 beforehand) and clears the other flags.
+//  SNAPSHOT  the snapshot masks and the seed of the next global relabel
+//            (lab = 1 where u_f(p, t) > 0, |V| elsewhere); lists the tile as
+//            the relabel's first list (every dirty flag and seed_count are 0
+//            beforehand).
 // Retired instances are left untouched: no active or dirty flag.
 // ---------------------------------------------------------------------------
 template <int TH>
-__global__ __launch_bounds__(NT) void k_boundary(Dev D, int32_t *act_cur, int32_t *act_next,
-                                                 int32_t *dirty_cur, int32_t *dirty_next,
-                                                 unsigned mode) {
-    const int t = blockIdx.x;
-    const Geo g = tile_geo<TH>(D, t);
+__global__ __launch_bounds__(NT) void k_boundary(Dev D, unsigned mode) {
+    static_assert(RELAX_TH % TH == 0, "sweep tiles nest in relaxation tiles");
+    constexpr int RWB = RELAX_TH / 4;  // rows per wavefront
+    const int rt = blockIdx.x;
+    const Geo g = tile_geo<RELAX_TH, true>(D, rt);
     const bool retired = D.done[g.inst] != 0;  // workgroup-uniform
-    const int c = threadIdx.x & (TW - 1);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int x = g.x0 + lane;
+    __shared__ uint32_t smask[NMASK][TW];
+    __shared__ uint32_t s_rows;
+    for (int i = threadIdx.x; i < NMASK * TW; i += NT) (&smask[0][0])[i] = 0;
+    if (threadIdx.x == 0) s_rows = 0;
+    uint32_t *tm = D.amask + size_t(rt) * NMASK * TW;
+    // the excess mask of the previous snapshot, read before it is replaced
+    const uint32_t oldE = (mode & BD_COUNT) ? tm[MK_E * TW + lane] : 0u;
+    __syncthreads();
     unsigned long long n_exact = 0, n_act = 0;
-    if (!retired) {
+    uint32_t my[NMASK] = {0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t act_rows = 0;
+    if (!retired && x < g.W) {
 #pragma unroll
-        for (int k = 0; k < TH / RPP; ++k) {
-            const int r = (threadIdx.x >> 6) + RPP * k;
-            const int y = g.y0 + r, x = g.x0 + c;
-            if (y >= g.H || x >= g.W) continue;
+        for (int i = 0; i < RWB; ++i) {
+            const int r = w * RWB + i, y = g.y0 + r;
+            if (y >= g.H) break;
             const int64_t p = g.off + int64_t(y) * g.W + x;
             const int32_t ev = D.e[p];
             int32_t hv = 0;
@@ -297,46 +308,68 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D, int32_t *act_cur, int32_
                 hv = D.h[p];
             }
             if (mode & BD_COUNT) {
-                n_exact += ((D.arcs[p] & AR_E) && hv < g.HV) ? 1 : 0;
-                n_act += (ev > 0 && hv < g.HV) ? 1 : 0;
+                n_exact += (((oldE >> r) & 1u) && hv < g.HV) ? 1 : 0;
+                const bool a = ev > 0 && hv < g.HV;
+                n_act += a ? 1 : 0;
+                act_rows |= uint32_t(a) << r;
             }
             if (mode & BD_SNAPSHOT) {
                 const int32_t rs = D.rs[p];
-                const int b = (D.rr[p] > 0 ? AR_R : 0) | (D.rl[p] > 0 ? AR_L : 0) |
-                              (D.rd[p] > 0 ? AR_D : 0) | (D.ru[p] > 0 ? AR_U : 0) |
-                              (rs > 0 ? AR_T : 0) | (ev > 0 ? AR_E : 0);
-                D.arcs[p] = uint8_t(b);
+                my[MK_R] |= uint32_t(D.rr[p] > 0) << r;
+                my[MK_L] |= uint32_t(D.rl[p] > 0) << r;
+                my[MK_D] |= uint32_t(D.rd[p] > 0) << r;
+                my[MK_U] |= uint32_t(D.ru[p] > 0) << r;
+                my[MK_T] |= uint32_t(rs > 0) << r;
+                my[MK_E] |= uint32_t(ev > 0) << r;
                 D.lab[p] = rs > 0 ? 1 : g.HV;
             }
         }
+    }
+    if (mode & BD_SNAPSHOT) {
+#pragma unroll
+        for (int m = 0; m < NMASK; ++m)
+            if (my[m]) atomicOr(&smask[m][lane], my[m]);
+    }
+    if (act_rows) atomicOr(&s_rows, act_rows);
+    __syncthreads();
+    if ((mode & BD_SNAPSHOT) && !retired) {
+        for (int i = threadIdx.x; i < NMASK * TW; i += NT) tm[i] = (&smask[0][0])[i];
+        if (threadIdx.x == 0 && atomicExch(&D.dirty[0][rt], 1) == 0)
+            D.dlist[0][atomicAdd(&D.sc->seed_count, 1)] = rt;
     }
     if (mode & BD_COUNT) {
         const unsigned long long se = block_sum_u64(n_exact);
         const unsigned long long sa = block_sum_u64(n_act);
         if (threadIdx.x == 0) {
-            act_cur[t] = sa > 0 ? 1 : 0;
-            act_next[t] = 0;
             if (se) atomicAdd(&D.inst_exact[g.inst], se);
             if (sa) atomicAdd(&D.inst_active[g.inst], sa);
+            // the sweep tiles this tile holds: rows k*TH .. k*TH + TH - 1
+            const Inst I = D.inst[g.inst];
+            const uint32_t rows = s_rows;
+            constexpr uint32_t SEG = TH >= 32 ? 0xFFFFFFFFu : ((1u << (TH & 31)) - 1u);
+            for (int k = 0; k < RELAX_TH / TH; ++k) {
+                if (g.y0 + k * TH >= g.H) break;
+                const int st = I.tile_base + (g.ty * (RELAX_TH / TH) + k) * g.tiles_x + g.tx;
+                const bool a = ((rows >> (k * TH)) & SEG) != 0;
+                D.act[0][st] = a ? 1 : 0;
+                D.act[1][st] = 0;
+                D.act[2][st] = 0;
+                if (a) D.alist[0][atomicAdd(&D.sc->act_cnt[0], 1)] = st;
+            }
         }
-    }
-    if ((mode & BD_SNAPSHOT) && threadIdx.x == 0) {
-        // the relaxation tile holding this tile (TH divides RELAX_TH)
-        const int rt = D.inst[g.inst].tile_base_r + (g.y0 / RELAX_TH) * g.tiles_x + g.tx;
-        dirty_cur[rt] = retired ? 0 : 1;
-        dirty_next[rt] = 0;
     }
 }
 
-// Cut-closure seed: label 0 for pixels holding excess, |V| elsewhere.
+// Cut-closure seed: label 0 for pixels holding excess, |V| elsewhere; every
+// relaxation tile is listed (every dirty flag and seed_count are 0
+// beforehand).
 template <int TH>
-__global__ __launch_bounds__(NT) void k_cut_seed(Dev D, int32_t *dirty_cur,
-                                                 int32_t *dirty_next) {
+__global__ __launch_bounds__(NT) void k_cut_seed(Dev D) {
     const int t = blockIdx.x;
     const Geo g = tile_geo<TH, true>(D, t);
     if (threadIdx.x == 0) {
-        dirty_cur[t] = 1;
-        dirty_next[t] = 0;
+        D.dirty[0][t] = 1;
+        D.dlist[0][atomicAdd(&D.sc->seed_count, 1)] = t;
     }
     const int c = threadIdx.x & (TW - 1);
 #pragma unroll
@@ -368,14 +401,15 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 //   BFS (CUT = false): lab(p) = min(lab(p), lab(q) + 1) over arcs p->q with
 //     u_f > 0 in the snapshot -- the backward BFS of Algorithm 4.4 from t;
 //     its least fixpoint is the BFS level, |V| where t is unreachable (the
-//     gap of Section 4.2).  It reads the snapshot bytes, never the live
+//     gap of Section 4.2).  It reads the snapshot masks, never the live
 //     residuals, so push sweeps may run meanwhile.
 //   CUT (CUT = true):  lab(p) = min(lab(p), lab(q)) over arcs q->p with
-//     u_f > 0 -- forward reachability from the excess pixels.
+//     u_f > 0 -- forward reachability from the excess pixels (the run has
+//     stopped; live residuals).
 // Labels only decrease and every value read from a neighbouring tile is an
 // upper bound of its final value, so concurrent tiles reach the same least
-// fixpoint; tiles whose edge labels changed mark their neighbours dirty for
-// the next pass.
+// fixpoint; tiles whose edge labels changed put their neighbours on the
+// next pass's list.
 //
 // A pass runs on 64 x 32 tiles, four wavefronts per tile (one workgroup):
 // wavefront w holds rows 8w .. 8w+7 in registers (lane c owns column c) and
@@ -386,29 +420,33 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 // are exchanged through LDS and the four relax again until a workgroup vote
 // finds no lowered boundary.  A label thus crosses 32 rows in one pass, with
 // the latency of an 8-row tile per wavefront.
+//
+// Work list: the pass relaxes the tiles of list `cur` (cnt_cur entries;
+// workgroup b takes entry b, so the tiles spread over the whole chip however
+// they cluster on the grid) and appends the neighbours whose halo changed to
+// the next list, once each (the flag), counting them in cnt_next.  A pass
+// whose list is empty returns at once, so a round can carry more passes than
+// its global relabel needs at little cost.
+// ---------------------------------------------------------------------------
 constexpr int RW = 8;  // rows per wavefront of the cooperative relaxation
 
-// A pass whose predecessor marked no tile (prev_count = 0) has nothing to do
-// and returns at once, so a round can carry more passes than its global
-// relabel needs at little cost.
 template <bool CUT>
-__global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
-                                               int32_t *dirty_next,
-                                               int32_t *pass_count,
-                                               const int32_t *prev_count) {
+__global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *cnt_cur,
+                                               int32_t *cnt_next) {
     static_assert(RELAX_TH == 4 * RW, "four wavefronts per relaxation tile");
-    if (prev_count && *prev_count == 0) return;  // grid-uniform
+    const int n = *cnt_cur;
+    if (int(blockIdx.x) >= n) return;         // workgroup-uniform
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int t = block_group();
-    if (t >= D.ntiles_r) return;              // workgroup-uniform
-    if (!CUT && t == 0 && threadIdx.x == 0) atomicAdd(&D.counters[6], 1ull);
-    const int flag = dirty_cur[t];
+    if (!CUT && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&D.counters[6], 1ull);
+    const int t = D.dlist[cur][blockIdx.x];
+    const int nxt = next3(cur);
     __shared__ int32_t edge[4][2][64];        // row 0 and row 7 of each wavefront
     __shared__ int s_ch;
-    if (threadIdx.x == 0) s_ch = 0;
-    __syncthreads();                          // every thread has read the flag
-    if (flag == 0) return;                    // workgroup-uniform
-    if (threadIdx.x == 0) dirty_cur[t] = 0;
+    if (threadIdx.x == 0) {
+        s_ch = 0;
+        D.dirty[cur][t] = 0;
+    }
+    __syncthreads();
     const Geo g = tile_geo<RELAX_TH, true>(D, t);
     constexpr int INC = CUT ? 0 : 1;
     const int HV = g.HV;
@@ -417,6 +455,15 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
     const int yw = g.y0 + RW * w;             // first row of this wavefront
     int32_t d[RW], d0[RW];
     uint32_t mR = 0, mL = 0, mD = 0, mU = 0;  // bit r: arc usable in row r
+    if (!CUT) {
+        // this wavefront's eight rows of the column's snapshot masks
+        const uint32_t *tm = D.amask + size_t(t) * NMASK * TW + lane;
+        const int sh = RW * w;
+        mR = (tm[MK_R * TW] >> sh) & 0xFFu;
+        mL = (tm[MK_L * TW] >> sh) & 0xFFu;
+        mD = (tm[MK_D * TW] >> sh) & 0xFFu;
+        mU = (tm[MK_U * TW] >> sh) & 0xFFu;
+    }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         const int y = yw + r;
@@ -424,13 +471,8 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
         if (colv && y < g.H) {
             const int64_t p = g.off + int64_t(y) * g.W + x;
             d[r] = D.lab[p];
-            if (!CUT) {
-                const uint32_t b = D.arcs[p];
-                mR |= ((b & AR_R) ? 1u : 0u) << r;
-                mL |= ((b & AR_L) ? 1u : 0u) << r;
-                mD |= ((b & AR_D) ? 1u : 0u) << r;
-                mU |= ((b & AR_U) ? 1u : 0u) << r;
-            } else {
+            if (CUT) {
+                // arcs into p: from the right neighbour (its left arc), etc.
                 if (x + 1 < g.W) mR |= uint32_t(D.rl[p + 1] > 0) << r;
                 if (x > 0) mL |= uint32_t(D.rr[p - 1] > 0) << r;
                 if (y + 1 < g.H) mD |= uint32_t(D.ru[p + g.W] > 0) << r;
@@ -539,8 +581,8 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int32_t *dirty_cur,
         if ((bits & 4) && g.ty + 1 < g.tiles_y) nb[2] = t + g.tiles_x;
         if ((bits & 8) && g.ty > 0) nb[3] = t - g.tiles_x;
         for (int i = 0; i < 4; ++i)
-            if (nb[i] >= 0 && atomicExch(&dirty_next[nb[i]], 1) == 0)
-                atomicAdd(pass_count, 1);
+            if (nb[i] >= 0 && atomicExch(&D.dirty[nxt][nb[i]], 1) == 0)
+                D.dlist[nxt][atomicAdd(cnt_next, 1)] = nb[i];
     }
 }
 
@@ -627,14 +669,19 @@ __global__ void k_finish(Dev D, const int32_t *pass_count, int P) {
 // only shrink by their owner's pushes, heights only grow between global
 // relabels), the staleness Hong's argument admits.
 // ---------------------------------------------------------------------------
+// Work list: the launch reads list `cur` (wavefront i takes entry i, so the
+// active tiles spread one per SIMD over the chip however they cluster on the
+// grid), appends the tiles to visit next to the next list (once each: the
+// flag) and clears the count of the third, which the launch before read.
 template <int TH>
-__global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
-                                              int32_t *act_next, int L) {
+__global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
     const int lane = threadIdx.x & 63;
-    const int t = wave_tile();
-    if (t >= D.ntiles) return;           // wave-uniform
-    if (act_cur[t] == 0) return;         // wave-uniform (same address)
-    if (lane == 0) act_cur[t] = 0;
+    const int nxt = next3(cur);
+    if (blockIdx.x == 0 && threadIdx.x == 0) D.sc->act_cnt[prev3(cur)] = 0;
+    const int i = int(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (i >= D.sc->act_cnt[cur]) return;  // wave-uniform
+    const int t = D.alist[cur][i];
+    if (lane == 0) D.act[cur][t] = 0;
     const Geo g = tile_geo<TH>(D, t);
     const int HV = g.HV;
     const int x = g.x0 + lane;
@@ -823,11 +870,11 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int32_t *act_cur,
     const bool a_l = __any(touch_l), a_r = __any(touch_r);
     const bool a_u = __any(touch_u), a_d = __any(touch_d);
     if (lane == 0) {
-        if (a_end) act_next[t] = 1;
-        if (a_l) act_next[t - 1] = 1;
-        if (a_r) act_next[t + 1] = 1;
-        if (a_u) act_next[t - g.tiles_x] = 1;
-        if (a_d) act_next[t + g.tiles_x] = 1;
+        const int nb[5] = {a_end ? t : -1, a_l ? t - 1 : -1, a_r ? t + 1 : -1,
+                           a_u ? t - g.tiles_x : -1, a_d ? t + g.tiles_x : -1};
+        for (int k = 0; k < 5; ++k)
+            if (nb[k] >= 0 && atomicExch(&D.act[nxt][nb[k]], 1) == 0)
+                D.alist[nxt][atomicAdd(&D.sc->act_cnt[nxt], 1)] = nb[k];
         if (pushes) atomicAdd(&D.counters[0], pushes);
         if (relabels) atomicAdd(&D.counters[1], relabels);
         atomicAdd(&D.counters[2], 1ull);
@@ -860,8 +907,11 @@ __global__ __launch_bounds__(NT) void k_flow_value(Dev D, int64_t *flow) {
 struct Layout {
     int32_t *st[7];
     int32_t *lab;
-    uint8_t *arcs;
-    int32_t *tile_inst, *tile_inst_r, *act[2], *dirty[2], *done;
+    uint32_t *amask;
+    int32_t *tile_inst, *tile_inst_r, *done;
+    int32_t *act[3], *alist[3];  // sweep work lists (flags, entries)
+    int32_t *dirty_all;          // the three relaxation flag arrays, back to back
+    int32_t *dlist[3];
     Inst *inst;
     unsigned long long *inst_cnt;  // active [B], then exact [B]
     unsigned long long *counters;
@@ -871,13 +921,15 @@ struct Layout {
 static Carver carve(Carver cv, int64_t N, int64_t T, int64_t TR, int B, Layout *L) {
     for (int i = 0; i < 7; ++i) L->st[i] = cv.take<int32_t>(size_t(N));
     L->lab = cv.take<int32_t>(size_t(N));
-    L->arcs = cv.take<uint8_t>(size_t(N));
+    L->amask = cv.take<uint32_t>(size_t(TR) * NMASK * TW);
     L->tile_inst = cv.take<int32_t>(size_t(T));
     L->tile_inst_r = cv.take<int32_t>(size_t(TR));
-    L->act[0] = cv.take<int32_t>(size_t(T));
-    L->act[1] = cv.take<int32_t>(size_t(T));
-    L->dirty[0] = cv.take<int32_t>(size_t(TR));
-    L->dirty[1] = cv.take<int32_t>(size_t(TR));
+    for (int i = 0; i < 3; ++i) {
+        L->act[i] = cv.take<int32_t>(size_t(T));
+        L->alist[i] = cv.take<int32_t>(size_t(T));
+        L->dlist[i] = cv.take<int32_t>(size_t(TR));
+    }
+    L->dirty_all = cv.take<int32_t>(size_t(3) * TR);
     L->inst = cv.take<Inst>(size_t(B));
     L->inst_cnt = cv.take<unsigned long long>(size_t(2) * B);
     L->done = cv.take<int32_t>(size_t(B));
@@ -907,23 +959,22 @@ struct Kern {
     static void init(hipStream_t s, const Dev &D) {
         hipLaunchKernelGGL(k_init<TH>, dim3(D.ntiles), dim3(NT), 0, s, D);
     }
-    static void boundary(hipStream_t s, const Dev &D, const Layout &Lw, unsigned mode) {
-        hipLaunchKernelGGL(k_boundary<TH>, dim3(D.ntiles), dim3(NT), 0, s, D, Lw.act[0],
-                           Lw.act[1], Lw.dirty[0], Lw.dirty[1], mode);
+    static void boundary(hipStream_t s, const Dev &D, unsigned mode) {
+        hipLaunchKernelGGL(k_boundary<TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D, mode);
     }
     // the relaxation kernels run on the RELAX_TH tiling, one 4-wavefront
-    // workgroup per tile
-    static void cut_seed(hipStream_t s, const Dev &D, int32_t *a, int32_t *b) {
-        hipLaunchKernelGGL(k_cut_seed<RELAX_TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D, a, b);
+    // workgroup per listed tile
+    static void cut_seed(hipStream_t s, const Dev &D) {
+        hipLaunchKernelGGL(k_cut_seed<RELAX_TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D);
     }
-    static void relax(bool cut, hipStream_t s, const Dev &D, int32_t *a, int32_t *b,
-                      int32_t *pc, const int32_t *prev) {
+    static void relax(bool cut, hipStream_t s, const Dev &D, int cur, const int32_t *cnt_cur,
+                      int32_t *cnt_next) {
         const dim3 gw(D.ntiles_r);
-        if (cut) hipLaunchKernelGGL((k_relax4<true>), gw, dim3(NT), 0, s, D, a, b, pc, prev);
-        else hipLaunchKernelGGL((k_relax4<false>), gw, dim3(NT), 0, s, D, a, b, pc, prev);
+        if (cut) hipLaunchKernelGGL((k_relax4<true>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
+        else hipLaunchKernelGGL((k_relax4<false>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
     }
-    static void sweep(hipStream_t s, const Dev &D, int32_t *a, int32_t *b, int L) {
-        hipLaunchKernelGGL(k_sweep<TH>, dim3((D.ntiles + 3) / 4), dim3(NT), 0, s, D, a, b, L);
+    static void sweep(hipStream_t s, const Dev &D, int cur, int L) {
+        hipLaunchKernelGGL(k_sweep<TH>, dim3((D.ntiles + 3) / 4), dim3(NT), 0, s, D, cur, L);
     }
     static void flow(hipStream_t s, const Dev &D, int64_t *f) {
         hipLaunchKernelGGL(k_flow_value<TH>, dim3(D.ntiles), dim3(NT), 0, s, D, f);
@@ -941,28 +992,30 @@ struct Params {
     bool noalloc;  // allocation-free call: no graphs, events, streams or pinned memory
 };
 
-// Runs relaxation passes until no tile is dirty (host checks once per batch
-// of passes; a pass after one that marked nothing returns at once).
+// Runs relaxation passes from the seeded list 0 until a pass lists no tile
+// (host checks once per batch of passes; a pass after one that listed
+// nothing returns at once).  A batch starts from the count the last one
+// ended with, carried in seed_count.
+__global__ void k_carry(int32_t *dst, const int32_t *src) { *dst = *src; }
+
 template <int TH>
 static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
                                     Layout &Lw, EventTimer &tm, int64_t *passes) {
     int batch = 8;
-    int sel = 0;
+    int64_t g = 0;  // passes so far: pass g reads list g mod 3
     const int64_t guard = 16 * int64_t(D.ntiles_r) + 1024;
-    for (int64_t done_passes = 0;; done_passes += batch) {
-        if (done_passes > guard) {
+    int32_t *pc = Lw.sc->pass_count;
+    for (;;) {
+        if (g > guard) {
             set_error("relaxation did not reach its fixpoint within %lld passes",
                       (long long)guard);
             return LPR_EBUDGET;
         }
-        int32_t *pc = Lw.sc->pass_count;
         LPR_TRY(fill_i32(pc, 0, batch, s));
         const int ev = tm.begin();
-        for (int i = 0; i < batch; ++i) {
-            Kern<TH>::relax(cut, s, D, Lw.dirty[sel], Lw.dirty[sel ^ 1], pc + i,
-                            i ? pc + i - 1 : nullptr);
-            sel ^= 1;
-        }
+        for (int i = 0; i < batch; ++i, ++g)
+            Kern<TH>::relax(cut, s, D, int(g % 3), i ? pc + i - 1 : &Lw.sc->seed_count,
+                            pc + i);
         tm.end(ev);
         LPR_TRY_HIP(hipGetLastError());
         *passes += batch;
@@ -970,11 +1023,28 @@ static lpr_status relax_to_fixpoint(bool cut, hipStream_t s, const Dev &D,
         LPR_TRY_HIP(hipMemcpyAsync(&last, pc + batch - 1, sizeof(int32_t),
                                    hipMemcpyDeviceToHost, s));
         LPR_TRY_HIP(hipStreamSynchronize(s));
-        // at the fixpoint both flag buffers are clear: every flagged tile
-        // was processed (and cleared its flag) and the last pass marked none
+        // at the fixpoint every flag is clear again: each listed tile cleared
+        // its own and the last pass listed none
         if (last == 0) return LPR_OK;
+        hipLaunchKernelGGL(k_carry, dim3(1), dim3(1), 0, s, &Lw.sc->seed_count,
+                           pc + batch - 1);
         batch = std::min(batch * 2, MAX_PASS_SLOTS);
     }
+}
+
+// Ahead of a boundary kernel: a count clears the counts of the sweep lists
+// it rebuilds; a snapshot clears every relaxation flag and the seed count.
+template <int TH>
+static lpr_status enqueue_boundary(hipStream_t s, const Dev &D, Layout &Lw, unsigned mode) {
+    if (mode & BD_SNAPSHOT) {
+        LPR_TRY(fill_i32(Lw.dirty_all, 0, 3 * int64_t(D.ntiles_r), s));
+        LPR_TRY(fill_i32(&Lw.sc->seed_count, 0, (mode & BD_COUNT) ? 4 : 1, s));
+    } else if (mode & BD_COUNT) {
+        LPR_TRY(fill_i32(Lw.sc->act_cnt, 0, 3, s));
+    }
+    Kern<TH>::boundary(s, D, mode);
+    LPR_TRY_HIP(hipGetLastError());
+    return LPR_OK;
 }
 
 // Adopt the labels of the global relabel just finished, count, retire.
@@ -982,7 +1052,7 @@ template <int TH>
 static lpr_status enqueue_adopt(hipStream_t s, const Dev &D, Layout &Lw, int B,
                                 unsigned extra, const int32_t *pass_count, int P) {
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.inst_cnt), 0, 2 * int64_t(B), s));
-    Kern<TH>::boundary(s, D, Lw, BD_ADOPT | BD_COUNT | extra);
+    LPR_TRY(enqueue_boundary<TH>(s, D, Lw, BD_ADOPT | BD_COUNT | extra));
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, D, pass_count, P);
     LPR_TRY_HIP(hipGetLastError());
     return LPR_OK;
@@ -992,23 +1062,21 @@ template <int TH>
 static lpr_status enqueue_sweeps(hipStream_t s, const Dev &D, Layout &Lw, int K, int L,
                                  EventTimer *tm) {
     const int ev = tm ? tm->begin() : -1;
-    for (int k = 0; k < K; ++k)
-        Kern<TH>::sweep(s, D, Lw.act[k & 1], Lw.act[(k & 1) ^ 1], L);
+    for (int k = 0; k < K; ++k) Kern<TH>::sweep(s, D, k % 3, L);
     if (tm) tm->end(ev);
     LPR_TRY_HIP(hipGetLastError());
     return LPR_OK;
 }
 
 // P relaxation passes of the global relabel seeded at the last snapshot
-// (dirty flags start in buffer 0).
+// (its list is list 0).
 template <int TH>
 static lpr_status enqueue_passes(hipStream_t s, const Dev &D, Layout &Lw, int P,
                                  EventTimer *tm) {
     int32_t *pc = Lw.sc->pass_count;
     const int ev = tm ? tm->begin() : -1;
     for (int i = 0; i < P; ++i)
-        Kern<TH>::relax(false, s, D, Lw.dirty[i & 1], Lw.dirty[(i & 1) ^ 1], pc + i,
-                        i ? pc + i - 1 : nullptr);
+        Kern<TH>::relax(false, s, D, i % 3, i ? pc + i - 1 : &Lw.sc->seed_count, pc + i);
     if (tm) tm->end(ev);
     LPR_TRY_HIP(hipGetLastError());
     return LPR_OK;
@@ -1021,7 +1089,7 @@ template <int TH>
 static lpr_status enqueue_seq_round(hipStream_t s, const Dev &D, Layout &Lw, int B, int K,
                                     int L, int P, EventTimer *t_sweep, EventTimer *t_bfs) {
     LPR_TRY(enqueue_sweeps<TH>(s, D, Lw, K, L, t_sweep));
-    Kern<TH>::boundary(s, D, Lw, BD_SNAPSHOT);
+    LPR_TRY(enqueue_boundary<TH>(s, D, Lw, BD_SNAPSHOT));
     LPR_TRY(fill_i32(Lw.sc->pass_count, 0, P, s));
     LPR_TRY(enqueue_passes<TH>(s, D, Lw, P, t_bfs));
     return enqueue_adopt<TH>(s, D, Lw, B, 0, Lw.sc->pass_count, P);
@@ -1232,19 +1300,18 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(Lw.counters), 0, 8, s));
     LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(Lw.sc), 0,
                      int64_t(sizeof(Scalars) / sizeof(int32_t)), s));
-    LPR_TRY(fill_i32(Lw.dirty[1], 0, D.ntiles_r, s));
     Kern<TH>::init(s, D);
     LPR_TRY_HIP(hipGetLastError());
 
     // An exact global relabel on the current state, to its fixpoint under
     // host control, then adopt, count and retire.
     auto exact_relabel = [&]() -> lpr_status {
-        Kern<TH>::boundary(s, D, Lw, BD_SNAPSHOT);
+        LPR_TRY(enqueue_boundary<TH>(s, D, Lw, BD_SNAPSHOT));
         LPR_TRY(relax_to_fixpoint<TH>(false, s, D, Lw, t_bfs, &bfs_passes));
         LPR_TRY(enqueue_adopt<TH>(s, D, Lw, B, 0, nullptr, 0));
         if (P.arg) {
             // the snapshot the first asynchronous relabel works on
-            Kern<TH>::boundary(s, D, Lw, BD_SNAPSHOT);
+            LPR_TRY(enqueue_boundary<TH>(s, D, Lw, BD_SNAPSHOT));
             LPR_TRY(fill_i32(Lw.sc->pass_count, 0, MAX_PASS_SLOTS, s));
         }
         LPR_TRY_HIP(hipGetLastError());
@@ -1351,7 +1418,9 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
     LPR_TRY_HIP(hipGetLastError());
     if (side) {
         // every instance takes part in the closure
-        Kern<TH>::cut_seed(s, D, Lw.dirty[0], Lw.dirty[1]);
+        LPR_TRY(fill_i32(Lw.dirty_all, 0, 3 * int64_t(D.ntiles_r), s));
+        LPR_TRY(fill_i32(&Lw.sc->seed_count, 0, 1, s));
+        Kern<TH>::cut_seed(s, D);
         LPR_TRY_HIP(hipGetLastError());
         EventTimer none(s);
         LPR_TRY(relax_to_fixpoint<TH>(true, s, D, Lw, none, &cut_passes));
@@ -1589,7 +1658,13 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     D.ru = Lw.st[5];
     D.rs = Lw.st[6];
     D.lab = Lw.lab;
-    D.arcs = Lw.arcs;
+    D.amask = Lw.amask;
+    for (int i = 0; i < 3; ++i) {
+        D.act[i] = Lw.act[i];
+        D.alist[i] = Lw.alist[i];
+        D.dirty[i] = Lw.dirty_all + int64_t(i) * TR;
+        D.dlist[i] = Lw.dlist[i];
+    }
     D.cap_src = caps[0];
     D.cap_snk = caps[1];
     D.cap_r = caps[2];
