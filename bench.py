@@ -48,10 +48,12 @@ SWEEP_BYTES_PER_PIXEL = 28
 SWEEP_BYTES_PER_RELABEL = 4
 SWEEP_BYTES_PER_PUSH = 16
 # Bytes one pass of the global-relabel relaxation moves per pixel of a
-# relaxed tile: the label and the four neighbour residuals read, the label
-# written.  (A whole global relabel also reads the sink residual once, in the
-# seed kernel, which makes the 28 B per pixel of one work-efficient BFS.)
-RELAX_BYTES_PER_PIXEL = 24
+# relaxed tile: the label read, the tile's four arc masks of the snapshot
+# (four 32-bit words per column of 32 rows: 0.5 B per pixel) and the label
+# written.  The snapshot itself (the residuals, sink residual and excess
+# read, the masks and seed written: about 29 B per pixel once per global
+# relabel) is taken by the round-boundary kernel.
+RELAX_BYTES_PER_PIXEL = 8.5
 # Bytes per cost entry a row scan of the refine reads (the int32 cost row).
 ASSIGN_BYTES_PER_ENTRY = 4
 GRID_SRC = os.path.join(ROOT, "paper_1110_6231_amd", "csrc", "grid_maxflow.hip")
@@ -61,7 +63,14 @@ GRID_SRC = os.path.join(ROOT, "paper_1110_6231_amd", "csrc", "grid_maxflow.hip")
 # by what the same counters read for a plain copy of known size (FETCH_SIZE
 # x 2.0, WRITE_SIZE x 1.0).  Each entry holds the sha256 of the kernel's
 # source file at measurement time; a changed source reports null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("k_sweep<16>", "batched"): {
+        "source_sha256": "139fed459f1345fbcc9fdb01637fb834f8a04c71150524ba34609da6520010e1",
+        "bytes_per_launch": 74102962},
+    ("k_relax4<false>", "batched"): {
+        "source_sha256": "139fed459f1345fbcc9fdb01637fb834f8a04c71150524ba34609da6520010e1",
+        "bytes_per_launch": 6592042},
+}
 
 
 def parse():
@@ -600,15 +609,15 @@ def main():
         assert cpu_flows == [int(f) for f in g["flows"]], \
             "the oracle's flow values differ from the GPU's"
         out["cpu_baseline"] = cb
+    if args.grid_only:
+        print(json.dumps(out), flush=True)
+        return
     big = g["insts"][-1]
     out["grid_2048"] = dict(workload="the 2048x2048 graph cut with pair weights x4 "
                                      "alone (lpr_grid_maxflow)",
                             **grid_single_leg(args, torch, lpr, big,
                                               want_flow=cpu_flows[-1] if not args.no_cpu
                                               else None, reps=3))
-    if args.grid_only:
-        print(json.dumps(out), flush=True)
-        return
     import oracle
     w2 = synth.grid_blobs(1024, 1024, seed=0)
     want2 = None

@@ -117,9 +117,12 @@ typedef struct {
 } lpr_grid_opts;
 
 typedef struct {
-    int64_t rounds;          /* global relabels performed (BFS + gap)       */
-    int64_t sweeps;          /* push-sweep launches                         */
-    int64_t bfs_passes;      /* tile-relaxation launches of the BFS         */
+    int64_t rounds;          /* global relabels performed (BFS + gap) while
+                                an instance was still unretired            */
+    int64_t sweeps;          /* push-sweep launches enqueued                */
+    int64_t bfs_passes;      /* relaxation launches of the global relabels
+                                enqueued (a launch whose list is empty
+                                returns at once)                          */
     int64_t tiles_swept;     /* tiles processed, summed over sweep launches */
     int64_t pushes;          /* push operations                             */
     int64_t relabels;        /* relabel operations                          */
@@ -140,6 +143,7 @@ typedef struct {
     double total_ms;         /* wall time of the device work (HIP events)   */
     int32_t async_relabel;   /* 1 if the asynchronous global relabel ran    */
     int32_t rounds_per_check;/* rounds between host reads actually used     */
+    int64_t bfs_passes_with_work; /* relaxation launches that relaxed a tile */
 } lpr_grid_stats;
 
 /* Device workspace bytes needed by lpr_grid_maxflow for an H x W grid. */

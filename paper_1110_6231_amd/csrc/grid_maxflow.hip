@@ -1287,7 +1287,9 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
         t_bfs_b.enable();
     }
     double sweep_ms = 0, bfs_ms = 0;
-    int64_t bfs_passes = 0, cut_passes = 0, rounds_enq = 0;
+    // launches enqueued (graph replays included): relaxation passes of the
+    // global relabel, push sweeps, cut-closure passes
+    int64_t bfs_passes = 0, sweep_launches = 0, cut_passes = 0, rounds_enq = 0;
 
     LPR_TRY_HIP(hipMemcpyAsync(Lw.inst, insts.data(), sizeof(Inst) * B,
                                hipMemcpyHostToDevice, s));
@@ -1331,6 +1333,8 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
         const int nr = int(std::min<int64_t>(R, P.max_rounds - rounds_enq));
         for (int r = 0; r < nr; ++r) {
             ++rounds_enq;
+            sweep_launches += P.K;
+            bfs_passes += PB;
             if (!P.arg) {
                 if (use_graph) {
                     GraphKey key = base_key;
@@ -1438,8 +1442,9 @@ static lpr_status solve(const Params &P, int B, const std::vector<Inst> &insts,
         // rounds counts the exact relabels too (the first one included);
         // sweeps ran K per round after the first relabel
         stats->rounds = rounds;
-        stats->sweeps = int64_t(P.K) * std::max<int64_t>(0, rounds - 1);
-        stats->bfs_passes = int64_t(cnt[6]);
+        stats->sweeps = sweep_launches;
+        stats->bfs_passes = bfs_passes;
+        stats->bfs_passes_with_work = int64_t(cnt[6]);
         stats->cut_passes = cut_passes;
         stats->pushes = int64_t(cnt[0]);
         stats->relabels = int64_t(cnt[1]);
@@ -1506,11 +1511,14 @@ static Sched default_sched(int64_t N) {
     load_sched_file_locked();
     const auto it = g_sched.find(size_class(N));
     if (it != g_sched.end()) return it->second;
-    // measured on MI355X: 64 x 8 tiles for the 1024 x 1024 graph cut
-    // (2.2 ms against 2.3-2.5 ms with 64 x 16), 64 x 16 tiles from 2^22
-    // pixels on (the batched workload with a 2048 x 2048 grid: 14.9 ms
-    // against 18.3 ms)
-    return N >= (int64_t(1) << 22) ? Sched{16, 16, 4, 0, 4} : Sched{8, 16, 4, 0, 4};
+    // the schedule search on MI355X: 64 x 8 tiles, 16 local iterations for
+    // the 1024 x 1024 graph cut (2.1 ms); 64 x 8 tiles, 32 iterations for the
+    // 2048 x 2048 grid alone (10.0 ms); 64 x 16 tiles, 32 iterations for the
+    // batched workload of 10.5 M pixels (13.4 ms); 4 sweeps per round and the
+    // relabel between the sweeps throughout
+    if (N >= (int64_t(1) << 23)) return Sched{16, 32, 4, 0, 2};
+    if (N >= (int64_t(1) << 22)) return Sched{8, 32, 4, 0, 2};
+    return Sched{8, 16, 4, 0, 2};
 }
 
 static void store_sched(int64_t N, const Sched &sc) {

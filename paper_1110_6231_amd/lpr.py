@@ -87,7 +87,8 @@ class GridStats(ctypes.Structure):
                 ("sweep_ms", ctypes.c_double), ("bfs_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double),
                 ("async_relabel", ctypes.c_int32),
-                ("rounds_per_check", ctypes.c_int32)]
+                ("rounds_per_check", ctypes.c_int32),
+                ("bfs_passes_with_work", ctypes.c_int64)]
 
 
 class AssignOpts(ctypes.Structure):
