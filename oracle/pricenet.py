@@ -18,7 +18,15 @@ move with their column (equivariant to column order):
   f13     = v2(y) - mean_y v2, where u2(x) = min_y (z(x,y) - f10(y)) and
             v2(y) = min_x (z(x,y) - u2(x))  (two alternating min passes of
             the dual problem started from f10)
-  f14     = s(y) - mean_y s, s(y) = -TAU log sum_x exp(-rr(x,y) / TAU)
+  f14     = g(y) - mean_y g: the column potential of the entropic (Sinkhorn)
+            dual of the assignment with costs z after SINK_ITERS alternating
+            updates at a falling temperature tau_k = max(SINK_TAU_MIN,
+            SINK_TAU0 SINK_RATE^k), k = 0, 1, ..., from g = 0:
+              f(x) = -tau log sum_y exp(-(z(x,y) - g(y)) / tau)   (rows)
+              g(y) = -tau log sum_x exp(-(z(x,y) - f(x)) / tau)   (columns)
+            As tau falls, f + g tends to an optimal dual of the assignment
+            LP (every column update leaves z - f - g >= 0), which is what
+            the network is asked to predict.
   f15     = log(n) / 6
 
 Network (DeepSets-style, equivariant over columns; H0 = features [n, 16]):
@@ -39,7 +47,10 @@ import numpy as np
 
 F_IN = 16
 WIDTH = 128
-TAU = 0.1
+SINK_TAU0 = 0.3
+SINK_RATE = 0.7
+SINK_TAU_MIN = 0.003
+SINK_ITERS = 16
 LAYERS = [(F_IN, WIDTH), (WIDTH, WIDTH), (WIDTH, WIDTH)]
 
 
@@ -80,6 +91,33 @@ def init_params(seed=0):
     return np.concatenate(parts).astype(np.float32)
 
 
+def sinkhorn_potentials(z, tau0=SINK_TAU0, rate=SINK_RATE, tau_min=SINK_TAU_MIN,
+                        iters=SINK_ITERS):
+    """Row and column potentials (f, g) of the entropic dual of the
+    assignment with cost matrix z: `iters` alternating exact updates, each
+    a log-sum-exp at temperature tau, computed around its minimum,
+        f(x) = -tau log sum_y exp(-(z(x,y) - g(y)) / tau)
+        g(y) = -tau log sum_x exp(-(z(x,y) - f(x)) / tau),
+    from g = 0, with tau = tau0 first and multiplied by `rate` after every
+    iteration down to tau_min.  Returns (f, g, last tau)."""
+    z = np.asarray(z, np.float64)
+    n = z.shape[0]
+    f = np.zeros(n)
+    g = np.zeros(n)
+    tau = tau0
+    last = tau
+    for _ in range(iters):
+        a = z - g[None, :]
+        m = a.min(axis=1)
+        f = m - tau * np.log(np.exp(-(a - m[:, None]) / tau).sum(axis=1))
+        b = z - f[:, None]
+        m = b.min(axis=0)
+        g = m - tau * np.log(np.exp(-(b - m[None, :]) / tau).sum(axis=0))
+        last = tau
+        tau = max(tau_min, tau * rate)
+    return f, g, last
+
+
 def features(cost, maximize=False):
     """[n, 16] float64 features and the cost scale sc (see module doc)."""
     c = np.asarray(cost, np.float64)
@@ -104,9 +142,8 @@ def features(cost, maximize=False):
     u2 = (z - f[:, 10][None, :]).min(axis=1)
     v2 = (z - u2[:, None]).min(axis=0)
     f[:, 13] = v2 - v2.mean()
-    m = rr.min(axis=0)
-    s = m - TAU * np.log(np.exp(-(rr - m[None, :]) / TAU).sum(axis=0))
-    f[:, 14] = s - s.mean()
+    _, gs, _ = sinkhorn_potentials(z)
+    f[:, 14] = gs - gs.mean()
     f[:, 15] = np.log(n) / 6.0
     return f, sc
 
