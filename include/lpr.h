@@ -465,10 +465,14 @@ lpr_status lpr_assign_sparse_solve(int32_t n, int32_t m, const int32_t *row_ptr,
  *
  * Features: 16 per column, symmetric over rows -- with sc = mean|c| and
  * z = c/sc, rr = z - rowmin(z): the 8 smallest z of the column, mean and std
- * of z, the 2 smallest rr, mean rr, a two-pass min-plus dual estimate and a
- * soft minimum of rr at temperature 0.1 (both centred per instance), log(n)/6.
+ * of z, the 2 smallest rr, mean rr, a two-pass min-plus dual estimate, the
+ * column potential of an annealed Sinkhorn (entropic) dual of the assignment
+ * (16 alternating log-sum-exp updates, temperature 0.3 falling by 0.7 per
+ * step to 0.003; both centred per instance), and log(n)/6.
  * Network per instance (columns as the set): H_l = relu(H_{l-1} W_l +
- * mean_cols(H_{l-1}) U_l + b_l) for l = 1..3 (width 128), q = H_3 w_o + b_o.
+ * mean_cols(H_{l-1}) U_l + b_l) for l = 1..3 (width 128), q = H_3 w_o + b_o
+ * + f14: the network predicts a correction to the Sinkhorn potential, which
+ * reaches the prediction at float32 precision (a skip connection).
  * Parameters: one float32 vector of lpr_pricenet_param_count() values,
  * W1 [16,128], U1 [16,128], b1 [128], W2 [128,128], U2 [128,128], b2 [128],
  * W3, U3 [128,128], b3 [128], w_o [128], b_o [1], row-major, concatenated.

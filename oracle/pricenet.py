@@ -31,12 +31,16 @@ move with their column (equivariant to column order):
 
 Network (DeepSets-style, equivariant over columns; H0 = features [n, 16]):
   H_l = relu(H_{l-1} W_l + 1 mean_y(H_{l-1}) U_l + 1 b_l),  l = 1, 2, 3
-  q   = H_3 w_o + b_o                     (normalised price per column)
+  q   = H_3 w_o + b_o + f14               (normalised price per column)
+The last term is a skip connection: the network predicts the correction to
+the Sinkhorn potential, so its bf16 rounding falls on the correction and the
+potential reaches the prices at full precision.
 Widths: 16 -> 128 -> 128 -> 128 -> 1.  Parameter vector layout (float32 on
 the device): W1 [16,128], U1 [16,128], b1 [128], W2, U2 [128,128], b2,
 W3, U3 [128,128], b3, w_o [128], b_o [1] -- each row-major, concatenated.
 
-Loss over a batch of instances with centred targets t (normalised prices):
+Loss over a batch of instances with centred targets t (normalised prices),
+q including the skip term (which does not depend on the parameters):
   L = (1 / sum_i n_i) sum_i sum_y ((q_y - mean_i q) - t_y)^2
 Scaled integer start prices for the solver: p(y) = rint((q_y - mean q) sc
 (2n+1)), and the starting epsilon max(1, rint(kappa sc (2n+1))).
@@ -149,7 +153,8 @@ def features(cost, maximize=False):
 
 
 def forward(theta, feats_list):
-    """Outputs q per instance and the cache for backward."""
+    """Network outputs H_3 w_o + b_o per instance (without the skip term)
+    and the cache for backward."""
     P = unpack(theta)
     outs, caches = [], []
     for X in feats_list:
@@ -166,14 +171,31 @@ def forward(theta, feats_list):
     return outs, caches
 
 
-def loss_and_grad(theta, feats_list, targets):
-    """Shift-invariant MSE over a batch and its gradient (float64)."""
+def _skips(feats_list, skip_list):
+    if skip_list is not None:
+        return [np.asarray(s, np.float64) for s in skip_list]
+    return [np.asarray(X, np.float64)[:, 14] for X in feats_list]
+
+
+def predict_q(theta, feats_list, skip_list=None):
+    """Normalised price prediction per instance: the network output plus
+    the skip term f14 (taken from skip_list when given, else from the
+    features)."""
+    outs = forward(theta, feats_list)[0]
+    return [q + sk for q, sk in zip(outs, _skips(feats_list, skip_list))]
+
+
+def loss_and_grad(theta, feats_list, targets, skip_list=None):
+    """Shift-invariant MSE over a batch and its gradient (float64); the
+    prediction includes the skip term, which has no parameters."""
     P = unpack(theta)
     outs, caches = forward(theta, feats_list)
     N = sum(len(t) for t in targets)
     L = 0.0
     grads = [np.zeros_like(p) for p in P]
-    for q, t, (cache, H3) in zip(outs, targets, caches):
+    for q0, sk, t, (cache, H3) in zip(outs, _skips(feats_list, skip_list), targets,
+                                      caches):
+        q = q0 + sk
         r = (q - q.mean()) - (np.asarray(t, np.float64) - np.mean(t))
         L += (r ** 2).sum() / N
         dq = 2.0 * r / N            # d/dq of the centred residual (sum r = 0)
@@ -193,11 +215,11 @@ def loss_and_grad(theta, feats_list, targets):
 
 
 def predict_prices(theta, cost, maximize=False):
-    """Integer scaled start prices for one instance: the centred network
-    output in units of sc, scaled by the solver's cost scale S = 2n+1 and
-    rounded half to even."""
+    """Integer scaled start prices for one instance: the centred prediction
+    (network output plus f14) in units of sc, scaled by the solver's cost
+    scale S = 2n+1 and rounded half to even."""
     f, sc = features(cost, maximize)
-    q = forward(theta, [f])[0][0]
+    q = predict_q(theta, [f])[0]
     q = q - q.mean()
     n = f.shape[0]
     return np.rint(q * sc * (2 * n + 1)).astype(np.int64)

@@ -14,11 +14,19 @@
 //   f10,f11 2 smallest rr(.,y)             f12     mean rr(.,y)
 //   f13     v2(y) - mean v2 with u2(x) = min_y (z - f10(y)),
 //           v2(y) = min_x (z - u2(x))
-//   f14     s(y) - mean s, s(y) = -TAU log sum_x exp(-rr(x,y)/TAU)
+//   f14     g(y) - mean g: the column potential of the entropic (Sinkhorn)
+//           dual of the assignment with costs z after SINK_ITERS
+//           alternating exact updates at a falling temperature tau,
+//             f(x) = -tau log sum_y exp(-(z(x,y) - g(y)) / tau),
+//             g(y) = -tau log sum_x exp(-(z(x,y) - f(x)) / tau),
+//           from g = 0, tau = SINK_TAU0 times SINK_RATE per step down to
+//           SINK_TAU_MIN; as tau falls f + g tends to an optimal dual of
+//           the assignment, the quantity the network predicts
 //   f15     log(n) / 6
 // Network over the columns of each instance (H0 = features):
 //   H_l = relu(H_{l-1} W_l + mean_cols(H_{l-1}) U_l + b_l), l = 1..3 (width
-//   128), q = H_3 w_o + b_o.  Parameters: one float32 vector, W1 [16,128],
+//   128), q = H_3 w_o + b_o + f14 (a skip connection: the network predicts
+//   the correction to the Sinkhorn potential).  Parameters: one float32 vector, W1 [16,128],
 //   U1 [16,128], b1, W2, U2 [128,128], b2, W3, U3, b3, w_o [128], b_o.
 // Loss: (1 / sum n) sum ((q - mean q) - t)^2 per instance, t centred.
 //
@@ -39,7 +47,10 @@ namespace net {
 constexpr int F_IN = 16;
 constexpr int F_PAD = 32;   // features padded to one MFMA K-step
 constexpr int WID = 128;
-constexpr float TAU = 0.1f;
+constexpr double SINK_TAU0 = 0.3;
+constexpr double SINK_RATE = 0.7;
+constexpr double SINK_TAU_MIN = 0.003;
+constexpr int SINK_ITERS = 16;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -66,37 +77,62 @@ __device__ inline float from_bf16(__bf16 b) { return (float)b; }
 // ---------------------------------------------------------------------------
 // Feature passes
 // ---------------------------------------------------------------------------
-// Row pass 1: min_y c(x,y) and the instance's sum of |c|.  grid = (row
-// blocks, B): block (i, b) takes rows ROWS1 i .. ROWS1 (i+1) - 1 of instance
-// b, one wavefront per row in turn, and adds its part of the sum with one
-// atomic (the instance's rows then meet in few device-scope atomics).
+// Row pass 1: min_y c(x,y), the instance's sum and maximum of |c|, and a
+// saturated int16 copy of sign * c that the later passes read instead of the
+// int32 input when the instance's costs fit (half the bytes per pass).
+// grid = (row blocks, B): block (i, b) takes rows ROWS1 i .. ROWS1 (i+1) - 1
+// of instance b, one wavefront per row in turn, and adds its part of the sum
+// with one atomic (the instance's rows then meet in few device-scope
+// atomics).
 constexpr int ROWS1 = 16;
+constexpr int C16_MAX = 32767;
 __global__ __launch_bounds__(256) void k_feat_rows1(const NInst *inst,
                                                     const int32_t *costs,
                                                     int32_t sign, int32_t *rowmin,
-                                                    unsigned long long *abssum) {
+                                                    unsigned long long *abssum,
+                                                    int16_t *c16, unsigned *cmax) {
     const NInst I = inst[blockIdx.y];
     const int x0 = blockIdx.x * ROWS1;
     if (x0 >= I.n) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long s = 0;
+    unsigned amax = 0;
     for (int x = x0 + wave; x < min(x0 + ROWS1, I.n); x += 4) {
-        const int32_t *row = costs + I.cost_off + int64_t(x) * I.n;
+        const int64_t base = I.cost_off + int64_t(x) * I.n;
+        const int32_t *row = costs + base;
         int mn = INT_MAX;
         for (int y = lane; y < I.n; y += 64) {
             const int c = sign * row[y];
             mn = min(mn, c);
-            s += unsigned(c < 0 ? -c : c);
+            const unsigned a = unsigned(c < 0 ? -c : c);
+            s += a;
+            amax = max(amax, a);
+            c16[base + y] = int16_t(max(-C16_MAX, min(C16_MAX, c)));
         }
         for (int o = 32; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, 64));
         if (lane == 0) rowmin[I.row_off + x] = mn;
     }
+    for (int o = 32; o > 0; o >>= 1) amax = max(amax, unsigned(__shfl_xor(int(amax), o, 64)));
+    if (lane == 0 && amax) atomicMax(&cmax[blockIdx.y], amax);
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     __shared__ unsigned long long part[4];
     if (lane == 0) part[wave] = s;
     __syncthreads();
     if (threadIdx.x == 0) atomicAdd(&abssum[blockIdx.y], part[0] + part[1] + part[2] + part[3]);
 }
+
+// sign * c at entry idx of the packed costs: from the int16 copy when the
+// instance's |c| fits it, else from the int32 input
+struct Costs {
+    const int32_t *c32;
+    const int16_t *c16;
+    const unsigned *cmax;
+    int32_t sign;
+    __device__ bool small(int b) const { return cmax[b] <= unsigned(C16_MAX); }
+    __device__ int at(bool s16, int64_t idx) const {
+        return s16 ? int(c16[idx]) : sign * c32[idx];
+    }
+};
 
 __device__ inline float inst_scale(const NInst &I, const unsigned long long *abssum, int b) {
     const double m = double(abssum[b]) / (double(I.n) * double(I.n));
@@ -109,39 +145,37 @@ constexpr int FEAT_AHEAD = 32;
 
 // Column pass 1: one thread per stacked column.
 __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
-                                                    const int32_t *rinst,
-                                                    const int32_t *costs,
-                                                    int32_t sign, int32_t R,
-                                                    const int32_t *rowmin,
+                                                    const int32_t *rinst, Costs CV,
+                                                    int32_t R, const int32_t *rowmin,
                                                     const unsigned long long *abssum,
-                                                    float *F, float *sval) {
+                                                    float *F) {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= R) return;
     const int b = rinst[r];
     const NInst I = inst[b];
     const int y = r - I.row_off, n = I.n;
     const float inv = 1.0f / inst_scale(I, abssum, b);
-    const int32_t *col = costs + I.cost_off + y;
+    const bool s16 = CV.small(b);
+    const int64_t col = I.cost_off + y;
     const int32_t *rm = rowmin + I.row_off;
     float top[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) top[k] = INFINITY;
     float r0 = INFINITY, r1 = INFINITY;
     float sz = 0.f, szz = 0.f, srr = 0.f;
-    float lm = INFINITY, ls = 0.f;  // running min of rr and sum exp(-(rr-lm)/TAU)
     // the loads of FEAT_AHEAD rows are in flight before the first is used
     int cb[FEAT_AHEAD], mb[FEAT_AHEAD];
     for (int x0 = 0; x0 < n; x0 += FEAT_AHEAD) {
 #pragma unroll
         for (int a = 0; a < FEAT_AHEAD; ++a) {
             const int x = x0 + a < n ? x0 + a : n - 1;
-            cb[a] = col[int64_t(x) * n];
+            cb[a] = CV.at(s16, col + int64_t(x) * n);
             mb[a] = rm[x];
         }
 #pragma unroll
         for (int a = 0; a < FEAT_AHEAD; ++a) {
             if (x0 + a >= n) break;
-            const int c = sign * cb[a];
+            const int c = cb[a];
             const float z = float(c) * inv;
             const float rr = float(c - mb[a]) * inv;
             sz += z;
@@ -164,12 +198,6 @@ __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
                     r1 = rr;
                 }
             }
-            if (rr < lm) {
-                ls = ls * __expf((rr - lm) / TAU) + 1.0f;
-                lm = rr;
-            } else {
-                ls += __expf(-(rr - lm) / TAU);
-            }
         }
     }
     float *f = F + int64_t(r) * F_IN;
@@ -180,14 +208,119 @@ __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
     f[10] = r0;
     f[11] = n > 1 ? r1 : r0;
     f[12] = srr / n;
-    sval[r] = lm - TAU * __logf(ls);
+}
+
+// Sinkhorn passes of f14.  A log-sum-exp of -v/tau over values v is carried
+// as (m, s) = (min v, sum exp(-(v - m)/tau)) and equals m - tau log s; every
+// exponent is <= 0, so nothing overflows however small tau is.  (inf, 0) is
+// the empty pair.
+__device__ inline void lse_add(float &m, float &s, float v, float k) {
+    const float d = v - m;
+    const float e = __expf(-fabsf(d) * k);
+    const bool lt = d < 0.f;
+    s = lt ? fmaf(s, e, 1.0f) : s + e;
+    m = lt ? v : m;
+}
+
+__device__ inline void lse_merge(float &m, float &s, float m2, float s2, float k) {
+    if (s2 == 0.f) return;
+    if (s == 0.f) {
+        m = m2;
+        s = s2;
+        return;
+    }
+    const float d = m2 - m;
+    const float e = __expf(-fabsf(d) * k);
+    if (d < 0.f) {
+        s = fmaf(s, e, s2);
+        m = m2;
+    } else {
+        s = fmaf(s2, e, s);
+    }
+}
+
+// Row update f(x) = -tau log sum_y exp(-(z(x,y) - g(y))/tau): SINK_RL lanes
+// per stacked row (64 / SINK_RL rows per wavefront), the row's columns
+// strided over them, then a butterfly merge inside each lane group.
+constexpr int SINK_RL = 16;
+__global__ __launch_bounds__(256) void k_sink_rows(const NInst *inst, const int32_t *rinst,
+                                                   Costs CV, int32_t R,
+                                                   const unsigned long long *abssum,
+                                                   const float *g, float *f, float tau) {
+    const int l = threadIdx.x & (SINK_RL - 1);
+    const int r = blockIdx.x * (256 / SINK_RL) + threadIdx.x / SINK_RL;
+    const float k = 1.0f / tau;
+    float m = INFINITY, s = 0.f;
+    if (r < R) {
+        const int b = rinst[r];
+        const NInst I = inst[b];
+        const int x = r - I.row_off;
+        const float inv = 1.0f / inst_scale(I, abssum, b);
+        const bool s16 = CV.small(b);
+        const int64_t row = I.cost_off + int64_t(x) * I.n;
+        const float *gi = g + I.row_off;
+        for (int y = l; y < I.n; y += SINK_RL)
+            lse_add(m, s, float(CV.at(s16, row + y)) * inv - gi[y], k);
+    }
+    for (int o = SINK_RL / 2; o > 0; o >>= 1) {
+        const float m2 = __shfl_xor(m, o, 64), s2 = __shfl_xor(s, o, 64);
+        lse_merge(m, s, m2, s2, k);
+    }
+    if (r < R && l == 0) f[r] = m - tau * __logf(s);
+}
+
+// Column update g(y) = -tau log sum_x exp(-(z(x,y) - f(x))/tau).  A
+// workgroup takes 64 adjacent stacked columns (the lanes, so a row's loads
+// coalesce) and SINK_CW row chunks (the wavefronts: wavefront w takes rows
+// w, w + SINK_CW, ...); the chunks' partial sums are merged in LDS.
+constexpr int SINK_CW = 8;
+constexpr int SINK_AHEAD = 16;  // rows of a chunk loaded ahead
+__global__ __launch_bounds__(64 * SINK_CW) void k_sink_cols(
+    const NInst *inst, const int32_t *rinst, Costs CV, int32_t R,
+    const unsigned long long *abssum, const float *f, float *g, float tau) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = blockIdx.x * 64 + lane;
+    const float k = 1.0f / tau;
+    __shared__ float sm[SINK_CW][64], ss[SINK_CW][64];
+    float m = INFINITY, s = 0.f;
+    if (r < R) {
+        const int b = rinst[r];
+        const NInst I = inst[b];
+        const int y = r - I.row_off, n = I.n;
+        const float inv = 1.0f / inst_scale(I, abssum, b);
+        const bool s16 = CV.small(b);
+        const int64_t col = I.cost_off + y;
+        const float *fi = f + I.row_off;
+        for (int x0 = w; x0 < n; x0 += SINK_CW * SINK_AHEAD) {
+            int cb[SINK_AHEAD];
+            float fb[SINK_AHEAD];
+#pragma unroll
+            for (int a = 0; a < SINK_AHEAD; ++a) {
+                const int x = x0 + a * SINK_CW;
+                const int xc = x < n ? x : x0;  // a valid row; its value is not used
+                cb[a] = CV.at(s16, col + int64_t(xc) * n);
+                fb[a] = fi[xc];
+            }
+#pragma unroll
+            for (int a = 0; a < SINK_AHEAD; ++a) {
+                if (x0 + a * SINK_CW >= n) break;
+                lse_add(m, s, float(cb[a]) * inv - fb[a], k);
+            }
+        }
+    }
+    sm[w][lane] = m;
+    ss[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && r < R) {
+        for (int j = 1; j < SINK_CW; ++j) lse_merge(m, s, sm[j][lane], ss[j][lane], k);
+        g[r] = m - tau * __logf(s);
+    }
 }
 
 // Row pass 2: u2(x) = min_y (z(x,y) - f10(y)).
 __global__ __launch_bounds__(256) void k_feat_rows2(const NInst *inst,
-                                                    const int32_t *rinst,
-                                                    const int32_t *costs,
-                                                    int32_t sign, int32_t R,
+                                                    const int32_t *rinst, Costs CV,
+                                                    int32_t R,
                                                     const unsigned long long *abssum,
                                                     const float *F, float *u2) {
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -197,19 +330,19 @@ __global__ __launch_bounds__(256) void k_feat_rows2(const NInst *inst,
     const NInst I = inst[b];
     const int x = r - I.row_off;
     const float inv = 1.0f / inst_scale(I, abssum, b);
-    const int32_t *row = costs + I.cost_off + int64_t(x) * I.n;
+    const bool s16 = CV.small(b);
+    const int64_t row = I.cost_off + int64_t(x) * I.n;
     float mn = INFINITY;
     for (int y = lane; y < I.n; y += 64)
-        mn = fminf(mn, float(sign * row[y]) * inv - F[int64_t(I.row_off + y) * F_IN + 10]);
+        mn = fminf(mn, float(CV.at(s16, row + y)) * inv - F[int64_t(I.row_off + y) * F_IN + 10]);
     for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
     if (lane == 0) u2[r] = mn;
 }
 
 // Column pass 2: v2(y) = min_x (z(x,y) - u2(x)).
 __global__ __launch_bounds__(256) void k_feat_cols2(const NInst *inst,
-                                                    const int32_t *rinst,
-                                                    const int32_t *costs,
-                                                    int32_t sign, int32_t R,
+                                                    const int32_t *rinst, Costs CV,
+                                                    int32_t R,
                                                     const unsigned long long *abssum,
                                                     const float *u2, float *v2) {
     const int r = blockIdx.x * 256 + threadIdx.x;
@@ -218,7 +351,8 @@ __global__ __launch_bounds__(256) void k_feat_cols2(const NInst *inst,
     const NInst I = inst[b];
     const int y = r - I.row_off, n = I.n;
     const float inv = 1.0f / inst_scale(I, abssum, b);
-    const int32_t *col = costs + I.cost_off + y;
+    const bool s16 = CV.small(b);
+    const int64_t col = I.cost_off + y;
     float mn = INFINITY;
     for (int x0 = 0; x0 < n; x0 += FEAT_AHEAD) {
         int cb[FEAT_AHEAD];
@@ -226,12 +360,12 @@ __global__ __launch_bounds__(256) void k_feat_cols2(const NInst *inst,
 #pragma unroll
         for (int a = 0; a < FEAT_AHEAD; ++a) {
             const int x = x0 + a < n ? x0 + a : n - 1;  // a repeat is harmless for a min
-            cb[a] = col[int64_t(x) * n];
+            cb[a] = CV.at(s16, col + int64_t(x) * n);
             ub[a] = u2[I.row_off + x];
         }
 #pragma unroll
         for (int a = 0; a < FEAT_AHEAD; ++a)
-            mn = fminf(mn, float(sign * cb[a]) * inv - ub[a]);
+            mn = fminf(mn, float(cb[a]) * inv - ub[a]);
     }
     v2[r] = mn;
 }
@@ -390,14 +524,16 @@ __global__ __launch_bounds__(256) void k_act_fwd(const int32_t *rinst, int32_t R
     }
 }
 
-// q[r] = H3[r] . w_o + b_o
+// q = H_3 w_o + b_o + f14: the skip term (float32 feature, no parameter)
+// carries the Sinkhorn potential to the prediction at full precision.
 __global__ __launch_bounds__(256) void k_head(const __bf16 *H, int32_t R,
-                                              const float *params, float *q) {
+                                              const float *params, const float *F,
+                                              float *q) {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= R) return;
     float s = params[OFF_BO];
     for (int j = 0; j < WID; ++j) s += from_bf16(H[int64_t(r) * WID + j]) * params[OFF_WO + j];
-    q[r] = s;
+    q[r] = s + F[int64_t(r) * F_IN + 14];
 }
 
 // Centred q -> integer scaled prices p = rint(q * sc * (2n+1)), and the
@@ -590,6 +726,8 @@ struct Layout {
     NInst *inst;
     int32_t *rinst, *rowmin;
     unsigned long long *abssum;
+    unsigned *cmax;   // per instance max |c|
+    int16_t *c16;     // saturated int16 copy of sign * c, packed like the input
     float *F, *sval, *u2, *v2;
     __bf16 *X0, *X0T;
     float *Z[3];
@@ -602,12 +740,14 @@ struct Layout {
 
 static int64_t pad64(int64_t r) { return (r + 63) / 64 * 64; }
 
-static Carver carve(Carver cv, int B, int64_t R, Layout *L) {
+static Carver carve(Carver cv, int B, int64_t R, int64_t E, Layout *L) {
     const int64_t Rp = pad64(R);
     L->inst = cv.take<NInst>(B);
     L->rinst = cv.take<int32_t>(R);
     L->rowmin = cv.take<int32_t>(R);
     L->abssum = cv.take<unsigned long long>(B);
+    L->cmax = cv.take<unsigned>(B);
+    L->c16 = cv.take<int16_t>(E);
     L->F = cv.take<float>(R * F_IN);
     L->sval = cv.take<float>(R);
     L->u2 = cv.take<float>(R);
@@ -642,9 +782,15 @@ static int64_t total_rows(int B, const int32_t *n) {
     return R;
 }
 
+static int64_t total_entries(int B, const int32_t *n) {
+    int64_t E = 0;
+    for (int b = 0; b < B; ++b) E += int64_t(n[b]) * n[b];
+    return E;
+}
+
 static size_t workspace_bytes(int B, const int32_t *n) {
     Layout L;
-    return carve(Carver(), B, total_rows(B, n), &L).used();
+    return carve(Carver(), B, total_rows(B, n), total_entries(B, n), &L).used();
 }
 
 struct Ctx {
@@ -694,7 +840,7 @@ static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
         set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
         return LPR_ENOMEM;
     }
-    carve(Carver(ws, ws_bytes), B, R, &C.L);
+    carve(Carver(ws, ws_bytes), B, R, total_entries(B, n), &C.L);
     C.rinst.resize(R);
     for (int b = 0; b < B; ++b)
         std::fill(C.rinst.begin() + C.insts[b].row_off,
@@ -711,19 +857,32 @@ static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign, bool 
     Layout &L = C.L;
     const int R = int(C.R);
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.abssum), 0, C.B, C.s));
+    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.cmax), 0, C.B, C.s));
+    const Costs CV{costs, L.c16, L.cmax, sign};
     // padding rows of the bf16 input are zero
     LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0), 0, C.Rp * F_PAD / 2, C.s));
     if (train) LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0T), 0, C.Rp * F_PAD / 2, C.s));
     int nmax = 0;
     for (const NInst &I : C.insts) nmax = std::max(nmax, int(I.n));
     hipLaunchKernelGGL(k_feat_rows1, dim3(ceil_div(nmax, ROWS1), C.B), dim3(256), 0, C.s,
-                       L.inst, costs, sign, L.rowmin, L.abssum);
+                       L.inst, costs, sign, L.rowmin, L.abssum, L.c16, L.cmax);
     hipLaunchKernelGGL(k_feat_cols1, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
-                       L.inst, L.rinst, costs, sign, R, L.rowmin, L.abssum, L.F, L.sval);
+                       L.inst, L.rinst, CV, R, L.rowmin, L.abssum, L.F);
+    // f14: annealed Sinkhorn potentials, rows into u2 (scratch until the
+    // next pass), columns into sval, from g = 0
+    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.sval), 0, R, C.s));
+    double tau = SINK_TAU0;
+    for (int it = 0; it < SINK_ITERS; ++it) {
+        hipLaunchKernelGGL(k_sink_rows, dim3(ceil_div(R, 256 / SINK_RL)), dim3(256), 0, C.s,
+                           L.inst, L.rinst, CV, R, L.abssum, L.sval, L.u2, float(tau));
+        hipLaunchKernelGGL(k_sink_cols, dim3(ceil_div(R, 64)), dim3(64 * SINK_CW), 0, C.s,
+                           L.inst, L.rinst, CV, R, L.abssum, L.u2, L.sval, float(tau));
+        tau = std::max(SINK_TAU_MIN, tau * SINK_RATE);
+    }
     hipLaunchKernelGGL(k_feat_rows2, dim3(ceil_div(R, 4)), dim3(256), 0, C.s,
-                       L.inst, L.rinst, costs, sign, R, L.abssum, L.F, L.u2);
+                       L.inst, L.rinst, CV, R, L.abssum, L.F, L.u2);
     hipLaunchKernelGGL(k_feat_cols2, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
-                       L.inst, L.rinst, costs, sign, R, L.abssum, L.u2, L.v2);
+                       L.inst, L.rinst, CV, R, L.abssum, L.u2, L.v2);
     hipLaunchKernelGGL(k_feat_finish, dim3(C.B), dim3(256), 0, C.s, L.inst,
                        int32_t(C.Rp), L.F, L.sval, L.v2, L.X0, train ? L.X0T : nullptr);
     LPR_TRY_HIP(hipGetLastError());
@@ -760,7 +919,7 @@ static lpr_status run_forward(Ctx &C, const float *params, bool train) {
         ldin = WID;
     }
     hipLaunchKernelGGL(k_head, dim3(ceil_div(R, 256)), dim3(256), 0, C.s, L.H[2], R,
-                       params, L.q);
+                       params, L.F, L.q);
     LPR_TRY_HIP(hipGetLastError());
     return LPR_OK;
 }

@@ -3,13 +3,19 @@
 Data: seeded optical-flow-like instances from the training branch of the
 generator (disjoint from the evaluation instances), n ~ U{64..512}.
 Targets: the column prices of optimal solutions produced by the library's own
-cost-scaling solver.  Optimal prices are not unique, so after each round the
-targets are refreshed with the prices of solves started from the network's
-current prediction (the optimum nearest to what the network can express).
+cost-scaling solver.  Optimal prices are not unique; the network predicts a
+correction to the Sinkhorn potential f14 (its skip term), so the first
+targets are the optimum the solver reaches from f14 alone (a zero network),
+the one nearest to it, and after each round they are refreshed with the
+prices of solves started from the network's current prediction.  A
+correction the network cannot predict then averages to zero instead of
+pulling the start towards an arbitrary optimum.
 The starting epsilon is calibrated on held-out validation instances: per
 instance eps0 = kappa * sc * (2n+1) (sc = mean |c|), kappa chosen from a grid
-by measured time-to-optimal.  The plain start (p = 0, eps0 = max|c| (2n+1))
-is the reference.
+by measured time-to-optimal, both for the trained network and for the same
+network with its correction head at zero (prediction = f14 alone); the
+faster of the two is saved, and the metadata records both times and the
+choice.  The plain start (p = 0, eps0 = max|c| (2n+1)) is the reference.
 
 Usage: python -m paper_1110_6231_amd.train_pricenet --out weights.npz
 """
@@ -29,18 +35,20 @@ if ROOT not in sys.path:
 
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                "pricenet_weights.npz")
-KAPPA_GRID = [2.0 ** k for k in range(-8, 2)]
+KAPPA_GRID = [2.0 ** k for k in range(-12, 0)]
+WIDTH_OUT = 128   # w_o has this many entries, then b_o: the correction head
 
 
 def init_params(seed=0):
-    """He-style initialisation of the flat parameter vector (float32)."""
+    """He-style initialisation of the flat parameter vector (float32); the
+    head starts at zero, so the first prediction is the skip term f14."""
     g = np.random.default_rng(np.random.SeedSequence([77, seed]))
     parts = []
     for (k, m) in ((16, 128), (128, 128), (128, 128)):
         parts += [g.normal(0, np.sqrt(1.0 / k), (k, m)).ravel(),
                   g.normal(0, np.sqrt(1.0 / k), (k, m)).ravel(),
                   np.zeros(m)]
-    parts += [g.normal(0, np.sqrt(1.0 / 128), 128), np.zeros(1)]
+    parts += [np.zeros(128), np.zeros(1)]
     return np.concatenate(parts).astype(np.float32)
 
 
@@ -83,7 +91,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--rounds", type=int, default=6)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--refresh-kappa", type=float, default=0.0625)
+    ap.add_argument("--refresh-kappa", type=float, default=1.0 / 64)
     args = ap.parse_args()
 
     import torch
@@ -102,7 +110,8 @@ def main():
         synth.assign_batch(seed=1000, count=64, train=True))
     print(f"[train] {len(train)} minibatches, data ready "
           f"{time.perf_counter() - t_start:.1f}s", flush=True)
-    targets = [lpr.lpr_assign_solve_batched(p)[2] for p in train]
+    zero = torch.zeros(len(init_params(0)), dtype=torch.float32, device="cuda")
+    targets = [learned_solve(p, zero, args.refresh_kappa, lpr)[2] for p in train]
     params = torch.as_tensor(init_params(0), device="cuda")
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
@@ -123,29 +132,47 @@ def main():
         for p in train:
             _, _, pr, _ = learned_solve(p, params, args.refresh_kappa, lpr)
             targets.append(pr)
-    # calibrate kappa on validation instances by measured time-to-optimal
+    # calibrate kappa on validation instances by measured time-to-optimal,
+    # for the trained network and for the same network with its correction
+    # head at zero (the prediction is then the skip term f14 alone); keep
+    # the faster (model selection by the quantity the start is for)
     t_plain, (_, tot_plain, _, st_plain) = timed(
         lambda: lpr.lpr_assign_solve_batched(val), torch)
-    best = None
-    for kappa in KAPPA_GRID:
-        t, (_, tot, _, st) = timed(
-            lambda: learned_solve(val, params, kappa, lpr), torch)
-        assert torch.equal(tot, tot_plain)
-        print(f"[calib] kappa {kappa:7.2f}: {t * 1e3:8.2f} ms "
-              f"(plain {t_plain * 1e3:.2f} ms), ops "
-              f"{st['pushes'] + st['relabels']} vs "
-              f"{st_plain['pushes'] + st_plain['relabels']}", flush=True)
-        if best is None or t < best[0]:
-            best = (t, kappa)
+    zero_head = params.clone()
+    zero_head[-(WIDTH_OUT + 1):] = 0.0
+    results = {}
+    for name, cand in (("trained", params), ("zero_correction", zero_head)):
+        best = None
+        for kappa in KAPPA_GRID:
+            t, (_, tot, _, st) = timed(
+                lambda: learned_solve(val, cand, kappa, lpr), torch)
+            assert torch.equal(tot, tot_plain)
+            print(f"[calib] {name} kappa {kappa:9.6f}: {t * 1e3:8.2f} ms "
+                  f"(plain {t_plain * 1e3:.2f} ms), ops "
+                  f"{st['pushes'] + st['relabels']} vs "
+                  f"{st_plain['pushes'] + st_plain['relabels']}", flush=True)
+            if best is None or t < best[0]:
+                best = (t, kappa)
+        results[name] = best
+    chosen = min(results, key=lambda k: results[k][0])
+    t_best, kappa_best = results[chosen]
+    out_params = params if chosen == "trained" else zero_head
     meta = {"features": 16, "width": 128, "layers": 3, "steps": step,
             "rounds": args.rounds, "epochs": args.epochs, "lr": args.lr,
             "train_instances": 256 * args.train_batches,
-            "val_speedup": t_plain / best[0], "kappa_grid": KAPPA_GRID}
-    np.savez(args.out, params=params.cpu().numpy(), kappa=np.float64(best[1]),
+            "refresh_kappa": args.refresh_kappa,
+            "correction": chosen,
+            "val_ms": {k: round(v[0] * 1e3, 3) for k, v in results.items()},
+            "val_kappa": {k: v[1] for k, v in results.items()},
+            "val_plain_ms": round(t_plain * 1e3, 3),
+            "val_speedup": t_plain / t_best, "kappa_grid": KAPPA_GRID}
+    np.savez(args.out, params=out_params.cpu().numpy(), kappa=np.float64(kappa_best),
              meta=np.array(json.dumps(meta)))
-    print(f"[train] saved {args.out}: kappa {best[1]}, validation speedup "
-          f"{t_plain / best[0]:.2f}x, {time.perf_counter() - t_start:.1f}s",
-          flush=True)
+    print(f"[train] saved {args.out}: {chosen} correction, kappa {kappa_best}, "
+          f"validation speedup {t_plain / t_best:.2f}x (trained "
+          f"{results['trained'][0] * 1e3:.2f} ms, zero correction "
+          f"{results['zero_correction'][0] * 1e3:.2f} ms), "
+          f"{time.perf_counter() - t_start:.1f}s", flush=True)
 
 
 if __name__ == "__main__":

@@ -153,9 +153,13 @@ def test_loss_shift_invariance():
     theta2 = theta.copy(); theta2[-1] += 5.0     # output bias
     L2, _ = P.loss_and_grad(theta2, feats, targets)
     assert math.isclose(L0, L1, rel_tol=1e-12) and math.isclose(L0, L2, rel_tol=1e-12)
-    q = P.forward(theta, feats)[0]
+    q = P.predict_q(theta, feats)
     Lz, _ = P.loss_and_grad(theta, feats, [qq - qq.mean() for qq in q])
     assert Lz < 1e-20
+    # the skip term is the feature f14: a zero network predicts it alone
+    zero = np.zeros_like(theta)
+    for qq, X in zip(P.predict_q(zero, feats), feats):
+        np.testing.assert_array_equal(qq, X[:, 14])
 
 
 def test_bf16_rounding_matches_torch():
@@ -195,30 +199,37 @@ def _exact_round(fr):
 
 def test_predict_prices_closed_forms():
     """Start prices of hand-set networks against closed forms in exact
-    rational arithmetic: a zero head gives all-zero prices whatever the
-    bias; a network passing the column mean of z = c / sc gives
-    p(y) = round((colmean(y) - mean) (2n+1)); maximising negates the costs,
-    and the same network read through -f gives the negated closed form."""
+    rational arithmetic, on additive costs c(x,y) = a(x) + b(y), where the
+    skip term f14 is the centred b / sc exactly: a zero head gives
+    p(y) = round((b(y) - mean b) (2n+1)) whatever the bias; a network
+    passing the column mean of z = c / sc (centred, also (b - mean b) / sc)
+    doubles it; maximising negates the costs, and the same network read
+    through -f gives the negated closed form; a network reading another
+    feature (the column std, constant here) gives the skip term alone."""
     from fractions import Fraction
-    c = synth.assign_random_small(13, 5, lo=0, hi=400)
-    n = c.shape[0]
+    g = np.random.default_rng(5)
+    n = 13
+    a = g.integers(0, 200, n)
+    b = g.integers(0, 200, n)
+    c = (a[:, None] + b[None, :]).astype(np.int64)
+    tb = int(b.sum())
+
+    def closed(mult):
+        return np.array([_exact_round(Fraction(mult * (n * int(v) - tb) * (2 * n + 1), n))
+                         for v in b], np.int64)
+
     theta = P.init_params(3)
     theta[-129:-1] = 0.0                  # w_o = 0
     theta[-1] = 7.25                      # b_o
-    np.testing.assert_array_equal(P.predict_prices(theta, c), np.zeros(n, np.int64))
-    colsum = [int(v) for v in c.astype(np.int64).sum(axis=0)]
-    total = sum(colsum)
-    want = np.array([_exact_round(Fraction((n * cs - total) * (2 * n + 1), n * n))
-                     for cs in colsum], np.int64)
-    got = P.predict_prices(_one_hot_net(8), c)
-    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(P.predict_prices(theta, c), closed(1))
+    want = closed(2)
+    np.testing.assert_array_equal(P.predict_prices(_one_hot_net(8), c), want)
     # maximise: z = -c / sc, f8 = -colmean / sc; relu(-f8) then a head of -1
     got = P.predict_prices(_one_hot_net(8, -1.0, -1.0), c, maximize=True)
-    want_max = np.array([_exact_round(Fraction(-(n * cs - total) * (2 * n + 1), n * n))
-                         for cs in colsum], np.int64)
-    np.testing.assert_array_equal(got, want_max)
-    # a different feature index would be caught: f0 (column minimum) differs
-    assert not np.array_equal(P.predict_prices(_one_hot_net(0), c), want)
+    np.testing.assert_array_equal(got, closed(-2))
+    # a different feature index would be caught: f9 (column std) is constant
+    np.testing.assert_array_equal(P.predict_prices(_one_hot_net(9), c), closed(1))
+    assert not np.array_equal(P.predict_prices(_one_hot_net(9), c), want)
 
 
 def test_start_epsilon_closed_form():
