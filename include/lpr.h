@@ -359,6 +359,8 @@ typedef struct {
                                 start                                     */
     int64_t scan_entries;    /* cost entries read by row scans: scans x n,
                                 summed over instances                     */
+    int64_t price_update_steps; /* bucket steps of the price updates (one
+                                per distinct label reached), summed       */
     double kernel_ms;   /* with LPR_ASSIGN_TIME_KERNELS: solve kernel time */
     double total_ms;    /* device time of the whole call (HIP events)      */
 } lpr_assign_stats;

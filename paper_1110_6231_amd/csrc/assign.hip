@@ -117,7 +117,8 @@ struct AArgs {
     unsigned long long *counters;  // refines, phases, pushes, relabels, scans,
                                    // price updates, wall-clock ticks in them,
                                    // fixing reruns, warm-start restarts,
-                                   // cost entries read by row scans
+                                   // cost entries read by row scans,
+                                   // price-update steps
     int32_t *status;  // per instance: 0 ok, 1 budget, 2 range, 3 internal
 };
 
@@ -435,11 +436,11 @@ struct PU {
 // bucket is empty; prices drop by eps x label, and by eps x (last label + 1)
 // for the nodes not scanned.
 // Called by the whole workgroup between phases; `fl` is n ints of scratch
-// for the column frontier.
+// for the column frontier.  Returns the number of steps (labels scanned).
 template <typename T>
-__device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
-                             const T *__restrict__ CT, int n, int64_t sgnS,
-                             int64_t eps, int tid) {
+__device__ int price_update(const Shared &L, const PU &U, int32_t *fl,
+                            const T *__restrict__ CT, int n, int64_t sgnS,
+                            int64_t eps, int tid) {
     // per-level shared values, double-buffered by level parity so that no
     // barrier is spent resetting them and every read precedes the next write:
     // frontier size, active nodes scanned, next level
@@ -469,8 +470,9 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
     __syncthreads();
     int left = s_rem;  // active nodes not scanned yet (same in every thread)
     int64_t level = 0;
-    int par = 0;
+    int par = 0, steps = 0;
     for (;;) {
+        ++steps;
         // columns labelled `level`
         for (int y = tid; y < n; y += NT)
             if (!U.fy[y] && U.ly[y] == level) {
@@ -571,6 +573,7 @@ __device__ void price_update(const Shared &L, const PU &U, int32_t *fl,
     }
     for (int y = tid; y < n; y += NT) L.py[y] -= eps * (U.fy[y] ? U.ly[y] : far);
     __syncthreads();
+    return steps;
 }
 
 // Arc fixing (Section 5's second heuristic): for an eps-optimal flow, an arc
@@ -851,11 +854,12 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
         if (CT && A.pu_start && s_ny > 0) {
             // every row is matched here, so the row list is free scratch
             const uint64_t t0 = wall_clock64();
-            price_update(L, U, L.xl, CT, n, sgnS, eps, tid);
+            const int steps = price_update(L, U, L.xl, CT, n, sgnS, eps, tid);
             if (tid == 0) {
                 s_pu_mark = s_cnt[2];
                 atomicAdd(&s_cnt[5], 1ull);
                 atomicAdd(&s_cnt[6], (unsigned long long)(wall_clock64() - t0));
+                atomicAdd(&s_cnt[10], (unsigned long long)steps);
             }
             __syncthreads();
         }
@@ -909,11 +913,12 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
             if (nx <= tail_enter) {
                 if (CT && s_cnt[2] - s_pu_mark >= period) {
                     const uint64_t t0 = wall_clock64();
-                    price_update(L, U, L.yl, CT, n, sgnS, eps, tid);
+                    const int steps = price_update(L, U, L.yl, CT, n, sgnS, eps, tid);
                     if (tid == 0) {
                         s_pu_mark = s_cnt[2];
                         atomicAdd(&s_cnt[5], 1ull);
                         atomicAdd(&s_cnt[6], (unsigned long long)(wall_clock64() - t0));
+                        atomicAdd(&s_cnt[10], (unsigned long long)steps);
                     }
                     __syncthreads();
                 }
@@ -1332,6 +1337,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         stats->fixing_reruns = int64_t(cnt[7]);
         stats->warm_restarts = int64_t(cnt[8]);
         stats->scan_entries = int64_t(cnt[9]);
+        stats->price_update_steps = int64_t(cnt[10]);
         stats->kernel_ms = kms;
         stats->total_ms = tms;
     }

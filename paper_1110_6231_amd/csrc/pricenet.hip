@@ -210,17 +210,15 @@ __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
     f[12] = srr / n;
 }
 
-// Sinkhorn passes of f14.  A log-sum-exp of -v/tau over values v is carried
-// as (m, s) = (min v, sum exp(-(v - m)/tau)) and equals m - tau log s; every
-// exponent is <= 0, so nothing overflows however small tau is.  (inf, 0) is
-// the empty pair.
-__device__ inline void lse_add(float &m, float &s, float v, float k) {
-    const float d = v - m;
-    const float e = __expf(-fabsf(d) * k);
-    const bool lt = d < 0.f;
-    s = lt ? fmaf(s, e, 1.0f) : s + e;
-    m = lt ? v : m;
-}
+// Sinkhorn passes of f14.  A log-sum-exp of -v/tau over values v is m -
+// tau log s with m = min v and s = sum exp(-(v - m)/tau): every exponent is
+// <= 0 and the minimum's term is 1, so nothing overflows however small tau
+// is.  The row pass takes the minimum first and then the sum over the same
+// entries (a row is short and its second read hits the cache), so neither
+// loop carries a dependence beyond its accumulators; the column pass, whose
+// second read would come from further away, carries the pair (m, s) along
+// instead, rescaled once per group of rows ((inf, 0) is the empty pair).
+constexpr float LOG2E = 1.4426950408889634f;
 
 __device__ inline void lse_merge(float &m, float &s, float m2, float s2, float k) {
     if (s2 == 0.f) return;
@@ -241,7 +239,7 @@ __device__ inline void lse_merge(float &m, float &s, float m2, float s2, float k
 
 // Row update f(x) = -tau log sum_y exp(-(z(x,y) - g(y))/tau): SINK_RL lanes
 // per stacked row (64 / SINK_RL rows per wavefront), the row's columns
-// strided over them, then a butterfly merge inside each lane group.
+// strided over them, reduced inside each lane group by butterfly shuffles.
 constexpr int SINK_RL = 16;
 __global__ __launch_bounds__(256) void k_sink_rows(const NInst *inst, const int32_t *rinst,
                                                    Costs CV, int32_t R,
@@ -249,30 +247,56 @@ __global__ __launch_bounds__(256) void k_sink_rows(const NInst *inst, const int3
                                                    const float *g, float *f, float tau) {
     const int l = threadIdx.x & (SINK_RL - 1);
     const int r = blockIdx.x * (256 / SINK_RL) + threadIdx.x / SINK_RL;
-    const float k = 1.0f / tau;
-    float m = INFINITY, s = 0.f;
-    if (r < R) {
+    const bool live = r < R;
+    int n = 0;
+    int64_t row = 0;
+    float inv = 1.f;
+    bool s16 = true;
+    const float *gi = g;
+    if (live) {
         const int b = rinst[r];
         const NInst I = inst[b];
-        const int x = r - I.row_off;
-        const float inv = 1.0f / inst_scale(I, abssum, b);
-        const bool s16 = CV.small(b);
-        const int64_t row = I.cost_off + int64_t(x) * I.n;
-        const float *gi = g + I.row_off;
-        for (int y = l; y < I.n; y += SINK_RL)
-            lse_add(m, s, float(CV.at(s16, row + y)) * inv - gi[y], k);
+        n = I.n;
+        inv = 1.0f / inst_scale(I, abssum, b);
+        s16 = CV.small(b);
+        row = I.cost_off + int64_t(r - I.row_off) * n;
+        gi = g + I.row_off;
     }
-    for (int o = SINK_RL / 2; o > 0; o >>= 1) {
-        const float m2 = __shfl_xor(m, o, 64), s2 = __shfl_xor(s, o, 64);
-        lse_merge(m, s, m2, s2, k);
+    auto v = [&](int y) { return float(CV.at(s16, row + y)) * inv - gi[y]; };
+    constexpr int U = 4 * SINK_RL;
+    float m0 = INFINITY, m1 = INFINITY, m2 = INFINITY, m3 = INFINITY;
+    int y = l;
+    for (; y + 3 * SINK_RL < n; y += U) {
+        m0 = fminf(m0, v(y));
+        m1 = fminf(m1, v(y + SINK_RL));
+        m2 = fminf(m2, v(y + 2 * SINK_RL));
+        m3 = fminf(m3, v(y + 3 * SINK_RL));
     }
-    if (r < R && l == 0) f[r] = m - tau * __logf(s);
+    for (; y < n; y += SINK_RL) m0 = fminf(m0, v(y));
+    float m = fminf(fminf(m0, m1), fminf(m2, m3));
+    for (int o = SINK_RL / 2; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+    const float kl = LOG2E / tau;
+    auto e = [&](int yy) { return __builtin_amdgcn_exp2f((m - v(yy)) * kl); };
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    y = l;
+    for (; y + 3 * SINK_RL < n; y += U) {
+        s0 += e(y);
+        s1 += e(y + SINK_RL);
+        s2 += e(y + 2 * SINK_RL);
+        s3 += e(y + 3 * SINK_RL);
+    }
+    for (; y < n; y += SINK_RL) s0 += e(y);
+    float s = (s0 + s1) + (s2 + s3);
+    for (int o = SINK_RL / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (live && l == 0) f[r] = m - tau * __logf(s);
 }
 
 // Column update g(y) = -tau log sum_x exp(-(z(x,y) - f(x))/tau).  A
 // workgroup takes 64 adjacent stacked columns (the lanes, so a row's loads
 // coalesce) and SINK_CW row chunks (the wavefronts: wavefront w takes rows
-// w, w + SINK_CW, ...); the chunks' partial sums are merged in LDS.
+// w, w + SINK_CW, ...); the chunks' pairs are merged in LDS.  Each group of
+// SINK_AHEAD rows is folded into the pair (m, s) at once: its minimum
+// first, then one rescale of s and independent exponentials.
 constexpr int SINK_CW = 8;
 constexpr int SINK_AHEAD = 16;  // rows of a chunk loaded ahead
 __global__ __launch_bounds__(64 * SINK_CW) void k_sink_cols(
@@ -280,7 +304,7 @@ __global__ __launch_bounds__(64 * SINK_CW) void k_sink_cols(
     const unsigned long long *abssum, const float *f, float *g, float tau) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = blockIdx.x * 64 + lane;
-    const float k = 1.0f / tau;
+    const float k = 1.0f / tau, kl = LOG2E / tau;
     __shared__ float sm[SINK_CW][64], ss[SINK_CW][64];
     float m = INFINITY, s = 0.f;
     if (r < R) {
@@ -301,11 +325,23 @@ __global__ __launch_bounds__(64 * SINK_CW) void k_sink_cols(
                 cb[a] = CV.at(s16, col + int64_t(xc) * n);
                 fb[a] = fi[xc];
             }
+            // rows past n count as +inf: their terms are exp2(-inf) = 0
+            float vb[SINK_AHEAD];
 #pragma unroll
-            for (int a = 0; a < SINK_AHEAD; ++a) {
-                if (x0 + a * SINK_CW >= n) break;
-                lse_add(m, s, float(cb[a]) * inv - fb[a], k);
-            }
+            for (int a = 0; a < SINK_AHEAD; ++a)
+                vb[a] = x0 + a * SINK_CW < n ? float(cb[a]) * inv - fb[a] : INFINITY;
+            float mq[4] = {vb[0], vb[1], vb[2], vb[3]};
+#pragma unroll
+            for (int a = 4; a < SINK_AHEAD; ++a) mq[a & 3] = fminf(mq[a & 3], vb[a]);
+            // row x0 is below n, so mn is finite; with m = inf the old sum
+            // (0) is scaled by exp2(-inf) = 0
+            const float mn = fminf(m, fminf(fminf(mq[0], mq[1]), fminf(mq[2], mq[3])));
+            float sq[4] = {s * __builtin_amdgcn_exp2f((mn - m) * kl), 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int a = 0; a < SINK_AHEAD; ++a)
+                sq[a & 3] += __builtin_amdgcn_exp2f((mn - vb[a]) * kl);
+            s = (sq[0] + sq[1]) + (sq[2] + sq[3]);
+            m = mn;
         }
     }
     sm[w][lane] = m;

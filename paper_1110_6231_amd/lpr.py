@@ -111,6 +111,7 @@ class AssignStats(ctypes.Structure):
                 ("fixing_reruns", ctypes.c_int64),
                 ("warm_restarts", ctypes.c_int64),
                 ("scan_entries", ctypes.c_int64),
+                ("price_update_steps", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
