@@ -318,7 +318,10 @@ typedef struct {
     int64_t price_update_period;    /* pushes between global price updates
                                        (Algorithm 5.3), which run when a
                                        refine reaches its last few active
-                                       rows; 0 -> n, -1 -> never             */
+                                       rows; 0 -> n/2 for n <= 512 and n
+                                       above (measured best on the batched
+                                       and the n = 1024 workloads), -1 ->
+                                       never                               */
     int32_t tail_rows;              /* a refine switches to one wavefront
                                        running operations back to back once
                                        at most this many rows are active;

@@ -103,7 +103,8 @@ struct AArgs {
     int64_t warm_max_ops;          // > 0: budget of a warm start before it
                                    // restarts from the plain start; 0: the
                                    // default 2 n^2 + 2^16; < 0: never
-    int64_t pu_period;             // pushes between price updates; 0: n, < 0: never
+    int64_t pu_period;             // pushes between price updates; 0: n/2 up to
+                                   // n = 512, n above; < 0: never
     int32_t tail_rows;             // serial tail threshold (active rows)
     int32_t pu_start;              // price update after each refine's first push
     int32_t arc_fixing;            // keep candidate lists of unfixed arcs
@@ -760,7 +761,8 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     U.fy = U.fx + n;
     int64_t *py = L.py, *px = L.px;
     const unsigned long long period =
-        A.pu_period > 0 ? (unsigned long long)A.pu_period : (unsigned long long)n;
+        A.pu_period > 0 ? (unsigned long long)A.pu_period
+                        : (unsigned long long)(n > 512 ? n : max(1, n / 2));
     if (A.pu_period < 0) CT = nullptr;
     // the tail's cost per operation grows with n (one row scan), a phase's
     // barrier cost does not

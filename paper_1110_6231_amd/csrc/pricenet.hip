@@ -66,10 +66,21 @@ constexpr int KIN[3] = {F_IN, WID, WID};    // true input width per layer
 constexpr int KPAD[3] = {F_PAD, WID, WID};  // padded input width
 
 struct NInst {
-    int64_t cost_off;
+    int64_t cost_off;  // first entry of the instance in the int32 input
+    int64_t c16_off;   // first entry in the int16 copy (rows ld entries apart)
     int32_t n;
-    int32_t row_off;  // first stacked row (column) of the instance
+    int32_t ld;        // row stride of the int16 copy: n rounded up to 8
+    int32_t row_off;   // first stacked row (column) of the instance
+    int32_t p_off;     // first entry of the instance's padded potentials
 };
+
+// Row stride of the int16 copy and of the padded potentials: a multiple of 8
+// entries, so that every row starts 16-byte aligned and 8 costs (or 8
+// potentials, 32 bytes) are one aligned vector load.
+__host__ __device__ inline int ld16(int n) { return (n + 7) & ~7; }
+typedef int int4v __attribute__((ext_vector_type(4)));
+typedef int int2v __attribute__((ext_vector_type(2)));
+typedef float float4v __attribute__((ext_vector_type(4)));
 
 __device__ inline __bf16 to_bf16(float f) { return (__bf16)f; }
 __device__ inline float from_bf16(__bf16 b) { return (float)b; }
@@ -79,7 +90,8 @@ __device__ inline float from_bf16(__bf16 b) { return (float)b; }
 // ---------------------------------------------------------------------------
 // Row pass 1: min_y c(x,y), the instance's sum and maximum of |c|, and a
 // saturated int16 copy of sign * c that the later passes read instead of the
-// int32 input when the instance's costs fit (half the bytes per pass).
+// int32 input when the instance's costs fit (half the bytes per pass), its
+// rows padded with zeros to ld16(n) entries.
 // grid = (row blocks, B): block (i, b) takes rows ROWS1 i .. ROWS1 (i+1) - 1
 // of instance b, one wavefront per row in turn, and adds its part of the sum
 // with one atomic (the instance's rows then meet in few device-scope
@@ -98,8 +110,8 @@ __global__ __launch_bounds__(256) void k_feat_rows1(const NInst *inst,
     unsigned long long s = 0;
     unsigned amax = 0;
     for (int x = x0 + wave; x < min(x0 + ROWS1, I.n); x += 4) {
-        const int64_t base = I.cost_off + int64_t(x) * I.n;
-        const int32_t *row = costs + base;
+        const int32_t *row = costs + I.cost_off + int64_t(x) * I.n;
+        int16_t *crow = c16 + I.c16_off + int64_t(x) * I.ld;
         int mn = INT_MAX;
         for (int y = lane; y < I.n; y += 64) {
             const int c = sign * row[y];
@@ -107,8 +119,9 @@ __global__ __launch_bounds__(256) void k_feat_rows1(const NInst *inst,
             const unsigned a = unsigned(c < 0 ? -c : c);
             s += a;
             amax = max(amax, a);
-            c16[base + y] = int16_t(max(-C16_MAX, min(C16_MAX, c)));
+            crow[y] = int16_t(max(-C16_MAX, min(C16_MAX, c)));
         }
+        if (lane < I.ld - I.n) crow[I.n + lane] = 0;  // padding
         for (int o = 32; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, 64));
         if (lane == 0) rowmin[I.row_off + x] = mn;
     }
@@ -121,16 +134,50 @@ __global__ __launch_bounds__(256) void k_feat_rows1(const NInst *inst,
     if (threadIdx.x == 0) atomicAdd(&abssum[blockIdx.y], part[0] + part[1] + part[2] + part[3]);
 }
 
-// sign * c at entry idx of the packed costs: from the int16 copy when the
-// instance's |c| fits it, else from the int32 input
+// sign * c(x, y) of an instance: from the int16 copy when the instance's |c|
+// fits it, else from the int32 input
 struct Costs {
     const int32_t *c32;
     const int16_t *c16;
     const unsigned *cmax;
     int32_t sign;
     __device__ bool small(int b) const { return cmax[b] <= unsigned(C16_MAX); }
-    __device__ int at(bool s16, int64_t idx) const {
-        return s16 ? int(c16[idx]) : sign * c32[idx];
+    __device__ int at(bool s16, const NInst &I, int x, int y) const {
+        return s16 ? int(c16[I.c16_off + int64_t(x) * I.ld + y])
+                   : sign * c32[I.cost_off + int64_t(x) * I.n + y];
+    }
+    // entries y0 .. y0+7 of row x (y0 a multiple of 8); entries at or past n
+    // are 0
+    __device__ void at8(bool s16, const NInst &I, int x, int y0, int (&c)[8]) const {
+        if (s16) {
+            const int4v w = *reinterpret_cast<const int4v *>(c16 + I.c16_off +
+                                                             int64_t(x) * I.ld + y0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                c[2 * k] = int(int16_t(w[k] & 0xffff));
+                c[2 * k + 1] = w[k] >> 16;
+            }
+        } else {
+            const int32_t *row = c32 + I.cost_off + int64_t(x) * I.n;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) c[k] = y0 + k < I.n ? sign * row[y0 + k] : 0;
+        }
+    }
+    // entries y0 .. y0+3 of row x (y0 a multiple of 4, y0 < n); entries at
+    // or past n are 0 (int16 padding) or not read (int32)
+    __device__ void at4(bool s16, const NInst &I, int x, int y0, int (&c)[4]) const {
+        if (s16) {
+            const int2v w = *reinterpret_cast<const int2v *>(c16 + I.c16_off +
+                                                             int64_t(x) * I.ld + y0);
+            c[0] = int(int16_t(w[0] & 0xffff));
+            c[1] = w[0] >> 16;
+            c[2] = int(int16_t(w[1] & 0xffff));
+            c[3] = w[1] >> 16;
+        } else {
+            const int32_t *row = c32 + I.cost_off + int64_t(x) * I.n;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = y0 + k < I.n ? sign * row[y0 + k] : 0;
+        }
     }
 };
 
@@ -156,7 +203,6 @@ __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
     const int y = r - I.row_off, n = I.n;
     const float inv = 1.0f / inst_scale(I, abssum, b);
     const bool s16 = CV.small(b);
-    const int64_t col = I.cost_off + y;
     const int32_t *rm = rowmin + I.row_off;
     float top[8];
 #pragma unroll
@@ -169,7 +215,7 @@ __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
 #pragma unroll
         for (int a = 0; a < FEAT_AHEAD; ++a) {
             const int x = x0 + a < n ? x0 + a : n - 1;
-            cb[a] = CV.at(s16, col + int64_t(x) * n);
+            cb[a] = CV.at(s16, I, x, y);
             mb[a] = rm[x];
         }
 #pragma unroll
@@ -210,147 +256,219 @@ __global__ __launch_bounds__(256) void k_feat_cols1(const NInst *inst,
     f[12] = srr / n;
 }
 
-// Sinkhorn passes of f14.  A log-sum-exp of -v/tau over values v is m -
-// tau log s with m = min v and s = sum exp(-(v - m)/tau): every exponent is
-// <= 0 and the minimum's term is 1, so nothing overflows however small tau
-// is.  The row pass takes the minimum first and then the sum over the same
-// entries (a row is short and its second read hits the cache), so neither
-// loop carries a dependence beyond its accumulators; the column pass, whose
-// second read would come from further away, carries the pair (m, s) along
-// instead, rescaled once per group of rows ((inf, 0) is the empty pair).
+// Sinkhorn passes of f14: one workgroup per instance runs every iteration
+// (instances are independent, so no grid-wide step is needed), with g in
+// LDS.  A row x of an iteration, v(y) = z(x,y) - g(y) with the g of the
+// iteration before, gives
+//   m = min_y v,  e(y) = exp2((m - v(y)) log2(e) / tau),  s = sum_y e,
+//   f(x) = m - tau ln s,
+// and the same e also give the column update: exp((g(y) + f(x) - z(x,y)) /
+// tau) = e(y) / s, so
+//   g'(y) = -tau ln sum_x exp(-(z(x,y) - f(x)) / tau) = g(y) - tau ln S(y),
+//   S(y) = sum_x e(x,y) / s(x).
+// One read of the matrix per iteration, and every term is <= 1 (no
+// overflow).  S(y) is the column's mass under the row-normalised plan; if
+// it falls below 2^-100 (a column nearly no row wants, where float32 loses
+// the sum), that column is recomputed directly from the f of the iteration
+// with its own minimum (both log-sum-exps are then taken exactly as the
+// definition reads).
 constexpr float LOG2E = 1.4426950408889634f;
-
-__device__ inline void lse_merge(float &m, float &s, float m2, float s2, float k) {
-    if (s2 == 0.f) return;
-    if (s == 0.f) {
-        m = m2;
-        s = s2;
-        return;
-    }
-    const float d = m2 - m;
-    const float e = __expf(-fabsf(d) * k);
-    if (d < 0.f) {
-        s = fmaf(s, e, s2);
-        m = m2;
-    } else {
-        s = fmaf(s2, e, s);
-    }
+constexpr int SINK_W = 16;  // wavefronts per workgroup
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ inline float lane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// min and sum over the 64 lanes of a fully active wavefront, wave-uniform:
+// DPP inside rows of 16 lanes, then the four row results
+__device__ inline float wave_minf(float v) {
+    v = fminf(v, dpp_f<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = fminf(v, dpp_f<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = fminf(v, dpp_f<0x141>(v));  // row_half_mirror
+    v = fminf(v, dpp_f<0x140>(v));  // row_mirror
+    return fminf(fminf(lane_f(v, 0), lane_f(v, 16)), fminf(lane_f(v, 32), lane_f(v, 48)));
+}
+__device__ inline float wave_sumf(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
 }
 
-// Row update f(x) = -tau log sum_y exp(-(z(x,y) - g(y))/tau): SINK_RL lanes
-// per stacked row (64 / SINK_RL rows per wavefront), the row's columns
-// strided over them, reduced inside each lane group by butterfly shuffles.
-constexpr int SINK_RL = 16;
-__global__ __launch_bounds__(256) void k_sink_rows(const NInst *inst, const int32_t *rinst,
-                                                   Costs CV, int32_t R,
-                                                   const unsigned long long *abssum,
-                                                   const float *g, float *f, float tau) {
-    const int l = threadIdx.x & (SINK_RL - 1);
-    const int r = blockIdx.x * (256 / SINK_RL) + threadIdx.x / SINK_RL;
-    const bool live = r < R;
-    int n = 0;
-    int64_t row = 0;
-    float inv = 1.f;
-    bool s16 = true;
-    const float *gi = g;
-    if (live) {
-        const int b = rinst[r];
-        const NInst I = inst[b];
-        n = I.n;
-        inv = 1.0f / inst_scale(I, abssum, b);
-        s16 = CV.small(b);
-        row = I.cost_off + int64_t(r - I.row_off) * n;
-        gi = g + I.row_off;
-    }
-    auto v = [&](int y) { return float(CV.at(s16, row + y)) * inv - gi[y]; };
-    constexpr int U = 4 * SINK_RL;
-    float m0 = INFINITY, m1 = INFINITY, m2 = INFINITY, m3 = INFINITY;
-    int y = l;
-    for (; y + 3 * SINK_RL < n; y += U) {
-        m0 = fminf(m0, v(y));
-        m1 = fminf(m1, v(y + SINK_RL));
-        m2 = fminf(m2, v(y + 2 * SINK_RL));
-        m3 = fminf(m3, v(y + 3 * SINK_RL));
-    }
-    for (; y < n; y += SINK_RL) m0 = fminf(m0, v(y));
-    float m = fminf(fminf(m0, m1), fminf(m2, m3));
-    for (int o = SINK_RL / 2; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
-    const float kl = LOG2E / tau;
-    auto e = [&](int yy) { return __builtin_amdgcn_exp2f((m - v(yy)) * kl); };
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    y = l;
-    for (; y + 3 * SINK_RL < n; y += U) {
-        s0 += e(y);
-        s1 += e(y + SINK_RL);
-        s2 += e(y + 2 * SINK_RL);
-        s3 += e(y + 3 * SINK_RL);
-    }
-    for (; y < n; y += SINK_RL) s0 += e(y);
-    float s = (s0 + s1) + (s2 + s3);
-    for (int o = SINK_RL / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (live && l == 0) f[r] = m - tau * __logf(s);
-}
-
-// Column update g(y) = -tau log sum_x exp(-(z(x,y) - f(x))/tau).  A
-// workgroup takes 64 adjacent stacked columns (the lanes, so a row's loads
-// coalesce) and SINK_CW row chunks (the wavefronts: wavefront w takes rows
-// w, w + SINK_CW, ...); the chunks' pairs are merged in LDS.  Each group of
-// SINK_AHEAD rows is folded into the pair (m, s) at once: its minimum
-// first, then one rescale of s and independent exponentials.
-constexpr int SINK_CW = 8;
-constexpr int SINK_AHEAD = 16;  // rows of a chunk loaded ahead
-__global__ __launch_bounds__(64 * SINK_CW) void k_sink_cols(
-    const NInst *inst, const int32_t *rinst, Costs CV, int32_t R,
-    const unsigned long long *abssum, const float *f, float *g, float tau) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r = blockIdx.x * 64 + lane;
-    const float k = 1.0f / tau, kl = LOG2E / tau;
-    __shared__ float sm[SINK_CW][64], ss[SINK_CW][64];
-    float m = INFINITY, s = 0.f;
-    if (r < R) {
-        const int b = rinst[r];
-        const NInst I = inst[b];
-        const int y = r - I.row_off, n = I.n;
-        const float inv = 1.0f / inst_scale(I, abssum, b);
-        const bool s16 = CV.small(b);
-        const int64_t col = I.cost_off + y;
-        const float *fi = f + I.row_off;
-        for (int x0 = w; x0 < n; x0 += SINK_CW * SINK_AHEAD) {
-            int cb[SINK_AHEAD];
-            float fb[SINK_AHEAD];
-#pragma unroll
-            for (int a = 0; a < SINK_AHEAD; ++a) {
-                const int x = x0 + a * SINK_CW;
-                const int xc = x < n ? x : x0;  // a valid row; its value is not used
-                cb[a] = CV.at(s16, col + int64_t(xc) * n);
-                fb[a] = fi[xc];
-            }
-            // rows past n count as +inf: their terms are exp2(-inf) = 0
-            float vb[SINK_AHEAD];
-#pragma unroll
-            for (int a = 0; a < SINK_AHEAD; ++a)
-                vb[a] = x0 + a * SINK_CW < n ? float(cb[a]) * inv - fb[a] : INFINITY;
-            float mq[4] = {vb[0], vb[1], vb[2], vb[3]};
-#pragma unroll
-            for (int a = 4; a < SINK_AHEAD; ++a) mq[a & 3] = fminf(mq[a & 3], vb[a]);
-            // row x0 is below n, so mn is finite; with m = inf the old sum
-            // (0) is scaled by exp2(-inf) = 0
-            const float mn = fminf(m, fminf(fminf(mq[0], mq[1]), fminf(mq[2], mq[3])));
-            float sq[4] = {s * __builtin_amdgcn_exp2f((mn - m) * kl), 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int a = 0; a < SINK_AHEAD; ++a)
-                sq[a & 3] += __builtin_amdgcn_exp2f((mn - vb[a]) * kl);
-            s = (sq[0] + sq[1]) + (sq[2] + sq[3]);
-            m = mn;
-        }
-    }
-    sm[w][lane] = m;
-    ss[w][lane] = s;
+// V: 8-entry groups per lane per row (rows up to 512 V entries); RW: rows a
+// wavefront takes at once (their loads and reductions overlap).  ids[] lists
+// the instances of this launch; g is written to gpad[p_off + y].  Dynamic
+// LDS: (SINK_W + 2) ld floats (g, SINK_W partial column sums, f).
+template <int V, int RW>
+__global__ __launch_bounds__(64 * SINK_W) void k_sinkhorn(const NInst *inst,
+                                                          const int32_t *ids, Costs CV,
+                                                          const unsigned long long *abssum,
+                                                          float *gpad) {
+    extern __shared__ float sh[];
+    const int b = ids[blockIdx.x];
+    const NInst I = inst[b];
+    const int n = I.n, ld = I.ld;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float inv = 1.0f / inst_scale(I, abssum, b);
+    const bool s16 = CV.small(b);
+    float *gs = sh, *part = sh + ld, *fs = sh + (SINK_W + 1) * ld;
+    for (int y = threadIdx.x; y < ld; y += 64 * SINK_W) gs[y] = 0.f;
     __syncthreads();
-    if (w == 0 && r < R) {
-        for (int j = 1; j < SINK_CW; ++j) lse_merge(m, s, sm[j][lane], ss[j][lane], k);
-        g[r] = m - tau * __logf(s);
+    double t = SINK_TAU0;
+    for (int it = 0; it < SINK_ITERS; ++it) {
+        const float tau = float(t), kl = LOG2E / tau;
+        float acc[V][8];
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[j][k] = 0.f;
+        // rows x0 .. x0+RW-1 of this wavefront, their costs in c: v, the
+        // row minima and sums, f, and the column partial sums
+        auto rows = [&](int x0, const int (&c)[RW][V][8]) {
+            float gv[V][8];
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int yc = min(8 * (lane + 64 * j), ld - 8);
+                const float4v g0 = *reinterpret_cast<const float4v *>(gs + yc);
+                const float4v g1 = *reinterpret_cast<const float4v *>(gs + yc + 4);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    gv[j][k] = g0[k];
+                    gv[j][k + 4] = g1[k];
+                }
+            }
+            float z[RW][V][8];
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int y = 8 * (lane + 64 * j) + k;
+                        z[r][j][k] = x0 + r < n && y < n ? float(c[r][j][k]) * inv - gv[j][k]
+                                                         : INFINITY;
+                    }
+            float m[RW], sr[RW];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                float mm = INFINITY;
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) mm = fminf(mm, z[r][j][k]);
+                m[r] = wave_minf(mm);
+            }
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                float ss = 0.f;
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        z[r][j][k] = __builtin_amdgcn_exp2f((m[r] - z[r][j][k]) * kl);
+                        ss += z[r][j][k];
+                    }
+                sr[r] = wave_sumf(ss);
+            }
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                if (x0 + r >= n) break;
+                const float rs = 1.0f / sr[r];
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc[j][k] = fmaf(z[r][j][k], rs, acc[j][k]);
+                if (lane == 0) fs[x0 + r] = m[r] - tau * __logf(sr[r]);
+            }
+        };
+        // every load is unconditional, from a clamped valid address (a row
+        // past n repeats row n-1, a group past ld repeats the last one);
+        // the values are masked in rows()
+        if (s16) {
+            // the int16 rows of the next step are loaded while this step's
+            // are processed
+            auto load = [&](int x0, int4v (&q)[RW][V]) {
+#pragma unroll
+                for (int r = 0; r < RW; ++r)
+#pragma unroll
+                    for (int j = 0; j < V; ++j) {
+                        const int xr = min(x0 + r, n - 1);
+                        const int yc = min(8 * (lane + 64 * j), ld - 8);
+                        q[r][j] = *reinterpret_cast<const int4v *>(CV.c16 + I.c16_off +
+                                                                   int64_t(xr) * ld + yc);
+                    }
+            };
+            int4v q[RW][V];
+            if (RW * w < n) load(RW * w, q);
+            for (int x0 = RW * w; x0 < n; x0 += RW * SINK_W) {
+                int4v qn[RW][V];
+                if (x0 + RW * SINK_W < n) load(x0 + RW * SINK_W, qn);
+                int c[RW][V][8];
+#pragma unroll
+                for (int r = 0; r < RW; ++r)
+#pragma unroll
+                    for (int j = 0; j < V; ++j)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            c[r][j][2 * k] = int(int16_t(q[r][j][k] & 0xffff));
+                            c[r][j][2 * k + 1] = q[r][j][k] >> 16;
+                        }
+                rows(x0, c);
+#pragma unroll
+                for (int r = 0; r < RW; ++r)
+#pragma unroll
+                    for (int j = 0; j < V; ++j) q[r][j] = qn[r][j];
+            }
+        } else {
+            for (int x0 = RW * w; x0 < n; x0 += RW * SINK_W) {
+                int c[RW][V][8];
+#pragma unroll
+                for (int r = 0; r < RW; ++r)
+#pragma unroll
+                    for (int j = 0; j < V; ++j) {
+                        const int32_t *row = CV.c32 + I.cost_off + int64_t(min(x0 + r, n - 1)) * n;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            c[r][j][k] = CV.sign * row[min(8 * (lane + 64 * j) + k, n - 1)];
+                    }
+                rows(x0, c);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const int y0 = 8 * (lane + 64 * j);
+            if (y0 < ld)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) part[w * ld + y0 + k] = acc[j][k];
+        }
+        __syncthreads();  // every row read g and wrote its f and partial sums
+        for (int y = threadIdx.x; y < n; y += 64 * SINK_W) {
+            float S = 0.f;
+#pragma unroll
+            for (int q = 0; q < SINK_W; ++q) S += part[q * ld + y];
+            float gy;
+            if (S >= 0x1p-100f) {
+                gy = gs[y] - tau * __logf(S);
+            } else {
+                float mm = INFINITY;
+                for (int x = 0; x < n; ++x)
+                    mm = fminf(mm, float(CV.at(s16, I, x, y)) * inv - fs[x]);
+                float ss = 0.f;
+                for (int x = 0; x < n; ++x)
+                    ss += __builtin_amdgcn_exp2f(
+                        (mm - (float(CV.at(s16, I, x, y)) * inv - fs[x])) * kl);
+                gy = mm - tau * __logf(ss);
+            }
+            gs[y] = gy;  // every read of the old g ended at the barrier above
+        }
+        __syncthreads();
+        t = std::max(SINK_TAU_MIN, t * SINK_RATE);
     }
+    for (int y = threadIdx.x; y < n; y += 64 * SINK_W) gpad[I.p_off + y] = gs[y];
 }
 
 // Row pass 2: u2(x) = min_y (z(x,y) - f10(y)).
@@ -367,10 +485,9 @@ __global__ __launch_bounds__(256) void k_feat_rows2(const NInst *inst,
     const int x = r - I.row_off;
     const float inv = 1.0f / inst_scale(I, abssum, b);
     const bool s16 = CV.small(b);
-    const int64_t row = I.cost_off + int64_t(x) * I.n;
     float mn = INFINITY;
     for (int y = lane; y < I.n; y += 64)
-        mn = fminf(mn, float(CV.at(s16, row + y)) * inv - F[int64_t(I.row_off + y) * F_IN + 10]);
+        mn = fminf(mn, float(CV.at(s16, I, x, y)) * inv - F[int64_t(I.row_off + y) * F_IN + 10]);
     for (int o = 32; o > 0; o >>= 1) mn = fminf(mn, __shfl_xor(mn, o, 64));
     if (lane == 0) u2[r] = mn;
 }
@@ -388,7 +505,6 @@ __global__ __launch_bounds__(256) void k_feat_cols2(const NInst *inst,
     const int y = r - I.row_off, n = I.n;
     const float inv = 1.0f / inst_scale(I, abssum, b);
     const bool s16 = CV.small(b);
-    const int64_t col = I.cost_off + y;
     float mn = INFINITY;
     for (int x0 = 0; x0 < n; x0 += FEAT_AHEAD) {
         int cb[FEAT_AHEAD];
@@ -396,7 +512,7 @@ __global__ __launch_bounds__(256) void k_feat_cols2(const NInst *inst,
 #pragma unroll
         for (int a = 0; a < FEAT_AHEAD; ++a) {
             const int x = x0 + a < n ? x0 + a : n - 1;  // a repeat is harmless for a min
-            cb[a] = CV.at(s16, col + int64_t(x) * n);
+            cb[a] = CV.at(s16, I, x, y);
             ub[a] = u2[I.row_off + x];
         }
 #pragma unroll
@@ -410,7 +526,7 @@ __global__ __launch_bounds__(256) void k_feat_cols2(const NInst *inst,
 // input (row-major [Rp, 32] and, when XT is not null, transposed [32, Rp];
 // zero padded).
 __global__ __launch_bounds__(256) void k_feat_finish(const NInst *inst, int32_t Rp,
-                                                     float *F, const float *sval,
+                                                     float *F, const float *gpad,
                                                      const float *v2, __bf16 *X,
                                                      __bf16 *XT) {
     const NInst I = inst[blockIdx.x];
@@ -418,7 +534,7 @@ __global__ __launch_bounds__(256) void k_feat_finish(const NInst *inst, int32_t 
     float a = 0.f, c = 0.f;
     for (int y = threadIdx.x; y < I.n; y += 256) {
         a += v2[I.row_off + y];
-        c += sval[I.row_off + y];
+        c += gpad[I.p_off + y];
     }
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o, 64);
@@ -436,7 +552,7 @@ __global__ __launch_bounds__(256) void k_feat_finish(const NInst *inst, int32_t 
         const int r = I.row_off + y;
         float *f = F + int64_t(r) * F_IN;
         f[13] = v2[r] - mv;
-        f[14] = sval[r] - ms;
+        f[14] = gpad[I.p_off + y] - ms;
         f[15] = ln;
         for (int k = 0; k < F_PAD; ++k) {
             const __bf16 v = to_bf16(k < F_IN ? f[k] : 0.f);
@@ -763,8 +879,10 @@ struct Layout {
     int32_t *rinst, *rowmin;
     unsigned long long *abssum;
     unsigned *cmax;   // per instance max |c|
-    int16_t *c16;     // saturated int16 copy of sign * c, packed like the input
-    float *F, *sval, *u2, *v2;
+    int16_t *c16;     // saturated int16 copy of sign * c, rows padded to ld16(n)
+    int32_t *sids;    // instances of the Sinkhorn launches, grouped by row length
+    float *gpad;      // Sinkhorn column potentials, ld16(n) entries per instance
+    float *F, *u2, *v2;
     __bf16 *X0, *X0T;
     float *Z[3];
     __bf16 *H[3], *HT[3];
@@ -776,16 +894,33 @@ struct Layout {
 
 static int64_t pad64(int64_t r) { return (r + 63) / 64 * 64; }
 
-static Carver carve(Carver cv, int B, int64_t R, int64_t E, Layout *L) {
-    const int64_t Rp = pad64(R);
+// Sizes of a batch: R stacked columns, P padded potentials (sum of
+// ld16(n)), E16 entries of the padded int16 copy.
+struct Sizes {
+    int64_t R = 0, P = 0, E16 = 0;
+};
+
+static Sizes sizes(int B, const int32_t *n) {
+    Sizes z;
+    for (int b = 0; b < B; ++b) {
+        z.R += n[b];
+        z.P += ld16(n[b]);
+        z.E16 += int64_t(n[b]) * ld16(n[b]);
+    }
+    return z;
+}
+
+static Carver carve(Carver cv, int B, const Sizes &z, Layout *L) {
+    const int64_t R = z.R, Rp = pad64(R);
     L->inst = cv.take<NInst>(B);
     L->rinst = cv.take<int32_t>(R);
     L->rowmin = cv.take<int32_t>(R);
     L->abssum = cv.take<unsigned long long>(B);
     L->cmax = cv.take<unsigned>(B);
-    L->c16 = cv.take<int16_t>(E);
+    L->c16 = cv.take<int16_t>(z.E16);
+    L->sids = cv.take<int32_t>(B);
+    L->gpad = cv.take<float>(z.P);
     L->F = cv.take<float>(R * F_IN);
-    L->sval = cv.take<float>(R);
     L->u2 = cv.take<float>(R);
     L->v2 = cv.take<float>(R);
     L->X0 = cv.take<__bf16>(Rp * F_PAD);
@@ -812,21 +947,9 @@ static Carver carve(Carver cv, int B, int64_t R, int64_t E, Layout *L) {
     return cv;
 }
 
-static int64_t total_rows(int B, const int32_t *n) {
-    int64_t R = 0;
-    for (int b = 0; b < B; ++b) R += n[b];
-    return R;
-}
-
-static int64_t total_entries(int B, const int32_t *n) {
-    int64_t E = 0;
-    for (int b = 0; b < B; ++b) E += int64_t(n[b]) * n[b];
-    return E;
-}
-
 static size_t workspace_bytes(int B, const int32_t *n) {
     Layout L;
-    return carve(Carver(), B, total_rows(B, n), total_entries(B, n), &L).used();
+    return carve(Carver(), B, sizes(B, n), &L).used();
 }
 
 struct Ctx {
@@ -835,7 +958,8 @@ struct Ctx {
     Layout L;
     hipStream_t s;
     std::vector<NInst> insts;
-    std::vector<int32_t> rinst;
+    std::vector<int32_t> rinst, sids;
+    int sclass[3] = {0, 0, 0};  // Sinkhorn instances per row-length class
 };
 
 static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
@@ -852,7 +976,7 @@ static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
     }
     C.B = B;
     C.insts.resize(B);
-    int64_t R = 0;
+    int64_t R = 0, P = 0, E16 = 0;
     for (int b = 0; b < B; ++b) {
         if (n[b] < 1 || n[b] > LPR_ASSIGN_MAX_N) {
             set_error("instance %d: n = %d outside [1, %d]", b, n[b], LPR_ASSIGN_MAX_N);
@@ -862,8 +986,10 @@ static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
             set_error("cost_offset is not the prefix sum of n^2 at %d", b);
             return LPR_EINVAL;
         }
-        C.insts[b] = NInst{cost_offset[b], n[b], int32_t(R)};
+        C.insts[b] = NInst{cost_offset[b], E16, n[b], ld16(n[b]), int32_t(R), int32_t(P)};
         R += n[b];
+        P += ld16(n[b]);
+        E16 += int64_t(n[b]) * ld16(n[b]);
     }
     if (R >= (int64_t(1) << 28)) {
         set_error("too many columns");
@@ -876,7 +1002,7 @@ static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
         set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
         return LPR_ENOMEM;
     }
-    carve(Carver(ws, ws_bytes), B, R, total_entries(B, n), &C.L);
+    carve(Carver(ws, ws_bytes), B, sizes(B, n), &C.L);
     C.rinst.resize(R);
     for (int b = 0; b < B; ++b)
         std::fill(C.rinst.begin() + C.insts[b].row_off,
@@ -885,6 +1011,21 @@ static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
     LPR_TRY_HIP(hipMemcpyAsync(C.L.inst, C.insts.data(), sizeof(NInst) * B,
                                hipMemcpyHostToDevice, C.s));
     LPR_TRY_HIP(hipMemcpyAsync(C.L.rinst, C.rinst.data(), sizeof(int32_t) * R,
+                               hipMemcpyHostToDevice, C.s));
+    // Sinkhorn launches: instances with rows up to 512, 1024, 2048 entries,
+    // the largest first in each
+    C.sids.clear();
+    for (int cls = 0; cls < 3; ++cls) {
+        const int lo = cls == 0 ? 0 : 256 << cls, hi = 512 << cls;
+        std::vector<int32_t> ids;
+        for (int b = 0; b < B; ++b)
+            if (n[b] > lo && n[b] <= hi) ids.push_back(b);
+        std::stable_sort(ids.begin(), ids.end(),
+                         [&](int32_t a, int32_t c) { return n[a] > n[c]; });
+        C.sclass[cls] = int(ids.size());
+        C.sids.insert(C.sids.end(), ids.begin(), ids.end());
+    }
+    LPR_TRY_HIP(hipMemcpyAsync(C.L.sids, C.sids.data(), sizeof(int32_t) * B,
                                hipMemcpyHostToDevice, C.s));
     return LPR_OK;
 }
@@ -904,23 +1045,36 @@ static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign, bool 
                        L.inst, costs, sign, L.rowmin, L.abssum, L.c16, L.cmax);
     hipLaunchKernelGGL(k_feat_cols1, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
                        L.inst, L.rinst, CV, R, L.rowmin, L.abssum, L.F);
-    // f14: annealed Sinkhorn potentials, rows into u2 (scratch until the
-    // next pass), columns into sval, from g = 0
-    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.sval), 0, R, C.s));
-    double tau = SINK_TAU0;
-    for (int it = 0; it < SINK_ITERS; ++it) {
-        hipLaunchKernelGGL(k_sink_rows, dim3(ceil_div(R, 256 / SINK_RL)), dim3(256), 0, C.s,
-                           L.inst, L.rinst, CV, R, L.abssum, L.sval, L.u2, float(tau));
-        hipLaunchKernelGGL(k_sink_cols, dim3(ceil_div(R, 64)), dim3(64 * SINK_CW), 0, C.s,
-                           L.inst, L.rinst, CV, R, L.abssum, L.u2, L.sval, float(tau));
-        tau = std::max(SINK_TAU_MIN, tau * SINK_RATE);
+    // f14: annealed Sinkhorn potentials, one workgroup per instance
+    {
+        const int32_t *ids = L.sids;
+        for (int cls = 0; cls < 3; ++cls) {
+            const int cnt = C.sclass[cls];
+            if (!cnt) continue;
+            const size_t lds = sizeof(float) * (SINK_W + 2) * (512 << cls);
+            const void *fn = cls == 0   ? reinterpret_cast<const void *>(k_sinkhorn<1, 4>)
+                             : cls == 1 ? reinterpret_cast<const void *>(k_sinkhorn<2, 2>)
+                                        : reinterpret_cast<const void *>(k_sinkhorn<4, 1>);
+            LPR_TRY_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            int(lds)));
+            if (cls == 0)
+                hipLaunchKernelGGL((k_sinkhorn<1, 4>), dim3(cnt), dim3(64 * SINK_W), lds, C.s,
+                                   L.inst, ids, CV, L.abssum, L.gpad);
+            else if (cls == 1)
+                hipLaunchKernelGGL((k_sinkhorn<2, 2>), dim3(cnt), dim3(64 * SINK_W), lds, C.s,
+                                   L.inst, ids, CV, L.abssum, L.gpad);
+            else
+                hipLaunchKernelGGL((k_sinkhorn<4, 1>), dim3(cnt), dim3(64 * SINK_W), lds, C.s,
+                                   L.inst, ids, CV, L.abssum, L.gpad);
+            ids += cnt;
+        }
     }
     hipLaunchKernelGGL(k_feat_rows2, dim3(ceil_div(R, 4)), dim3(256), 0, C.s,
                        L.inst, L.rinst, CV, R, L.abssum, L.F, L.u2);
     hipLaunchKernelGGL(k_feat_cols2, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
                        L.inst, L.rinst, CV, R, L.abssum, L.u2, L.v2);
     hipLaunchKernelGGL(k_feat_finish, dim3(C.B), dim3(256), 0, C.s, L.inst,
-                       int32_t(C.Rp), L.F, L.sval, L.v2, L.X0, train ? L.X0T : nullptr);
+                       int32_t(C.Rp), L.F, L.gpad, L.v2, L.X0, train ? L.X0T : nullptr);
     LPR_TRY_HIP(hipGetLastError());
     return LPR_OK;
 }

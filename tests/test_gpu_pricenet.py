@@ -95,6 +95,26 @@ def test_features_match_oracle():
         np.testing.assert_allclose(F[a:b], fw, atol=3e-3, rtol=1e-3)
 
 
+def test_sinkhorn_column_nobody_wants():
+    """One column far dearer than the rest for every row: its mass under the
+    row-normalised plan underflows float32 at once, so the GPU takes that
+    column's update directly from the row potentials (its own minimum and
+    sum).  f14 must still match the oracle; the other instances of the
+    batch, of all three row-length classes of the Sinkhorn launch, too."""
+    c = synth.assign_random_small(64, 7, lo=0, hi=100).copy()
+    c[:, 5] = 30000
+    mats = [c, synth.assign_points(600, seed=4, instance=1),
+            synth.assign_points(1100, seed=4, instance=2)]
+    packed = _packed(mats)
+    print("[net] sinkhorn fallback", packed.ns, flush=True)
+    F, _ = lpr.lpr_pricenet_features(packed)
+    F = F.cpu().numpy()
+    for k, m in enumerate(mats):
+        fw, _ = P.features(m)
+        a, b = packed.row_offset[k], packed.row_offset[k + 1]
+        np.testing.assert_allclose(F[a:b, 14], fw[:, 14], atol=3e-3, rtol=1e-3)
+
+
 def test_forward_and_gradient_match_oracle():
     mats = [synth.assign_points(n, seed=3, instance=k + 1)
             for k, n in enumerate([64, 97, 200])]
