@@ -290,15 +290,14 @@ def assign_single(torch, lpr, synth, reps=3):
 def assign_leg(args, torch, lpr, synth):
     dev = torch.device("cuda:0")
     out, cost1024 = assign_single(torch, lpr, synth)
-    from paper_1110_6231_amd.train_pricenet import learned_solve, load_weights
+    from paper_1110_6231_amd.train_pricenet import learned_solve, load_predictor
     mats = synth.assign_batch(seed=0)
     packed = lpr.PackedAssign.from_matrices(mats, device=dev)
     wsb = torch.empty(lpr.lpr_assign_batched_workspace(packed.ns),
                       dtype=torch.uint8, device=dev)
     wsn = torch.empty(lpr.lpr_pricenet_workspace(packed.ns), dtype=torch.uint8,
                       device=dev)
-    theta, kappa, _ = load_weights()
-    params = torch.as_tensor(theta, device=dev)
+    params, kappa, meta = load_predictor(dev)
     timed = lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_TIME_KERNELS)
 
     def plain(opts=None):
@@ -332,7 +331,8 @@ def assign_leg(args, torch, lpr, synth):
                                   "ms_per_batch": round(tl * 1e3, 3),
                                   "ops": stl["pushes"] + stl["relabels"],
                                   "warm_restarts": stl["warm_restarts"],
-                                  "kappa": kappa},
+                                  "kappa": kappa,
+                                  "correction": meta.get("correction")},
                       "time_to_optimal_plain_over_learned": round(tp / tl, 3),
                       "ops_plain_over_learned": round(
                           (stp["pushes"] + stp["relabels"]) /

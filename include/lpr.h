@@ -504,8 +504,11 @@ lpr_status lpr_pricenet_features(int32_t B, const int32_t *n,
                                  float *feats, float *scales, void *workspace,
                                  size_t workspace_bytes, void *stream);
 
-/* Forward pass.  params: device float [param_count].  Outputs (device, each
- * may be NULL): q float [sum n] (raw network output); col_prices int64
+/* Forward pass.  params: device float [param_count], or NULL for a model
+ * whose correction is zero: the prediction is then f14 alone, and the
+ * feature passes only the network reads and the network itself are skipped
+ * (the same q as a network with w_o = 0, b_o = 0).  Outputs (device, each
+ * may be NULL): q float [sum n] (raw prediction); col_prices int64
  * [sum n], the scaled start prices rint((q - mean q) * sc * (2n+1)) to pass
  * as lpr_assign_opts.init_col_prices; eps0 int64 [B], the starting epsilon
  * max(1, rint(kappa * sc * (2n+1))) per instance to pass as

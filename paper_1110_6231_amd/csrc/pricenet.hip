@@ -329,17 +329,19 @@ __global__ __launch_bounds__(64 * SINK_W) void k_sinkhorn(const NInst *inst,
         // rows x0 .. x0+RW-1 of this wavefront, their costs in c: v, the
         // row minima and sums, f, and the column partial sums
         auto rows = [&](int x0, const int (&c)[RW][V][8]) {
-            float gv[V][8];
+            // -g of the lane's columns, +inf past n (also in a group the
+            // clamp repeats), so that v = c / sc - g is one fma, and +inf
+            // there; rows past n are computed and dropped
+            float ng[V][8];
 #pragma unroll
             for (int j = 0; j < V; ++j) {
-                const int yc = min(8 * (lane + 64 * j), ld - 8);
+                const int y0 = 8 * (lane + 64 * j);
+                const int yc = min(y0, ld - 8);
                 const float4v g0 = *reinterpret_cast<const float4v *>(gs + yc);
                 const float4v g1 = *reinterpret_cast<const float4v *>(gs + yc + 4);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    gv[j][k] = g0[k];
-                    gv[j][k + 4] = g1[k];
-                }
+                for (int k = 0; k < 8; ++k)
+                    ng[j][k] = y0 + k < n ? -(k < 4 ? g0[k] : g1[k - 4]) : INFINITY;
             }
             float z[RW][V][8];
 #pragma unroll
@@ -347,11 +349,7 @@ __global__ __launch_bounds__(64 * SINK_W) void k_sinkhorn(const NInst *inst,
 #pragma unroll
                 for (int j = 0; j < V; ++j)
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int y = 8 * (lane + 64 * j) + k;
-                        z[r][j][k] = x0 + r < n && y < n ? float(c[r][j][k]) * inv - gv[j][k]
-                                                         : INFINITY;
-                    }
+                    for (int k = 0; k < 8; ++k) z[r][j][k] = fmaf(float(c[r][j][k]), inv, ng[j][k]);
             float m[RW], sr[RW];
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
@@ -364,12 +362,14 @@ __global__ __launch_bounds__(64 * SINK_W) void k_sinkhorn(const NInst *inst,
             }
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
+                // exp2((m - v) kl) with the product m kl taken once
+                const float mk = m[r] * kl;
                 float ss = 0.f;
 #pragma unroll
                 for (int j = 0; j < V; ++j)
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
-                        z[r][j][k] = __builtin_amdgcn_exp2f((m[r] - z[r][j][k]) * kl);
+                        z[r][j][k] = __builtin_amdgcn_exp2f(fmaf(z[r][j][k], -kl, mk));
                         ss += z[r][j][k];
                     }
                 sr[r] = wave_sumf(ss);
@@ -560,6 +560,22 @@ __global__ __launch_bounds__(256) void k_feat_finish(const NInst *inst, int32_t 
             if (XT) XT[int64_t(k) * Rp + r] = v;
         }
     }
+}
+
+// Prediction without a network (its correction taken as zero): q = f14, the
+// centred Sinkhorn potential, with the mean taken as k_feat_finish takes it
+// (the same value a network with a zero head adds to f14).
+__global__ __launch_bounds__(256) void k_q_sinkhorn(const NInst *inst, const float *gpad,
+                                                    float *q) {
+    const NInst I = inst[blockIdx.x];
+    __shared__ float red[4];
+    float c = 0.f;
+    for (int y = threadIdx.x; y < I.n; y += 256) c += gpad[I.p_off + y];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    const float ms = (red[0] + red[1] + red[2] + red[3]) / I.n;
+    for (int y = threadIdx.x; y < I.n; y += 256) q[I.row_off + y] = gpad[I.p_off + y] - ms;
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,21 +1046,20 @@ static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
     return LPR_OK;
 }
 
-static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign, bool train) {
+// Row pass 1 (row minima, scales, the int16 copy) and the Sinkhorn
+// potentials into gpad: what every prediction needs.  `net`: also the
+// network's other features and its bf16 input (`train`: transposed too).
+static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign, bool train,
+                               bool net = true) {
     Layout &L = C.L;
     const int R = int(C.R);
     LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.abssum), 0, C.B, C.s));
     LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.cmax), 0, C.B, C.s));
     const Costs CV{costs, L.c16, L.cmax, sign};
-    // padding rows of the bf16 input are zero
-    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0), 0, C.Rp * F_PAD / 2, C.s));
-    if (train) LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0T), 0, C.Rp * F_PAD / 2, C.s));
     int nmax = 0;
     for (const NInst &I : C.insts) nmax = std::max(nmax, int(I.n));
     hipLaunchKernelGGL(k_feat_rows1, dim3(ceil_div(nmax, ROWS1), C.B), dim3(256), 0, C.s,
                        L.inst, costs, sign, L.rowmin, L.abssum, L.c16, L.cmax);
-    hipLaunchKernelGGL(k_feat_cols1, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
-                       L.inst, L.rinst, CV, R, L.rowmin, L.abssum, L.F);
     // f14: annealed Sinkhorn potentials, one workgroup per instance
     {
         const int32_t *ids = L.sids;
@@ -1069,6 +1084,15 @@ static lpr_status run_features(Ctx &C, const int32_t *costs, int32_t sign, bool 
             ids += cnt;
         }
     }
+    if (!net) {
+        LPR_TRY_HIP(hipGetLastError());
+        return LPR_OK;
+    }
+    // padding rows of the bf16 input are zero
+    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0), 0, C.Rp * F_PAD / 2, C.s));
+    if (train) LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.X0T), 0, C.Rp * F_PAD / 2, C.s));
+    hipLaunchKernelGGL(k_feat_cols1, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
+                       L.inst, L.rinst, CV, R, L.rowmin, L.abssum, L.F);
     hipLaunchKernelGGL(k_feat_rows2, dim3(ceil_div(R, 4)), dim3(256), 0, C.s,
                        L.inst, L.rinst, CV, R, L.abssum, L.F, L.u2);
     hipLaunchKernelGGL(k_feat_cols2, dim3(ceil_div(R, 256)), dim3(256), 0, C.s,
@@ -1195,15 +1219,21 @@ extern "C" lpr_status lpr_pricenet_infer(int32_t B, const int32_t *n,
                                          float *q, int64_t *col_prices,
                                          int64_t *eps0, void *workspace,
                                          size_t workspace_bytes, void *stream) {
-    if (!params || (eps0 && !(kappa > 0.f))) {
+    if (eps0 && !(kappa > 0.f)) {
         clear_error();
-        set_error("NULL params, or eps0 requested with kappa <= 0");
+        set_error("eps0 requested with kappa <= 0");
         return LPR_EINVAL;
     }
     net::Ctx C;
     LPR_TRY(net::prepare(C, B, n, cost_offset, costs, workspace, workspace_bytes, stream));
-    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1, false));
-    LPR_TRY(net::run_forward(C, params, false));
+    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1, false, params != nullptr));
+    if (params) {
+        LPR_TRY(net::run_forward(C, params, false));
+    } else {
+        hipLaunchKernelGGL(net::k_q_sinkhorn, dim3(B), dim3(256), 0, C.s, C.L.inst, C.L.gpad,
+                           C.L.q);
+        LPR_TRY_HIP(hipGetLastError());
+    }
     if (col_prices || eps0) {
         hipLaunchKernelGGL(net::k_prices, dim3(B), dim3(256), 0, C.s, C.L.inst,
                            C.L.abssum, C.L.q, col_prices, kappa, eps0);

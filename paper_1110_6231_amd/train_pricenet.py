@@ -61,8 +61,21 @@ def load_weights(path=DEFAULT_WEIGHTS):
     return params, kappa, meta
 
 
+def load_predictor(device, path=DEFAULT_WEIGHTS):
+    """(params, kappa, meta) for inference: params is the device tensor of the
+    network, or None when the selected model is the zero correction (the
+    library then predicts f14 alone and skips the network and the features
+    only it reads; the prices are the same)."""
+    import torch
+    theta, kappa, meta = load_weights(path)
+    if meta.get("correction") == "zero_correction":
+        return None, kappa, meta
+    return torch.as_tensor(theta, device=device), kappa, meta
+
+
 def learned_solve(packed, params, kappa, lpr, ws_net=None, ws_solve=None):
-    """Features + network + warm-started solve, all in the library."""
+    """Features + network (or f14 alone, params None) + warm-started solve,
+    all in the library."""
     _, prices, eps = lpr.lpr_pricenet_infer(packed, params, kappa=kappa,
                                             workspace=ws_net)
     opts = lpr.make_assign_opts(init_col_prices=prices, eps0_per_instance=eps)

@@ -304,6 +304,25 @@ def test_start_prices_match_oracle_committed_weights():
         assert abs(int(eps[k]) - P.start_epsilon(m, kappa)) <= 1
 
 
+def test_prediction_without_network_equals_zero_head():
+    """params NULL (the selected model is the zero correction): the library
+    skips the network and the features only it reads, and must return the
+    same start prices and epsilons as the network with a zero head, whose
+    output is exactly its skip term f14."""
+    mats = [synth.assign_points(n, seed=11, instance=k + 1)
+            for k, n in enumerate([64, 333, 512, 700])]
+    packed = _packed(mats)
+    theta = P.init_params(1)
+    theta[-129:] = 0.0
+    params = torch.as_tensor(theta, device="cuda")
+    print("[net] prediction without network", packed.ns, flush=True)
+    q0, p0, e0 = lpr.lpr_pricenet_infer(packed, params, kappa=1 / 1024)
+    q1, p1, e1 = lpr.lpr_pricenet_infer(packed, None, kappa=1 / 1024)
+    assert torch.equal(p0, p1)
+    assert torch.equal(e0, e1)
+    assert torch.equal(q0, q1)
+
+
 def test_training_reduces_loss_and_solves_stay_exact():
     mats = synth.assign_batch(seed=0, count=12, train=True)
     packed = _packed(mats)
@@ -337,10 +356,9 @@ def test_learned_start_gain_on_held_out_instances():
     both exact; the learned start must need fewer push/relabel operations.
     The measured ratios are printed."""
     import time
-    from paper_1110_6231_amd.train_pricenet import learned_solve, load_weights
+    from paper_1110_6231_amd.train_pricenet import learned_solve, load_predictor
 
-    theta, kappa, meta = load_weights()
-    params = torch.as_tensor(theta, device="cuda")
+    params, kappa, meta = load_predictor("cuda")
     mats = synth.assign_batch(seed=0, count=64)
     packed = _packed(mats)
     _, tot_p, _, st_p = lpr.lpr_assign_solve_batched(packed)
@@ -373,9 +391,8 @@ def test_full_batched_workload_against_oracle(seed):
     committed network's start: every total equals the Hungarian oracle's,
     every assignment is a permutation costing that total, and every returned
     price vector certifies 1-optimality."""
-    from paper_1110_6231_amd.train_pricenet import learned_solve, load_weights
-    theta, kappa, _ = load_weights()
-    params = torch.as_tensor(theta, device="cuda")
+    from paper_1110_6231_amd.train_pricenet import learned_solve, load_predictor
+    params, kappa, _ = load_predictor("cuda")
     mats = synth.assign_batch(seed=seed)
     packed = _packed(mats)
     print(f"[net] full batched workload seed {seed}: {len(mats)} instances, "
