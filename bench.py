@@ -90,6 +90,10 @@ def parse():
     ap.add_argument("--assign-only", action="store_true",
                     help="only the n = 1024 assignment (for counter profiles "
                          "of its kernel)")
+    ap.add_argument("--batched-assign-only", action="store_true",
+                    help="only the batched assignment legs, plain and learned "
+                         "start (for kernel traces of the inference and solve "
+                         "kernels; no CPU oracle)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain copies of a known size (counter "
                          "calibration) and exit")
@@ -287,9 +291,9 @@ def assign_single(torch, lpr, synth, reps=3):
             "roofline": assign_roofline(sti)}, cost_np
 
 
-def assign_leg(args, torch, lpr, synth):
+def assign_leg(args, torch, lpr, synth, single=True):
     dev = torch.device("cuda:0")
-    out, cost1024 = assign_single(torch, lpr, synth)
+    out, cost1024 = assign_single(torch, lpr, synth) if single else ({}, None)
     from paper_1110_6231_amd.train_pricenet import learned_solve, load_predictor
     mats = synth.assign_batch(seed=0)
     packed = lpr.PackedAssign.from_matrices(mats, device=dev)
@@ -337,7 +341,7 @@ def assign_leg(args, torch, lpr, synth):
                       "ops_plain_over_learned": round(
                           (stp["pushes"] + stp["relabels"]) /
                           (stl["pushes"] + stl["relabels"]), 3)}
-    if not args.no_cpu:
+    if not args.no_cpu and single:
         cpu, want1024, want_batch = cpu_assign_leg(cost1024, mats)
         assert out["total"] == want1024, ("n=1024 total differs from the oracle",
                                           out["total"], want1024)
@@ -569,6 +573,10 @@ def main():
         return
     if args.assign_only:
         print(json.dumps({"assignment": assign_single(torch, lpr, synth)[0]}), flush=True)
+        return
+    if args.batched_assign_only:
+        print(json.dumps({"assignment": assign_leg(args, torch, lpr, synth, single=False)}),
+              flush=True)
         return
     g = grid_batched_leg(args, torch, lpr, synth)
     acc, st = g["acc"], g["st"]

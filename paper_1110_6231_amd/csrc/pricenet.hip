@@ -978,9 +978,11 @@ struct Ctx {
     int sclass[3] = {0, 0, 0};  // Sinkhorn instances per row-length class
 };
 
+// `rows`: also the per-column instance index the feature passes and the
+// network read (a prediction without the network needs none of it).
 static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
                           const int64_t *cost_offset, const int32_t *costs,
-                          void *ws, size_t ws_bytes, void *stream) {
+                          void *ws, size_t ws_bytes, void *stream, bool rows = true) {
     clear_error();
     if (B < 1 || !n || !cost_offset || !costs || !ws) {
         set_error("invalid arguments (NULL pointer or B < 1)");
@@ -1019,15 +1021,17 @@ static lpr_status prepare(Ctx &C, int32_t B, const int32_t *n,
         return LPR_ENOMEM;
     }
     carve(Carver(ws, ws_bytes), B, sizes(B, n), &C.L);
-    C.rinst.resize(R);
-    for (int b = 0; b < B; ++b)
-        std::fill(C.rinst.begin() + C.insts[b].row_off,
-                  C.rinst.begin() + C.insts[b].row_off + n[b], b);
+    C.rinst.resize(rows ? R : 0);
+    if (rows)
+        for (int b = 0; b < B; ++b)
+            std::fill(C.rinst.begin() + C.insts[b].row_off,
+                      C.rinst.begin() + C.insts[b].row_off + n[b], b);
     C.s = static_cast<hipStream_t>(stream);
     LPR_TRY_HIP(hipMemcpyAsync(C.L.inst, C.insts.data(), sizeof(NInst) * B,
                                hipMemcpyHostToDevice, C.s));
-    LPR_TRY_HIP(hipMemcpyAsync(C.L.rinst, C.rinst.data(), sizeof(int32_t) * R,
-                               hipMemcpyHostToDevice, C.s));
+    if (rows)
+        LPR_TRY_HIP(hipMemcpyAsync(C.L.rinst, C.rinst.data(), sizeof(int32_t) * R,
+                                   hipMemcpyHostToDevice, C.s));
     // Sinkhorn launches: instances with rows up to 512, 1024, 2048 entries,
     // the largest first in each
     C.sids.clear();
@@ -1225,7 +1229,8 @@ extern "C" lpr_status lpr_pricenet_infer(int32_t B, const int32_t *n,
         return LPR_EINVAL;
     }
     net::Ctx C;
-    LPR_TRY(net::prepare(C, B, n, cost_offset, costs, workspace, workspace_bytes, stream));
+    LPR_TRY(net::prepare(C, B, n, cost_offset, costs, workspace, workspace_bytes, stream,
+                         params != nullptr));
     LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1, false, params != nullptr));
     if (params) {
         LPR_TRY(net::run_forward(C, params, false));
