@@ -730,7 +730,9 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
     }
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     uint32_t acted = 0;                        // bit r: the pixel pushed or relabelled
-    unsigned long long pushes = 0, relabels = 0;  // wave-uniform
+    // this lane's pushes and relabels, summed over the wavefront once at
+    // the end (a ballot count per row would cost scalar 64-bit adds there)
+    uint32_t lane_push = 0, lane_relab = 0;
     for (int it = 0; it < L; ++it) {
         bool any = false;                      // wave-uniform
 #pragma unroll
@@ -786,11 +788,16 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
             rr[r] += inR;
             e[r] += inL + inR;
             acted |= active ? 1u << r : 0u;
-            pushes += __popcll(__ballot(push));
-            relabels += __popcll(__ballot(relab));
+            lane_push += push;
+            lane_relab += relab;
         }
         if (!any) break;
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        lane_push += __shfl_xor(lane_push, o, 64);
+        lane_relab += __shfl_xor(lane_relab, o, 64);
+    }
+    const unsigned long long pushes = lane_push, relabels = lane_relab;
     // Write back the pixels whose state can have changed (they or an in-tile
     // neighbour acted): plain stores where only this tile writes, an atomic
     // delta for the excess of pixels that other tiles can push into, and the
