@@ -65,11 +65,11 @@ GRID_SRC = os.path.join(ROOT, "paper_1110_6231_amd", "csrc", "grid_maxflow.hip")
 # source file at measurement time; a changed source reports null.
 MEASURED_TRAFFIC = {
     ("k_sweep<16>", "batched"): {
-        "source_sha256": "139fed459f1345fbcc9fdb01637fb834f8a04c71150524ba34609da6520010e1",
-        "bytes_per_launch": 74102962},
+        "source_sha256": "9608b8f3ad743c1a9b1f858fe0b3a6011456d10cf3bf7f8be78b3f679658d273",
+        "bytes_per_launch": 76444774},
     ("k_relax4<false>", "batched"): {
-        "source_sha256": "139fed459f1345fbcc9fdb01637fb834f8a04c71150524ba34609da6520010e1",
-        "bytes_per_launch": 6592042},
+        "source_sha256": "9608b8f3ad743c1a9b1f858fe0b3a6011456d10cf3bf7f8be78b3f679658d273",
+        "bytes_per_launch": 6658765},
 }
 
 
