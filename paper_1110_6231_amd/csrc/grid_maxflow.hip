@@ -744,21 +744,23 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
             const int32_t hr = from_right(h[r], hside[r]);
             const int32_t hd = r + 1 < TH ? h[r + 1] : bot;
             const int32_t hu = r > 0 ? h[r - 1] : top;
-            uint32_t key = rs[r] > 0 ? 0u : NONE;
-            key = min(key, rr[r] > 0 ? (uint32_t(hr) << 3) | 1u : NONE);
-            key = min(key, rl[r] > 0 ? (uint32_t(hl) << 3) | 2u : NONE);
-            key = min(key, rd[r] > 0 ? (uint32_t(hd) << 3) | 3u : NONE);
-            key = min(key, ru[r] > 0 ? (uint32_t(hu) << 3) | 4u : NONE);
+            const uint32_t kS = rs[r] > 0 ? 0u : NONE;
+            const uint32_t kR = rr[r] > 0 ? (uint32_t(hr) << 3) | 1u : NONE;
+            const uint32_t kL = rl[r] > 0 ? (uint32_t(hl) << 3) | 2u : NONE;
+            const uint32_t kD = rd[r] > 0 ? (uint32_t(hd) << 3) | 3u : NONE;
+            const uint32_t kU = ru[r] > 0 ? (uint32_t(hu) << 3) | 4u : NONE;
+            const uint32_t key = min(min(min(kS, kR), kL), min(kD, kU));
             const uint32_t best = key >> 3;    // NONE >> 3 exceeds every height
             const uint32_t dir = key & 7u;
             const bool push = active && best < uint32_t(h[r]);
             const bool relab = active && !push;
-            // PUSH delta = min(e', u_f(x, y~)) towards y~
-            // the chosen arc's residual (a masked maximum: a select chain over
-            // the arrays would make the compiler address them in memory)
-            const int32_t cap = max(max(max(dir == 0 ? rs[r] : 0, dir == 1 ? rr[r] : 0),
-                                        max(dir == 2 ? rl[r] : 0, dir == 3 ? rd[r] : 0)),
-                                    dir == 4 ? ru[r] : 0);
+            // PUSH delta = min(e', u_f(x, y~)) towards y~, u_f the chosen
+            // arc's residual (selected by constant-indexed registers)
+            int32_t cap = rs[r];
+            cap = dir == 1 ? rr[r] : cap;
+            cap = dir == 2 ? rl[r] : cap;
+            cap = dir == 3 ? rd[r] : cap;
+            cap = dir == 4 ? ru[r] : cap;
             const int32_t d = push ? min(e[r], cap) : 0;
             const int32_t dS = dir == 0 ? d : 0, dR = dir == 1 ? d : 0;
             const int32_t dL = dir == 2 ? d : 0, dD = dir == 3 ? d : 0;
@@ -779,7 +781,7 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
             }
             // RELABEL h(x) = h~ + 1 (owner only); no residual arc or a height
             // past |V| freezes the pixel (gap height)
-            if (relab) h[r] = best >= uint32_t(HV - 1) ? HV : int32_t(best) + 1;
+            if (relab) h[r] = int32_t(min(best + 1u, uint32_t(HV)));
             // hand the horizontal pushes of this row to the neighbour lanes
             // (lane 63's push right and lane 0's push left leave the wave)
             const int32_t inL = from_left(dR, 0);
