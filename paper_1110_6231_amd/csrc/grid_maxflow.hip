@@ -734,12 +734,11 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
     // the end (a ballot count per row would cost scalar 64-bit adds there)
     uint32_t lane_push = 0, lane_relab = 0;
     for (int it = 0; it < L; ++it) {
-        bool any = false;                      // wave-uniform
+        uint32_t act_it = 0;                   // bit r: the pixel acted in this iteration
 #pragma unroll
         for (int r = 0; r < TH; ++r) {
             const bool active = e[r] > 0 && h[r] < HV;
             if (!__any(active)) continue;      // wave-uniform skip
-            any = true;
             const int32_t hl = from_left(h[r], hside[r]);
             const int32_t hr = from_right(h[r], hside[r]);
             const int32_t hd = r + 1 < TH ? h[r + 1] : bot;
@@ -789,11 +788,12 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
             rl[r] += inL;
             rr[r] += inR;
             e[r] += inL + inR;
-            acted |= active ? 1u << r : 0u;
+            act_it |= active ? 1u << r : 0u;
             lane_push += push;
             lane_relab += relab;
         }
-        if (!any) break;
+        acted |= act_it;
+        if (!__any(act_it != 0)) break;        // no pixel of the tile acted
     }
     for (int o = 32; o > 0; o >>= 1) {
         lane_push += __shfl_xor(lane_push, o, 64);

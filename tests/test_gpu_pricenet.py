@@ -81,6 +81,9 @@ def test_features_match_oracle():
     mats = [synth.assign_points(n, seed=2, instance=k + 1)
             for k, n in enumerate([64, 150, 333])]
     mats.append(synth.assign_random_small(5, 3, lo=0, hi=9))
+    # the smallest instances: one padded cost group per row
+    mats.append(synth.assign_random_small(1, 5, lo=0, hi=9))
+    mats.append(synth.assign_random_small(2, 6, lo=-9, hi=9))
     # costs past the int16 range: the feature passes read the int32 input
     mats.append(synth.assign_random_small(70, 4, lo=-100000, hi=900000))
     packed = _packed(mats)
