@@ -273,8 +273,10 @@ __global__ __launch_bounds__(NT) void k_init(Dev D) {
 //            beforehand).
 // Retired instances are left untouched: no active or dirty flag.
 // ---------------------------------------------------------------------------
-template <int TH>
-__global__ __launch_bounds__(NT) void k_boundary(Dev D, unsigned mode) {
+// `mode` is a template argument, so that no branch on it separates a row's
+// loads from the next row's (the three combinations used are instantiated).
+template <int TH, unsigned mode>
+__global__ __launch_bounds__(NT) void k_boundary(Dev D) {
     static_assert(RELAX_TH % TH == 0, "sweep tiles nest in relaxation tiles");
     constexpr int RWB = RELAX_TH / 4;  // rows per wavefront
     const int rt = blockIdx.x;
@@ -294,34 +296,46 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D, unsigned mode) {
     uint32_t my[NMASK] = {0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t act_rows = 0;
     if (!retired && x < g.W) {
+        // every load of the wavefront's rows first, then the stores: a store
+        // between them would keep the next row's loads behind it (the
+        // arrays could alias), one memory latency per row.  Rows past H
+        // read row y0 (which exists) and are dropped.
+        int32_t ev[RWB], hv[RWB], rsv[RWB], rrv[RWB], rlv[RWB], rdv[RWB], ruv[RWB];
+#pragma unroll
+        for (int i = 0; i < RWB; ++i) {
+            const int y = g.y0 + w * RWB + i;
+            const int64_t p = g.off + int64_t(y < g.H ? y : g.y0) * g.W + x;
+            ev[i] = D.e[p];
+            hv[i] = (mode & BD_ADOPT) ? D.lab[p] : (mode & BD_COUNT) ? D.h[p] : 0;
+            rsv[i] = rrv[i] = rlv[i] = rdv[i] = ruv[i] = 0;
+            if (mode & BD_SNAPSHOT) {
+                rsv[i] = D.rs[p];
+                rrv[i] = D.rr[p];
+                rlv[i] = D.rl[p];
+                rdv[i] = D.rd[p];
+                ruv[i] = D.ru[p];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < RWB; ++i) {
             const int r = w * RWB + i, y = g.y0 + r;
             if (y >= g.H) break;
             const int64_t p = g.off + int64_t(y) * g.W + x;
-            const int32_t ev = D.e[p];
-            int32_t hv = 0;
-            if (mode & BD_ADOPT) {
-                hv = D.lab[p];
-                D.h[p] = hv;
-            } else if (mode & BD_COUNT) {
-                hv = D.h[p];
-            }
+            if (mode & BD_ADOPT) D.h[p] = hv[i];
             if (mode & BD_COUNT) {
-                n_exact += (((oldE >> r) & 1u) && hv < g.HV) ? 1 : 0;
-                const bool a = ev > 0 && hv < g.HV;
+                n_exact += (((oldE >> r) & 1u) && hv[i] < g.HV) ? 1 : 0;
+                const bool a = ev[i] > 0 && hv[i] < g.HV;
                 n_act += a ? 1 : 0;
                 act_rows |= uint32_t(a) << r;
             }
             if (mode & BD_SNAPSHOT) {
-                const int32_t rs = D.rs[p];
-                my[MK_R] |= uint32_t(D.rr[p] > 0) << r;
-                my[MK_L] |= uint32_t(D.rl[p] > 0) << r;
-                my[MK_D] |= uint32_t(D.rd[p] > 0) << r;
-                my[MK_U] |= uint32_t(D.ru[p] > 0) << r;
-                my[MK_T] |= uint32_t(rs > 0) << r;
-                my[MK_E] |= uint32_t(ev > 0) << r;
-                D.lab[p] = rs > 0 ? 1 : g.HV;
+                my[MK_R] |= uint32_t(rrv[i] > 0) << r;
+                my[MK_L] |= uint32_t(rlv[i] > 0) << r;
+                my[MK_D] |= uint32_t(rdv[i] > 0) << r;
+                my[MK_U] |= uint32_t(ruv[i] > 0) << r;
+                my[MK_T] |= uint32_t(rsv[i] > 0) << r;
+                my[MK_E] |= uint32_t(ev[i] > 0) << r;
+                D.lab[p] = rsv[i] > 0 ? 1 : g.HV;
             }
         }
     }
@@ -969,7 +983,15 @@ struct Kern {
         hipLaunchKernelGGL(k_init<TH>, dim3(D.ntiles), dim3(NT), 0, s, D);
     }
     static void boundary(hipStream_t s, const Dev &D, unsigned mode) {
-        hipLaunchKernelGGL(k_boundary<TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D, mode);
+        if (mode == BD_SNAPSHOT)
+            hipLaunchKernelGGL((k_boundary<TH, BD_SNAPSHOT>), dim3(D.ntiles_r), dim3(NT), 0, s,
+                               D);
+        else if (mode == (BD_ADOPT | BD_COUNT))
+            hipLaunchKernelGGL((k_boundary<TH, BD_ADOPT | BD_COUNT>), dim3(D.ntiles_r),
+                               dim3(NT), 0, s, D);
+        else
+            hipLaunchKernelGGL((k_boundary<TH, BD_ADOPT | BD_COUNT | BD_SNAPSHOT>),
+                               dim3(D.ntiles_r), dim3(NT), 0, s, D);
     }
     // the relaxation kernels run on the RELAX_TH tiling, one 4-wavefront
     // workgroup per listed tile
