@@ -96,6 +96,13 @@ const char *lpr_version(void);
 #define LPR_GRID_SYNC_RELABEL 0x8 /* global relabel between the sweeps (the
                                      scheme of Algorithm 4.8); with neither
                                      flag the tuned schedule decides */
+#define LPR_GRID_SEGMENTED_SCAN 0x10 /* relax the rows of the global relabel
+                                     and of the cut closure with segmented
+                                     scans that test every lane, the form a
+                                     batch uses anyway when an instance has
+                                     more than 2^25 - 66 pixels (the default
+                                     form offsets the labels by multiples
+                                     of 2^25); same results, for testing */
 
 typedef struct {
     int32_t sweeps_per_relabel; /* push-sweep launches between global

@@ -119,6 +119,39 @@ __device__ __forceinline__ int32_t scan_from_right(int32_t v, int dr, int lane) 
     return v;
 }
 
+// Plain (unsegmented) min scans: prefix_min gives lane x the minimum over
+// lanes 0..x, suffix_min the minimum over lanes x..63.  Every step is one DPP
+// min with no lane condition.  The relaxation turns its segmented scans into
+// these by adding to each lane a multiple of 2^OFF_SHIFT that grows with the
+// segment's distance from the scan's end, so no lane of another segment can
+// win (exact while the labels and that multiple stay below 2^31).
+constexpr int OFF_SHIFT = 25;
+constexpr int32_t OFFSET_SCAN_MAX_HV = (1 << OFF_SHIFT) - 64;
+__device__ __forceinline__ int32_t prefix_min(int32_t v) {
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    // rows 1 and 3 take lane 15 / 47, then rows 2 and 3 take lane 31
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x142, 0xA, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x143, 0xC, 0xF, false));
+    return v;
+}
+__device__ __forceinline__ int32_t suffix_min(int32_t v, int lane) {
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x101, 0xF, 0xF, false));  // row_shl:1
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x102, 0xF, 0xF, false));  // row_shl:2
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x104, 0xF, 0xF, false));  // row_shl:4
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x108, 0xF, 0xF, false));  // row_shl:8
+    // the first lane of each 16-lane row now holds that row's minimum; a row
+    // takes the minimum of the rows to its right
+    const int32_t a = __builtin_amdgcn_readlane(v, 16);
+    const int32_t b = __builtin_amdgcn_readlane(v, 32);
+    const int32_t c = __builtin_amdgcn_readlane(v, 48);
+    const int32_t bc = min(b, c);
+    const int32_t t = lane < 32 ? (lane < 16 ? min(a, bc) : bc) : (lane < 48 ? c : INT_MAX);
+    return min(v, t);
+}
+
 struct Inst {
     int64_t off;      // first pixel of the instance in the packed arrays
     int32_t H, W;
@@ -175,6 +208,7 @@ struct Dev {
     int32_t *dirty[3], *dlist[3];  // relaxation tiles to relax
     int32_t ntiles, ntiles_r;
     int32_t ninst;
+    int32_t seg_scan;  // relax rows with the segmented scans (host's choice)
 };
 
 __device__ __forceinline__ int next3(int i) { return i == 2 ? 0 : i + 1; }
@@ -435,6 +469,16 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 // finds no lowered boundary.  A label thus crosses 32 rows in one pass, with
 // the latency of an 8-row tile per wavefront.
 //
+// Row scans (SEG = false): lane x of a row takes the minimum over its segment
+// (the lanes joined to it by usable arcs) of the label shifted by its column
+// distance.  Adding (segments between the lane and the scan's end) x 2^25 to
+// every lane makes each other segment's values larger than any label of the
+// lane's own, so a plain prefix / suffix minimum gives the segmented one;
+// the multiples are fixed for the pass and kept per row.  This needs every
+// label at most 2^25 - 64 (instances of at most 2^25 - 66 pixels); a batch
+// with a larger instance uses the segmented scans with a lane test per step
+// (SEG = true).
+//
 // Work list: the pass relaxes the tiles of list `cur` (cnt_cur entries;
 // workgroup b takes entry b, so the tiles spread over the whole chip however
 // they cluster on the grid) and appends the neighbours whose halo changed to
@@ -444,7 +488,7 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 // ---------------------------------------------------------------------------
 constexpr int RW = 8;  // rows per wavefront of the cooperative relaxation
 
-template <bool CUT>
+template <bool CUT, bool SEG>
 __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *cnt_cur,
                                                int32_t *cnt_next) {
     static_assert(RELAX_TH == 4 * RW, "four wavefronts per relaxation tile");
@@ -496,8 +540,10 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
         d0[r] = d[r];
     }
     // halo: the tile's row above / below (wavefronts 0 / 3), columns left and
-    // right (lanes 0 / 63); the rows between wavefronts come from LDS
-    int32_t top = HV, bot = HV, hside[RW];
+    // right (lanes 0 / 63); the rows between wavefronts come from LDS.  hs[r]
+    // is what the side halo offers lane 0 / 63 of row r (its label + INC
+    // where the arc is usable, else INT_MAX), fixed for the pass.
+    int32_t top = HV, bot = HV, hs[RW];
     if (w == 0 && colv && g.y0 > 0) top = D.lab[g.off + int64_t(g.y0 - 1) * g.W + x];
     if (w == 3 && colv && g.y0 + RELAX_TH < g.H)
         bot = D.lab[g.off + int64_t(g.y0 + RELAX_TH) * g.W + x];
@@ -505,19 +551,35 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         const int y = yw + r;
-        hside[r] = HV;
-        if ((lane == 0 || lane == 63) && hx >= 0 && hx < g.W && y < g.H)
-            hside[r] = D.lab[g.off + int64_t(y) * g.W + hx];
+        const bool use = (lane == 0 && ((mL >> r) & 1u)) || (lane == 63 && ((mR >> r) & 1u));
+        hs[r] = INT_MAX;
+        if (use && hx >= 0 && hx < g.W && y < g.H)
+            hs[r] = D.lab[g.off + int64_t(y) * g.W + hx] + INC;
     }
-    int32_t seg[RW];
+    // per row: the segment extents (SEG) or the scan offsets, less / plus the
+    // column shift of the min-plus form
+    int32_t segL[RW], segR[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
         const uint64_t brkL = __ballot(!((mL >> r) & 1u)) | 1ull;
         const uint64_t brkR = __ballot(!((mR >> r) & 1u)) | (1ull << 63);
-        const uint64_t low = lane == 63 ? ~0ull : (2ull << lane) - 1;
-        const int sx = 63 - __clzll((long long)(brkL & low));
-        const int ex = lane + __ffsll((unsigned long long)(brkR >> lane)) - 1;
-        seg[r] = (lane - sx) | ((ex - lane) << 8);
+        if constexpr (SEG) {
+            const uint64_t low = lane == 63 ? ~0ull : (2ull << lane) - 1;
+            const int sx = 63 - __clzll((long long)(brkL & low));
+            const int ex = lane + __ffsll((unsigned long long)(brkR >> lane)) - 1;
+            segL[r] = lane - sx;
+            segR[r] = ex - lane;
+        } else {
+            // breaks at or left of the lane (left scan), strictly left of it
+            // (right scan): the lane's segment index in each direction
+            const uint32_t bl = __builtin_amdgcn_mbcnt_hi(
+                uint32_t(brkL >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkL), 0u));
+            const uint32_t gl = bl + uint32_t((brkL >> lane) & 1ull);
+            const uint32_t gr = __builtin_amdgcn_mbcnt_hi(
+                uint32_t(brkR >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkR), 0u));
+            segL[r] = int32_t((64u - gl) << OFF_SHIFT) - INC * lane;
+            segR[r] = int32_t(gr << OFF_SHIFT) + INC * lane;
+        }
     }
     edge[w][0][lane] = d[0];
     edge[w][1][lane] = d[RW - 1];
@@ -527,15 +589,18 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
     uint32_t rows = (1u << RW) - 1;           // wavefront-uniform
     for (;;) {
         __syncthreads();                      // the edges above were read
-        while (rows) {
+        while ((rows = __builtin_amdgcn_readfirstlane(rows)) != 0) {
 #pragma unroll
             for (int r = 0; r < RW; ++r) {
                 if (!((rows >> r) & 1u)) continue;
-                int32_t nd = d[r];
-                if (lane == 0 && (mL >> r) & 1u) nd = min(nd, hside[r] + INC);
-                if (lane == 63 && (mR >> r) & 1u) nd = min(nd, hside[r] + INC);
-                nd = scan_from_left(nd - INC * lane, seg[r] & 0xff, lane) + INC * lane;
-                nd = scan_from_right(nd + INC * lane, seg[r] >> 8, lane) - INC * lane;
+                int32_t nd = min(d[r], hs[r]);
+                if constexpr (SEG) {
+                    nd = scan_from_left(nd - INC * lane, segL[r], lane) + INC * lane;
+                    nd = scan_from_right(nd + INC * lane, segR[r], lane) - INC * lane;
+                } else {
+                    nd = prefix_min(nd + segL[r]) - segL[r];
+                    nd = suffix_min(nd + segR[r], lane) - segR[r];
+                }
                 d[r] = nd;
             }
             rows = 0;
@@ -1001,8 +1066,13 @@ struct Kern {
     static void relax(bool cut, hipStream_t s, const Dev &D, int cur, const int32_t *cnt_cur,
                       int32_t *cnt_next) {
         const dim3 gw(D.ntiles_r);
-        if (cut) hipLaunchKernelGGL((k_relax4<true>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
-        else hipLaunchKernelGGL((k_relax4<false>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
+        if (D.seg_scan) {
+            if (cut) hipLaunchKernelGGL((k_relax4<true, true>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
+            else hipLaunchKernelGGL((k_relax4<false, true>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
+        } else {
+            if (cut) hipLaunchKernelGGL((k_relax4<true, false>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
+            else hipLaunchKernelGGL((k_relax4<false, false>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
+        }
     }
     static void sweep(hipStream_t s, const Dev &D, int cur, int L) {
         hipLaunchKernelGGL(k_sweep<TH>, dim3((D.ntiles + 3) / 4), dim3(NT), 0, s, D, cur, L);
@@ -1155,11 +1225,12 @@ struct GraphKey {
     const void *ws;
     const void *caps[6];
     int64_t N;
-    int B, T, TR, TH, K, L, P, kind;
+    int B, T, TR, TH, K, L, P, kind, seg;
     bool operator==(const GraphKey &o) const {
         return device == o.device && ws == o.ws && N == o.N && B == o.B &&
                T == o.T && TR == o.TR && TH == o.TH && K == o.K && L == o.L &&
-               P == o.P && kind == o.kind && std::equal(caps, caps + 6, o.caps);
+               P == o.P && kind == o.kind && seg == o.seg &&
+               std::equal(caps, caps + 6, o.caps);
     }
 };
 
@@ -1721,6 +1792,9 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     D.ntiles = int32_t(T);
     D.ntiles_r = int32_t(TR);
     D.ninst = B;
+    D.seg_scan = (opts && (opts->flags & LPR_GRID_SEGMENTED_SCAN)) ? 1 : 0;
+    for (int b = 0; b < B; ++b)
+        if (insts[b].HV > OFFSET_SCAN_MAX_HV) D.seg_scan = 1;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GraphKey key{};
     LPR_TRY_HIP(hipGetDevice(&key.device));
@@ -1731,6 +1805,7 @@ static lpr_status run(int32_t B, const int32_t *H, const int32_t *W,
     key.T = int(T);
     key.TR = int(TR);
     key.TH = P.TH;
+    key.seg = D.seg_scan;
     // the call's HIP events (not on the allocation-free path, which times the
     // call on the host clock instead)
     std::optional<CallTimer> call;

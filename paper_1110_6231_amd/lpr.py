@@ -34,6 +34,7 @@ LPR_GRID_TIME_KERNELS = 0x1
 LPR_GRID_NO_GRAPH = 0x2
 LPR_GRID_ASYNC_RELABEL = 0x4
 LPR_GRID_SYNC_RELABEL = 0x8
+LPR_GRID_SEGMENTED_SCAN = 0x10
 LPR_ASSIGN_TIME_KERNELS = 0x1
 LPR_ASSIGN_NO_START_UPDATE = 0x2
 LPR_ASSIGN_ARC_FIXING = 0x4

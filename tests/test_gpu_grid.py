@@ -100,6 +100,39 @@ def test_blobs_medium_and_long_paths(mode):
     check_against_oracle(synth.grid_blobs(200, 260, seed=3, pair_scale=200.0), o)
 
 
+def serpentine(H, W, seed):
+    """One path through every pixel: full rows joined at alternating ends,
+    one weak arc in the middle row; the BFS labels run up to H*W."""
+    g = np.random.default_rng(seed)
+    hf = g.integers(60, 100, (H, W - 1))
+    hf[H // 2, W // 2] = 30
+    vf = np.zeros((H - 1, W), np.int64)
+    for r in range(H - 1):
+        vf[r, W - 1 if r % 2 == 0 else 0] = g.integers(60, 100)
+    src = np.zeros((H, W), np.int32)
+    snk = np.zeros((H, W), np.int32)
+    src[0, 0] = 77
+    snk[H - 1, W - 1 if (H - 1) % 2 == 0 else 0] = 91
+    return synth.grid_from_pairs(H, W, src, snk, hf, hf, vf, vf, f"serpentine{H}x{W}")
+
+
+@MODES
+@pytest.mark.parametrize("scan", [0, lpr.LPR_GRID_SEGMENTED_SCAN],
+                         ids=["offset", "segmented"])
+def test_row_scan_forms(scan, mode):
+    """The relaxation's two forms of row scan (labels offset per segment, or
+    a lane test per step) reach the same least fixpoint: the oracle's flow
+    and minimal cut on rows cut into many segments (sparse arcs), on a path
+    through every pixel and on a blob image."""
+    o = lpr.make_grid_opts(flags=mode | scan)
+    check_against_oracle(synth.grid_random_small(100, 129, seed=5, max_cap=4,
+                                                 max_term=12, density=0.5), o)
+    check_against_oracle(synth.grid_random_small(67, 200, seed=6, density=0.9), o)
+    st = check_against_oracle(serpentine(33, 130, seed=7), o)
+    assert st["rounds"] >= 1
+    check_against_oracle(synth.grid_blobs(200, 260, seed=3, pair_scale=200.0), o)
+
+
 def test_closed_forms():
     H, W = 70, 90
     z = np.zeros(H * W, np.int32)
