@@ -152,6 +152,20 @@ __device__ __forceinline__ int32_t suffix_min(int32_t v, int lane) {
     return min(v, t);
 }
 
+// Appends the values of the lanes with `take` to a work list: one atomic add
+// on the list's count reserves their slots (in lane order), so a wavefront
+// that lists several tiles waits for one round trip, not one per tile.
+__device__ __forceinline__ void list_append(int32_t *list, int32_t *cnt, bool take, int32_t v,
+                                            int lane) {
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int lead = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == lead) base = atomicAdd(cnt, __popcll(m));
+    base = __builtin_amdgcn_readlane(base, lead);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1))] = v;
+}
+
 struct Inst {
     int64_t off;      // first pixel of the instance in the packed arrays
     int32_t H, W;
@@ -382,28 +396,36 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
     __syncthreads();
     if ((mode & BD_SNAPSHOT) && !retired) {
         for (int i = threadIdx.x; i < NMASK * TW; i += NT) tm[i] = (&smask[0][0])[i];
-        if (threadIdx.x == 0 && atomicExch(&D.dirty[0][rt], 1) == 0)
+        // the flags were cleared before this launch and each relaxation tile
+        // seeds only itself: no exchange needed
+        if (threadIdx.x == 0) {
+            D.dirty[0][rt] = 1;
             D.dlist[0][atomicAdd(&D.sc->seed_count, 1)] = rt;
+        }
     }
     if (mode & BD_COUNT) {
         const unsigned long long se = block_sum_u64(n_exact);
         const unsigned long long sa = block_sum_u64(n_act);
-        if (threadIdx.x == 0) {
-            if (se) atomicAdd(&D.inst_exact[g.inst], se);
-            if (sa) atomicAdd(&D.inst_active[g.inst], sa);
-            // the sweep tiles this tile holds: rows k*TH .. k*TH + TH - 1
-            const Inst I = D.inst[g.inst];
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            if (lane == 0) {
+                if (se) atomicAdd(&D.inst_exact[g.inst], se);
+                if (sa) atomicAdd(&D.inst_active[g.inst], sa);
+            }
+            // lane k: the sweep tile of rows k*TH .. k*TH + TH - 1 of this tile
             const uint32_t rows = s_rows;
             constexpr uint32_t SEG = TH >= 32 ? 0xFFFFFFFFu : ((1u << (TH & 31)) - 1u);
-            for (int k = 0; k < RELAX_TH / TH; ++k) {
-                if (g.y0 + k * TH >= g.H) break;
-                const int st = I.tile_base + (g.ty * (RELAX_TH / TH) + k) * g.tiles_x + g.tx;
-                const bool a = ((rows >> (k * TH)) & SEG) != 0;
+            const int k = lane;
+            int st = -1;
+            bool a = false;
+            if (k < RELAX_TH / TH && g.y0 + k * TH < g.H) {
+                st = D.inst[g.inst].tile_base + (g.ty * (RELAX_TH / TH) + k) * g.tiles_x + g.tx;
+                a = ((rows >> (k * TH)) & SEG) != 0;
                 D.act[0][st] = a ? 1 : 0;
                 D.act[1][st] = 0;
                 D.act[2][st] = 0;
-                if (a) D.alist[0][atomicAdd(&D.sc->act_cnt[0], 1)] = st;
             }
+            list_append(D.alist[0], &D.sc->act_cnt[0], a, st, lane);
         }
     }
 }
@@ -495,7 +517,10 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
     const int n = *cnt_cur;
     if (int(blockIdx.x) >= n) return;         // workgroup-uniform
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (!CUT && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&D.counters[6], 1ull);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // statistics: once per pass
+        if (!CUT) atomicAdd(&D.counters[6], 1ull);
+        atomicAdd(&D.counters[CUT ? 4 : 3], (unsigned long long)n);
+    }
     const int t = D.dlist[cur][blockIdx.x];
     const int nxt = next3(cur);
     __shared__ int32_t edge[4][2][64];        // row 0 and row 7 of each wavefront
@@ -651,17 +676,15 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
         if (bits) atomicOr(&s_ch, bits);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (w == 0) {  // lane i of wavefront 0 flags neighbour i (right, left, below, above)
         const int bits = s_ch;
-        atomicAdd(&D.counters[CUT ? 4 : 3], 1ull);
-        int nb[4] = {-1, -1, -1, -1};
-        if ((bits & 1) && g.tx + 1 < g.tiles_x) nb[0] = t + 1;
-        if ((bits & 2) && g.tx > 0) nb[1] = t - 1;
-        if ((bits & 4) && g.ty + 1 < g.tiles_y) nb[2] = t + g.tiles_x;
-        if ((bits & 8) && g.ty > 0) nb[3] = t - g.tiles_x;
-        for (int i = 0; i < 4; ++i)
-            if (nb[i] >= 0 && atomicExch(&D.dirty[nxt][nb[i]], 1) == 0)
-                D.dlist[nxt][atomicAdd(cnt_next, 1)] = nb[i];
+        int nb = -1;
+        if (lane == 0 && (bits & 1) && g.tx + 1 < g.tiles_x) nb = t + 1;
+        if (lane == 1 && (bits & 2) && g.tx > 0) nb = t - 1;
+        if (lane == 2 && (bits & 4) && g.ty + 1 < g.tiles_y) nb = t + g.tiles_x;
+        if (lane == 3 && (bits & 8) && g.ty > 0) nb = t - g.tiles_x;
+        const bool fresh = nb >= 0 && atomicExch(&D.dirty[nxt][nb], 1) == 0;
+        list_append(D.dlist[nxt], cnt_next, fresh, nb, lane);
     }
 }
 
@@ -756,7 +779,11 @@ template <int TH>
 __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
     const int lane = threadIdx.x & 63;
     const int nxt = next3(cur);
-    if (blockIdx.x == 0 && threadIdx.x == 0) D.sc->act_cnt[prev3(cur)] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        D.sc->act_cnt[prev3(cur)] = 0;
+        // statistics: every listed tile is visited once by this launch
+        atomicAdd(&D.counters[2], (unsigned long long)D.sc->act_cnt[cur]);
+    }
     const int i = int(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (i >= D.sc->act_cnt[cur]) return;  // wave-uniform
     const int t = D.alist[cur][i];
@@ -957,15 +984,19 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
     const bool a_end = __any(active_end);
     const bool a_l = __any(touch_l), a_r = __any(touch_r);
     const bool a_u = __any(touch_u), a_d = __any(touch_d);
+    // lanes 0..4 flag the tile itself and its left, right, upper and lower
+    // neighbours for the next sweep
+    int nb = -1;
+    if (lane == 0 && a_end) nb = t;
+    if (lane == 1 && a_l) nb = t - 1;
+    if (lane == 2 && a_r) nb = t + 1;
+    if (lane == 3 && a_u) nb = t - g.tiles_x;
+    if (lane == 4 && a_d) nb = t + g.tiles_x;
+    const bool fresh = nb >= 0 && atomicExch(&D.act[nxt][nb], 1) == 0;
+    list_append(D.alist[nxt], &D.sc->act_cnt[nxt], fresh, nb, lane);
     if (lane == 0) {
-        const int nb[5] = {a_end ? t : -1, a_l ? t - 1 : -1, a_r ? t + 1 : -1,
-                           a_u ? t - g.tiles_x : -1, a_d ? t + g.tiles_x : -1};
-        for (int k = 0; k < 5; ++k)
-            if (nb[k] >= 0 && atomicExch(&D.act[nxt][nb[k]], 1) == 0)
-                D.alist[nxt][atomicAdd(&D.sc->act_cnt[nxt], 1)] = nb[k];
         if (pushes) atomicAdd(&D.counters[0], pushes);
         if (relabels) atomicAdd(&D.counters[1], relabels);
-        atomicAdd(&D.counters[2], 1ull);
         if (n_atomic) atomicAdd(&D.counters[5], (unsigned long long)n_atomic);
     }
 }
