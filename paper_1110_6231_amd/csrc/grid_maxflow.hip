@@ -502,13 +502,16 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 // (SEG = true).
 //
 // Work list: the pass relaxes the tiles of list `cur` (cnt_cur entries;
-// workgroup b takes entry b, so the tiles spread over the whole chip however
-// they cluster on the grid) and appends the neighbours whose halo changed to
-// the next list, once each (the flag), counting them in cnt_next.  A pass
-// whose list is empty returns at once, so a round can carry more passes than
-// its global relabel needs at little cost.
+// workgroup b takes entries b, b + G, b + 2G, ... of a grid of G <=
+// RELAX_GRID workgroups, so the tiles spread over the whole chip however they
+// cluster on the grid) and appends the neighbours whose halo changed to the
+// next list, once each (the flag), counting them in cnt_next.  A pass whose
+// list is empty returns at once (a launch of at most RELAX_GRID workgroups),
+// so a round can carry more passes than its global relabel needs at little
+// cost.
 // ---------------------------------------------------------------------------
 constexpr int RW = 8;  // rows per wavefront of the cooperative relaxation
+constexpr int RELAX_GRID = 2048;  // most workgroups of a relaxation launch
 
 template <bool CUT, bool SEG>
 __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *cnt_cur,
@@ -521,170 +524,177 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
         if (!CUT) atomicAdd(&D.counters[6], 1ull);
         atomicAdd(&D.counters[CUT ? 4 : 3], (unsigned long long)n);
     }
-    const int t = D.dlist[cur][blockIdx.x];
     const int nxt = next3(cur);
     __shared__ int32_t edge[4][2][64];        // row 0 and row 7 of each wavefront
     __shared__ int s_ch;
-    if (threadIdx.x == 0) {
-        s_ch = 0;
-        D.dirty[cur][t] = 0;
-    }
-    __syncthreads();
-    const Geo g = tile_geo<RELAX_TH, true>(D, t);
-    constexpr int INC = CUT ? 0 : 1;
-    const int HV = g.HV;
-    const int x = g.x0 + lane;
-    const bool colv = x < g.W;
-    const int yw = g.y0 + RW * w;             // first row of this wavefront
-    int32_t d[RW], d0[RW];
-    uint32_t mR = 0, mL = 0, mD = 0, mU = 0;  // bit r: arc usable in row r
-    if (!CUT) {
-        // this wavefront's eight rows of the column's snapshot masks
-        const uint32_t *tm = D.amask + size_t(t) * NMASK * TW + lane;
-        const int sh = RW * w;
-        mR = (tm[MK_R * TW] >> sh) & 0xFFu;
-        mL = (tm[MK_L * TW] >> sh) & 0xFFu;
-        mD = (tm[MK_D * TW] >> sh) & 0xFFu;
-        mU = (tm[MK_U * TW] >> sh) & 0xFFu;
-    }
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int y = yw + r;
-        d[r] = HV;
-        if (colv && y < g.H) {
-            const int64_t p = g.off + int64_t(y) * g.W + x;
-            d[r] = D.lab[p];
-            if (CUT) {
-                // arcs into p: from the right neighbour (its left arc), etc.
-                if (x + 1 < g.W) mR |= uint32_t(D.rl[p + 1] > 0) << r;
-                if (x > 0) mL |= uint32_t(D.rr[p - 1] > 0) << r;
-                if (y + 1 < g.H) mD |= uint32_t(D.ru[p + g.W] > 0) << r;
-                if (y > 0) mU |= uint32_t(D.rd[p - g.W] > 0) << r;
-            }
+    // the grid holds at most RELAX_GRID workgroups (a pass whose list is
+    // short or empty costs a small launch); each takes every gridDim-th entry
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        const int t = D.dlist[cur][b];
+        // the LDS of the last tile: every read of edge[] ended before the
+        // workgroup vote that closed its loop, and s_ch was read by wavefront 0
+        // (this thread's own) after the barrier that followed every update
+        if (threadIdx.x == 0) {
+            s_ch = 0;
+            D.dirty[cur][t] = 0;
         }
-        d0[r] = d[r];
-    }
-    // halo: the tile's row above / below (wavefronts 0 / 3), columns left and
-    // right (lanes 0 / 63); the rows between wavefronts come from LDS.  hs[r]
-    // is what the side halo offers lane 0 / 63 of row r (its label + INC
-    // where the arc is usable, else INT_MAX), fixed for the pass.
-    int32_t top = HV, bot = HV, hs[RW];
-    if (w == 0 && colv && g.y0 > 0) top = D.lab[g.off + int64_t(g.y0 - 1) * g.W + x];
-    if (w == 3 && colv && g.y0 + RELAX_TH < g.H)
-        bot = D.lab[g.off + int64_t(g.y0 + RELAX_TH) * g.W + x];
-    const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const int y = yw + r;
-        const bool use = (lane == 0 && ((mL >> r) & 1u)) || (lane == 63 && ((mR >> r) & 1u));
-        hs[r] = INT_MAX;
-        if (use && hx >= 0 && hx < g.W && y < g.H)
-            hs[r] = D.lab[g.off + int64_t(y) * g.W + hx] + INC;
-    }
-    // per row: the segment extents (SEG) or the scan offsets, less / plus the
-    // column shift of the min-plus form
-    int32_t segL[RW], segR[RW];
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const uint64_t brkL = __ballot(!((mL >> r) & 1u)) | 1ull;
-        const uint64_t brkR = __ballot(!((mR >> r) & 1u)) | (1ull << 63);
-        if constexpr (SEG) {
-            const uint64_t low = lane == 63 ? ~0ull : (2ull << lane) - 1;
-            const int sx = 63 - __clzll((long long)(brkL & low));
-            const int ex = lane + __ffsll((unsigned long long)(brkR >> lane)) - 1;
-            segL[r] = lane - sx;
-            segR[r] = ex - lane;
-        } else {
-            // breaks at or left of the lane (left scan), strictly left of it
-            // (right scan): the lane's segment index in each direction
-            const uint32_t bl = __builtin_amdgcn_mbcnt_hi(
-                uint32_t(brkL >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkL), 0u));
-            const uint32_t gl = bl + uint32_t((brkL >> lane) & 1ull);
-            const uint32_t gr = __builtin_amdgcn_mbcnt_hi(
-                uint32_t(brkR >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkR), 0u));
-            segL[r] = int32_t((64u - gl) << OFF_SHIFT) - INC * lane;
-            segR[r] = int32_t(gr << OFF_SHIFT) + INC * lane;
+        __syncthreads();
+        const Geo g = tile_geo<RELAX_TH, true>(D, t);
+        constexpr int INC = CUT ? 0 : 1;
+        const int HV = g.HV;
+        const int x = g.x0 + lane;
+        const bool colv = x < g.W;
+        const int yw = g.y0 + RW * w;             // first row of this wavefront
+        int32_t d[RW], d0[RW];
+        uint32_t mR = 0, mL = 0, mD = 0, mU = 0;  // bit r: arc usable in row r
+        if (!CUT) {
+            // this wavefront's eight rows of the column's snapshot masks
+            const uint32_t *tm = D.amask + size_t(t) * NMASK * TW + lane;
+            const int sh = RW * w;
+            mR = (tm[MK_R * TW] >> sh) & 0xFFu;
+            mL = (tm[MK_L * TW] >> sh) & 0xFFu;
+            mD = (tm[MK_D * TW] >> sh) & 0xFFu;
+            mU = (tm[MK_U * TW] >> sh) & 0xFFu;
         }
-    }
-    edge[w][0][lane] = d[0];
-    edge[w][1][lane] = d[RW - 1];
-    __syncthreads();
-    if (w > 0) top = edge[w - 1][1][lane];
-    if (w < 3) bot = edge[w + 1][0][lane];
-    uint32_t rows = (1u << RW) - 1;           // wavefront-uniform
-    for (;;) {
-        __syncthreads();                      // the edges above were read
-        while ((rows = __builtin_amdgcn_readfirstlane(rows)) != 0) {
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                if (!((rows >> r) & 1u)) continue;
-                int32_t nd = min(d[r], hs[r]);
-                if constexpr (SEG) {
-                    nd = scan_from_left(nd - INC * lane, segL[r], lane) + INC * lane;
-                    nd = scan_from_right(nd + INC * lane, segR[r], lane) - INC * lane;
-                } else {
-                    nd = prefix_min(nd + segL[r]) - segL[r];
-                    nd = suffix_min(nd + segR[r], lane) - segR[r];
+    #pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int y = yw + r;
+            d[r] = HV;
+            if (colv && y < g.H) {
+                const int64_t p = g.off + int64_t(y) * g.W + x;
+                d[r] = D.lab[p];
+                if (CUT) {
+                    // arcs into p: from the right neighbour (its left arc), etc.
+                    if (x + 1 < g.W) mR |= uint32_t(D.rl[p + 1] > 0) << r;
+                    if (x > 0) mL |= uint32_t(D.rr[p - 1] > 0) << r;
+                    if (y + 1 < g.H) mD |= uint32_t(D.ru[p + g.W] > 0) << r;
+                    if (y > 0) mU |= uint32_t(D.rd[p - g.W] > 0) << r;
                 }
-                d[r] = nd;
             }
-            rows = 0;
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const int32_t up = r == 0 ? top : d[r - 1];
-                const int32_t nd = (mU >> r) & 1u ? min(d[r], up + INC) : d[r];
-                if (__any(nd < d[r])) rows |= 1u << r;
-                d[r] = nd;
-            }
-#pragma unroll
-            for (int r = RW - 1; r >= 0; --r) {
-                const int32_t dn = r == RW - 1 ? bot : d[r + 1];
-                const int32_t nd = (mD >> r) & 1u ? min(d[r], dn + INC) : d[r];
-                if (__any(nd < d[r])) rows |= 1u << r;
-                d[r] = nd;
+            d0[r] = d[r];
+        }
+        // halo: the tile's row above / below (wavefronts 0 / 3), columns left and
+        // right (lanes 0 / 63); the rows between wavefronts come from LDS.  hs[r]
+        // is what the side halo offers lane 0 / 63 of row r (its label + INC
+        // where the arc is usable, else INT_MAX), fixed for the pass.
+        int32_t top = HV, bot = HV, hs[RW];
+        if (w == 0 && colv && g.y0 > 0) top = D.lab[g.off + int64_t(g.y0 - 1) * g.W + x];
+        if (w == 3 && colv && g.y0 + RELAX_TH < g.H)
+            bot = D.lab[g.off + int64_t(g.y0 + RELAX_TH) * g.W + x];
+        const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
+    #pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int y = yw + r;
+            const bool use = (lane == 0 && ((mL >> r) & 1u)) || (lane == 63 && ((mR >> r) & 1u));
+            hs[r] = INT_MAX;
+            if (use && hx >= 0 && hx < g.W && y < g.H)
+                hs[r] = D.lab[g.off + int64_t(y) * g.W + hx] + INC;
+        }
+        // per row: the segment extents (SEG) or the scan offsets, less / plus the
+        // column shift of the min-plus form
+        int32_t segL[RW], segR[RW];
+    #pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const uint64_t brkL = __ballot(!((mL >> r) & 1u)) | 1ull;
+            const uint64_t brkR = __ballot(!((mR >> r) & 1u)) | (1ull << 63);
+            if constexpr (SEG) {
+                const uint64_t low = lane == 63 ? ~0ull : (2ull << lane) - 1;
+                const int sx = 63 - __clzll((long long)(brkL & low));
+                const int ex = lane + __ffsll((unsigned long long)(brkR >> lane)) - 1;
+                segL[r] = lane - sx;
+                segR[r] = ex - lane;
+            } else {
+                // breaks at or left of the lane (left scan), strictly left of it
+                // (right scan): the lane's segment index in each direction
+                const uint32_t bl = __builtin_amdgcn_mbcnt_hi(
+                    uint32_t(brkL >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkL), 0u));
+                const uint32_t gl = bl + uint32_t((brkL >> lane) & 1ull);
+                const uint32_t gr = __builtin_amdgcn_mbcnt_hi(
+                    uint32_t(brkR >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkR), 0u));
+                segL[r] = int32_t((64u - gl) << OFF_SHIFT) - INC * lane;
+                segR[r] = int32_t(gr << OFF_SHIFT) + INC * lane;
             }
         }
         edge[w][0][lane] = d[0];
         edge[w][1][lane] = d[RW - 1];
         __syncthreads();
-        if (w > 0) {
-            const int32_t v = edge[w - 1][1][lane];
-            if (__any(v < top)) rows |= 1u;
-            top = min(top, v);
+        if (w > 0) top = edge[w - 1][1][lane];
+        if (w < 3) bot = edge[w + 1][0][lane];
+        uint32_t rows = (1u << RW) - 1;           // wavefront-uniform
+        for (;;) {
+            __syncthreads();                      // the edges above were read
+            while ((rows = __builtin_amdgcn_readfirstlane(rows)) != 0) {
+    #pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    if (!((rows >> r) & 1u)) continue;
+                    int32_t nd = min(d[r], hs[r]);
+                    if constexpr (SEG) {
+                        nd = scan_from_left(nd - INC * lane, segL[r], lane) + INC * lane;
+                        nd = scan_from_right(nd + INC * lane, segR[r], lane) - INC * lane;
+                    } else {
+                        nd = prefix_min(nd + segL[r]) - segL[r];
+                        nd = suffix_min(nd + segR[r], lane) - segR[r];
+                    }
+                    d[r] = nd;
+                }
+                rows = 0;
+    #pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    const int32_t up = r == 0 ? top : d[r - 1];
+                    const int32_t nd = (mU >> r) & 1u ? min(d[r], up + INC) : d[r];
+                    if (__any(nd < d[r])) rows |= 1u << r;
+                    d[r] = nd;
+                }
+    #pragma unroll
+                for (int r = RW - 1; r >= 0; --r) {
+                    const int32_t dn = r == RW - 1 ? bot : d[r + 1];
+                    const int32_t nd = (mD >> r) & 1u ? min(d[r], dn + INC) : d[r];
+                    if (__any(nd < d[r])) rows |= 1u << r;
+                    d[r] = nd;
+                }
+            }
+            edge[w][0][lane] = d[0];
+            edge[w][1][lane] = d[RW - 1];
+            __syncthreads();
+            if (w > 0) {
+                const int32_t v = edge[w - 1][1][lane];
+                if (__any(v < top)) rows |= 1u;
+                top = min(top, v);
+            }
+            if (w < 3) {
+                const int32_t v = edge[w + 1][0][lane];
+                if (__any(v < bot)) rows |= 1u << (RW - 1);
+                bot = min(bot, v);
+            }
+            if (!__syncthreads_or(rows != 0)) break;
         }
-        if (w < 3) {
-            const int32_t v = edge[w + 1][0][lane];
-            if (__any(v < bot)) rows |= 1u << (RW - 1);
-            bot = min(bot, v);
+        bool ch_top = false, ch_bot = false, ch_col = false;
+    #pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            if (d[r] == d0[r]) continue;
+            D.lab[g.off + int64_t(yw + r) * g.W + x] = d[r];
+            ch_col = true;
+            if (w == 0 && r == 0) ch_top = true;
+            if (w == 3 && r == RW - 1) ch_bot = true;
         }
-        if (!__syncthreads_or(rows != 0)) break;
-    }
-    bool ch_top = false, ch_bot = false, ch_col = false;
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        if (d[r] == d0[r]) continue;
-        D.lab[g.off + int64_t(yw + r) * g.W + x] = d[r];
-        ch_col = true;
-        if (w == 0 && r == 0) ch_top = true;
-        if (w == 3 && r == RW - 1) ch_bot = true;
-    }
-    const bool e_top = __any(ch_top), e_bot = __any(ch_bot);
-    const bool e_left = __any(lane == 0 && ch_col), e_right = __any(lane == 63 && ch_col);
-    if (lane == 0) {
-        const int bits = (e_right ? 1 : 0) | (e_left ? 2 : 0) | (e_bot ? 4 : 0) |
-                         (e_top ? 8 : 0);
-        if (bits) atomicOr(&s_ch, bits);
-    }
-    __syncthreads();
-    if (w == 0) {  // lane i of wavefront 0 flags neighbour i (right, left, below, above)
-        const int bits = s_ch;
-        int nb = -1;
-        if (lane == 0 && (bits & 1) && g.tx + 1 < g.tiles_x) nb = t + 1;
-        if (lane == 1 && (bits & 2) && g.tx > 0) nb = t - 1;
-        if (lane == 2 && (bits & 4) && g.ty + 1 < g.tiles_y) nb = t + g.tiles_x;
-        if (lane == 3 && (bits & 8) && g.ty > 0) nb = t - g.tiles_x;
-        const bool fresh = nb >= 0 && atomicExch(&D.dirty[nxt][nb], 1) == 0;
-        list_append(D.dlist[nxt], cnt_next, fresh, nb, lane);
+        const bool e_top = __any(ch_top), e_bot = __any(ch_bot);
+        const bool e_left = __any(lane == 0 && ch_col), e_right = __any(lane == 63 && ch_col);
+        if (lane == 0) {
+            const int bits = (e_right ? 1 : 0) | (e_left ? 2 : 0) | (e_bot ? 4 : 0) |
+                             (e_top ? 8 : 0);
+            if (bits) atomicOr(&s_ch, bits);
+        }
+        __syncthreads();
+        if (w == 0) {  // lane i of wavefront 0 flags neighbour i (right, left, below, above)
+            const int bits = s_ch;
+            int nb = -1;
+            if (lane == 0 && (bits & 1) && g.tx + 1 < g.tiles_x) nb = t + 1;
+            if (lane == 1 && (bits & 2) && g.tx > 0) nb = t - 1;
+            if (lane == 2 && (bits & 4) && g.ty + 1 < g.tiles_y) nb = t + g.tiles_x;
+            if (lane == 3 && (bits & 8) && g.ty > 0) nb = t - g.tiles_x;
+            const bool fresh = nb >= 0 && atomicExch(&D.dirty[nxt][nb], 1) == 0;
+            list_append(D.dlist[nxt], cnt_next, fresh, nb, lane);
+        }
     }
 }
 
@@ -1096,7 +1106,7 @@ struct Kern {
     }
     static void relax(bool cut, hipStream_t s, const Dev &D, int cur, const int32_t *cnt_cur,
                       int32_t *cnt_next) {
-        const dim3 gw(D.ntiles_r);
+        const dim3 gw(std::min(D.ntiles_r, RELAX_GRID));
         if (D.seg_scan) {
             if (cut) hipLaunchKernelGGL((k_relax4<true, true>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
             else hipLaunchKernelGGL((k_relax4<false, true>), gw, dim3(NT), 0, s, D, cur, cnt_cur, cnt_next);
