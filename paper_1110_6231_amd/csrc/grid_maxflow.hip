@@ -1655,12 +1655,11 @@ static Sched default_sched(int64_t N) {
     const auto it = g_sched.find(size_class(N));
     if (it != g_sched.end()) return it->second;
     // the schedule search on MI355X: 64 x 8 tiles, 16 local iterations for
-    // the 1024 x 1024 graph cut (2.1 ms); 64 x 8 tiles, 32 iterations for the
-    // 2048 x 2048 grid alone (10.0 ms); 64 x 16 tiles, 32 iterations for the
-    // batched workload of 10.5 M pixels (13.4 ms); 4 sweeps per round and the
-    // relabel between the sweeps throughout
-    if (N >= (int64_t(1) << 23)) return Sched{16, 32, 4, 0, 2};
-    if (N >= (int64_t(1) << 22)) return Sched{8, 32, 4, 0, 2};
+    // the 1024 x 1024 graph cut (2.0 ms); 64 x 16 tiles, 16 iterations for the
+    // 2048 x 2048 grid alone (8.3 ms) and for the batched workload of 10.5 M
+    // pixels (11.3 ms); 4 sweeps per round and the relabel between the
+    // sweeps throughout
+    if (N >= (int64_t(1) << 22)) return Sched{16, 16, 4, 0, 2};
     return Sched{8, 16, 4, 0, 2};
 }
 
