@@ -275,19 +275,34 @@ __device__ inline unsigned long long block_sum_u64(unsigned long long v) {
 template <int TH>
 __global__ __launch_bounds__(NT) void k_init(Dev D) {
     const Geo g = tile_geo<TH>(D, blockIdx.x);
+    // every row's six loads first, from a clamped valid pixel (the arcs that
+    // leave the grid are read and then zeroed), then the checks and stores
     const int c = threadIdx.x & (TW - 1);
+    const int x = g.x0 + c;
+    const int xc = min(x, g.W - 1);
+    int32_t v[TH / RPP][6];
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int y = min(g.y0 + (threadIdx.x >> 6) + RPP * k, g.H - 1);
+        const int64_t p = g.off + int64_t(y) * g.W + xc;
+        v[k][0] = D.cap_src[p];
+        v[k][1] = D.cap_snk[p];
+        v[k][2] = D.cap_r[p];
+        v[k][3] = D.cap_l[p];
+        v[k][4] = D.cap_d[p];
+        v[k][5] = D.cap_u[p];
+    }
     int bad = 0;
 #pragma unroll
     for (int k = 0; k < TH / RPP; ++k) {
-        const int r = (threadIdx.x >> 6) + RPP * k;
-        const int y = g.y0 + r, x = g.x0 + c;
+        const int y = g.y0 + (threadIdx.x >> 6) + RPP * k;
         if (y >= g.H || x >= g.W) continue;
         const int64_t p = g.off + int64_t(y) * g.W + x;
-        const int32_t src = D.cap_src[p], snk = D.cap_snk[p];
-        const int32_t cr = (x + 1 < g.W) ? D.cap_r[p] : 0;
-        const int32_t cl = (x > 0) ? D.cap_l[p] : 0;
-        const int32_t cd = (y + 1 < g.H) ? D.cap_d[p] : 0;
-        const int32_t cu = (y > 0) ? D.cap_u[p] : 0;
+        const int32_t src = v[k][0], snk = v[k][1];
+        const int32_t cr = (x + 1 < g.W) ? v[k][2] : 0;
+        const int32_t cl = (x > 0) ? v[k][3] : 0;
+        const int32_t cd = (y + 1 < g.H) ? v[k][4] : 0;
+        const int32_t cu = (y > 0) ? v[k][5] : 0;
         const int32_t mn = min(min(min(src, snk), min(cr, cl)), min(cd, cu));
         const int32_t mx = max(max(max(src, snk), max(cr, cl)), max(cd, cu));
         if (mn < 0) bad |= 1;
@@ -441,28 +456,40 @@ __global__ __launch_bounds__(NT) void k_cut_seed(Dev D) {
         D.dirty[0][t] = 1;
         D.dlist[0][atomicAdd(&D.sc->seed_count, 1)] = t;
     }
+    // every row's load first, from a clamped valid pixel, then the stores
     const int c = threadIdx.x & (TW - 1);
+    const int x = g.x0 + c;
+    const int xc = min(x, g.W - 1);
+    int32_t ev[TH / RPP];
 #pragma unroll
     for (int k = 0; k < TH / RPP; ++k) {
-        const int r = (threadIdx.x >> 6) + RPP * k;
-        const int y = g.y0 + r, x = g.x0 + c;
-        if (y >= g.H || x >= g.W) continue;
-        const int64_t p = g.off + int64_t(y) * g.W + x;
-        D.lab[p] = D.e[p] > 0 ? 0 : g.HV;
+        const int y = min(g.y0 + (threadIdx.x >> 6) + RPP * k, g.H - 1);
+        ev[k] = D.e[g.off + int64_t(y) * g.W + xc];
+    }
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int y = g.y0 + (threadIdx.x >> 6) + RPP * k;
+        if (y < g.H && x < g.W) D.lab[g.off + int64_t(y) * g.W + x] = ev[k] > 0 ? 0 : g.HV;
     }
 }
 
 template <int TH>
 __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
     const Geo g = tile_geo<TH>(D, blockIdx.x);
+    // every row's load first, from a clamped valid pixel, then the stores
     const int c = threadIdx.x & (TW - 1);
+    const int x = g.x0 + c;
+    const int xc = min(x, g.W - 1);
+    int32_t lv[TH / RPP];
 #pragma unroll
     for (int k = 0; k < TH / RPP; ++k) {
-        const int r = (threadIdx.x >> 6) + RPP * k;
-        const int y = g.y0 + r, x = g.x0 + c;
-        if (y >= g.H || x >= g.W) continue;
-        const int64_t p = g.off + int64_t(y) * g.W + x;
-        side[p] = D.lab[p] < g.HV ? 1 : 0;
+        const int y = min(g.y0 + (threadIdx.x >> 6) + RPP * k, g.H - 1);
+        lv[k] = D.lab[g.off + int64_t(y) * g.W + xc];
+    }
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int y = g.y0 + (threadIdx.x >> 6) + RPP * k;
+        if (y < g.H && x < g.W) side[g.off + int64_t(y) * g.W + x] = lv[k] < g.HV ? 1 : 0;
     }
 }
 
@@ -1015,15 +1042,24 @@ __global__ __launch_bounds__(256) void k_sweep(Dev D, int cur, int L) {
 template <int TH>
 __global__ __launch_bounds__(NT) void k_flow_value(Dev D, int64_t *flow) {
     const Geo g = tile_geo<TH>(D, blockIdx.x);
+    // every row's loads first, from a clamped valid pixel; rows and columns
+    // past the grid add nothing
     const int c = threadIdx.x & (TW - 1);
+    const int x = g.x0 + c;
+    const int xc = min(x, g.W - 1);
+    int32_t cv[TH / RPP], rv[TH / RPP];
+#pragma unroll
+    for (int k = 0; k < TH / RPP; ++k) {
+        const int y = min(g.y0 + (threadIdx.x >> 6) + RPP * k, g.H - 1);
+        const int64_t p = g.off + int64_t(y) * g.W + xc;
+        cv[k] = D.cap_snk[p];
+        rv[k] = D.rs[p];
+    }
     unsigned long long s = 0;
 #pragma unroll
     for (int k = 0; k < TH / RPP; ++k) {
-        const int r = (threadIdx.x >> 6) + RPP * k;
-        const int y = g.y0 + r, x = g.x0 + c;
-        if (y >= g.H || x >= g.W) continue;
-        const int64_t p = g.off + int64_t(y) * g.W + x;
-        s += (unsigned long long)(int64_t(D.cap_snk[p]) - D.rs[p]);
+        const int y = g.y0 + (threadIdx.x >> 6) + RPP * k;
+        if (y < g.H && x < g.W) s += (unsigned long long)(int64_t(cv[k]) - rv[k]);
     }
     const unsigned long long tot = block_sum_u64(s);
     if (threadIdx.x == 0 && tot)
