@@ -283,7 +283,8 @@ def assign_single(torch, lpr, synth, reps=3):
         opts=lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_TIME_KERNELS))
     assert tot2 == tot
     return {"workload": "dense assignment n=1024, weights U{0..1000}, "
-                        "max-weight, alpha=8, plain start",
+                        "max-weight, plain start (built-in schedule: alpha 6 at "
+                        "n >= 1024)",
             "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(dt * 1e3, 3),
             "total": tot, "refines": st["refines"], "phases": st["phases"],
             "pushes": st["pushes"], "relabels": st["relabels"],

@@ -304,7 +304,10 @@ lpr_status lpr_grid_tune(int32_t B, const int32_t *H, const int32_t *W,
                                      refines and the solve is not faster */
 
 typedef struct {
-    int32_t alpha;                  /* epsilon divisor per refine; 0 -> 8    */
+    int32_t alpha;                  /* epsilon divisor per refine; 0 -> the
+                                       tuned default (lpr_assign_tune), else
+                                       6 when the largest instance has
+                                       n >= 1024 and 8 below               */
     int32_t flags;                  /* LPR_ASSIGN_* bits                     */
     int64_t eps0;                   /* initial epsilon of the Min-Cost loop in
                                        scaled units (costs times 2n+1); the
@@ -325,14 +328,14 @@ typedef struct {
     int64_t price_update_period;    /* pushes between global price updates
                                        (Algorithm 5.3), which run when a
                                        refine reaches its last few active
-                                       rows; 0 -> n/2 for n <= 512 and n
-                                       above (measured best on the batched
-                                       and the n = 1024 workloads), -1 ->
-                                       never                               */
+                                       rows; 0 -> n q / 4 for an instance of
+                                       size n (q = price_update_quarters),
+                                       -1 -> never                         */
     int32_t tail_rows;              /* a refine switches to one wavefront
                                        running operations back to back once
                                        at most this many rows are active;
-                                       0 -> min(32, max(8, 8192 / n))        */
+                                       0 -> the tuned default, else
+                                       min(32, max(8, 8192 / n))             */
     int32_t fixing_shift;           /* for tests of the rerun path: divides
                                        the arc-fixing bound by
                                        2^fixing_shift (0..63; 0 = the
@@ -351,6 +354,12 @@ typedef struct {
                                        max|c| (2n+1)); max_ops still bounds
                                        the whole solve.  0 -> 2 n^2 + 2^16,
                                        -1 -> never                         */
+    int32_t price_update_quarters;  /* q of the default period n q / 4
+                                       (1..64); 0 -> the tuned default, else
+                                       2 for n <= 512 and 4 above (measured
+                                       best on the batched and the n = 1024
+                                       workloads)                          */
+    int32_t reserved;               /* must be 0                            */
 } lpr_assign_opts;
 
 typedef struct {
@@ -373,6 +382,13 @@ typedef struct {
                                 per distinct label reached), summed       */
     double kernel_ms;   /* with LPR_ASSIGN_TIME_KERNELS: solve kernel time */
     double total_ms;    /* device time of the whole call (HIP events)      */
+    int32_t alpha;      /* schedule used: epsilon divisor per refine,       */
+    int32_t price_update_quarters; /* q of the period n q / 4 (0: the rule
+                                of 2 for n <= 512 and 4 above, or a
+                                price_update_period was given),            */
+    int32_t tail_rows;  /* and the tail threshold (0: min(32, max(8,
+                                8192 / n)) per instance)                   */
+    int32_t reserved;
 } lpr_assign_stats;
 
 /* Device workspace bytes needed by lpr_assign_solve for size n. */
@@ -429,6 +445,31 @@ lpr_status lpr_assign_solve_batched(int32_t B, const int32_t *n,
                                     const lpr_assign_opts *opts,
                                     lpr_assign_stats *stats, void *workspace,
                                     size_t workspace_bytes, void *stream);
+
+/*
+ * Schedule autotuner for the assignment solver (the tuning the paper does
+ * by hand for its refine: alpha and the price-update heuristic, Section 5).
+ * Solves the given batch (the arguments of lpr_assign_solve_batched; `base`
+ * may be NULL or carry a start -- init_col_prices, eps0, eps0_per_instance
+ * -- and budgets, which every trial keeps; its alpha, period, quarters and
+ * tail fields must be 0) under every schedule of alpha {4, 6, 8, 16} x
+ * price-update period n q / 4, q in {1, 2, 4, 8} x tail rows {per-instance
+ * rule, 8, 32}, each `reps` times after one warm-up run (1 <= reps <= 100),
+ * timed with HIP events.  It returns the fastest in `best` (host, may be
+ * NULL; a copy of `base` with the schedule fields set) with its time in ms
+ * (host, may be NULL).  The winner becomes this process's default for the
+ * batch's size class (floor(log2(sum of n^2))) and kind of start (plain, or
+ * from given prices or epsilon) -- used whenever those fields of the options
+ * are 0 -- and is written to the file named by the environment variable
+ * LPR_ASSIGN_TUNE_FILE, if set, which later processes read.  Every schedule
+ * must give the same optimal totals; a disagreement returns LPR_EDEVICE.
+ * Other errors as for lpr_assign_solve_batched.
+ */
+lpr_status lpr_assign_tune(int32_t B, const int32_t *n, const int64_t *cost_offset,
+                           const int32_t *costs, int32_t maximize, int32_t *row_to_col,
+                           int64_t *totals, const lpr_assign_opts *base, int32_t reps,
+                           lpr_assign_opts *best, double *best_ms, void *workspace,
+                           size_t workspace_bytes, void *stream);
 
 /* Most arcs a sparse assignment instance may list (parallel arcs included). */
 #define LPR_ASSIGN_SPARSE_MAX_ARCS (1 << 26)

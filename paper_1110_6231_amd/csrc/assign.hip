@@ -46,6 +46,10 @@
 //     int16 copy of the costs.
 #include <algorithm>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -103,8 +107,10 @@ struct AArgs {
     int64_t warm_max_ops;          // > 0: budget of a warm start before it
                                    // restarts from the plain start; 0: the
                                    // default 2 n^2 + 2^16; < 0: never
-    int64_t pu_period;             // pushes between price updates; 0: n/2 up to
-                                   // n = 512, n above; < 0: never
+    int64_t pu_period;             // pushes between price updates; 0: n pu_q / 4;
+                                   // < 0: never
+    int32_t pu_q;                  // q of the default period; 0: 2 up to
+                                   // n = 512, 4 above
     int32_t tail_rows;             // serial tail threshold (active rows)
     int32_t pu_start;              // price update after each refine's first push
     int32_t arc_fixing;            // keep candidate lists of unfixed arcs
@@ -760,9 +766,10 @@ __device__ void solve_instance(const AArgs &A, const AInst &I, int slot,
     U.fx = reinterpret_cast<uint8_t *>(U.ly + n);
     U.fy = U.fx + n;
     int64_t *py = L.py, *px = L.px;
+    const int pu_q = A.pu_q > 0 ? A.pu_q : (n > 512 ? 4 : 2);
     const unsigned long long period =
         A.pu_period > 0 ? (unsigned long long)A.pu_period
-                        : (unsigned long long)(n > 512 ? n : max(1, n / 2));
+                        : (unsigned long long)max(1, n * pu_q / 4);
     if (A.pu_period < 0) CT = nullptr;
     // the tail's cost per operation grows with n (one row scan), a phase's
     // barrier cost does not
@@ -1177,6 +1184,75 @@ static size_t workspace_bytes(int B, const int32_t *n) {
     return carve(Carver(), B, n, &L).used();
 }
 
+// ---------------------------------------------------------------------------
+// Tuned schedules (lpr_assign_tune): alpha, the price-update quarters and the
+// tail threshold per size class (floor(log2(sum of n^2))), kind of start
+// (plain or warm) and form (dense or sparse); 0 in a field keeps the
+// built-in rule.
+// ---------------------------------------------------------------------------
+struct ASched {
+    int alpha, q, tail;
+};
+
+static std::mutex g_asched_mu;
+static std::map<int, ASched> g_asched;
+static bool g_asched_loaded = false;
+
+static int sched_key(int B, const int32_t *n, bool warm, int sparse) {
+    int64_t e = 0;
+    for (int b = 0; b < B; ++b) e += int64_t(n[b]) * n[b];
+    int c = 0;
+    while (c < 62 && (int64_t(1) << (c + 1)) <= e) ++c;
+    return c * 4 + (warm ? 2 : 0) + (sparse ? 1 : 0);
+}
+
+static bool valid_asched(const ASched &a) {
+    return (a.alpha == 0 || (a.alpha >= 2 && a.alpha <= 1024)) && a.q >= 0 && a.q <= 64 &&
+           a.tail >= 0 && a.tail <= 4096;
+}
+
+static void load_asched_file_locked() {
+    if (g_asched_loaded) return;
+    g_asched_loaded = true;
+    const char *path = std::getenv("LPR_ASSIGN_TUNE_FILE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    int k;
+    ASched a;
+    while (std::fscanf(f, "%d %d %d %d", &k, &a.alpha, &a.q, &a.tail) == 4)
+        if (k >= 0 && k < 256 && valid_asched(a)) g_asched[k] = a;
+    std::fclose(f);
+}
+
+static ASched default_asched(int key) {
+    std::lock_guard<std::mutex> lk(g_asched_mu);
+    load_asched_file_locked();
+    const auto it = g_asched.find(key);
+    return it != g_asched.end() ? it->second : ASched{0, 0, 0};
+}
+
+static void store_asched(int key, const ASched &a) {
+    std::lock_guard<std::mutex> lk(g_asched_mu);
+    load_asched_file_locked();
+    g_asched[key] = a;
+    const char *path = std::getenv("LPR_ASSIGN_TUNE_FILE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    for (const auto &e : g_asched)
+        std::fprintf(f, "%d %d %d %d\n", e.first, e.second.alpha, e.second.q, e.second.tail);
+    std::fclose(f);
+}
+
+// Forgets the schedule of a key, so that a tuning trial's 0 fields mean the
+// built-in rules.
+static void erase_asched(int key) {
+    std::lock_guard<std::mutex> lk(g_asched_mu);
+    load_asched_file_locked();
+    g_asched.erase(key);
+}
+
 static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
                       const int32_t *costs, int32_t maximize,
                       int32_t *row_to_col, int64_t *totals, int64_t *col_prices,
@@ -1219,10 +1295,16 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         set_error("too many rows");
         return LPR_EINVAL;
     }
-    int32_t alpha = 8;
+    // the tuned schedule of this size class and kind of start fills the
+    // schedule fields the options leave 0
+    const bool warm = opts && (opts->init_col_prices || opts->eps0 || opts->eps0_per_instance);
+    const ASched ds = default_asched(sched_key(B, n, warm, sparse));
+    // built-in alpha: 6 once the largest instance has n >= 1024, 8 below
+    // (the measured best on the n = 1024 and the batched workloads)
+    int32_t alpha = ds.alpha ? ds.alpha : (nmax >= 1024 ? 6 : 8);
     int64_t eps0 = 0, max_ops = 64 * int64_t(nmax) * nmax + (int64_t(1) << 20);
     int64_t max_ms = 20000, pu_period = 0, warm_max_ops = 0;
-    int32_t tail_rows = 0, pu_start = 1, arc_fixing = 0, fixing_shift = 0;
+    int32_t tail_rows = ds.tail, pu_q = ds.q, pu_start = 1, arc_fixing = 0, fixing_shift = 0;
     const int64_t *init = nullptr, *eps0_inst = nullptr;
     bool timing = false;
     if (opts) {
@@ -1233,12 +1315,19 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         if (opts->max_ops) max_ops = opts->max_ops;
         if (opts->max_ms) max_ms = opts->max_ms;
         pu_period = opts->price_update_period;
-        tail_rows = opts->tail_rows;
+        if (opts->tail_rows) tail_rows = opts->tail_rows;
+        if (opts->price_update_quarters) pu_q = opts->price_update_quarters;
         pu_start = (opts->flags & LPR_ASSIGN_NO_START_UPDATE) == 0;
         arc_fixing = (opts->flags & LPR_ASSIGN_ARC_FIXING) != 0;
         fixing_shift = opts->fixing_shift;
         warm_max_ops = opts->warm_max_ops;
         timing = (opts->flags & LPR_ASSIGN_TIME_KERNELS) != 0;
+        if (opts->price_update_quarters < 0 || opts->price_update_quarters > 64 ||
+            opts->reserved != 0) {
+            set_error("invalid lpr_assign_opts (price_update_quarters outside 0..64 or "
+                      "reserved not 0)");
+            return LPR_EINVAL;
+        }
     }
     if (alpha < 2 || eps0 < 0 || max_ops < 0 || max_ms < 0 || tail_rows < 0 ||
         tail_rows > 4096 || fixing_shift < 0 || fixing_shift > 63 || warm_max_ops < -1) {
@@ -1290,6 +1379,7 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     A.max_ops = max_ops;
     A.warm_max_ops = warm_max_ops;
     A.pu_period = pu_period;
+    A.pu_q = pu_q;
     A.tail_rows = tail_rows;
     A.pu_start = pu_start;
     A.arc_fixing = arc_fixing;
@@ -1342,6 +1432,10 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         stats->price_update_steps = int64_t(cnt[10]);
         stats->kernel_ms = kms;
         stats->total_ms = tms;
+        stats->alpha = alpha;
+        stats->price_update_quarters = pu_period != 0 ? 0 : pu_q;
+        stats->tail_rows = tail_rows;
+        stats->reserved = 0;
     }
     for (int b = 0; b < B; ++b) {
         if (status[b] == 2) {
@@ -1406,6 +1500,78 @@ extern "C" lpr_status lpr_assign_solve_batched(
     return assign::run(B, n, cost_offset, costs, maximize, row_to_col, totals,
                        col_prices, opts, stats, workspace, workspace_bytes,
                        stream);
+}
+
+extern "C" lpr_status lpr_assign_tune(int32_t B, const int32_t *n,
+                                      const int64_t *cost_offset, const int32_t *costs,
+                                      int32_t maximize, int32_t *row_to_col,
+                                      int64_t *totals, const lpr_assign_opts *base,
+                                      int32_t reps, lpr_assign_opts *best,
+                                      double *best_ms, void *workspace,
+                                      size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (B < 1 || !n || !totals || reps < 1 || reps > 100) {
+        set_error("invalid tuning arguments");
+        return LPR_EINVAL;
+    }
+    lpr_assign_opts o = base ? *base : lpr_assign_opts{};
+    if (o.alpha || o.price_update_period || o.price_update_quarters || o.tail_rows) {
+        set_error("the schedule fields of the base options must be 0");
+        return LPR_EINVAL;
+    }
+    o.flags &= ~LPR_ASSIGN_TIME_KERNELS;
+    const bool warm = base && (base->init_col_prices || base->eps0 || base->eps0_per_instance);
+    const int key = assign::sched_key(B, n, warm, 0);
+    assign::erase_asched(key);
+    static const int alphas[4] = {4, 6, 8, 16};
+    static const int qs[4] = {1, 2, 4, 8};
+    static const int tails[3] = {0, 8, 32};
+    std::vector<int64_t> ref(B), got(B);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool have_ref = false;
+    double best_t = 1e300;
+    assign::ASched best_s{8, 0, 0};
+    for (int a : alphas)
+        for (int q : qs)
+            for (int tl : tails) {
+                o.alpha = a;
+                o.price_update_quarters = q;
+                o.tail_rows = tl;
+                // the fastest of `reps` runs after a warm-up, its totals
+                // checked against the first schedule's
+                double t_min = 1e300;
+                for (int r = 0; r <= reps; ++r) {
+                    lpr_assign_stats st{};
+                    LPR_TRY(assign::run(B, n, cost_offset, costs, maximize, row_to_col,
+                                        totals, nullptr, &o, &st, workspace,
+                                        workspace_bytes, stream));
+                    if (r > 0) t_min = std::min(t_min, st.total_ms);
+                }
+                LPR_TRY_HIP(hipMemcpyAsync(got.data(), totals, sizeof(int64_t) * B,
+                                           hipMemcpyDeviceToHost, s));
+                LPR_TRY_HIP(hipStreamSynchronize(s));
+                if (!have_ref) {
+                    ref = got;
+                    have_ref = true;
+                } else if (got != ref) {
+                    set_error("schedules disagree on an optimal total (alpha %d, quarters "
+                              "%d, tail rows %d)", a, q, tl);
+                    return LPR_EDEVICE;
+                }
+                if (t_min < best_t) {
+                    best_t = t_min;
+                    best_s = assign::ASched{a, q, tl};
+                }
+            }
+    assign::store_asched(key, best_s);
+    if (best) {
+        *best = base ? *base : lpr_assign_opts{};
+        best->alpha = best_s.alpha;
+        best->price_update_quarters = best_s.q;
+        best->tail_rows = best_s.tail;
+    }
+    if (best_ms) *best_ms = best_t;
+    return LPR_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -47,7 +47,7 @@ EXPORTED = [
     "lpr_grid_maxflow_batched_workspace", "lpr_grid_maxflow_batched",
     "lpr_grid_tune",
     "lpr_assign_workspace", "lpr_assign_solve",
-    "lpr_assign_batched_workspace", "lpr_assign_solve_batched",
+    "lpr_assign_batched_workspace", "lpr_assign_solve_batched", "lpr_assign_tune",
     "lpr_assign_sparse_workspace", "lpr_assign_sparse_solve",
     "lpr_pricenet_param_count", "lpr_pricenet_workspace",
     "lpr_pricenet_features", "lpr_pricenet_infer", "lpr_pricenet_train_step",
@@ -101,7 +101,9 @@ class AssignOpts(ctypes.Structure):
                 ("eps0_per_instance", ctypes.c_void_p),
                 ("price_update_period", ctypes.c_int64),
                 ("tail_rows", ctypes.c_int32), ("fixing_shift", ctypes.c_int32),
-                ("warm_max_ops", ctypes.c_int64)]
+                ("warm_max_ops", ctypes.c_int64),
+                ("price_update_quarters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class AssignStats(ctypes.Structure):
@@ -113,7 +115,10 @@ class AssignStats(ctypes.Structure):
                 ("warm_restarts", ctypes.c_int64),
                 ("scan_entries", ctypes.c_int64),
                 ("price_update_steps", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("alpha", ctypes.c_int32),
+                ("price_update_quarters", ctypes.c_int32),
+                ("tail_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GraphOpts(ctypes.Structure):
@@ -193,6 +198,11 @@ def lib():
                                            ctypes.POINTER(AssignOpts),
                                            ctypes.POINTER(AssignStats), vp, sz,
                                            vp]
+    L.lpr_assign_tune.restype = ctypes.c_int
+    L.lpr_assign_tune.argtypes = [i32, i32p, i64p, vp, i32, vp, vp,
+                                  ctypes.POINTER(AssignOpts), i32,
+                                  ctypes.POINTER(AssignOpts),
+                                  ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.lpr_assign_sparse_workspace.restype = sz
     L.lpr_assign_sparse_workspace.argtypes = [i32, i32]
     L.lpr_assign_sparse_solve.restype = ctypes.c_int
@@ -410,8 +420,10 @@ def lpr_grid_tune(Hs, Ws, caps_packed, reps=2, workspace=None, stream=None):
 def make_assign_opts(alpha=0, eps0=0, init_col_prices=None, max_ops=0,
                      flags=0, max_ms=0, eps0_per_instance=None,
                      price_update_period=0, tail_rows=0,
-                     fixing_shift=0, warm_max_ops=0) -> AssignOpts:
+                     fixing_shift=0, warm_max_ops=0,
+                     price_update_quarters=0) -> AssignOpts:
     o = AssignOpts()
+    o.price_update_quarters = price_update_quarters
     o.warm_max_ops = warm_max_ops
     o.max_ms = max_ms
     o.price_update_period = price_update_period
@@ -537,6 +549,32 @@ def lpr_assign_solve_batched(packed: PackedAssign, maximize=False,
         _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "lpr_assign_solve_batched")
     return r2c, tots, prices, _struct_dict(st)
+
+
+def lpr_assign_tune(packed: PackedAssign, maximize=False,
+                    base: AssignOpts | None = None, reps=2, workspace=None,
+                    stream=None):
+    """Schedule search (lpr_assign_tune).  Returns (schedule dict, best ms,
+    totals of the batch as an int64 tensor)."""
+    import torch
+    B = len(packed.ns)
+    dev = packed.costs.device
+    rows = int(packed.row_offset[-1])
+    r2c = torch.empty(rows, dtype=torch.int32, device=dev)
+    tots = torch.zeros(B, dtype=torch.int64, device=dev)
+    ws = workspace if workspace is not None else _workspace(
+        lpr_assign_batched_workspace(packed.ns), dev)
+    best = AssignOpts()
+    ms = ctypes.c_double(0.0)
+    rc = lib().lpr_assign_tune(
+        B, _i32_arr(packed.ns), _i64_arr(packed.cost_offset), _ptr(packed.costs),
+        int(bool(maximize)), _ptr(r2c), _ptr(tots),
+        ctypes.byref(base) if base is not None else None, int(reps),
+        ctypes.byref(best), ctypes.byref(ms), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_assign_tune")
+    sched = {"alpha": best.alpha, "price_update_quarters": best.price_update_quarters,
+             "tail_rows": best.tail_rows}
+    return sched, ms.value, tots
 
 
 # ---------------------------------------------------------------------------

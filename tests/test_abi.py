@@ -133,6 +133,41 @@ def test_sparse_assignment_host_checks():
     assert f(4, 4, fake, fake, fake, *common, 16, None) == lpr.LPR_ENOMEM
 
 
+def test_assign_tune_host_checks():
+    """The assignment tuner rejects, on the host and before anything reaches
+    the device, a repetition count outside 1..100, missing sizes or totals,
+    and base options that already fix a schedule field; the option checks of
+    every solve reject a quarter count outside 0..64 and a nonzero reserved
+    field."""
+    import ctypes
+    L = lpr.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below is rejected
+    n = (ctypes.c_int32 * 1)(4)
+    off = (ctypes.c_int64 * 2)(0, 16)
+    ms = ctypes.c_double(0)
+
+    def tune(base, reps, nn=n, totals=fake):
+        return L.lpr_assign_tune(1, nn, off, fake, 0, fake, totals, base, reps, None,
+                                 ctypes.byref(ms), fake, 1 << 30, None)
+
+    assert tune(None, 0) == lpr.LPR_EINVAL
+    assert tune(None, 101) == lpr.LPR_EINVAL
+    assert tune(None, 1, nn=None) == lpr.LPR_EINVAL
+    assert tune(None, 1, totals=None) == lpr.LPR_EINVAL
+    for field, value in (("alpha", 4), ("price_update_period", 100),
+                         ("price_update_quarters", 2), ("tail_rows", 8)):
+        o = lpr.make_assign_opts()
+        setattr(o, field, value)
+        assert tune(ctypes.byref(o), 1) == lpr.LPR_EINVAL, field
+    for field, value in (("price_update_quarters", 65), ("price_update_quarters", -1),
+                         ("reserved", 1)):
+        o = lpr.make_assign_opts()
+        setattr(o, field, value)
+        rc = L.lpr_assign_solve(4, fake, 0, fake, fake, None, ctypes.byref(o), None,
+                                fake, 1 << 30, None)
+        assert rc == lpr.LPR_EINVAL, field
+
+
 def test_mincost_flow_host_checks():
     """Sizes and argument checks of the min-cost flow entry point, decided on
     the host before anything reaches the device."""

@@ -298,3 +298,34 @@ def test_errors():
         lpr.lpr_assign_solve(c, opts=lpr.make_assign_opts(alpha=1))
     assert e.value.status == lpr.LPR_EINVAL
     check(c)
+
+
+def test_autotuner_is_exact_and_sets_default():
+    """lpr_assign_tune: every schedule it tries gives the oracle's totals, the
+    winner is one of the searched schedules, and later solves of that size
+    class and kind of start use it when their options leave the fields 0;
+    options that set a field still override it."""
+    mats = [synth.assign_random_small(n, seed=n, lo=0, hi=500) for n in (33, 47, 61, 70)]
+    packed = lpr.PackedAssign.from_matrices(mats)
+    want = [oracle.assign(m)[1] for m in mats]
+    print("[assign] tuner on 4 instances", flush=True)
+    sched, ms, tots = lpr.lpr_assign_tune(packed, reps=1)
+    assert tots.cpu().numpy().tolist() == want
+    assert sched["alpha"] in (4, 6, 8, 16)
+    assert sched["price_update_quarters"] in (1, 2, 4, 8)
+    assert sched["tail_rows"] in (0, 8, 32)
+    assert ms > 0
+    _, tot, _, st = lpr.lpr_assign_solve_batched(packed)
+    assert tot.cpu().numpy().tolist() == want
+    assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (
+        sched["alpha"], sched["price_update_quarters"], sched["tail_rows"])
+    o = lpr.make_assign_opts(alpha=5, price_update_quarters=3, tail_rows=12)
+    _, tot, _, st = lpr.lpr_assign_solve_batched(packed, opts=o)
+    assert tot.cpu().numpy().tolist() == want
+    assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (5, 3, 12)
+    # a warm start is its own kind: untuned, it keeps the built-in rules
+    eps = torch.full((len(mats),), 1 << 12, dtype=torch.int64, device="cuda")
+    _, tot, _, st = lpr.lpr_assign_solve_batched(
+        packed, opts=lpr.make_assign_opts(eps0_per_instance=eps))
+    assert tot.cpu().numpy().tolist() == want
+    assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (8, 0, 0)
