@@ -306,8 +306,8 @@ lpr_status lpr_grid_tune(int32_t B, const int32_t *H, const int32_t *W,
 typedef struct {
     int32_t alpha;                  /* epsilon divisor per refine; 0 -> the
                                        tuned default (lpr_assign_tune), else
-                                       6 when the largest instance has
-                                       n >= 1024 and 8 below               */
+                                       6 for dense calls whose largest
+                                       instance has n >= 1024, 8 otherwise  */
     int32_t flags;                  /* LPR_ASSIGN_* bits                     */
     int64_t eps0;                   /* initial epsilon of the Min-Cost loop in
                                        scaled units (costs times 2n+1); the

@@ -1299,9 +1299,10 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     // schedule fields the options leave 0
     const bool warm = opts && (opts->init_col_prices || opts->eps0 || opts->eps0_per_instance);
     const ASched ds = default_asched(sched_key(B, n, warm, sparse));
-    // built-in alpha: 6 once the largest instance has n >= 1024, 8 below
-    // (the measured best on the n = 1024 and the batched workloads)
-    int32_t alpha = ds.alpha ? ds.alpha : (nmax >= 1024 ? 6 : 8);
+    // built-in alpha: 6 for dense calls whose largest instance has
+    // n >= 1024, 8 otherwise (measured: the dense n = 1024 workload is
+    // faster at 6, the batched one and the sparse n = 2048 one at 8)
+    int32_t alpha = ds.alpha ? ds.alpha : (nmax >= 1024 && !sparse ? 6 : 8);
     int64_t eps0 = 0, max_ops = 64 * int64_t(nmax) * nmax + (int64_t(1) << 20);
     int64_t max_ms = 20000, pu_period = 0, warm_max_ops = 0;
     int32_t tail_rows = ds.tail, pu_q = ds.q, pu_start = 1, arc_fixing = 0, fixing_shift = 0;
