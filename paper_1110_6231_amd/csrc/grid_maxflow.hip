@@ -318,6 +318,130 @@ __global__ __launch_bounds__(NT) void k_init(Dev D) {
     if (bad) atomicOr(&D.sc->err, bad);
 }
 
+constexpr int RW = 8;  // rows per wavefront of the cooperative relaxation
+constexpr int RELAX_GRID = 2048;  // most workgroups of a relaxation launch
+
+// The in-tile fixpoint of one relaxation tile: wavefront w holds rows
+// RW w .. RW w + RW - 1 (labels d, lane c = column c) with the arcs usable in
+// each direction (bit r of mR, mL, mD, mU), the halo above / below the
+// wavefront (top, bot) and what the side halo offers lanes 0 / 63 (hs); on
+// return every label is at the least fixpoint of the tile given the halo.
+// Called by the whole workgroup (barriers inside); `edge` is its LDS.
+template <bool SEG, int INC>
+__device__ __forceinline__ void tile_fixpoint(int32_t (&d)[RW], uint32_t mR, uint32_t mL,
+                                              uint32_t mD, uint32_t mU,
+                                              const int32_t (&hs)[RW], int32_t top,
+                                              int32_t bot, int lane, int w,
+                                              int32_t (&edge)[4][2][64]) {
+    // per row: the segment extents (SEG) or the scan offsets, less / plus the
+    // column shift of the min-plus form
+    int32_t segL[RW], segR[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const uint64_t brkL = __ballot(!((mL >> r) & 1u)) | 1ull;
+        const uint64_t brkR = __ballot(!((mR >> r) & 1u)) | (1ull << 63);
+        if constexpr (SEG) {
+            const uint64_t low = lane == 63 ? ~0ull : (2ull << lane) - 1;
+            const int sx = 63 - __clzll((long long)(brkL & low));
+            const int ex = lane + __ffsll((unsigned long long)(brkR >> lane)) - 1;
+            segL[r] = lane - sx;
+            segR[r] = ex - lane;
+        } else {
+            // breaks at or left of the lane (left scan), strictly left of it
+            // (right scan): the lane's segment index in each direction
+            const uint32_t bl = __builtin_amdgcn_mbcnt_hi(
+                uint32_t(brkL >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkL), 0u));
+            const uint32_t gl = bl + uint32_t((brkL >> lane) & 1ull);
+            const uint32_t gr = __builtin_amdgcn_mbcnt_hi(
+                uint32_t(brkR >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkR), 0u));
+            segL[r] = int32_t((64u - gl) << OFF_SHIFT) - INC * lane;
+            segR[r] = int32_t(gr << OFF_SHIFT) + INC * lane;
+        }
+    }
+    edge[w][0][lane] = d[0];
+    edge[w][1][lane] = d[RW - 1];
+    __syncthreads();
+    if (w > 0) top = edge[w - 1][1][lane];
+    if (w < 3) bot = edge[w + 1][0][lane];
+    uint32_t rows = (1u << RW) - 1;           // wavefront-uniform
+    for (;;) {
+        __syncthreads();                      // the edges above were read
+        while ((rows = __builtin_amdgcn_readfirstlane(rows)) != 0) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                if (!((rows >> r) & 1u)) continue;
+                int32_t nd = min(d[r], hs[r]);
+                if constexpr (SEG) {
+                    nd = scan_from_left(nd - INC * lane, segL[r], lane) + INC * lane;
+                    nd = scan_from_right(nd + INC * lane, segR[r], lane) - INC * lane;
+                } else {
+                    nd = prefix_min(nd + segL[r]) - segL[r];
+                    nd = suffix_min(nd + segR[r], lane) - segR[r];
+                }
+                d[r] = nd;
+            }
+            rows = 0;
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int32_t up = r == 0 ? top : d[r - 1];
+                const int32_t nd = (mU >> r) & 1u ? min(d[r], up + INC) : d[r];
+                if (__any(nd < d[r])) rows |= 1u << r;
+                d[r] = nd;
+            }
+#pragma unroll
+            for (int r = RW - 1; r >= 0; --r) {
+                const int32_t dn = r == RW - 1 ? bot : d[r + 1];
+                const int32_t nd = (mD >> r) & 1u ? min(d[r], dn + INC) : d[r];
+                if (__any(nd < d[r])) rows |= 1u << r;
+                d[r] = nd;
+            }
+        }
+        edge[w][0][lane] = d[0];
+        edge[w][1][lane] = d[RW - 1];
+        __syncthreads();
+        if (w > 0) {
+            const int32_t v = edge[w - 1][1][lane];
+            if (__any(v < top)) rows |= 1u;
+            top = min(top, v);
+        }
+        if (w < 3) {
+            const int32_t v = edge[w + 1][0][lane];
+            if (__any(v < bot)) rows |= 1u << (RW - 1);
+            bot = min(bot, v);
+        }
+        if (!__syncthreads_or(rows != 0)) break;
+    }
+}
+
+// After a tile's fixpoint: the sides where a label dropped below the value
+// the neighbour across read (right 1, left 2, below 4, above 8) are gathered
+// in s_ch (0 beforehand), and lanes 0..3 of wavefront 0 list those
+// neighbours on the given list (once each: the flags).  Called by the whole
+// workgroup.
+__device__ __forceinline__ void tile_list_changed(const Dev &D, const Geo &g, int t,
+                                                  bool ch_top, bool ch_bot, bool ch_col,
+                                                  int lane, int w, int &s_ch,
+                                                  int32_t *dirty, int32_t *list,
+                                                  int32_t *cnt) {
+    const bool e_top = __any(ch_top), e_bot = __any(ch_bot);
+    const bool e_left = __any(lane == 0 && ch_col), e_right = __any(lane == 63 && ch_col);
+    if (lane == 0) {
+        const int bits = (e_right ? 1 : 0) | (e_left ? 2 : 0) | (e_bot ? 4 : 0) | (e_top ? 8 : 0);
+        if (bits) atomicOr(&s_ch, bits);
+    }
+    __syncthreads();
+    if (w == 0) {
+        const int bits = s_ch;
+        int nb = -1;
+        if (lane == 0 && (bits & 1) && g.tx + 1 < g.tiles_x) nb = t + 1;
+        if (lane == 1 && (bits & 2) && g.tx > 0) nb = t - 1;
+        if (lane == 2 && (bits & 4) && g.ty + 1 < g.tiles_y) nb = t + g.tiles_x;
+        if (lane == 3 && (bits & 8) && g.ty > 0) nb = t - g.tiles_x;
+        const bool fresh = nb >= 0 && atomicExch(&dirty[nb], 1) == 0;
+        list_append(list, cnt, fresh, nb, lane);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Round boundary, over the relaxation tiling (64 x 32, four wavefronts of
 // eight rows).  Per pixel, in this order:
@@ -330,18 +454,24 @@ __global__ __launch_bounds__(NT) void k_init(Dev D) {
 //            the current excess.  Lists every sweep tile (64 x TH) with an
 //            active pixel as the sweeps' first list (buffer 0; the three
 //            counts are 0 beforehand) and clears the other flags.
-//  SNAPSHOT  the snapshot masks and the seed of the next global relabel
-//            (lab = 1 where u_f(p, t) > 0, |V| elsewhere); lists the tile as
-//            the relabel's first list (every dirty flag and seed_count are 0
-//            beforehand).
+//  SNAPSHOT  the snapshot masks and the next global relabel's first pass:
+//            the seeds (1 where u_f(p, t) > 0, |V| elsewhere) relaxed inside
+//            the tile to their fixpoint, with the halo at the neighbouring
+//            pixels' seeds (upper bounds of their levels, read from the sink
+//            residuals, which no kernel changes during this launch); the
+//            labels are stored and the neighbours across a side where a label
+//            fell below its seed form the relabel's first list (every dirty
+//            flag and seed_count are 0 beforehand).  A tile no neighbour
+//            lists is at its fixpoint for the halo it will see.
 // Retired instances are left untouched: no active or dirty flag.
 // ---------------------------------------------------------------------------
 // `mode` is a template argument, so that no branch on it separates a row's
 // loads from the next row's (the three combinations used are instantiated).
-template <int TH, unsigned mode>
+template <int TH, unsigned mode, bool SEG>
 __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
     static_assert(RELAX_TH % TH == 0, "sweep tiles nest in relaxation tiles");
     constexpr int RWB = RELAX_TH / 4;  // rows per wavefront
+    static_assert(RWB == RW, "the relaxation's row layout");
     const int rt = blockIdx.x;
     const Geo g = tile_geo<RELAX_TH, true>(D, rt);
     const bool retired = D.done[g.inst] != 0;  // workgroup-uniform
@@ -349,6 +479,8 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
     const int x = g.x0 + lane;
     __shared__ uint32_t smask[NMASK][TW];
     __shared__ uint32_t s_rows;
+    __shared__ int32_t edge[4][2][64];  // the fused first relaxation pass
+    __shared__ int s_ch;
     for (int i = threadIdx.x; i < NMASK * TW; i += NT) (&smask[0][0])[i] = 0;
     if (threadIdx.x == 0) s_rows = 0;
     uint32_t *tm = D.amask + size_t(rt) * NMASK * TW;
@@ -358,6 +490,9 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
     unsigned long long n_exact = 0, n_act = 0;
     uint32_t my[NMASK] = {0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t act_rows = 0;
+    int32_t d[RWB];  // the seeds of the next relabel (snapshot)
+#pragma unroll
+    for (int i = 0; i < RWB; ++i) d[i] = g.HV;
     if (!retired && x < g.W) {
         // every load of the wavefront's rows first, then the stores: a store
         // between them would keep the next row's loads behind it (the
@@ -398,7 +533,7 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
                 my[MK_U] |= uint32_t(ruv[i] > 0) << r;
                 my[MK_T] |= uint32_t(rsv[i] > 0) << r;
                 my[MK_E] |= uint32_t(ev[i] > 0) << r;
-                D.lab[p] = rsv[i] > 0 ? 1 : g.HV;
+                d[i] = rsv[i] > 0 ? 1 : g.HV;
             }
         }
     }
@@ -409,13 +544,48 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
     }
     if (act_rows) atomicOr(&s_rows, act_rows);
     __syncthreads();
-    if ((mode & BD_SNAPSHOT) && !retired) {
-        for (int i = threadIdx.x; i < NMASK * TW; i += NT) tm[i] = (&smask[0][0])[i];
-        // the flags were cleared before this launch and each relaxation tile
-        // seeds only itself: no exchange needed
-        if (threadIdx.x == 0) {
-            D.dirty[0][rt] = 1;
-            D.dlist[0][atomicAdd(&D.sc->seed_count, 1)] = rt;
+    if constexpr ((mode & BD_SNAPSHOT) != 0) {
+        if (!retired) {  // workgroup-uniform
+            for (int i = threadIdx.x; i < NMASK * TW; i += NT) tm[i] = (&smask[0][0])[i];
+            // the relabel's first pass on this tile: this wavefront's rows of
+            // the masks, the halo at the neighbouring pixels' seeds
+            if (threadIdx.x == 0) s_ch = 0;
+            const int sh = RW * w;
+            const uint32_t mR = (my[MK_R] >> sh) & 0xFFu, mL = (my[MK_L] >> sh) & 0xFFu;
+            const uint32_t mD = (my[MK_D] >> sh) & 0xFFu, mU = (my[MK_U] >> sh) & 0xFFu;
+            const bool colv = x < g.W;
+            const int yw = g.y0 + RW * w;
+            const int HV = g.HV;
+            auto seed = [&](int64_t q) { return D.rs[q] > 0 ? 1 : HV; };
+            int32_t top = HV, bot = HV, hs[RW], d0[RW];
+            if (w == 0 && colv && g.y0 > 0) top = seed(g.off + int64_t(g.y0 - 1) * g.W + x);
+            if (w == 3 && colv && g.y0 + RELAX_TH < g.H)
+                bot = seed(g.off + int64_t(g.y0 + RELAX_TH) * g.W + x);
+            const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int y = yw + r;
+                const bool use =
+                    (lane == 0 && ((mL >> r) & 1u)) || (lane == 63 && ((mR >> r) & 1u));
+                hs[r] = INT_MAX;
+                if (use && hx >= 0 && hx < g.W && y < g.H)
+                    hs[r] = seed(g.off + int64_t(y) * g.W + hx) + 1;
+                d0[r] = d[r];
+            }
+            tile_fixpoint<SEG, 1>(d, mR, mL, mD, mU, hs, top, bot, lane, w, edge);
+            // every label is stored (the array holds the last relabel's)
+            bool ch_top = false, ch_bot = false, ch_col = false;
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                if (!colv || yw + r >= g.H) continue;
+                D.lab[g.off + int64_t(yw + r) * g.W + x] = d[r];
+                if (d[r] == d0[r]) continue;
+                ch_col = true;
+                if (w == 0 && r == 0) ch_top = true;
+                if (w == 3 && r == RW - 1) ch_bot = true;
+            }
+            tile_list_changed(D, g, rt, ch_top, ch_bot, ch_col, lane, w, s_ch, D.dirty[0],
+                              D.dlist[0], &D.sc->seed_count);
         }
     }
     if (mode & BD_COUNT) {
@@ -429,13 +599,13 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
             }
             // lane k: the sweep tile of rows k*TH .. k*TH + TH - 1 of this tile
             const uint32_t rows = s_rows;
-            constexpr uint32_t SEG = TH >= 32 ? 0xFFFFFFFFu : ((1u << (TH & 31)) - 1u);
+            constexpr uint32_t TMASK = TH >= 32 ? 0xFFFFFFFFu : ((1u << (TH & 31)) - 1u);
             const int k = lane;
             int st = -1;
             bool a = false;
             if (k < RELAX_TH / TH && g.y0 + k * TH < g.H) {
                 st = D.inst[g.inst].tile_base + (g.ty * (RELAX_TH / TH) + k) * g.tiles_x + g.tx;
-                a = ((rows >> (k * TH)) & SEG) != 0;
+                a = ((rows >> (k * TH)) & TMASK) != 0;
                 D.act[0][st] = a ? 1 : 0;
                 D.act[1][st] = 0;
                 D.act[2][st] = 0;
@@ -537,9 +707,6 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 // so a round can carry more passes than its global relabel needs at little
 // cost.
 // ---------------------------------------------------------------------------
-constexpr int RW = 8;  // rows per wavefront of the cooperative relaxation
-constexpr int RELAX_GRID = 2048;  // most workgroups of a relaxation launch
-
 template <bool CUT, bool SEG>
 __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *cnt_cur,
                                                int32_t *cnt_next) {
@@ -583,7 +750,7 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
             mD = (tm[MK_D * TW] >> sh) & 0xFFu;
             mU = (tm[MK_U * TW] >> sh) & 0xFFu;
         }
-    #pragma unroll
+#pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int y = yw + r;
             d[r] = HV;
@@ -609,7 +776,7 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
         if (w == 3 && colv && g.y0 + RELAX_TH < g.H)
             bot = D.lab[g.off + int64_t(g.y0 + RELAX_TH) * g.W + x];
         const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
-    #pragma unroll
+#pragma unroll
         for (int r = 0; r < RW; ++r) {
             const int y = yw + r;
             const bool use = (lane == 0 && ((mL >> r) & 1u)) || (lane == 63 && ((mR >> r) & 1u));
@@ -617,86 +784,9 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
             if (use && hx >= 0 && hx < g.W && y < g.H)
                 hs[r] = D.lab[g.off + int64_t(y) * g.W + hx] + INC;
         }
-        // per row: the segment extents (SEG) or the scan offsets, less / plus the
-        // column shift of the min-plus form
-        int32_t segL[RW], segR[RW];
-    #pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            const uint64_t brkL = __ballot(!((mL >> r) & 1u)) | 1ull;
-            const uint64_t brkR = __ballot(!((mR >> r) & 1u)) | (1ull << 63);
-            if constexpr (SEG) {
-                const uint64_t low = lane == 63 ? ~0ull : (2ull << lane) - 1;
-                const int sx = 63 - __clzll((long long)(brkL & low));
-                const int ex = lane + __ffsll((unsigned long long)(brkR >> lane)) - 1;
-                segL[r] = lane - sx;
-                segR[r] = ex - lane;
-            } else {
-                // breaks at or left of the lane (left scan), strictly left of it
-                // (right scan): the lane's segment index in each direction
-                const uint32_t bl = __builtin_amdgcn_mbcnt_hi(
-                    uint32_t(brkL >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkL), 0u));
-                const uint32_t gl = bl + uint32_t((brkL >> lane) & 1ull);
-                const uint32_t gr = __builtin_amdgcn_mbcnt_hi(
-                    uint32_t(brkR >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(brkR), 0u));
-                segL[r] = int32_t((64u - gl) << OFF_SHIFT) - INC * lane;
-                segR[r] = int32_t(gr << OFF_SHIFT) + INC * lane;
-            }
-        }
-        edge[w][0][lane] = d[0];
-        edge[w][1][lane] = d[RW - 1];
-        __syncthreads();
-        if (w > 0) top = edge[w - 1][1][lane];
-        if (w < 3) bot = edge[w + 1][0][lane];
-        uint32_t rows = (1u << RW) - 1;           // wavefront-uniform
-        for (;;) {
-            __syncthreads();                      // the edges above were read
-            while ((rows = __builtin_amdgcn_readfirstlane(rows)) != 0) {
-    #pragma unroll
-                for (int r = 0; r < RW; ++r) {
-                    if (!((rows >> r) & 1u)) continue;
-                    int32_t nd = min(d[r], hs[r]);
-                    if constexpr (SEG) {
-                        nd = scan_from_left(nd - INC * lane, segL[r], lane) + INC * lane;
-                        nd = scan_from_right(nd + INC * lane, segR[r], lane) - INC * lane;
-                    } else {
-                        nd = prefix_min(nd + segL[r]) - segL[r];
-                        nd = suffix_min(nd + segR[r], lane) - segR[r];
-                    }
-                    d[r] = nd;
-                }
-                rows = 0;
-    #pragma unroll
-                for (int r = 0; r < RW; ++r) {
-                    const int32_t up = r == 0 ? top : d[r - 1];
-                    const int32_t nd = (mU >> r) & 1u ? min(d[r], up + INC) : d[r];
-                    if (__any(nd < d[r])) rows |= 1u << r;
-                    d[r] = nd;
-                }
-    #pragma unroll
-                for (int r = RW - 1; r >= 0; --r) {
-                    const int32_t dn = r == RW - 1 ? bot : d[r + 1];
-                    const int32_t nd = (mD >> r) & 1u ? min(d[r], dn + INC) : d[r];
-                    if (__any(nd < d[r])) rows |= 1u << r;
-                    d[r] = nd;
-                }
-            }
-            edge[w][0][lane] = d[0];
-            edge[w][1][lane] = d[RW - 1];
-            __syncthreads();
-            if (w > 0) {
-                const int32_t v = edge[w - 1][1][lane];
-                if (__any(v < top)) rows |= 1u;
-                top = min(top, v);
-            }
-            if (w < 3) {
-                const int32_t v = edge[w + 1][0][lane];
-                if (__any(v < bot)) rows |= 1u << (RW - 1);
-                bot = min(bot, v);
-            }
-            if (!__syncthreads_or(rows != 0)) break;
-        }
+        tile_fixpoint<SEG, INC>(d, mR, mL, mD, mU, hs, top, bot, lane, w, edge);
         bool ch_top = false, ch_bot = false, ch_col = false;
-    #pragma unroll
+#pragma unroll
         for (int r = 0; r < RW; ++r) {
             if (d[r] == d0[r]) continue;
             D.lab[g.off + int64_t(yw + r) * g.W + x] = d[r];
@@ -704,24 +794,8 @@ __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *c
             if (w == 0 && r == 0) ch_top = true;
             if (w == 3 && r == RW - 1) ch_bot = true;
         }
-        const bool e_top = __any(ch_top), e_bot = __any(ch_bot);
-        const bool e_left = __any(lane == 0 && ch_col), e_right = __any(lane == 63 && ch_col);
-        if (lane == 0) {
-            const int bits = (e_right ? 1 : 0) | (e_left ? 2 : 0) | (e_bot ? 4 : 0) |
-                             (e_top ? 8 : 0);
-            if (bits) atomicOr(&s_ch, bits);
-        }
-        __syncthreads();
-        if (w == 0) {  // lane i of wavefront 0 flags neighbour i (right, left, below, above)
-            const int bits = s_ch;
-            int nb = -1;
-            if (lane == 0 && (bits & 1) && g.tx + 1 < g.tiles_x) nb = t + 1;
-            if (lane == 1 && (bits & 2) && g.tx > 0) nb = t - 1;
-            if (lane == 2 && (bits & 4) && g.ty + 1 < g.tiles_y) nb = t + g.tiles_x;
-            if (lane == 3 && (bits & 8) && g.ty > 0) nb = t - g.tiles_x;
-            const bool fresh = nb >= 0 && atomicExch(&D.dirty[nxt][nb], 1) == 0;
-            list_append(D.dlist[nxt], cnt_next, fresh, nb, lane);
-        }
+        tile_list_changed(D, g, t, ch_top, ch_bot, ch_col, lane, w, s_ch, D.dirty[nxt],
+                          D.dlist[nxt], cnt_next);
     }
 }
 
@@ -1125,15 +1199,18 @@ struct Kern {
         hipLaunchKernelGGL(k_init<TH>, dim3(D.ntiles), dim3(NT), 0, s, D);
     }
     static void boundary(hipStream_t s, const Dev &D, unsigned mode) {
-        if (mode == BD_SNAPSHOT)
-            hipLaunchKernelGGL((k_boundary<TH, BD_SNAPSHOT>), dim3(D.ntiles_r), dim3(NT), 0, s,
-                               D);
-        else if (mode == (BD_ADOPT | BD_COUNT))
-            hipLaunchKernelGGL((k_boundary<TH, BD_ADOPT | BD_COUNT>), dim3(D.ntiles_r),
-                               dim3(NT), 0, s, D);
+        constexpr unsigned AC = BD_ADOPT | BD_COUNT, ACS = BD_ADOPT | BD_COUNT | BD_SNAPSHOT;
+        const dim3 gr(D.ntiles_r), bl(NT);
+        if (mode == AC)
+            hipLaunchKernelGGL((k_boundary<TH, AC, false>), gr, bl, 0, s, D);
+        else if (mode == BD_SNAPSHOT && D.seg_scan)
+            hipLaunchKernelGGL((k_boundary<TH, BD_SNAPSHOT, true>), gr, bl, 0, s, D);
+        else if (mode == BD_SNAPSHOT)
+            hipLaunchKernelGGL((k_boundary<TH, BD_SNAPSHOT, false>), gr, bl, 0, s, D);
+        else if (D.seg_scan)
+            hipLaunchKernelGGL((k_boundary<TH, ACS, true>), gr, bl, 0, s, D);
         else
-            hipLaunchKernelGGL((k_boundary<TH, BD_ADOPT | BD_COUNT | BD_SNAPSHOT>),
-                               dim3(D.ntiles_r), dim3(NT), 0, s, D);
+            hipLaunchKernelGGL((k_boundary<TH, ACS, false>), gr, bl, 0, s, D);
     }
     // the relaxation kernels run on the RELAX_TH tiling, one 4-wavefront
     // workgroup per listed tile
