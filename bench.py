@@ -65,11 +65,11 @@ GRID_SRC = os.path.join(ROOT, "paper_1110_6231_amd", "csrc", "grid_maxflow.hip")
 # source file at measurement time; a changed source reports null.
 MEASURED_TRAFFIC = {
     ("k_sweep<16>", "batched"): {
-        "source_sha256": "87522d65d10bc71e9e8f45e8505609f1bd29e8b04a2e7e9a4fe37f15cee46c3c",
-        "bytes_per_launch": 65998726},
+        "source_sha256": "94f812ea51ae47530051e9b225f805f58025a4f6525c0c02d88756c673da4ebe",
+        "bytes_per_launch": 66429667},
     ("k_relax4<false>", "batched"): {
-        "source_sha256": "87522d65d10bc71e9e8f45e8505609f1bd29e8b04a2e7e9a4fe37f15cee46c3c",
-        "bytes_per_launch": 7006513},
+        "source_sha256": "94f812ea51ae47530051e9b225f805f58025a4f6525c0c02d88756c673da4ebe",
+        "bytes_per_launch": 5584948},
 }
 
 
