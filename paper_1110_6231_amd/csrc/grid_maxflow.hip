@@ -615,32 +615,68 @@ __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
     }
 }
 
-// Cut-closure seed: label 0 for pixels holding excess, |V| elsewhere; every
-// relaxation tile is listed (every dirty flag and seed_count are 0
-// beforehand).
-template <int TH>
+// Cut closure, first pass: the seeds (label 0 for pixels holding excess,
+// |V| elsewhere) relaxed inside each 64 x 32 tile to their fixpoint over the
+// live residual arcs into each pixel (the run has stopped), with the halo at
+// the neighbouring pixels' seeds; every label is stored and the neighbours
+// across a side where a label fell below its seed form the closure's first
+// list (every dirty flag and seed_count are 0 beforehand).  The layout and
+// the fixpoint are those of a relaxation pass.
+template <bool SEG>
 __global__ __launch_bounds__(NT) void k_cut_seed(Dev D) {
+    static_assert(RELAX_TH == 4 * RW, "four wavefronts per relaxation tile");
     const int t = blockIdx.x;
-    const Geo g = tile_geo<TH, true>(D, t);
-    if (threadIdx.x == 0) {
-        D.dirty[0][t] = 1;
-        D.dlist[0][atomicAdd(&D.sc->seed_count, 1)] = t;
-    }
-    // every row's load first, from a clamped valid pixel, then the stores
-    const int c = threadIdx.x & (TW - 1);
-    const int x = g.x0 + c;
-    const int xc = min(x, g.W - 1);
-    int32_t ev[TH / RPP];
+    const Geo g = tile_geo<RELAX_TH, true>(D, t);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ int32_t edge[4][2][64];
+    __shared__ int s_ch;
+    if (threadIdx.x == 0) s_ch = 0;
+    const int HV = g.HV;
+    const int x = g.x0 + lane;
+    const bool colv = x < g.W;
+    const int yw = g.y0 + RW * w;
+    auto seed = [&](int64_t q) { return D.e[q] > 0 ? 0 : HV; };
+    int32_t d[RW], d0[RW];
+    uint32_t mR = 0, mL = 0, mD = 0, mU = 0;  // bit r: an arc into the pixel of row r
 #pragma unroll
-    for (int k = 0; k < TH / RPP; ++k) {
-        const int y = min(g.y0 + (threadIdx.x >> 6) + RPP * k, g.H - 1);
-        ev[k] = D.e[g.off + int64_t(y) * g.W + xc];
+    for (int r = 0; r < RW; ++r) {
+        const int y = yw + r;
+        d[r] = HV;
+        if (colv && y < g.H) {
+            const int64_t p = g.off + int64_t(y) * g.W + x;
+            d[r] = seed(p);
+            if (x + 1 < g.W) mR |= uint32_t(D.rl[p + 1] > 0) << r;
+            if (x > 0) mL |= uint32_t(D.rr[p - 1] > 0) << r;
+            if (y + 1 < g.H) mD |= uint32_t(D.ru[p + g.W] > 0) << r;
+            if (y > 0) mU |= uint32_t(D.rd[p - g.W] > 0) << r;
+        }
+        d0[r] = d[r];
     }
+    int32_t top = HV, bot = HV, hs[RW];
+    if (w == 0 && colv && g.y0 > 0) top = seed(g.off + int64_t(g.y0 - 1) * g.W + x);
+    if (w == 3 && colv && g.y0 + RELAX_TH < g.H)
+        bot = seed(g.off + int64_t(g.y0 + RELAX_TH) * g.W + x);
+    const int hx = lane == 0 ? g.x0 - 1 : g.x0 + 64;
 #pragma unroll
-    for (int k = 0; k < TH / RPP; ++k) {
-        const int y = g.y0 + (threadIdx.x >> 6) + RPP * k;
-        if (y < g.H && x < g.W) D.lab[g.off + int64_t(y) * g.W + x] = ev[k] > 0 ? 0 : g.HV;
+    for (int r = 0; r < RW; ++r) {
+        const int y = yw + r;
+        const bool use = (lane == 0 && ((mL >> r) & 1u)) || (lane == 63 && ((mR >> r) & 1u));
+        hs[r] = INT_MAX;
+        if (use && hx >= 0 && hx < g.W && y < g.H) hs[r] = seed(g.off + int64_t(y) * g.W + hx);
     }
+    tile_fixpoint<SEG, 0>(d, mR, mL, mD, mU, hs, top, bot, lane, w, edge);
+    bool ch_top = false, ch_bot = false, ch_col = false;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        if (!colv || yw + r >= g.H) continue;
+        D.lab[g.off + int64_t(yw + r) * g.W + x] = d[r];
+        if (d[r] == d0[r]) continue;
+        ch_col = true;
+        if (w == 0 && r == 0) ch_top = true;
+        if (w == 3 && r == RW - 1) ch_bot = true;
+    }
+    tile_list_changed(D, g, t, ch_top, ch_bot, ch_col, lane, w, s_ch, D.dirty[0], D.dlist[0],
+                      &D.sc->seed_count);
 }
 
 template <int TH>
@@ -1215,7 +1251,10 @@ struct Kern {
     // the relaxation kernels run on the RELAX_TH tiling, one 4-wavefront
     // workgroup per listed tile
     static void cut_seed(hipStream_t s, const Dev &D) {
-        hipLaunchKernelGGL(k_cut_seed<RELAX_TH>, dim3(D.ntiles_r), dim3(NT), 0, s, D);
+        if (D.seg_scan)
+            hipLaunchKernelGGL(k_cut_seed<true>, dim3(D.ntiles_r), dim3(NT), 0, s, D);
+        else
+            hipLaunchKernelGGL(k_cut_seed<false>, dim3(D.ntiles_r), dim3(NT), 0, s, D);
     }
     static void relax(bool cut, hipStream_t s, const Dev &D, int cur, const int32_t *cnt_cur,
                       int32_t *cnt_next) {
