@@ -266,29 +266,42 @@ def assign_roofline(st):
 
 
 def assign_single(torch, lpr, synth, reps=3):
-    """The dense n = 1024 max-weight assignment, mean of `reps` solves."""
+    """The dense n = 1024 max-weight assignment at the workload's alpha = 8,
+    mean of `reps` solves; beside it the library's built-in schedule for this
+    size (alpha 6)."""
     dev = torch.device("cuda:0")
     cost_np = synth.assign_uniform(1024, seed=0)
     cost = torch.as_tensor(cost_np, device=dev)
     ws = torch.empty(lpr.lpr_assign_workspace(1024), dtype=torch.uint8, device=dev)
-    lpr.lpr_assign_solve(cost, maximize=True, workspace=ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        _, tot, _, st = lpr.lpr_assign_solve(cost, maximize=True, workspace=ws)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+    a8 = lpr.make_assign_opts(alpha=8)
+
+    def mean_ms(opts):
+        lpr.lpr_assign_solve(cost, maximize=True, workspace=ws, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, tot, _, st = lpr.lpr_assign_solve(cost, maximize=True, workspace=ws,
+                                                 opts=opts)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, tot, st
+
+    dt, tot, st = mean_ms(a8)
+    dt_builtin, tot_b, st_b = mean_ms(None)
+    assert tot_b == tot
     _, tot2, _, sti = lpr.lpr_assign_solve(
         cost, maximize=True, workspace=ws,
-        opts=lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_TIME_KERNELS))
+        opts=lpr.make_assign_opts(alpha=8, flags=lpr.LPR_ASSIGN_TIME_KERNELS))
     assert tot2 == tot
     return {"workload": "dense assignment n=1024, weights U{0..1000}, "
-                        "max-weight, plain start (built-in schedule: alpha 6 at "
-                        "n >= 1024)",
+                        "max-weight, alpha=8, plain start",
             "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(dt * 1e3, 3),
             "total": tot, "refines": st["refines"], "phases": st["phases"],
             "pushes": st["pushes"], "relabels": st["relabels"],
             "price_updates": st["price_updates"],
+            "builtin_schedule": {"alpha": st_b["alpha"],
+                                 "ms_per_solve": round(dt_builtin * 1e3, 3),
+                                 "solves_per_s": round(1.0 / dt_builtin, 3),
+                                 "refines": st_b["refines"], "phases": st_b["phases"]},
             "roofline": assign_roofline(sti)}, cost_np
 
 
