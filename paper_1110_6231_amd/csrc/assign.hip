@@ -138,13 +138,32 @@ __global__ __launch_bounds__(256) void k_prep(const AInst *inst,
     const AInst I = inst[blockIdx.y];
     const int n = I.n, ld = ld16(n);
     unsigned m = 0;
-    for (int r = blockIdx.x; r < n; r += gridDim.x) {
-        const int32_t *src = costs + I.cost_off + int64_t(r) * n;
-        int16_t *dst = c16 + 2 * I.c16_off + int64_t(r) * ld;
-        for (int k = threadIdx.x; k < ld; k += 256) {
-            const int32_t c = k < n ? src[k] : 0;
-            m = max(m, c < 0 ? 0u - unsigned(c) : unsigned(c));
-            dst[k] = int16_t(max(-32768, min(32767, c)));
+    // PR rows x 512 columns per step with every load issued first (from a
+    // clamped valid entry; padding columns store 0), then the stores: one
+    // memory latency per step instead of one per row and column block
+    constexpr int PR = 4;
+    for (int r0 = blockIdx.x * PR; r0 < n; r0 += gridDim.x * PR) {
+        for (int k0 = 0; k0 < ld; k0 += 512) {
+            int32_t v[PR][2];
+#pragma unroll
+            for (int i = 0; i < PR; ++i) {
+                const int32_t *src = costs + I.cost_off + int64_t(min(r0 + i, n - 1)) * n;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) v[i][j] = src[min(k0 + int(threadIdx.x) + 256 * j, n - 1)];
+            }
+#pragma unroll
+            for (int i = 0; i < PR; ++i) {
+                if (r0 + i >= n) break;
+                int16_t *dst = c16 + 2 * I.c16_off + int64_t(r0 + i) * ld;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int k = k0 + threadIdx.x + 256 * j;
+                    if (k >= ld) break;
+                    const int32_t c = k < n ? v[i][j] : 0;
+                    m = max(m, c < 0 ? 0u - unsigned(c) : unsigned(c));
+                    dst[k] = int16_t(max(-32768, min(32767, c)));
+                }
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) m = max(m, unsigned(__shfl_xor(int(m), o, 64)));
@@ -173,9 +192,18 @@ __global__ __launch_bounds__(256) void k_transpose(const AInst *inst,
     if (c0 >= n || r0 >= n || cm > unsigned(LPR_ASSIGN_MAX_COST)) return;
     __shared__ int32_t tile[64][65];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < 64; r += 4) {
-        const int row = r0 + r, col = c0 + tx;
-        tile[r][tx] = row < n && col < n ? costs[I.cost_off + int64_t(row) * n + col] : 0;
+    // the sixteen loads of a thread from clamped valid entries first, then
+    // the zeros outside the matrix
+    int32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int row = min(r0 + ty + 4 * i, n - 1), col = min(c0 + tx, n - 1);
+        v[i] = costs[I.cost_off + int64_t(row) * n + col];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = ty + 4 * i;
+        tile[r][tx] = r0 + r < n && c0 + tx < n ? v[i] : 0;
     }
     __syncthreads();
     const bool narrow = cm <= C16_MAX;

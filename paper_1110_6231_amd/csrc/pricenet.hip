@@ -113,13 +113,23 @@ __global__ __launch_bounds__(256) void k_feat_rows1(const NInst *inst,
         const int32_t *row = costs + I.cost_off + int64_t(x) * I.n;
         int16_t *crow = c16 + I.c16_off + int64_t(x) * I.ld;
         int mn = INT_MAX;
-        for (int y = lane; y < I.n; y += 64) {
-            const int c = sign * row[y];
-            mn = min(mn, c);
-            const unsigned a = unsigned(c < 0 ? -c : c);
-            s += a;
-            amax = max(amax, a);
-            crow[y] = int16_t(max(-C16_MAX, min(C16_MAX, c)));
+        // eight columns per lane per step, every load issued first (from a
+        // clamped valid column), then the uses
+        for (int y0 = 0; y0 < I.n; y0 += 512) {
+            int v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = row[min(y0 + lane + 64 * k, I.n - 1)];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int y = y0 + lane + 64 * k;
+                if (y >= I.n) break;
+                const int c = sign * v[k];
+                mn = min(mn, c);
+                const unsigned a = unsigned(c < 0 ? -c : c);
+                s += a;
+                amax = max(amax, a);
+                crow[y] = int16_t(max(-C16_MAX, min(C16_MAX, c)));
+            }
         }
         if (lane < I.ld - I.n) crow[I.n + lane] = 0;  // padding
         for (int o = 32; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, 64));
