@@ -340,3 +340,34 @@ def test_same_pixel_count_other_shape_reuses_buffers():
         assert v == want_v, (H, W, v, want_v, st)
         np.testing.assert_array_equal(side.cpu().numpy(), want_side)
         assert st["rounds"] >= 2, st   # at least one replayed round
+
+
+def test_instance_past_the_offset_scan_limit():
+    """An instance of more than 2^25 - 66 pixels, whose labels the offset
+    row scans cannot hold, solved through the segmented scans the library
+    picks for it: 16 400 independent rows of 2 048 pixels, each a chain from
+    a source arc a at column 0 to a sink arc b at the last column through
+    horizontal arcs of capacity 50.  Closed forms: the row's flow is
+    min(a, b, 50); its minimal source side is empty when a is the least,
+    column 0 when 50 is, the whole row when b is."""
+    H, W, c = 16400, 2048, 50
+    assert H * W > (1 << 25) - 66
+    r = np.arange(H)
+    a = np.array([31, 41, 61, 71])[r % 4]
+    b = np.array([33, 47, 53, 67, 77])[r % 5]
+    src = np.zeros((H, W), np.int32)
+    snk = np.zeros((H, W), np.int32)
+    src[:, 0] = a
+    snk[:, -1] = b
+    horiz = np.full((H, W - 1), c, np.int32)
+    vert = np.zeros((H - 1, W), np.int32)
+    inst = synth.grid_from_pairs(H, W, src, snk, horiz, horiz, vert, vert, "chains")
+    del src, snk, horiz, vert
+    v, side, st = gpu_solve(inst)
+    flow = np.minimum(np.minimum(a, b), c)
+    assert v == int(flow.sum())
+    side = side.reshape(H, W)
+    want = np.zeros((H, W), np.uint8)
+    want[flow == c, 0] = 1
+    want[flow == b, :] = 1
+    np.testing.assert_array_equal(side, want)
