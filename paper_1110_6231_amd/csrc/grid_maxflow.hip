@@ -466,7 +466,8 @@ __device__ __forceinline__ void tile_list_changed(const Dev &D, const Geo &g, in
 // Retired instances are left untouched: no active or dirty flag.
 // ---------------------------------------------------------------------------
 // `mode` is a template argument, so that no branch on it separates a row's
-// loads from the next row's (the three combinations used are instantiated).
+// loads from the next row's (the three combinations used are instantiated,
+// the two with SNAPSHOT in both row-scan forms).
 template <int TH, unsigned mode, bool SEG>
 __global__ __launch_bounds__(NT) void k_boundary(Dev D) {
     static_assert(RELAX_TH % TH == 0, "sweep tiles nest in relaxation tiles");
@@ -741,7 +742,9 @@ __global__ __launch_bounds__(NT) void k_cut_write(Dev D, uint8_t *side) {
 // next list, once each (the flag), counting them in cnt_next.  A pass whose
 // list is empty returns at once (a launch of at most RELAX_GRID workgroups),
 // so a round can carry more passes than its global relabel needs at little
-// cost.
+// cost.  The first pass of a global relabel (every tile from its seeds) runs
+// inside the snapshot launch (k_boundary), that of the cut closure inside
+// k_cut_seed; the passes here start from the lists those leave.
 // ---------------------------------------------------------------------------
 template <bool CUT, bool SEG>
 __global__ __launch_bounds__(256) void k_relax4(Dev D, int cur, const int32_t *cnt_cur,
