@@ -271,13 +271,17 @@ def _dev_i32(a, device):
     return torch.as_tensor(np.ascontiguousarray(a, np.int32), device=device)
 
 
+# Host arrays for the C-ABI go through numpy: building a ctypes array element
+# by element costs about 0.3 us per entry, which a batch of a few hundred
+# instances pays on every call.  The returned pointer keeps its array alive.
 def _i32_arr(vals):
-    arr = (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
-    return arr
+    a = np.ascontiguousarray(vals, dtype=np.int32)
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
 
 
 def _i64_arr(vals):
-    return (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+    a = np.ascontiguousarray(vals, dtype=np.int64)
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
 
 
 def _workspace(nbytes: int, device):
