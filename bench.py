@@ -313,7 +313,7 @@ def assign_leg(args, torch, lpr, synth, single=True):
     packed = lpr.PackedAssign.from_matrices(mats, device=dev)
     wsb = torch.empty(lpr.lpr_assign_batched_workspace(packed.ns),
                       dtype=torch.uint8, device=dev)
-    wsn = torch.empty(lpr.lpr_pricenet_workspace(packed.ns), dtype=torch.uint8,
+    wsl = torch.empty(lpr.lpr_assign_learned_workspace(packed.ns), dtype=torch.uint8,
                       device=dev)
     params, kappa, meta = load_predictor(dev)
     timed = lpr.make_assign_opts(flags=lpr.LPR_ASSIGN_TIME_KERNELS)
@@ -322,7 +322,7 @@ def assign_leg(args, torch, lpr, synth, single=True):
         return lpr.lpr_assign_solve_batched(packed, opts=opts, workspace=wsb)
 
     def learned():
-        return learned_solve(packed, params, kappa, lpr, ws_net=wsn, ws_solve=wsb)
+        return learned_solve(packed, params, kappa, lpr, workspace=wsl)
 
     def median_time(fn, k=5):
         fn()

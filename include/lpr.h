@@ -569,6 +569,32 @@ lpr_status lpr_pricenet_infer(int32_t B, const int32_t *n,
                               int64_t *eps0, void *workspace,
                               size_t workspace_bytes, void *stream);
 
+/* Prediction and warm-started batched solve in one call: lpr_pricenet_infer
+ * (col_prices and eps0 into the workspace) followed by
+ * lpr_assign_solve_batched with init_col_prices and eps0_per_instance set to
+ * them (Algorithm 5.0 from the predicted prices; exact whatever is
+ * predicted).  The solve's instance tables and cost copies are enqueued on a
+ * second stream of the library's (created on the first call of a thread on a
+ * device, default priority, kept until the process ends) so that they
+ * overlap the prediction; the call waits for everything the caller enqueued
+ * on `stream` before it and returns after completion like the other solves.
+ * params and kappa as for lpr_pricenet_infer (kappa > 0); row_to_col,
+ * totals, col_prices, opts and stats as for lpr_assign_solve_batched, where
+ * opts (or NULL) must leave init_col_prices, eps0 and eps0_per_instance
+ * unset.  workspace: device, at least lpr_assign_learned_workspace(B, n)
+ * bytes.  Errors: LPR_EINVAL (arguments, kappa <= 0, start fields set in
+ * opts), LPR_ENOMEM (workspace too small), and those of the two calls. */
+size_t lpr_assign_learned_workspace(int32_t B, const int32_t *n);
+lpr_status lpr_assign_solve_learned(int32_t B, const int32_t *n,
+                                    const int64_t *cost_offset,
+                                    const int32_t *costs, int32_t maximize,
+                                    const float *params, float kappa,
+                                    int32_t *row_to_col, int64_t *totals,
+                                    int64_t *col_prices,
+                                    const lpr_assign_opts *opts,
+                                    lpr_assign_stats *stats, void *workspace,
+                                    size_t workspace_bytes, void *stream);
+
 /* One training step on a batch.  target_prices: device int64 [sum n], scaled
  * column prices of an optimal solution (e.g. lpr_assign_solve's col_prices);
  * they are normalised to t = (p - mean p) / (sc (2n+1)) internally.  Loss

@@ -1286,8 +1286,9 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
                       int32_t *row_to_col, int64_t *totals, int64_t *col_prices,
                       const lpr_assign_opts *opts, lpr_assign_stats *stats,
                       void *workspace, size_t ws_bytes, void *stream,
-                      int32_t sparse = 0) {
-    if (!sparse) clear_error();
+                      int32_t sparse = 0, hipStream_t side = nullptr,
+                      hipEvent_t fork = nullptr, hipEvent_t join = nullptr) {
+    if (!sparse && !side) clear_error();
     if (B < 1 || !n || !cost_offset || !costs || !row_to_col || !totals ||
         !workspace) {
         set_error("invalid arguments (NULL pointer or B < 1)");
@@ -1377,20 +1378,32 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     hipStream_t s = static_cast<hipStream_t>(stream);
     CallTimer call(s);
     call.start();
+    // the tables, the counters and the cost copies go on `side` when the
+    // caller forks them there (they then overlap work the caller enqueued
+    // on `s` after `fork`); k_assign waits for them through `join`
+    hipStream_t sp = s;
+    if (side) {
+        LPR_TRY_HIP(hipStreamWaitEvent(side, fork, 0));
+        sp = side;
+    }
     LPR_TRY_HIP(hipMemcpyAsync(L.inst, insts.data(), sizeof(AInst) * B,
-                               hipMemcpyHostToDevice, s));
+                               hipMemcpyHostToDevice, sp));
     LPR_TRY_HIP(hipMemcpyAsync(L.order, order.data(), sizeof(int32_t) * B,
-                               hipMemcpyHostToDevice, s));
-    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.counters), 0, NCNT, s));
-    LPR_TRY(fill_i32(L.status, -1, B, s));
-    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.cmax), 0, B, s));
+                               hipMemcpyHostToDevice, sp));
+    LPR_TRY(fill_i64(reinterpret_cast<int64_t *>(L.counters), 0, NCNT, sp));
+    LPR_TRY(fill_i32(L.status, -1, B, sp));
+    LPR_TRY(fill_i32(reinterpret_cast<int32_t *>(L.cmax), 0, B, sp));
     const int gx = int(std::min<int64_t>(512, std::max<int64_t>(1, (nnmax + 4095) / 4096)));
-    hipLaunchKernelGGL(k_prep, dim3(gx, B), dim3(256), 0, s, L.inst, costs, L.c16, L.cmax);
+    hipLaunchKernelGGL(k_prep, dim3(gx, B), dim3(256), 0, sp, L.inst, costs, L.c16, L.cmax);
     LPR_TRY_HIP(hipGetLastError());
     const unsigned tiles = unsigned((nmax + 63) / 64);
-    hipLaunchKernelGGL(k_transpose, dim3(B, tiles, tiles), dim3(256), 0, s, L.inst,
+    hipLaunchKernelGGL(k_transpose, dim3(B, tiles, tiles), dim3(256), 0, sp, L.inst,
                        costs, L.cmax, L.c16);
     LPR_TRY_HIP(hipGetLastError());
+    if (side) {
+        LPR_TRY_HIP(hipEventRecord(join, side));
+        LPR_TRY_HIP(hipStreamWaitEvent(s, join, 0));
+    }
     AArgs A;
     A.inst = L.inst;
     A.order = L.order;
@@ -1485,6 +1498,15 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
         }
     }
     return LPR_OK;
+}
+
+lpr_status run_forked(int32_t B, const int32_t *n, const int64_t *cost_offset,
+                      const int32_t *costs, int32_t maximize, int32_t *row_to_col,
+                      int64_t *totals, int64_t *col_prices, const lpr_assign_opts *opts,
+                      lpr_assign_stats *stats, void *workspace, size_t ws_bytes,
+                      void *stream, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+    return run(B, n, cost_offset, costs, maximize, row_to_col, totals, col_prices, opts,
+               stats, workspace, ws_bytes, stream, 0, side, fork, join);
 }
 
 }  // namespace assign

@@ -127,6 +127,33 @@ lpr_status fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
     return LPR_OK;
 }
 
+lpr_status side_stream(hipStream_t *side, hipEvent_t *fork, hipEvent_t *join) {
+    struct Side {
+        int dev;
+        hipStream_t s;
+        hipEvent_t fork, join;
+    };
+    static thread_local std::vector<Side> cache;
+    int dev = 0;
+    LPR_TRY_HIP(hipGetDevice(&dev));
+    for (const Side &c : cache)
+        if (c.dev == dev) {
+            *side = c.s;
+            *fork = c.fork;
+            *join = c.join;
+            return LPR_OK;
+        }
+    Side c{dev, nullptr, nullptr, nullptr};
+    LPR_TRY_HIP(hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking));
+    LPR_TRY_HIP(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
+    LPR_TRY_HIP(hipEventCreateWithFlags(&c.join, hipEventDisableTiming));
+    cache.push_back(c);
+    *side = c.s;
+    *fork = c.fork;
+    *join = c.join;
+    return LPR_OK;
+}
+
 }  // namespace lpr
 
 extern "C" const char *lpr_last_error(void) { return lpr::g_err; }

@@ -102,4 +102,21 @@ __global__ void k_fill_i64(int64_t *p, int64_t v, int64_t n);
 lpr_status fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 lpr_status fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 
+// A second stream of the current device for this thread (default priority,
+// non-blocking) with two events for forking work onto it and joining it
+// back; created on the first call and kept until the process ends.
+lpr_status side_stream(hipStream_t *side, hipEvent_t *fork, hipEvent_t *join);
+
+namespace assign {
+// The batched dense solve (lpr_assign_solve_batched) with its instance
+// tables, counters and cost copies enqueued on `side` after `fork` (an event
+// the caller recorded on `stream`), and the solve kernel on `stream` after
+// them (through `join`).
+lpr_status run_forked(int32_t B, const int32_t *n, const int64_t *cost_offset,
+                      const int32_t *costs, int32_t maximize, int32_t *row_to_col,
+                      int64_t *totals, int64_t *col_prices, const lpr_assign_opts *opts,
+                      lpr_assign_stats *stats, void *workspace, size_t ws_bytes,
+                      void *stream, hipStream_t side, hipEvent_t fork, hipEvent_t join);
+}  // namespace assign
+
 }  // namespace lpr

@@ -1304,6 +1304,108 @@ extern "C" lpr_status lpr_pricenet_infer(int32_t B, const int32_t *n,
     return LPR_OK;
 }
 
+// Learned start and solve in one call: the workspace holds the network's
+// workspace, the start prices and starting epsilons, and the solve's
+// workspace, each 256-B aligned.
+static size_t learned_layout(int32_t B, const int32_t *n, void *ws, size_t ws_bytes,
+                             void **net_ws, size_t *net_bytes, int64_t **prices,
+                             int64_t **eps0, void **solve_ws, size_t *solve_bytes) {
+    int64_t R = 0;
+    for (int b = 0; b < B; ++b) R += n[b];
+    *net_bytes = net::workspace_bytes(B, n);
+    *solve_bytes = lpr_assign_batched_workspace(B, n);
+    Carver cv(ws, ws_bytes);
+    *net_ws = cv.take<uint8_t>(*net_bytes);
+    *prices = cv.take<int64_t>(size_t(R));
+    *eps0 = cv.take<int64_t>(size_t(B));
+    *solve_ws = cv.take<uint8_t>(*solve_bytes);
+    return cv.used();
+}
+
+extern "C" size_t lpr_assign_learned_workspace(int32_t B, const int32_t *n) {
+    if (B < 1 || !n) return 0;
+    for (int b = 0; b < B; ++b)
+        if (n[b] < 1 || n[b] > LPR_ASSIGN_MAX_N) return 0;
+    void *a, *c;
+    int64_t *p, *e;
+    size_t na, nc;
+    return learned_layout(B, n, nullptr, 0, &a, &na, &p, &e, &c, &nc);
+}
+
+extern "C" lpr_status lpr_assign_solve_learned(
+    int32_t B, const int32_t *n, const int64_t *cost_offset, const int32_t *costs,
+    int32_t maximize, const float *params, float kappa, int32_t *row_to_col,
+    int64_t *totals, int64_t *col_prices, const lpr_assign_opts *opts,
+    lpr_assign_stats *stats, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (B < 1 || !n || !workspace) {
+        set_error("invalid arguments (NULL pointer or B < 1)");
+        return LPR_EINVAL;
+    }
+    if (!(kappa > 0.f)) {
+        set_error("kappa must be > 0");
+        return LPR_EINVAL;
+    }
+    if (opts && (opts->init_col_prices || opts->eps0 || opts->eps0_per_instance)) {
+        set_error("the start prices and epsilons are the call's own (opts must leave "
+                  "init_col_prices, eps0 and eps0_per_instance unset)");
+        return LPR_EINVAL;
+    }
+    const size_t need = lpr_assign_learned_workspace(B, n);
+    if (need == 0) {
+        set_error("invalid instance sizes");
+        return LPR_EINVAL;
+    }
+    if (workspace_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", workspace_bytes, need);
+        return LPR_ENOMEM;
+    }
+    void *net_ws, *solve_ws;
+    size_t net_bytes, solve_bytes;
+    int64_t *prices, *eps0;
+    learned_layout(B, n, workspace, workspace_bytes, &net_ws, &net_bytes, &prices, &eps0,
+                   &solve_ws, &solve_bytes);
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
+    LPR_TRY(side_stream(&side, &ev_fork, &ev_join));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // everything the caller enqueued before is visible to the side stream
+    LPR_TRY_HIP(hipEventRecord(ev_fork, s));
+    // the prediction on `s` (C, and the host tables its copies read, stay
+    // alive until the solve below has synchronised the stream)
+    net::Ctx C;
+    LPR_TRY(net::prepare(C, B, n, cost_offset, costs, net_ws, net_bytes, stream,
+                         params != nullptr));
+    LPR_TRY(net::run_features(C, costs, maximize ? -1 : 1, false, params != nullptr));
+    if (params) {
+        LPR_TRY(net::run_forward(C, params, false));
+    } else {
+        hipLaunchKernelGGL(net::k_q_sinkhorn, dim3(B), dim3(256), 0, C.s, C.L.inst, C.L.gpad,
+                           C.L.q);
+        LPR_TRY_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(net::k_prices, dim3(B), dim3(256), 0, C.s, C.L.inst, C.L.abssum,
+                       C.L.q, prices, kappa, eps0);
+    LPR_TRY_HIP(hipGetLastError());
+    // the solve: its cost copies run on the side stream beside the
+    // prediction, the solve kernel after both
+    lpr_assign_opts o{};
+    if (opts) o = *opts;
+    o.init_col_prices = prices;
+    o.eps0_per_instance = eps0;
+    const lpr_status rc = assign::run_forked(B, n, cost_offset, costs, maximize, row_to_col,
+                                             totals, col_prices, &o, stats, solve_ws,
+                                             solve_bytes, stream, side, ev_fork, ev_join);
+    if (rc != LPR_OK) {
+        // a solve that stopped early (options rejected, say) may leave the
+        // prediction in flight: it reads C's host tables and writes the
+        // caller's workspace, so it has to end before either goes away
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(side);
+    }
+    return rc;
+}
+
 extern "C" lpr_status lpr_pricenet_train_step(int32_t B, const int32_t *n,
                                               const int64_t *cost_offset,
                                               const int32_t *costs, int32_t maximize,

@@ -51,6 +51,7 @@ EXPORTED = [
     "lpr_assign_sparse_workspace", "lpr_assign_sparse_solve",
     "lpr_pricenet_param_count", "lpr_pricenet_workspace",
     "lpr_pricenet_features", "lpr_pricenet_infer", "lpr_pricenet_train_step",
+    "lpr_assign_learned_workspace", "lpr_assign_solve_learned",
     "lpr_graph_maxflow_workspace", "lpr_graph_maxflow",
     "lpr_mincost_flow_workspace", "lpr_mincost_flow",
     "lpr_atomic_probe",
@@ -218,6 +219,12 @@ def lib():
     L.lpr_pricenet_infer.restype = ctypes.c_int
     L.lpr_pricenet_infer.argtypes = [i32, i32p, i64p, vp, i32, vp, ctypes.c_float,
                                      vp, vp, vp, vp, sz, vp]
+    L.lpr_assign_learned_workspace.restype = sz
+    L.lpr_assign_learned_workspace.argtypes = [i32, i32p]
+    L.lpr_assign_solve_learned.restype = ctypes.c_int
+    L.lpr_assign_solve_learned.argtypes = [i32, i32p, i64p, vp, i32, vp, ctypes.c_float,
+                                           vp, vp, vp, ctypes.POINTER(AssignOpts),
+                                           ctypes.POINTER(AssignStats), vp, sz, vp]
     L.lpr_pricenet_train_step.restype = ctypes.c_int
     L.lpr_pricenet_train_step.argtypes = [i32, i32p, i64p, vp, i32, vp, vp, vp, vp,
                                           vp, i32, ctypes.c_float, vp, vp, sz, vp]
@@ -636,6 +643,35 @@ def lpr_pricenet_infer(packed: PackedAssign, params, maximize=False,
         ws.numel(), _stream(stream))
     _check(rc, "lpr_pricenet_infer")
     return q, prices, eps
+
+
+def lpr_assign_learned_workspace(ns) -> int:
+    return int(lib().lpr_assign_learned_workspace(len(ns), _i32_arr(ns)))
+
+
+def lpr_assign_solve_learned(packed: PackedAssign, params, kappa, maximize=False,
+                             opts: AssignOpts | None = None, want_prices=True,
+                             workspace=None, stream=None):
+    """Predicted start (params None: f14 alone) and the warm-started batched
+    solve in one library call.  Returns (row_to_col packed int32, totals
+    int64 tensor [B], col_prices packed or None, stats)."""
+    import torch
+    B = len(packed.ns)
+    dev = packed.costs.device
+    rows = int(packed.row_offset[-1])
+    r2c = torch.empty(rows, dtype=torch.int32, device=dev)
+    tots = torch.zeros(B, dtype=torch.int64, device=dev)
+    prices = torch.empty(rows, dtype=torch.int64, device=dev) if want_prices else None
+    ws = workspace if workspace is not None else _workspace(
+        lpr_assign_learned_workspace(packed.ns), dev)
+    st = AssignStats()
+    rc = lib().lpr_assign_solve_learned(
+        B, _i32_arr(packed.ns), _i64_arr(packed.cost_offset), _ptr(packed.costs),
+        int(bool(maximize)), _ptr(params), float(kappa), _ptr(r2c), _ptr(tots),
+        _ptr(prices), ctypes.byref(opts) if opts is not None else None,
+        ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "lpr_assign_solve_learned")
+    return r2c, tots, prices, _struct_dict(st)
 
 
 def lpr_pricenet_train_step(packed: PackedAssign, target_prices, params,

@@ -73,13 +73,10 @@ def load_predictor(device, path=DEFAULT_WEIGHTS):
     return torch.as_tensor(theta, device=device), kappa, meta
 
 
-def learned_solve(packed, params, kappa, lpr, ws_net=None, ws_solve=None):
+def learned_solve(packed, params, kappa, lpr, workspace=None):
     """Features + network (or f14 alone, params None) + warm-started solve,
-    all in the library."""
-    _, prices, eps = lpr.lpr_pricenet_infer(packed, params, kappa=kappa,
-                                            workspace=ws_net)
-    opts = lpr.make_assign_opts(init_col_prices=prices, eps0_per_instance=eps)
-    return lpr.lpr_assign_solve_batched(packed, opts=opts, workspace=ws_solve)
+    one library call (lpr_assign_solve_learned)."""
+    return lpr.lpr_assign_solve_learned(packed, params, kappa, workspace=workspace)
 
 
 def timed(fn, torch, reps=5):

@@ -198,3 +198,35 @@ def test_mincost_flow_host_checks():
              1 << 30, None) == lpr.LPR_EINVAL
     assert f(4, 2, *arcs, ctypes.byref(tot), None, None, None, None, fake, 16,
              None) == lpr.LPR_ENOMEM
+
+
+def test_learned_solve_host_checks():
+    """The one-call learned solve sizes its workspace as the prediction's,
+    the start prices and epsilons and the solve's together, and rejects on
+    the host, before anything reaches the device, kappa <= 0, start fields
+    set in the options, missing sizes and a small workspace."""
+    import ctypes
+    L = lpr.lib()
+    n = (ctypes.c_int32 * 2)(40, 300)
+    off = (ctypes.c_int64 * 3)(0, 1600, 1600 + 90000)
+    need = L.lpr_assign_learned_workspace(2, n)
+    parts = (L.lpr_pricenet_workspace(2, n) + L.lpr_assign_batched_workspace(2, n) +
+             8 * (340 + 2))
+    assert parts <= need <= parts + 5 * 256
+    assert L.lpr_assign_learned_workspace(0, n) == 0
+    assert L.lpr_assign_learned_workspace(1, (ctypes.c_int32 * 1)(0)) == 0
+    assert L.lpr_assign_learned_workspace(1, (ctypes.c_int32 * 1)(lpr.LPR_ASSIGN_MAX_N + 1)) == 0
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below is rejected
+
+    def solve(kappa, opts=None, nn=n, ws_bytes=1 << 40):
+        return L.lpr_assign_solve_learned(2, nn, off, fake, 0, None, kappa, fake, fake,
+                                          None, opts, None, fake, ws_bytes, None)
+
+    assert solve(0.0) == lpr.LPR_EINVAL
+    assert solve(-1.0) == lpr.LPR_EINVAL
+    assert solve(0.01, nn=None) == lpr.LPR_EINVAL
+    for field in ("eps0", "init_col_prices", "eps0_per_instance"):
+        o = lpr.make_assign_opts()
+        setattr(o, field, 8)
+        assert solve(0.01, opts=ctypes.byref(o)) == lpr.LPR_EINVAL, field
+    assert solve(0.01, ws_bytes=need - 1) == lpr.LPR_ENOMEM

@@ -414,3 +414,68 @@ def test_full_batched_workload_against_oracle(seed):
             assert is_permutation(r2c[a:b], m.shape[0]), (name, k)
             assert int(m[np.arange(m.shape[0]), r2c[a:b]].astype(np.int64).sum()) == want[k]
             assert scaled_eps_certificate(m, r2c[a:b], prices[a:b]), (name, k)
+
+
+def test_learned_solve_in_one_call_matches_two_calls_and_oracle():
+    """lpr_assign_solve_learned (prediction and warm-started solve in one
+    call, the solve's cost copies on the library's second stream) against
+    lpr_pricenet_infer followed by lpr_assign_solve_batched, on a batch that
+    spans the three Sinkhorn launch classes and both cost widths: equal
+    totals, equal to the Hungarian oracle, permutations with certified
+    prices; then a second, smaller batch through the same call, and a call
+    on a stream of the caller's own."""
+    from paper_1110_6231_amd.train_pricenet import load_predictor
+    params, kappa, _ = load_predictor("cuda")
+    sizes = [700, 512, 300, 64, 33, 1, 1100, 257]
+    mats = [synth.assign_points(n, seed=3, instance=k + 1) for k, n in enumerate(sizes)]
+    mats[2] = mats[2] * 1000  # beyond int16: the int32 cost path
+    for rnd, batch in enumerate((mats, mats[3:6])):
+        packed = _packed(batch)
+        print(f"[net] one-call learned solve, batch {rnd}: n = {packed.ns}", flush=True)
+        want = np.array([oracle.assign(m)[1] for m in batch])
+        _, prices0, eps0 = lpr.lpr_pricenet_infer(packed, params, kappa=kappa)
+        two = lpr.lpr_assign_solve_batched(
+            packed, opts=lpr.make_assign_opts(init_col_prices=prices0,
+                                              eps0_per_instance=eps0))
+        one = lpr.lpr_assign_solve_learned(packed, params, kappa)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            own = lpr.lpr_assign_solve_learned(packed, params, kappa, stream=side)
+        side.synchronize()
+        offs = packed.row_offset
+        for name, (r2c, tots, prices, st) in (("two calls", two), ("one call", one),
+                                               ("own stream", own)):
+            np.testing.assert_array_equal(tots.cpu().numpy(), want, err_msg=name)
+            r2c, prices = r2c.cpu().numpy(), prices.cpu().numpy()
+            for k, m in enumerate(batch):
+                a, b = offs[k], offs[k + 1]
+                assert is_permutation(r2c[a:b], m.shape[0]), (name, k)
+                assert scaled_eps_certificate(m, r2c[a:b], prices[a:b]), (name, k)
+        assert one[3]["refines"] == two[3]["refines"]
+
+
+def test_learned_solve_in_one_call_rejects_bad_arguments():
+    """kappa <= 0, start fields already set in the options and a workspace
+    smaller than lpr_assign_learned_workspace are rejected before any work
+    is enqueued; options the solve rejects after the prediction was enqueued
+    end the call cleanly; a valid call afterwards is exact."""
+    from paper_1110_6231_amd.train_pricenet import load_predictor
+    params, kappa, _ = load_predictor("cuda")
+    packed = _packed([synth.assign_points(40, seed=0, instance=1)])
+    print("[net] one-call learned solve argument checks", flush=True)
+    with pytest.raises(lpr.LprError):
+        lpr.lpr_assign_solve_learned(packed, params, 0.0)
+    with pytest.raises(lpr.LprError):
+        lpr.lpr_assign_solve_learned(packed, params, kappa,
+                                     opts=lpr.make_assign_opts(eps0=5))
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lpr.LprError):
+        lpr.lpr_assign_solve_learned(packed, params, kappa, workspace=small)
+    # rejected by the solve after the prediction was enqueued
+    with pytest.raises(lpr.LprError):
+        lpr.lpr_assign_solve_learned(packed, params, kappa,
+                                     opts=lpr.make_assign_opts(alpha=1))
+    r2c, tots, _, _ = lpr.lpr_assign_solve_learned(packed, params, kappa)
+    mat = synth.assign_points(40, seed=0, instance=1)
+    assert int(tots[0]) == oracle.assign(mat)[1]
+    assert is_permutation(r2c.cpu().numpy(), 40)
