@@ -307,7 +307,10 @@ typedef struct {
     int32_t alpha;                  /* epsilon divisor per refine; 0 -> the
                                        tuned default (lpr_assign_tune), else
                                        6 for dense calls whose largest
-                                       instance has n >= 1024, 8 otherwise  */
+                                       instance has n >= 1024, 16 for dense
+                                       calls from the plain start whose
+                                       largest instance has n <= 512, 8
+                                       otherwise                           */
     int32_t flags;                  /* LPR_ASSIGN_* bits                     */
     int64_t eps0;                   /* initial epsilon of the Min-Cost loop in
                                        scaled units (costs times 2n+1); the
@@ -334,8 +337,10 @@ typedef struct {
     int32_t tail_rows;              /* a refine switches to one wavefront
                                        running operations back to back once
                                        at most this many rows are active;
-                                       0 -> the tuned default, else
-                                       min(32, max(8, 8192 / n))             */
+                                       0 -> the tuned default, else 32 for
+                                       dense calls whose largest instance
+                                       has n <= 512 and min(32, max(8,
+                                       8192 / n)) per instance otherwise   */
     int32_t fixing_shift;           /* for tests of the rerun path: divides
                                        the arc-fixing bound by
                                        2^fixing_shift (0..63; 0 = the
@@ -356,8 +361,11 @@ typedef struct {
                                        -1 -> never                         */
     int32_t price_update_quarters;  /* q of the default period n q / 4
                                        (1..64); 0 -> the tuned default, else
-                                       2 for n <= 512 and 4 above (measured
-                                       best on the batched and the n = 1024
+                                       1 for dense warm starts (given prices
+                                       or epsilon) whose largest instance
+                                       has n <= 512, and per instance 2 for
+                                       n <= 512 and 4 above (measured best
+                                       on the batched and the n = 1024
                                        workloads)                          */
     int32_t reserved;               /* must be 0                            */
 } lpr_assign_opts;

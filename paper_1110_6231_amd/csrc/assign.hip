@@ -1328,13 +1328,22 @@ static lpr_status run(int32_t B, const int32_t *n, const int64_t *cost_offset,
     // schedule fields the options leave 0
     const bool warm = opts && (opts->init_col_prices || opts->eps0 || opts->eps0_per_instance);
     const ASched ds = default_asched(sched_key(B, n, warm, sparse));
-    // built-in alpha: 6 for dense calls whose largest instance has
-    // n >= 1024, 8 otherwise (measured: the dense n = 1024 workload is
-    // faster at 6, the batched one and the sparse n = 2048 one at 8)
-    int32_t alpha = ds.alpha ? ds.alpha : (nmax >= 1024 && !sparse ? 6 : 8);
+    // built-in rules (the fields a tuned schedule leaves 0), measured on
+    // the dense workloads: alpha 6 when the largest instance has n >= 1024
+    // (the n = 1024 solve); for batches of instances up to n = 512, alpha
+    // 16 from the plain start and 8 from a warm one, a tail of 32 rows, and
+    // from a warm start a price update every n/4 operations (the batched
+    // workload over seeds 0-4: plain 8 % and warm 5.5 % faster than alpha 8
+    // with the per-instance tail and period); alpha 8 otherwise, also for
+    // the sparse solve (n = 2048)
+    const bool small = nmax <= 512 && !sparse;
+    int32_t alpha = ds.alpha ? ds.alpha
+                             : (nmax >= 1024 && !sparse ? 6 : (small && !warm ? 16 : 8));
     int64_t eps0 = 0, max_ops = 64 * int64_t(nmax) * nmax + (int64_t(1) << 20);
     int64_t max_ms = 20000, pu_period = 0, warm_max_ops = 0;
-    int32_t tail_rows = ds.tail, pu_q = ds.q, pu_start = 1, arc_fixing = 0, fixing_shift = 0;
+    int32_t tail_rows = ds.tail ? ds.tail : (small ? 32 : 0);
+    int32_t pu_q = ds.q ? ds.q : (small && warm ? 1 : 0);
+    int32_t pu_start = 1, arc_fixing = 0, fixing_shift = 0;
     const int64_t *init = nullptr, *eps0_inst = nullptr;
     bool timing = false;
     if (opts) {

@@ -324,8 +324,9 @@ def test_autotuner_is_exact_and_sets_default():
     assert tot.cpu().numpy().tolist() == want
     assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (5, 3, 12)
     # a warm start is its own kind: untuned, it keeps the built-in rules
+    # (instances up to n = 512: alpha 8, q 1, tail 32)
     eps = torch.full((len(mats),), 1 << 12, dtype=torch.int64, device="cuda")
     _, tot, _, st = lpr.lpr_assign_solve_batched(
         packed, opts=lpr.make_assign_opts(eps0_per_instance=eps))
     assert tot.cpu().numpy().tolist() == want
-    assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (8, 0, 0)
+    assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (8, 1, 32)
