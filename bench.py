@@ -324,19 +324,28 @@ def assign_leg(args, torch, lpr, synth, single=True):
     def learned():
         return learned_solve(packed, params, kappa, lpr, workspace=wsl)
 
-    def median_time(fn, k=5):
-        fn()
-        ts = []
+    def median_times(fa, fb, k=9):
+        """Median wall times of k solves of each start, alternating (after
+        one warm-up of each), with the last results."""
+        fa()
+        fb()
+        ta, tb = [], []
         for _ in range(k):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        return float(np.median(ts)), r
+            for fn, ts in ((fa, ta), (fb, tb)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                if fn is fa:
+                    ra = r
+                else:
+                    rb = r
+        return (float(np.median(ta)), float(np.median(tb)), ra[1], rb[1], ra[3], rb[3])
 
-    tp, (_, tot_p, _, stp) = median_time(plain)
-    tl, (_, tot_l, _, stl) = median_time(learned)
+    # a batch ends with its slowest instance, whose time varies by several
+    # per cent from run to run: medians of 9, the two starts interleaved
+    tp, tl, tot_p, tot_l, stp, stl = median_times(plain, learned)
     assert torch.equal(tot_p, tot_l), "learned start changed an optimum"
     sti = plain(timed)[3]
     out["batched"] = {"workload": "256 optical-flow-like instances, "
