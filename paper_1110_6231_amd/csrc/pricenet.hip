@@ -338,6 +338,24 @@ __device__ inline void wave_reduce4(const float (&v)[4], float (&out)[4]) {
     out[1] = lane_f(c, 32);
     out[3] = lane_f(c, 48);
 }
+// Two rows: after the halves swap, one register holds row 0 in lanes 0-31
+// and row 1 in lanes 32-63; swapping its 16-lane rows with themselves folds
+// each half onto 16 lanes, which the DPP steps then reduce.
+template <bool MIN>
+__device__ inline void wave_reduce2(const float (&v)[2], float (&out)[2]) {
+    const auto s01 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[0]),
+                                                      __float_as_uint(v[1]), false, false);
+    const float a = op2<MIN>(__uint_as_float(s01[0]), __uint_as_float(s01[1]));
+    const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(a),
+                                                    false, false);
+    float c = op2<MIN>(__uint_as_float(t[0]), __uint_as_float(t[1]));
+    c = op2<MIN>(c, dpp_f<0xB1>(c));
+    c = op2<MIN>(c, dpp_f<0x4E>(c));
+    c = op2<MIN>(c, dpp_f<0x141>(c));
+    c = op2<MIN>(c, dpp_f<0x140>(c));
+    out[0] = lane_f(c, 0);
+    out[1] = lane_f(c, 32);
+}
 
 // V: 8-entry groups per lane per row (rows up to 512 V entries); RW: rows a
 // wavefront takes at once (their loads and reductions overlap).  ids[] lists
@@ -403,6 +421,8 @@ __global__ __launch_bounds__(64 * SINK_W) void k_sinkhorn(const NInst *inst,
             }
             if constexpr (RW == 4) {
                 wave_reduce4<true>(part_r, m);
+            } else if constexpr (RW == 2) {
+                wave_reduce2<true>(part_r, m);
             } else {
 #pragma unroll
                 for (int r = 0; r < RW; ++r) m[r] = wave_minf(part_r[r]);
@@ -423,6 +443,8 @@ __global__ __launch_bounds__(64 * SINK_W) void k_sinkhorn(const NInst *inst,
             }
             if constexpr (RW == 4) {
                 wave_reduce4<false>(part_r, sr);
+            } else if constexpr (RW == 2) {
+                wave_reduce2<false>(part_r, sr);
             } else {
 #pragma unroll
                 for (int r = 0; r < RW; ++r) sr[r] = wave_sumf(part_r[r]);
