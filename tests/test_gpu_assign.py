@@ -330,3 +330,27 @@ def test_autotuner_is_exact_and_sets_default():
         packed, opts=lpr.make_assign_opts(eps0_per_instance=eps))
     assert tot.cpu().numpy().tolist() == want
     assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (8, 1, 32)
+
+
+def test_builtin_schedule_rules():
+    """With no tuned schedule for the size class, the built-in rules apply:
+    a dense batch whose largest instance has n <= 512 runs alpha 16 and a
+    32-row tail from the plain start, alpha 8, q 1 and a 32-row tail from a
+    warm start; n = 1024 runs alpha 6 with the per-instance period and
+    tail; the totals equal the oracle's under each."""
+    mats = [synth.assign_random_small(n, seed=n, lo=0, hi=900) for n in (100, 200)]
+    packed = lpr.PackedAssign.from_matrices(mats)
+    want = [oracle.assign(m)[1] for m in mats]
+    print("[assign] built-in schedule rules", flush=True)
+    _, tot, _, st = lpr.lpr_assign_solve_batched(packed)
+    assert tot.cpu().numpy().tolist() == want
+    assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (16, 0, 32)
+    eps = torch.full((2,), 1 << 10, dtype=torch.int64, device="cuda")
+    _, tot, _, st = lpr.lpr_assign_solve_batched(
+        packed, opts=lpr.make_assign_opts(eps0_per_instance=eps))
+    assert tot.cpu().numpy().tolist() == want
+    assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (8, 1, 32)
+    big = synth.assign_uniform(1024, seed=3)
+    _, tot1, _, st = lpr.lpr_assign_solve(big, maximize=True)
+    assert tot1 == oracle.assign(big, maximize=True)[1]
+    assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (6, 0, 0)
