@@ -317,8 +317,9 @@ def test_autotuner_is_exact_and_sets_default():
     assert ms > 0
     _, tot, _, st = lpr.lpr_assign_solve_batched(packed)
     assert tot.cpu().numpy().tolist() == want
+    # a tuned 0 is the built-in rule: a 32-row tail for instances up to 512
     assert (st["alpha"], st["price_update_quarters"], st["tail_rows"]) == (
-        sched["alpha"], sched["price_update_quarters"], sched["tail_rows"])
+        sched["alpha"], sched["price_update_quarters"], sched["tail_rows"] or 32)
     o = lpr.make_assign_opts(alpha=5, price_update_quarters=3, tail_rows=12)
     _, tot, _, st = lpr.lpr_assign_solve_batched(packed, opts=o)
     assert tot.cpu().numpy().tolist() == want
