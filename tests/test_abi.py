@@ -230,3 +230,23 @@ def test_learned_solve_host_checks():
         setattr(o, field, 8)
         assert solve(0.01, opts=ctypes.byref(o)) == lpr.LPR_EINVAL, field
     assert solve(0.01, ws_bytes=need - 1) == lpr.LPR_ENOMEM
+
+
+def test_host_array_marshalling():
+    """Host size and offset arrays reach the C-ABI as contiguous int32 /
+    int64 buffers with the caller's values; a value outside the type's range
+    is an error, not a silent wrap."""
+    import ctypes
+    import numpy as np
+    vals = [5, 0, -3, 2 ** 31 - 1]
+    p = lpr._i32_arr(vals)
+    assert [p[i] for i in range(4)] == vals
+    q = lpr._i64_arr(np.array([0, 2 ** 40, -7], dtype=np.int64))
+    assert [q[i] for i in range(3)] == [0, 2 ** 40, -7]
+    assert isinstance(p, ctypes.POINTER(ctypes.c_int32))
+    with pytest.raises(OverflowError):
+        lpr._i32_arr([2 ** 31])
+    # the sizes a batched call passes: the workspace size of an instance list
+    ns = [3, 7, 11]
+    assert lpr.lpr_assign_batched_workspace(ns) == lpr.lib().lpr_assign_batched_workspace(
+        3, (ctypes.c_int32 * 3)(*ns))

@@ -479,3 +479,7 @@ def test_learned_solve_in_one_call_rejects_bad_arguments():
     mat = synth.assign_points(40, seed=0, instance=1)
     assert int(tots[0]) == oracle.assign(mat)[1]
     assert is_permutation(r2c.cpu().numpy(), 40)
+    # without the price output (col_prices NULL)
+    r2c, tots, pr, _ = lpr.lpr_assign_solve_learned(packed, params, kappa,
+                                                     want_prices=False)
+    assert pr is None and int(tots[0]) == oracle.assign(mat)[1]
