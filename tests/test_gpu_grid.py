@@ -300,6 +300,39 @@ def test_full_batched_workload_against_golden(mode):
         off += inst.n_pixels
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_full_batched_workload_other_seeds(seed):
+    """The batched graph-cut workload drawn with other seeds (64 blob grids
+    plus the 2048 x 2048 grid with pair weights x4, 10.5 M pixels, one
+    call): every flow value and every minimal source side equal to the FIFO
+    oracle's, computed here over a pool of host threads (one instance per
+    task, largest first)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    insts = synth.grid_batch(seed=seed)
+    Hs = [i.H for i in insts]
+    Ws = [i.W for i in insts]
+    print(f"[grid] full batched workload seed {seed}: {len(insts)} grids, "
+          f"{sum(i.n_pixels for i in insts)} pixels", flush=True)
+    flows, side, st = lpr.lpr_grid_maxflow_batched(Hs, Ws, _pack(insts))
+    flows = flows.cpu().numpy()
+    side = side.cpu().numpy()
+    print(f"[grid] seed {seed} solved ({st['rounds']} global relabels); oracle next",
+          flush=True)
+    oracle.lib()
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    order = sorted(range(len(insts)), key=lambda k: -insts[k].n_pixels)
+    with ThreadPoolExecutor(cores) as ex:
+        got = dict(zip(order, ex.map(lambda k: oracle.grid_maxflow(insts[k], "fifo"),
+                                     order)))
+    off = 0
+    for k, inst in enumerate(insts):
+        want_v, want_side = got[k]
+        assert flows[k] == want_v, (seed, k, inst.name)
+        assert np.array_equal(side[off:off + inst.n_pixels], want_side), (seed, k)
+        off += inst.n_pixels
+
+
 def test_autotuner_is_exact_and_sets_default():
     insts = [synth.grid_blobs(160 + 40 * k, 230, seed=k) for k in range(3)]
     Hs = [i.H for i in insts]
