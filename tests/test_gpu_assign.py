@@ -50,10 +50,15 @@ def test_random_sizes(n):
 
 
 def test_uniform_config_n1024():
-    """The dense n = 1024 max-weight workload (weights U{0..1000}, alpha 8)."""
-    for seed in range(2):
-        st = check(synth.assign_uniform(1024, seed=seed), maximize=True)
-        print("[assign] n=1024 stats", st, flush=True)
+    """The dense n = 1024 max-weight workload (weights U{0..1000}) on seeds
+    0-4, at the workload's alpha 8 and at the built-in schedule: totals equal
+    to the Hungarian oracle's, permutations, certified prices."""
+    for seed in range(5):
+        c = synth.assign_uniform(1024, seed=seed)
+        st = check(c, maximize=True, opts=lpr.make_assign_opts(alpha=8))
+        st_b = check(c, maximize=True)
+        print(f"[assign] n=1024 seed {seed}: alpha 8 {st['refines']} refines, "
+              f"built-in alpha {st_b['alpha']} {st_b['refines']} refines", flush=True)
 
 
 def test_points_config():
